@@ -1,0 +1,1137 @@
+/*
+ * vafr_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow CPU reference for the VaFR hot path: the acuity-derived
+ * log-polar (LP) layout, one primary ray per LP texel, closest hit against a
+ * triangle soup, Lambert shading with one shadow ray, and the inverse map of
+ * the LP buffer onto display pixels.  It also covers the LMFR log-polar
+ * comparison mapping and the full-resolution ray cast.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  The product path never calls it, and it shares no
+ * code, header or table with the product path.
+ *
+ * Citations name sections and equations of "Visual Acuity Consistent Foveated
+ * Rendering towards Retinal Resolution" (Zhang, Gai, Li; arXiv 2503.23410).
+ * Where the paper is silent the reading taken is stated at the point of use.
+ *
+ * Precision: every mapping quantity is FP64 (libm).  The ray/triangle test is
+ * the FP32 watertight test of Woop, Benthin and Wald (JCGT 2013), written out
+ * with every rounding stated, because that test *is* the method being checked:
+ * given the same FP32 ray, it decides hits exactly.  Build with
+ * -ffp-contract=off so that no multiply-add is fused unless fmaf() says so.
+ *
+ * Parity pins: each function below is pinned by a test in tests/ against a
+ * value the paper prints, a closed form, an invariant or brute force; the
+ * path-tracing shading mode is the one part whose colour values are pinned
+ * only by closed-form special cases (see or_shade_path_rays).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_MAX_SEG 16
+#define OR_DEG (M_PI / 180.0)
+
+/* ------------------------------------------------------------------------ */
+/* Threads                                                                    */
+/* ------------------------------------------------------------------------ */
+
+void or_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int or_get_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Acuity model: Sec. 3.2.1 Eq. (2), segmented per Sec. 3.3 Eq. (12)         */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int n_seg;
+    double e_piv[OR_MAX_SEG + 1]; /* pivot eccentricities, degrees           */
+    double m[OR_MAX_SEG];         /* MAR slope on segment k (deg/cycle/deg)  */
+    double b[OR_MAX_SEG];         /* MAR intercept: omega_k(e) = m e + b     */
+    double c[OR_MAX_SEG];         /* additive constant of u on segment k     */
+    double u_piv[OR_MAX_SEG + 1]; /* u at each pivot                         */
+} or_acuity;
+
+int or_acuity_size(void) { return (int)sizeof(or_acuity); }
+
+/* MAR on segment k, Eq. (2): omega = m e + omega_0 with the segment's own
+ * slope and intercept (Eq. (12)). */
+static double seg_omega(const or_acuity* a, int k, double e) { return a->m[k] * e + a->b[k]; }
+
+/* Eq. (5) on segment k (Eq. (12)), before the constant c_k is added. */
+static double seg_u_raw(const or_acuity* a, int k, double e) {
+    if (a->m[k] == 0.0) return 2.0 * e / a->b[k];   /* limit m -> 0 of Eq. (5) */
+    return 2.0 * log(seg_omega(a, k, e)) / a->m[k];
+}
+
+/*
+ * Pivots -> segments.  Reading of Sec. 3.3: MAR (the reciprocal of the acuity
+ * f) is linear between consecutive pivots (e_k, f_k), i.e. Eq. (2) holds on
+ * each segment with omega(e_k) = 1/f_k and omega(e_{k+1}) = 1/f_{k+1}.  The
+ * constants c_k follow from u(0) = 0 and continuity of u at the pivots (the
+ * paper leaves c_0 and the c_k unspecified).  Returns 0 on success.
+ */
+int or_acuity_init(or_acuity* a, int n_piv, const double* ecc, const double* cpd) {
+    if (n_piv < 2 || n_piv > OR_MAX_SEG + 1) return -1;
+    if (ecc[0] != 0.0) return -1;
+    for (int k = 0; k < n_piv; ++k) {
+        if (!(cpd[k] > 0.0)) return -1;
+        if (k > 0 && !(ecc[k] > ecc[k - 1])) return -1;
+    }
+    memset(a, 0, sizeof(*a));
+    a->n_seg = n_piv - 1;
+    for (int k = 0; k < n_piv; ++k) a->e_piv[k] = ecc[k];
+    for (int k = 0; k < a->n_seg; ++k) {
+        double w0 = 1.0 / cpd[k], w1 = 1.0 / cpd[k + 1];
+        a->m[k] = (w1 - w0) / (ecc[k + 1] - ecc[k]);
+        a->b[k] = w0 - a->m[k] * ecc[k];
+    }
+    a->u_piv[0] = 0.0;
+    for (int k = 0; k < a->n_seg; ++k) {
+        a->c[k] = a->u_piv[k] - seg_u_raw(a, k, a->e_piv[k]);
+        a->u_piv[k + 1] = seg_u_raw(a, k, a->e_piv[k + 1]) + a->c[k];
+    }
+    return 0;
+}
+
+/* Segment holding eccentricity e; the last segment extends past the last
+ * pivot (needed for the last partial column and off-axis corners). */
+static int seg_of_e(const or_acuity* a, double e) {
+    int k = 0;
+    while (k < a->n_seg - 1 && e >= a->e_piv[k + 1]) ++k;
+    return k;
+}
+
+static int seg_of_u(const or_acuity* a, double u) {
+    int k = 0;
+    while (k < a->n_seg - 1 && u >= a->u_piv[k + 1]) ++k;
+    return k;
+}
+
+/* Eq. (2): minimum angle of resolution at eccentricity e (degrees). */
+double or_omega(const or_acuity* a, double e) { return seg_omega(a, seg_of_e(a, e), e); }
+
+/* Eq. (5) / Eq. (12): LP abscissa of eccentricity e (degrees). */
+double or_u(const or_acuity* a, double e) {
+    int k = seg_of_e(a, e);
+    return seg_u_raw(a, k, e) + a->c[k];
+}
+
+/* Eq. (10), segmented as Sec. 3.3 states: eccentricity of LP abscissa u. */
+double or_e_of_u(const or_acuity* a, double u) {
+    int k = seg_of_u(a, u);
+    if (a->m[k] == 0.0) return (u - a->c[k]) * a->b[k] / 2.0;
+    return (exp((u - a->c[k]) * a->m[k] / 2.0) - a->b[k]) / a->m[k];
+}
+
+/* Eq. (9): shading height l(e) = 360 sin(2e) / omega(e), angles in degrees. */
+double or_l(const or_acuity* a, double e) { return 360.0 * sin(2.0 * e * OR_DEG) / or_omega(a, e); }
+
+/* Eq. (8): LP ordinate of a point at eccentricity e and polar angle theta. */
+double or_v(const or_acuity* a, double e, double theta) {
+    return theta * sin(2.0 * e * OR_DEG) / or_omega(a, e);
+}
+
+void or_u_many(const or_acuity* a, const double* e, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = or_u(a, e[i]);
+}
+void or_e_many(const or_acuity* a, const double* u, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = or_e_of_u(a, u[i]);
+}
+void or_l_many(const or_acuity* a, const double* e, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = or_l(a, e[i]);
+}
+void or_omega_many(const or_acuity* a, const double* e, int64_t n, double* out) {
+    for (int64_t i = 0; i < n; ++i) out[i] = or_omega(a, e[i]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Constant-size LP buffer: Sec. 3.2.2                                        */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Discretisation (the paper gives the continuous sizes u(e_max) and l(e) but
+ * not the sampling): there are ceil(u(e_max)) columns; column i is sampled at
+ * its centre u = i + 1/2, i.e. at eccentricity e_i = e(i + 1/2) (Eq. (10));
+ * it holds n_i = ceil(l(e_i)) texels (Eq. (9)), rounded up so the tangential
+ * rate never drops below the acuity model; row j sits at polar angle
+ * theta_ij = 360 (j + 1/2) / n_i degrees so the rows tile the full circle.
+ */
+int or_vafr_layout_dims(const or_acuity* a, double e_max, int32_t* n_cols, int64_t* n_texels) {
+    double umax = or_u(a, e_max);
+    int32_t nc = (int32_t)ceil(umax);
+    int64_t tot = 0;
+    for (int32_t i = 0; i < nc; ++i) {
+        double e = or_e_of_u(a, i + 0.5);
+        tot += (int64_t)ceil(or_l(a, e));
+    }
+    *n_cols = nc;
+    *n_texels = tot;
+    return 0;
+}
+
+/*
+ * Tables of the layout.  dxy holds, per texel in column-major order
+ * (all rows of column 0, then column 1, ...), the film-plane offset of the
+ * texel's screen point from the gaze point, in units of the focal length:
+ * rho = tan e_i (Eq. (3) with the pixel pitch factored out) along the
+ * direction theta_ij (Eq. (11)).  FP64 throughout, rounded to FP32 once.
+ */
+int or_vafr_layout_fill(const or_acuity* a, double e_max, int32_t n_cols, int32_t* n_rows,
+                        int64_t* col_off, float* dxy, double* col_e) {
+    (void)e_max;
+    int64_t off = 0;
+    for (int32_t i = 0; i < n_cols; ++i) {
+        double e = or_e_of_u(a, i + 0.5);
+        int32_t n = (int32_t)ceil(or_l(a, e));
+        n_rows[i] = n;
+        col_off[i] = off;
+        if (col_e) col_e[i] = e;
+        double rho = tan(e * OR_DEG);
+        if (dxy) {
+            for (int32_t j = 0; j < n; ++j) {
+                double th = 360.0 * (j + 0.5) / n;
+                dxy[2 * (off + j) + 0] = (float)(rho * cos(th * OR_DEG));
+                dxy[2 * (off + j) + 1] = (float)(rho * sin(th * OR_DEG));
+            }
+        }
+        off += n;
+    }
+    col_off[n_cols] = off;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Display <-> film plane (Sec. 3.2.1, Eq. (3))                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Eq. (3) converts a pixel distance r to eccentricity with the constant c_r
+ * (film height / focal length / display height).  The display may have
+ * non-square pixels (a 16:9 panel with a square field of view), so the
+ * conversion is kept per axis: the film plane is at unit focal length and a
+ * pixel spans px = 2 tan(fov_x/2) / W horizontally and py = 2 tan(fov_y/2)/H
+ * vertically; for square pixels c_r = py.  Screen x grows right, y grows down;
+ * the continuous pixel point (x, y) maps to ((x - W/2) px, (y - H/2) py).
+ */
+void or_film_pitch(int32_t W, int32_t H, double fov_x_deg, double fov_y_deg, double* p) {
+    p[0] = 2.0 * tan(0.5 * fov_x_deg * OR_DEG) / W;
+    p[1] = 2.0 * tan(0.5 * fov_y_deg * OR_DEG) / H;
+}
+
+void or_gaze_film(int32_t W, int32_t H, const double* p, double gx, double gy, double* G) {
+    G[0] = (gx - 0.5 * W) * p[0];
+    G[1] = (gy - 0.5 * H) * p[1];
+}
+
+/*
+ * Forward map of a continuous pixel point to LP coordinates:
+ * e = atan(rho) (Eq. (3)), theta = polar angle of the offset from the gaze
+ * measured from +x toward +y (screen down) in [0, 360), u = u(e) (Eq. (5)),
+ * v = v(e, theta) (Eq. (8)).  Eccentricity is the angle subtended at the eye
+ * by the film-plane distance from the gaze point (the paper's Eq. (3) read
+ * literally), which keeps the map a translation of the gaze point.
+ */
+void or_vafr_forward(const or_acuity* a, int32_t W, int32_t H, const double* p, const double* G,
+                     int64_t n, const double* xy, double* u, double* v, double* e_out, double* th_out) {
+    for (int64_t i = 0; i < n; ++i) {
+        double X = (xy[2 * i] - 0.5 * W) * p[0];
+        double Y = (xy[2 * i + 1] - 0.5 * H) * p[1];
+        double dx = X - G[0], dy = Y - G[1];
+        double rho = sqrt(dx * dx + dy * dy);
+        double e = atan(rho) / OR_DEG;
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        if (u) u[i] = or_u(a, e);
+        if (v) v[i] = or_v(a, e, th);
+        if (e_out) e_out[i] = e;
+        if (th_out) th_out[i] = th;
+    }
+}
+
+/*
+ * Inverse map, Eqs. (10)-(11): e from u, theta = 360 v / l(e), then the
+ * screen point at film distance tan e from the gaze along theta.
+ */
+void or_vafr_inverse(const or_acuity* a, int32_t W, int32_t H, const double* p, const double* G,
+                     int64_t n, const double* u, const double* v, double* xy) {
+    for (int64_t i = 0; i < n; ++i) {
+        double e = or_e_of_u(a, u[i]);
+        double th = 360.0 * v[i] / or_l(a, e);
+        double rho = tan(e * OR_DEG);
+        double X = G[0] + rho * cos(th * OR_DEG);
+        double Y = G[1] + rho * sin(th * OR_DEG);
+        xy[2 * i] = X / p[0] + 0.5 * W;
+        xy[2 * i + 1] = Y / p[1] + 0.5 * H;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rays                                                                       */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * A primary ray leaves the eye (pinhole) through the continuous film point
+ * P = (Px, Py) (Sec. 6.1: a ray per LP texel from its screen position).
+ * Camera basis: right R, up U, forward F (unit focal length), film y down.
+ * The direction  D = Px R - Py U + F  is formed in FP64 from the FP32 basis,
+ * operation by operation ((Px*R - Py*U) + F, no fused multiply-add), and
+ * rounded to FP32 once; it is not normalised (the hit test does not need it).
+ * cam = {eye[3], right[3], up[3], forward[3]}.
+ */
+static void make_ray(const float* cam, double Px, double Py, float* o, float* d) {
+    for (int k = 0; k < 3; ++k) {
+        double a = Px * (double)cam[3 + k];
+        double b = Py * (double)cam[6 + k];
+        double s = a - b;
+        double t = s + (double)cam[9 + k];
+        o[k] = cam[k];
+        d[k] = (float)t;
+    }
+}
+
+/* VaFR: texel k's ray passes through P = G + dxy[k] (Sec. 6.1). */
+void or_vafr_rays(const float* dxy, const int64_t* idx, int64_t n, const double* G, const float* cam,
+                  float* org, float* dir) {
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t k = idx[i];
+        double Px = G[0] + (double)dxy[2 * k];
+        double Py = G[1] + (double)dxy[2 * k + 1];
+        make_ray(cam, Px, Py, org + 3 * i, dir + 3 * i);
+    }
+}
+
+/* Full resolution: one ray through each display pixel centre. */
+void or_full_rays(int32_t W, int32_t H, const double* p, const int64_t* pix, int64_t n, const float* cam,
+                  float* org, float* dir) {
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t x = pix[i] % W, y = pix[i] / W;
+        double Px = ((double)x + 0.5 - 0.5 * W) * p[0];
+        double Py = ((double)y + 0.5 - 0.5 * H) * p[1];
+        make_ray(cam, Px, Py, org + 3 * i, dir + 3 * i);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* LMFR log-polar comparison mapping: Sec. 3.1 Eq. (1), Sec. 4.1 Eq. (14)    */
+/* ------------------------------------------------------------------------ */
+
+/* LP buffer of the comparison: (W/delta) x (H/delta), rounded to the nearest
+ * integer (Sec. 2.1 and Sec. 5.2: delta^2 is the ratio of display pixels to
+ * LP pixels). */
+void or_lmfr_dims(int32_t W, int32_t H, double delta, int32_t* w, int32_t* h) {
+    *w = (int32_t)lround(W / delta);
+    *h = (int32_t)lround(H / delta);
+}
+
+/* L of Eq. (1): the log of the longest distance (pixels) from the gaze point
+ * to a screen corner. */
+double or_lmfr_L(int32_t W, int32_t H, double gx, double gy) {
+    double best = 0.0;
+    const double cx[4] = {0.0, (double)W, 0.0, (double)W};
+    const double cy[4] = {0.0, 0.0, (double)H, (double)H};
+    for (int c = 0; c < 4; ++c) {
+        double dx = cx[c] - gx, dy = cy[c] - gy;
+        double d = sqrt(dx * dx + dy * dy);
+        if (d > best) best = d;
+    }
+    return log(best);
+}
+
+/*
+ * Inverse of Eq. (1) with the LMFR kernel K(z) = z^alpha (Eq. (14), alpha =
+ * 4): texel (i, j) of the w x h buffer (column-major, k = i h + j) sits at
+ * z = ((i + 1/2)/w)^(1/alpha), pixel radius r = exp(L z) and polar angle
+ * theta = 360 (j + 1/2)/h from the gaze; its ray goes through
+ * P = G + (r cos theta px, r sin theta py).
+ */
+void or_lmfr_rays(int32_t W, int32_t H, const double* p, double gx, double gy, int32_t w, int32_t h,
+                  double alpha, const int64_t* idx, int64_t n, const float* cam, float* org, float* dir) {
+    double L = or_lmfr_L(W, H, gx, gy);
+    double G[2];
+    or_gaze_film(W, H, p, gx, gy, G);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t k = idx[q];
+        int64_t i = k / h, j = k % h;
+        double z = pow((i + 0.5) / w, 1.0 / alpha);
+        double r = exp(L * z);
+        double th = 360.0 * (j + 0.5) / h;
+        double Px = G[0] + (r * cos(th * OR_DEG)) * p[0];
+        double Py = G[1] + (r * sin(th * OR_DEG)) * p[1];
+        make_ray(cam, Px, Py, org + 3 * q, dir + 3 * q);
+    }
+}
+
+/* Forward map of Eq. (1) with K(z) = z^alpha for continuous pixel points;
+ * the radius is clamped to >= 1 pixel so that z >= 0. */
+void or_lmfr_forward(int32_t W, int32_t H, double gx, double gy, int32_t w, int32_t h, double alpha,
+                     int64_t n, const double* xy, double* u, double* v) {
+    double L = or_lmfr_L(W, H, gx, gy);
+    for (int64_t q = 0; q < n; ++q) {
+        double dx = xy[2 * q] - gx, dy = xy[2 * q + 1] - gy;
+        double r = sqrt(dx * dx + dy * dy);
+        if (r < 1.0) r = 1.0;
+        double z = log(r) / L;
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        u[q] = pow(z, alpha) * w;
+        v[q] = th / 360.0 * h;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2(1), 2013)       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+    int valid;
+} or_shear;
+
+/* Per-ray set-up: the axis of largest |d| becomes z (first such axis on
+ * ties), x and y follow cyclically and swap when d_z < 0 to keep the winding;
+ * the shear constants are correctly rounded FP32 quotients. */
+static void shear_init(const float* d, or_shear* s) {
+    int kz = 0;
+    if (fabsf(d[1]) > fabsf(d[kz])) kz = 1;
+    if (fabsf(d[2]) > fabsf(d[kz])) kz = 2;
+    int kx = kz + 1 == 3 ? 0 : kz + 1;
+    int ky = kx + 1 == 3 ? 0 : kx + 1;
+    if (d[kz] < 0.0f) { int t = kx; kx = ky; ky = t; }
+    s->kx = kx; s->ky = ky; s->kz = kz;
+    s->valid = d[kz] != 0.0f;
+    if (s->valid) {
+        s->Sx = d[kx] / d[kz];
+        s->Sy = d[ky] / d[kz];
+        s->Sz = 1.0f / d[kz];
+    }
+}
+
+typedef struct {
+    int hit;       /* edge test passed, det != 0 and t > 0 */
+    float t;       /* T / det, in units of |d|             */
+    double margin; /* hits: min edge weight / sum; misses: outside weight / sum */
+    int t_pos;     /* T / det > 0 (meaningful when det != 0) */
+} or_tri_res;
+
+/*
+ * Arithmetic (all FP32 unless stated):
+ *   A = v0 - o, B = v1 - o, C = v2 - o
+ *   Ax = fma(-Sx, A_kz, A_kx), Ay = fma(-Sy, A_kz, A_ky)     (same for B, C)
+ *   U = Cx By - Cy Bx, V = Ax Cy - Ay Cx, W = Bx Ay - By Ax  (no fused ops,
+ *       so an edge shared by two triangles gets exactly negated values)
+ *   if any of U, V, W is exactly zero: recompute all three from the FP32
+ *       operands in FP64 and round each to FP32
+ *   mixed signs -> miss (two-sided test); det = (U + V) + W; det == 0 -> miss
+ *   T = (U Sz A_kz + V Sz B_kz) + W Sz C_kz   (each Sz * _kz rounded first)
+ *   t = T / det (correctly rounded); hit iff t > 0.
+ */
+static void watertight(const float* o, const float* d, const or_shear* s, const float* v0,
+                       const float* v1, const float* v2, or_tri_res* r) {
+    (void)d; /* the ray enters only through its shear constants */
+    r->hit = 0;
+    r->t = INFINITY;
+    r->margin = 1.0;
+    r->t_pos = 0;
+    if (!s->valid) return;
+    const int kx = s->kx, ky = s->ky, kz = s->kz;
+    float A[3], B[3], C[3];
+    for (int k = 0; k < 3; ++k) {
+        A[k] = v0[k] - o[k];
+        B[k] = v1[k] - o[k];
+        C[k] = v2[k] - o[k];
+    }
+    float Ax = fmaf(-s->Sx, A[kz], A[kx]);
+    float Ay = fmaf(-s->Sy, A[kz], A[ky]);
+    float Bx = fmaf(-s->Sx, B[kz], B[kx]);
+    float By = fmaf(-s->Sy, B[kz], B[ky]);
+    float Cx = fmaf(-s->Sx, C[kz], C[kx]);
+    float Cy = fmaf(-s->Sy, C[kz], C[ky]);
+    float p1, p2;
+    p1 = Cx * By; p2 = Cy * Bx; float U = p1 - p2;
+    p1 = Ax * Cy; p2 = Ay * Cx; float V = p1 - p2;
+    p1 = Bx * Ay; p2 = By * Ax; float W = p1 - p2;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    int neg = (U < 0.0f) || (V < 0.0f) || (W < 0.0f);
+    int pos = (U > 0.0f) || (V > 0.0f) || (W > 0.0f);
+    double aU = fabs((double)U), aV = fabs((double)V), aW = fabs((double)W);
+    double S = aU + aV + aW;
+    float det = (U + V) + W;
+    float Az = s->Sz * A[kz];
+    float Bz = s->Sz * B[kz];
+    float Cz = s->Sz * C[kz];
+    float T = (U * Az + V * Bz) + W * Cz;
+    float t = det != 0.0f ? T / det : INFINITY;
+    r->t = t;
+    r->t_pos = det != 0.0f && t > 0.0f;
+    if (S > 0.0) {
+        if (neg && pos) {
+            double sn = (U < 0.0f ? aU : 0.0) + (V < 0.0f ? aV : 0.0) + (W < 0.0f ? aW : 0.0);
+            double sp = S - sn;
+            r->margin = (sn < sp ? sn : sp) / S;
+        } else {
+            double mn = aU < aV ? aU : aV;
+            mn = mn < aW ? mn : aW;
+            r->margin = mn / S;
+        }
+    }
+    if (neg && pos) return;
+    if (det == 0.0f) return;
+    r->hit = t > 0.0f;
+}
+
+/* Test-visible form: n rays x one triangle each (used by the pins). */
+void or_watertight_many(int64_t n, const float* org, const float* dir, const float* tri9, int32_t* hit,
+                        float* t, double* margin) {
+    for (int64_t i = 0; i < n; ++i) {
+        or_shear s;
+        or_tri_res r;
+        shear_init(dir + 3 * i, &s);
+        watertight(org + 3 * i, dir + 3 * i, &s, tri9 + 9 * i, tri9 + 9 * i + 3, tri9 + 9 * i + 6, &r);
+        hit[i] = r.hit;
+        t[i] = r.t;
+        margin[i] = r.margin;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Scene and the oracle's own BVH (spatial-midpoint splits, FP64 boxes)     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    double lo[3], hi[3];
+    int64_t left, right;  /* children; -1 for a leaf */
+    int64_t first, count; /* leaf triangle range in perm[] */
+} or_node;
+
+typedef struct {
+    int64_t n_tris;
+    float* tv;           /* 9 floats per triangle, original order and winding */
+    int use_bvh;
+    or_node* nodes;
+    int64_t n_nodes, cap_nodes;
+    int64_t* perm;
+    int max_depth;
+    double pad;          /* absolute box padding */
+} or_scene;
+
+static void tri_bounds(const or_scene* sc, int64_t t, double* lo, double* hi) {
+    const float* v = sc->tv + 9 * t;
+    for (int k = 0; k < 3; ++k) {
+        double a = v[k], b = v[3 + k], c = v[6 + k];
+        double mn = a < b ? a : b; mn = mn < c ? mn : c;
+        double mx = a > b ? a : b; mx = mx > c ? mx : c;
+        lo[k] = mn; hi[k] = mx;
+    }
+}
+
+static int64_t new_node(or_scene* sc) {
+    if (sc->n_nodes == sc->cap_nodes) {
+        sc->cap_nodes = sc->cap_nodes ? 2 * sc->cap_nodes : 1024;
+        sc->nodes = (or_node*)realloc(sc->nodes, sc->cap_nodes * sizeof(or_node));
+    }
+    return sc->n_nodes++;
+}
+
+/* Top-down build: split at the midpoint of the centroid bounds along their
+ * widest axis; if that leaves one side empty, split the range in half.
+ * Leaves hold at most 4 triangles.  Box padding makes every box test
+ * conservative (the FP64 slab test's own error is far below the padding). */
+static int64_t build_rec(or_scene* sc, double* cen, int64_t first, int64_t count, int depth) {
+    int64_t id = new_node(sc);
+    if (depth > sc->max_depth) sc->max_depth = depth;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t q = first; q < first + count; ++q) {
+        double tlo[3], thi[3];
+        int64_t t = sc->perm[q];
+        tri_bounds(sc, t, tlo, thi);
+        for (int k = 0; k < 3; ++k) {
+            if (tlo[k] < lo[k]) lo[k] = tlo[k];
+            if (thi[k] > hi[k]) hi[k] = thi[k];
+            double c = cen[3 * t + k];
+            if (c < clo[k]) clo[k] = c;
+            if (c > chi[k]) chi[k] = c;
+        }
+    }
+    or_node nd;
+    for (int k = 0; k < 3; ++k) { nd.lo[k] = lo[k] - sc->pad; nd.hi[k] = hi[k] + sc->pad; }
+    nd.left = nd.right = -1;
+    nd.first = first;
+    nd.count = count;
+    if (count <= 4) { sc->nodes[id] = nd; return id; }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+        if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+    double mid = 0.5 * (clo[ax] + chi[ax]);
+    int64_t i = first, j = first + count - 1;
+    while (i <= j) {
+        if (cen[3 * sc->perm[i] + ax] < mid) ++i;
+        else { int64_t tmp = sc->perm[i]; sc->perm[i] = sc->perm[j]; sc->perm[j] = tmp; --j; }
+    }
+    int64_t nl = i - first;
+    if (nl == 0 || nl == count) nl = count / 2;
+    int64_t l = build_rec(sc, cen, first, nl, depth + 1);
+    int64_t r = build_rec(sc, cen, first + nl, count - nl, depth + 1);
+    nd.left = l; nd.right = r; nd.count = 0;
+    sc->nodes[id] = nd;
+    return id;
+}
+
+or_scene* or_scene_create(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris, int use_bvh) {
+    or_scene* sc = (or_scene*)calloc(1, sizeof(or_scene));
+    sc->n_tris = n_tris;
+    sc->tv = (float*)malloc((size_t)(n_tris > 0 ? n_tris : 1) * 9 * sizeof(float));
+    double ext = 0.0;
+    for (int64_t t = 0; t < n_tris; ++t)
+        for (int c = 0; c < 3; ++c) {
+            int64_t vi = tri[3 * t + c];
+            if (vi < 0 || vi >= n_verts) { free(sc->tv); free(sc); return NULL; }
+            for (int k = 0; k < 3; ++k) {
+                float f = xyz[3 * vi + k];
+                sc->tv[9 * t + 3 * c + k] = f;
+                if (fabs((double)f) > ext) ext = fabs((double)f);
+            }
+        }
+    sc->pad = 1e-5 * (1.0 + ext);
+    sc->use_bvh = use_bvh && n_tris > 0;
+    if (sc->use_bvh) {
+        sc->perm = (int64_t*)malloc(n_tris * sizeof(int64_t));
+        double* cen = (double*)malloc(3 * n_tris * sizeof(double));
+        for (int64_t t = 0; t < n_tris; ++t) {
+            sc->perm[t] = t;
+            const float* v = sc->tv + 9 * t;
+            for (int k = 0; k < 3; ++k) cen[3 * t + k] = ((double)v[k] + (double)v[3 + k] + (double)v[6 + k]) / 3.0;
+        }
+        build_rec(sc, cen, 0, n_tris, 0);
+        free(cen);
+    }
+    return sc;
+}
+
+void or_scene_destroy(or_scene* sc) {
+    if (!sc) return;
+    free(sc->tv); free(sc->nodes); free(sc->perm); free(sc);
+}
+
+int64_t or_scene_nodes(const or_scene* sc) { return sc->n_nodes; }
+int or_scene_depth(const or_scene* sc) { return sc->max_depth; }
+
+/* FP64 slab test against the padded box over [0, tmax]. */
+static int box_hit(const or_node* nd, const float* o, const float* d, double tmax) {
+    double tn = 0.0, tf = tmax;
+    for (int k = 0; k < 3; ++k) {
+        double ok = o[k], dk = d[k];
+        if (dk == 0.0) {
+            if (ok < nd->lo[k] || ok > nd->hi[k]) return 0;
+            continue;
+        }
+        double t0 = (nd->lo[k] - ok) / dk, t1 = (nd->hi[k] - ok) / dk;
+        if (t0 > t1) { double tmp = t0; t0 = t1; t1 = tmp; }
+        if (t0 > tn) tn = t0;
+        if (t1 < tf) tf = t1;
+        if (tn > tf) return 0;
+    }
+    return 1;
+}
+
+#define OR_TIE 1e-6
+
+typedef struct {
+    int32_t id;       /* winner, -1 on miss */
+    float t;
+    double margin;    /* winner's edge margin */
+    float t2;         /* runner-up hit t */
+    float t_near_miss;/* smallest t among near-miss candidates in front */
+} or_closest;
+
+static void visit_closest(const or_scene* sc, int64_t tri_id, const float* o, const float* d,
+                          const or_shear* s, or_closest* c) {
+    const float* v = sc->tv + 9 * tri_id;
+    or_tri_res r;
+    watertight(o, d, s, v, v + 3, v + 6, &r);
+    if (r.hit) {
+        int32_t id = (int32_t)tri_id;
+        if (c->id < 0 || r.t < c->t || (r.t == c->t && id < c->id)) {
+            if (c->id >= 0 && c->t < c->t2) c->t2 = c->t;
+            c->id = id; c->t = r.t; c->margin = r.margin;
+        } else if (r.t < c->t2) {
+            c->t2 = r.t;
+        }
+    } else if (r.margin < OR_TIE && r.t_pos) {
+        if (r.t < c->t_near_miss) c->t_near_miss = r.t;
+    }
+}
+
+/*
+ * Closest hit: the winner is the smallest (t, triangle id) over all
+ * triangles hit with t > 0 (two-sided; equal t broken by the smaller id).
+ * flag = 1 marks a near tie: the winner's smallest barycentric weight is
+ * below 1e-6, a second hit lies within a relative 1e-6 in t, or a triangle
+ * missed by less than 1e-6 (normalised barycentric) lies in front of the
+ * winner (or anywhere along a missing ray).
+ */
+static void closest(const or_scene* sc, const float* o, const float* d, or_closest* c, uint8_t* flag) {
+    or_shear s;
+    shear_init(d, &s);
+    c->id = -1; c->t = INFINITY; c->margin = 1.0; c->t2 = INFINITY; c->t_near_miss = INFINITY;
+    if (!sc->use_bvh) {
+        for (int64_t t = 0; t < sc->n_tris; ++t) visit_closest(sc, t, o, d, &s, c);
+    } else {
+        int64_t stack[256];
+        int sp = 0;
+        int64_t* big = NULL;
+        int64_t* st = stack;
+        int cap = 256;
+        if (sc->max_depth + 2 > cap) {
+            cap = sc->max_depth + 2;
+            big = (int64_t*)malloc(cap * sizeof(int64_t));
+            st = big;
+        }
+        st[sp++] = 0;
+        while (sp) {
+            const or_node* nd = sc->nodes + st[--sp];
+            double tmax = c->id >= 0 ? (double)c->t * (1.0 + 4.0 * OR_TIE) : INFINITY;
+            if (!box_hit(nd, o, d, tmax)) continue;
+            if (nd->left < 0) {
+                for (int64_t q = nd->first; q < nd->first + nd->count; ++q)
+                    visit_closest(sc, sc->perm[q], o, d, &s, c);
+            } else {
+                st[sp++] = nd->right;
+                st[sp++] = nd->left;
+            }
+        }
+        free(big);
+    }
+    uint8_t f = 0;
+    if (c->id >= 0) {
+        if (c->margin < OR_TIE) f = 1;
+        if (c->t2 != INFINITY && ((double)c->t2 - (double)c->t) <= OR_TIE * (double)c->t) f = 1;
+        if (c->t_near_miss != INFINITY && (double)c->t_near_miss <= (double)c->t * (1.0 + OR_TIE)) f = 1;
+    } else if (c->t_near_miss != INFINITY) {
+        f = 1;
+    }
+    *flag = f;
+}
+
+/* Any hit with t > 0 (shadow ray).  Returns 1 iff some triangle passes the
+ * test.  The search stops at the first hit whose edge margin is at least 1e-6;
+ * otherwise every candidate is visited, so the answer is exact either way.
+ * flag = 1 when no such robust hit exists but some triangle in front is hit
+ * or missed within that margin. */
+static int anyhit(const or_scene* sc, const float* o, const float* d, uint8_t* flag) {
+    or_shear s;
+    shear_init(d, &s);
+    int robust = 0, near = 0, hit = 0;
+    int64_t stack[256];
+    int64_t* big = NULL;
+    int64_t* st = stack;
+    int sp = 0;
+    if (sc->use_bvh && sc->max_depth + 2 > 256) {
+        big = (int64_t*)malloc((sc->max_depth + 2) * sizeof(int64_t));
+        st = big;
+    }
+    int done_linear = 0;
+    if (sc->use_bvh) st[sp++] = 0;
+    while (!robust) {
+        int64_t first, count;
+        if (!sc->use_bvh) {
+            if (done_linear) break;
+            first = 0; count = sc->n_tris; done_linear = 1;
+        } else {
+            if (!sp) break;
+            const or_node* nd = sc->nodes + st[--sp];
+            if (!box_hit(nd, o, d, INFINITY)) continue;
+            if (nd->left >= 0) { st[sp++] = nd->right; st[sp++] = nd->left; continue; }
+            first = nd->first; count = nd->count;
+        }
+        for (int64_t q = first; q < first + count; ++q) {
+            int64_t tid = sc->use_bvh ? sc->perm[q] : q;
+            const float* v = sc->tv + 9 * tid;
+            or_tri_res r;
+            watertight(o, d, &s, v, v + 3, v + 6, &r);
+            if (r.hit) {
+                hit = 1;
+                if (r.margin >= OR_TIE) { robust = 1; break; }
+                near = 1;
+            } else if (r.margin < OR_TIE && r.t_pos) {
+                near = 1;
+            }
+        }
+    }
+    free(big);
+    *flag = (!robust && near) ? 1 : 0;
+    return hit;
+}
+
+/* Public closest-hit / any-hit over ray arrays (OpenMP over rays). */
+void or_trace_closest(const or_scene* sc, int64_t n, const float* org, const float* dir, int32_t* id, float* t,
+                      uint8_t* flag) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        or_closest c;
+        uint8_t f;
+        closest(sc, org + 3 * i, dir + 3 * i, &c, &f);
+        id[i] = c.id;
+        t[i] = c.id >= 0 ? c.t : INFINITY;
+        if (flag) flag[i] = f;
+    }
+}
+
+/* occluded = 1 iff some triangle is hit with t > 0 (edges included, as the
+ * watertight test decides them); near-edge-only cases are flagged. */
+void or_trace_any(const or_scene* sc, int64_t n, const float* org, const float* dir, uint8_t* occluded,
+                  uint8_t* flag) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        uint8_t f;
+        occluded[i] = (uint8_t)anyhit(sc, org + 3 * i, dir + 3 * i, &f);
+        if (flag) flag[i] = f;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Shading (Sec. 6.1: closest-hit shading, miss shader)                      */
+/* ------------------------------------------------------------------------ */
+
+/* 32-bit integer hash: the PCG-based hash of Jarzynski and Olano, "Hash
+ * Functions for GPU Rendering", JCGT 9(3), 2020. */
+static uint32_t pcg_hash(uint32_t v) {
+    uint32_t state = v * 747796405u + 2891336453u;
+    uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+/* Per-triangle albedo: 0.2 + 0.7 x (one byte of the hash) / 255 per channel. */
+static void albedo(int32_t id, float* a) {
+    uint32_t h = pcg_hash((uint32_t)id);
+    a[0] = 0.2f + 0.7f * (float)(h & 255u) / 255.0f;
+    a[1] = 0.2f + 0.7f * (float)((h >> 8) & 255u) / 255.0f;
+    a[2] = 0.2f + 0.7f * (float)((h >> 16) & 255u) / 255.0f;
+}
+
+void or_albedo_many(int64_t n, const int32_t* id, float* rgb) {
+    for (int64_t i = 0; i < n; ++i) albedo(id[i], rgb + 3 * i);
+}
+
+/*
+ * Geometric normal and shadow-ray origin, FP32, each rounding stated:
+ *   e1 = v1 - v0, e2 = v2 - v0, n = e1 x e2 (plain products and differences)
+ *   len = sqrt((nx nx + ny ny) + nz nz); n = n / len when len > 0
+ *   n is negated when (nx dx + ny dy) + nz dz > 0 (it faces the ray)
+ *   p = fma(t, d, o); eps = 1e-4 (1 + max |p_k|); o_s = fma(eps, n, p)
+ */
+static void hit_frame(const float* v, const float* o, const float* d, float t, float* n, float* p, float* os) {
+    float e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = v[3 + k] - v[k]; e2[k] = v[6 + k] - v[k]; }
+    float a, b;
+    a = e1[1] * e2[2]; b = e1[2] * e2[1]; n[0] = a - b;
+    a = e1[2] * e2[0]; b = e1[0] * e2[2]; n[1] = a - b;
+    a = e1[0] * e2[1]; b = e1[1] * e2[0]; n[2] = a - b;
+    float l2 = (n[0] * n[0] + n[1] * n[1]) + n[2] * n[2];
+    float len = sqrtf(l2);
+    if (len > 0.0f) { n[0] = n[0] / len; n[1] = n[1] / len; n[2] = n[2] / len; }
+    float nd = (n[0] * d[0] + n[1] * d[1]) + n[2] * d[2];
+    if (nd > 0.0f) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }
+    float mx = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+        p[k] = fmaf(t, d[k], o[k]);
+        float ap = fabsf(p[k]);
+        if (ap > mx) mx = ap;
+    }
+    float eps = 1e-4f * (1.0f + mx);
+    for (int k = 0; k < 3; ++k) os[k] = fmaf(eps, n[k], p[k]);
+}
+
+/*
+ * Lambert shading with one directional light and one shadow ray.
+ * sh = {light_dir[3] (unit, toward the light), light_rgb[3], ambient[3],
+ *       background[3], shadow (0/1)}.
+ * miss -> background; hit -> albedo (ambient + light max(0, n.l) vis), where
+ * vis = 0 iff the shadow ray from o_s along light_dir hits anything with
+ * t > 0.  The shadow ray is cast only when n.l > 0 (otherwise vis has no
+ * effect).  Alpha is 1.  rgba is FP32 linear, no tone map.
+ */
+void or_shade_rays(const or_scene* sc, int64_t n, const float* org, const float* dir, const float* sh,
+                   float* rgba, int32_t* id_out, uint8_t* flag_out) {
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; ++i) {
+        const float* o = org + 3 * i;
+        const float* d = dir + 3 * i;
+        or_closest c;
+        uint8_t f = 0;
+        closest(sc, o, d, &c, &f);
+        float* out = rgba + 4 * i;
+        if (c.id < 0) {
+            out[0] = sh[9]; out[1] = sh[10]; out[2] = sh[11]; out[3] = 1.0f;
+        } else {
+            const float* v = sc->tv + 9 * (int64_t)c.id;
+            float nrm[3], p[3], os[3], alb[3];
+            hit_frame(v, o, d, c.t, nrm, p, os);
+            albedo(c.id, alb);
+            float ndl = (nrm[0] * sh[0] + nrm[1] * sh[1]) + nrm[2] * sh[2];
+            float vis = 1.0f;
+            if (ndl > 0.0f && sh[12] != 0.0f) {
+                uint8_t sf = 0;
+                if (anyhit(sc, os, sh, &sf)) vis = 0.0f;
+                if (sf) f = 1;
+            }
+            float lam = ndl > 0.0f ? ndl : 0.0f;
+            for (int k = 0; k < 3; ++k) out[k] = alb[k] * (sh[6 + k] + sh[3 + k] * lam * vis);
+            out[3] = 1.0f;
+        }
+        if (id_out) id_out[i] = c.id;
+        if (flag_out) flag_out[i] = f;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Path-traced LP shading (Sec. 8: one sample per LP texel)                  */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Counter-based random numbers: u32 = pcg_hash chained over the key words
+ * (seed_lo, seed_hi, frame, view, texel, bounce*8 + dim); the float is the top
+ * 24 bits times 2^-24.
+ */
+static float rng01(uint32_t seed_lo, uint32_t seed_hi, uint32_t frame, uint32_t view, uint32_t texel,
+                   uint32_t slot) {
+    uint32_t h = pcg_hash(seed_lo);
+    h = pcg_hash(h ^ seed_hi);
+    h = pcg_hash(h ^ frame);
+    h = pcg_hash(h ^ view);
+    h = pcg_hash(h ^ texel);
+    h = pcg_hash(h ^ slot);
+    return (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+float or_rng01(uint64_t seed, uint32_t frame, uint32_t view, uint32_t texel, uint32_t slot) {
+    return rng01((uint32_t)seed, (uint32_t)(seed >> 32), frame, view, texel, slot);
+}
+
+/*
+ * Cosine-weighted direction about the unit normal n (Malley's method: a
+ * uniform point of the unit disk lifted to the hemisphere).  The disk point
+ * comes from rejection sampling of the square with up to 8 tries, each try
+ * using two fresh random slots; after 8 rejections the centre is used.  The
+ * tangent frame is that of Duff et al., "Building an Orthonormal Basis,
+ * Revisited", JCGT 6(1), 2017.  FP32, each rounding stated:
+ *   x = 2 r0 - 1, y = 2 r1 - 1, accept when (x x + y y) < 1
+ *   z = sqrt(max(0, (1 - x x) - y y))
+ *   s = copysign(1, nz), a = -1 / (s + nz), b = nx ny a
+ *   t1 = (1 + s nx nx a, s b, -s nx), t2 = (b, s + ny ny a, -ny)
+ *   w = (x t1 + y t2) + z n, per component with plain products and sums
+ */
+static void cosine_dir(const float* n, uint32_t slo, uint32_t shi, uint32_t frame, uint32_t view, uint32_t texel,
+                       uint32_t bounce, float* w) {
+    float x = 0.0f, y = 0.0f;
+    for (uint32_t tr = 0; tr < 8; ++tr) {
+        float r0 = rng01(slo, shi, frame, view, texel, bounce * 32u + 2u * tr + 0u);
+        float r1 = rng01(slo, shi, frame, view, texel, bounce * 32u + 2u * tr + 1u);
+        float xx = 2.0f * r0 - 1.0f, yy = 2.0f * r1 - 1.0f;
+        float q = xx * xx + yy * yy;
+        if (q < 1.0f) { x = xx; y = yy; break; }
+    }
+    float zz = (1.0f - x * x) - y * y;
+    float z = sqrtf(zz > 0.0f ? zz : 0.0f);
+    float s = copysignf(1.0f, n[2]);
+    float a = -1.0f / (s + n[2]);
+    float b = n[0] * n[1] * a;
+    float t1[3] = {1.0f + s * n[0] * n[0] * a, s * b, -s * n[0]};
+    float t2[3] = {b, s + n[1] * n[1] * a, -n[1]};
+    for (int k = 0; k < 3; ++k) {
+        float p1 = x * t1[k];
+        float p2 = y * t2[k];
+        float p3 = z * n[k];
+        w[k] = (p1 + p2) + p3;
+    }
+}
+
+/*
+ * One path sample per ray: at every vertex, next-event estimation toward the
+ * directional light (shadow ray) and a cosine-weighted continuation, up to
+ * `bounces` continuation rays (bounces = 2: the primary hit plus two more
+ * vertices).  Throughput is multiplied by the albedo at each vertex (the
+ * cosine-weighted pdf cancels the Lambert cosine).  A continuation ray that
+ * misses adds throughput x background (sky light).  No Russian roulette.
+ * pt = {seed (u64), frame, view, bounces}; texel ids are idx[].
+ */
+void or_shade_path_rays(const or_scene* sc, int64_t n, const float* org, const float* dir, const int64_t* idx,
+                        const float* sh, uint64_t seed, uint32_t frame, uint32_t view, int32_t bounces,
+                        float* rgba, int32_t* id_out, uint8_t* flag_out) {
+    uint32_t slo = (uint32_t)seed, shi = (uint32_t)(seed >> 32);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        float o[3] = {org[3 * i], org[3 * i + 1], org[3 * i + 2]};
+        float d[3] = {dir[3 * i], dir[3 * i + 1], dir[3 * i + 2]};
+        float thr[3] = {1.0f, 1.0f, 1.0f};
+        float L[3] = {0.0f, 0.0f, 0.0f};
+        uint8_t f = 0;
+        int32_t first_id = -1;
+        uint32_t texel = (uint32_t)idx[i];
+        for (int32_t bnc = 0; bnc <= bounces; ++bnc) {
+            or_closest c;
+            uint8_t cf = 0;
+            closest(sc, o, d, &c, &cf);
+            if (cf) f = 1;
+            if (bnc == 0) first_id = c.id;
+            if (c.id < 0) {
+                for (int k = 0; k < 3; ++k) L[k] += thr[k] * sh[9 + k];
+                break;
+            }
+            const float* v = sc->tv + 9 * (int64_t)c.id;
+            float nrm[3], p[3], os[3], alb[3];
+            hit_frame(v, o, d, c.t, nrm, p, os);
+            albedo(c.id, alb);
+            float ndl = (nrm[0] * sh[0] + nrm[1] * sh[1]) + nrm[2] * sh[2];
+            float vis = 0.0f;
+            if (ndl > 0.0f) {
+                uint8_t sf = 0;
+                vis = anyhit(sc, os, sh, &sf) ? 0.0f : 1.0f;
+                if (sf) f = 1;
+            }
+            for (int k = 0; k < 3; ++k) {
+                thr[k] = thr[k] * alb[k];
+                L[k] += thr[k] * (sh[6 + k] + sh[3 + k] * ndl * vis);
+            }
+            if (bnc == bounces) break;
+            float w[3];
+            cosine_dir(nrm, slo, shi, frame, view, texel, (uint32_t)bnc, w);
+            for (int k = 0; k < 3; ++k) { o[k] = os[k]; d[k] = w[k]; }
+        }
+        float* out = rgba + 4 * i;
+        out[0] = L[0]; out[1] = L[1]; out[2] = L[2]; out[3] = 1.0f;
+        if (id_out) id_out[i] = first_id;
+        if (flag_out) flag_out[i] = f;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Inverse mapping / reconstruction (Sec. 3.2.3, Eqs. (10)-(11))             */
+/* ------------------------------------------------------------------------ */
+
+static double fmod_pos(double a, double m) {
+    double r = fmod(a, m);
+    return r < 0.0 ? r + m : r;
+}
+
+/*
+ * Each display pixel centre is forward-mapped to (u, theta) (Eqs. (3), (5)),
+ * and the LP buffer is sampled there (the paper's inverse-mapping pass; its
+ * filter is not stated).  Filter: u is clamped to [1/2, N_c - 1/2]; the two
+ * columns around u - 1/2 are blended linearly; inside each column the two
+ * rows around theta/360 n_i - 1/2 are blended linearly with wrap-around in
+ * theta (rows tile the circle), which keeps the filter continuous in angle
+ * although neighbouring columns hold different row counts.
+ * pflag (optional) marks pixels that read a texel whose tflag is set.
+ */
+void or_vafr_reconstruct(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
+                         const float* lp, int32_t W, int32_t H, const double* p, const double* G,
+                         const int64_t* pix, int64_t n, float* out, const uint8_t* tflag, uint8_t* pflag) {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t x = pix[q] % W, y = pix[q] / W;
+        double X = ((double)x + 0.5 - 0.5 * W) * p[0];
+        double Y = ((double)y + 0.5 - 0.5 * H) * p[1];
+        double dx = X - G[0], dy = Y - G[1];
+        double rho = sqrt(dx * dx + dy * dy);
+        double e = atan(rho) / OR_DEG;
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        double u = or_u(a, e);
+        if (u < 0.5) u = 0.5;
+        if (u > n_cols - 0.5) u = n_cols - 0.5;
+        double ac = u - 0.5;
+        int64_t i0 = (int64_t)floor(ac);
+        if (i0 > n_cols - 1) i0 = n_cols - 1;
+        int64_t i1 = i0 + 1 < n_cols ? i0 + 1 : n_cols - 1;
+        double wc = ac - (double)i0;
+        double acc[4] = {0, 0, 0, 0};
+        uint8_t fl = 0;
+        for (int side = 0; side < 2; ++side) {
+            int64_t i = side ? i1 : i0;
+            double wi = side ? wc : 1.0 - wc;
+            int64_t ni = n_rows[i];
+            double s = th / 360.0 * (double)ni - 0.5;
+            double fs = floor(s);
+            double tt = s - fs;
+            int64_t j0 = (int64_t)fmod_pos(fs, (double)ni);
+            int64_t j1 = (j0 + 1) % ni;
+            int64_t k0 = col_off[i] + j0, k1 = col_off[i] + j1;
+            for (int ch = 0; ch < 4; ++ch)
+                acc[ch] += wi * ((1.0 - tt) * (double)lp[4 * k0 + ch] + tt * (double)lp[4 * k1 + ch]);
+            if (tflag && (tflag[k0] || tflag[k1])) fl = 1;
+        }
+        for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = (float)acc[ch];
+        if (pflag) pflag[q] = fl;
+    }
+}
+
+/*
+ * LMFR reconstruction: the pixel centre maps through Eq. (1) with K(z) =
+ * z^alpha to (u, v); the dense w x h buffer is sampled bilinearly at
+ * (u - 1/2, v - 1/2), clamped in u and wrapped in v.
+ */
+void or_lmfr_reconstruct(int32_t W, int32_t H, double gx, double gy, int32_t w, int32_t h, double alpha,
+                         const float* lp, const int64_t* pix, int64_t n, float* out, const uint8_t* tflag,
+                         uint8_t* pflag) {
+    double L = or_lmfr_L(W, H, gx, gy);
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t x = pix[q] % W, y = pix[q] / W;
+        double dx = (double)x + 0.5 - gx, dy = (double)y + 0.5 - gy;
+        double r = sqrt(dx * dx + dy * dy);
+        if (r < 1.0) r = 1.0;
+        double z = log(r) / L;
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        double u = pow(z, alpha) * w;
+        double v = th / 360.0 * h;
+        if (u < 0.5) u = 0.5;
+        if (u > w - 0.5) u = w - 0.5;
+        double ac = u - 0.5;
+        int64_t i0 = (int64_t)floor(ac);
+        if (i0 > w - 1) i0 = w - 1;
+        int64_t i1 = i0 + 1 < w ? i0 + 1 : w - 1;
+        double wc = ac - (double)i0;
+        double s = v - 0.5;
+        double fs = floor(s);
+        double tt = s - fs;
+        int64_t j0 = (int64_t)fmod_pos(fs, (double)h);
+        int64_t j1 = (j0 + 1) % h;
+        double acc[4] = {0, 0, 0, 0};
+        uint8_t fl = 0;
+        int64_t ks[4] = {i0 * h + j0, i0 * h + j1, i1 * h + j0, i1 * h + j1};
+        double ws[4] = {(1 - wc) * (1 - tt), (1 - wc) * tt, wc * (1 - tt), wc * tt};
+        for (int c = 0; c < 4; ++c) {
+            for (int ch = 0; ch < 4; ++ch) acc[ch] += ws[c] * (double)lp[4 * ks[c] + ch];
+            if (tflag && tflag[ks[c]]) fl = 1;
+        }
+        for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = (float)acc[ch];
+        if (pflag) pflag[q] = fl;
+    }
+}

@@ -1,0 +1,292 @@
+"""Pins for the oracle's mapping math (layout, forward/inverse maps, LMFR).
+
+Each test fixes part of the oracle against something other than itself: a
+number the paper prints (tests/golden/paper_numbers.json), a closed form, a
+differential law stated by the paper, or an invariant.
+"""
+import math
+
+import numpy as np
+import pytest
+
+E_PIV = (0.0, 10.0, 20.0, 30.0, 60.0)
+
+
+def _gauss_legendre(f, a, b, n=200):
+    x, w = np.polynomial.legendre.leggauss(n)
+    xm = 0.5 * (b - a) * x + 0.5 * (b + a)
+    return 0.5 * (b - a) * np.sum(w * f(xm))
+
+
+def test_acuity_at_pivots_matches_printed_values(acuity, paper):
+    """omega(e_k) = 1/f_k at every pivot (Sec. 3.3 prints f_k)."""
+    piv = paper["acuity_pivots"]
+    om = acuity.omega(np.array(piv["ecc_deg"], float))
+    assert np.allclose(1.0 / om, piv["cpd"], rtol=1e-12)
+
+
+def test_u_starts_at_zero_and_is_continuous(acuity):
+    """u(0) = 0 and u has no jump at the interior pivots."""
+    assert abs(acuity.u(0.0)[0]) < 1e-12
+    for e in E_PIV[1:-1]:
+        lo, hi = acuity.u(e - 1e-9)[0], acuity.u(e + 1e-9)[0]
+        assert abs(hi - lo) < 1e-6
+
+
+def test_density_law_half_du_de_equals_acuity(acuity):
+    """Sec. 3.2.1 Eq. (4) and Sec. 4.1 Eqs. (13), (18): (1/2) du/de = f(e)
+    = 1/omega(e).  Central differences away from the pivots."""
+    rng = np.random.default_rng(11)
+    es = np.concatenate([rng.uniform(0.01, 59.99, 400), [0.5, 5.0, 15.0, 25.0, 45.0]])
+    es = es[np.min(np.abs(es[:, None] - np.array(E_PIV)[None, :]), axis=1) > 1e-3]
+    h = 1e-5
+    d = (acuity.u(es + h) - acuity.u(es - h)) / (2 * h)
+    f = 1.0 / acuity.omega(es)
+    assert np.max(np.abs(0.5 * d / f - 1.0)) < 1e-7
+    # a few values readable from the pivots: f(5) = 1/(0.0075*5 + 0.025) = 16
+    assert abs(0.5 * (acuity.u(5 + h)[0] - acuity.u(5 - h)[0]) / (2 * h) - 16.0) < 1e-6
+
+
+def test_inverse_map_inverts_forward_radial_map(acuity):
+    """Sec. 3.2.3 Eq. (10): e(u(e)) = e over every segment and past e_max."""
+    es = np.concatenate([np.linspace(0, 68, 2001), [10, 20, 30, 60]])
+    back = acuity.e_of_u(acuity.u(es))
+    assert np.max(np.abs(back - es)) < 1e-10
+
+
+def test_lp_area_matches_printed_shading_points(acuity, paper):
+    """Sec. 3.2.2: the valid LP region is the area under l(e(u)) for
+    u in [0, u(60)]; the paper prints 1,061,735 shading points.  Changing
+    any segment constant, the factor 2 of Eq. (4), the 360 of Eq. (9) or the
+    degree convention moves this by far more than the tolerance."""
+    umax = acuity.u(paper["e_max_deg"]["value"])[0]
+    piv_u = acuity.u(np.array(E_PIV))
+    area = 0.0
+    for a, b in zip(piv_u[:-1], piv_u[1:]):
+        b = min(b, umax)
+        area += _gauss_legendre(lambda u: acuity.l(acuity.e_of_u(u)), a, b)
+    assert abs(area - paper["lp_shading_points"]["value"]) < 5.0
+
+
+def test_discrete_layout_count_near_printed(layout, paper):
+    """Discretised buffer: within 0.2% of the printed 1,061,735 texels and of
+    Table 1's constant VaFR_Dup column (1,061K at every resolution)."""
+    printed = paper["lp_shading_points"]["value"]
+    assert abs(layout.n_texels - printed) / printed < 2e-3
+    for v in paper["table1_rays_per_eye"]["VaFR_Dup_K"].values():
+        assert abs(layout.n_texels / 1000.0 - v) / v < 3e-3
+    assert layout.n_cols == math.ceil(layout.acuity.u(60.0)[0])
+    assert layout.col_off[-1] == layout.n_texels
+    assert np.all(np.diff(layout.col_off) == layout.n_rows)
+
+
+def test_ceil_is_robust_in_fp64(layout):
+    """n_i = ceil(l(e_i)) is far from an integer boundary for every column,
+    so any correctly rounded FP64 evaluation gives the same table."""
+    e = layout.col_e
+    lval = layout.acuity.l(e)
+    assert np.min(np.abs(lval - np.round(lval))) > 1e-4
+    assert np.all(layout.n_rows == np.ceil(lval))
+
+
+def test_isotropy_tangential_equals_radial(acuity):
+    """Sec. 3.2.1 Eq. (6): r dtheta/dv = dr/du, here on the film plane
+    (r = tan e, theta in radians) with dtheta/dv = 2 pi / l(e) (Eq. (9))."""
+    rng = np.random.default_rng(12)
+    es = rng.uniform(0.05, 59.9, 300)
+    es = es[np.min(np.abs(es[:, None] - np.array(E_PIV)[None, :]), axis=1) > 1e-3]
+    r = np.tan(np.radians(es))
+    lhs = r * 2.0 * np.pi / acuity.l(es)
+    u = acuity.u(es)
+    h = 1e-5
+    dr_du = (np.tan(np.radians(acuity.e_of_u(u + h))) - np.tan(np.radians(acuity.e_of_u(u - h)))) / (2 * h)
+    assert np.max(np.abs(lhs / dr_du - 1.0)) < 1e-7
+
+
+def test_grid_tangential_spacing_never_coarser(layout):
+    """Rounding rows up keeps the angular step 360/n_i <= 360/l(e_i)."""
+    lval = layout.acuity.l(layout.col_e)
+    assert np.all(360.0 / layout.n_rows <= 360.0 / lval + 1e-12)
+
+
+def test_fovea_is_unit_polar_grid(acuity, layout):
+    """Near e = 0, u ~ 2e/omega_0 and l ~ 4 pi e/omega_0, so l/u -> 2 pi: the
+    LP buffer is a polar grid of unit spacing at the gaze point."""
+    for e in (1e-3, 1e-4):
+        ratio = acuity.l(e)[0] / acuity.u(e)[0]
+        assert abs(ratio - 2 * np.pi) < 1e-2 * e * 100
+    assert layout.n_rows[0] == 4
+    assert abs(acuity.l(layout.col_e[0])[0] - 3.1386) < 1e-3
+
+
+def test_full_rate_fovea_at_8k(layout, O):
+    """Sec. 1 puts the fovea at about 2 x 1.5 degrees; inside e <= 1 degree the
+    LP texel spacing (radial and tangential) is at most one display pixel at
+    7680 x 4320 over 100 x 100 degrees (about 38 ppd < 2 f(1 deg) = 61.5).
+    At 11520 x 6480 (Sec. 4.3, retinal) the same check fails by design."""
+    def max_spacing_px(W, H):
+        p = O.film_pitch(W, H, 100.0, 100.0)
+        pmin = p.min()
+        e = layout.col_e
+        sel = np.nonzero(e <= 1.0)[0]
+        rad = np.tan(np.radians(e[sel + 1])) - np.tan(np.radians(e[sel]))
+        tan_ = np.tan(np.radians(e[sel])) * 2 * np.pi / layout.n_rows[sel]
+        return max(rad.max(), tan_.max()) / pmin
+    assert max_spacing_px(7680, 4320) <= 1.0
+    assert max_spacing_px(11520, 6480) > 1.0
+
+
+def test_round_trip_pixel_lp_pixel(acuity, O):
+    """Eqs. (3), (5), (8) forward and Eqs. (10), (11) back: pixel -> (u, v) ->
+    pixel within 1e-9 px, including the segment boundaries and e -> 0."""
+    rng = np.random.default_rng(13)
+    for (W, H), gaze in (((7680, 4320), (3840.0, 2160.0)), ((1920, 1080), (300.5, 900.25)),
+                         ((640, 360), (10.0, 350.0))):
+        p = O.film_pitch(W, H, 100.0, 100.0)
+        G = O.gaze_film(W, H, p, *gaze)
+        xy = rng.uniform([0, 0], [W, H], (5000, 2))
+        # points exactly on the segment boundaries and close to the gaze point
+        ang = rng.uniform(0, 2 * np.pi, 8)
+        extra = []
+        for e in (10.0, 20.0, 30.0, 1e-6, 1e-3):
+            rho = np.tan(np.radians(e))
+            X = G[0] + rho * np.cos(ang)
+            Y = G[1] + rho * np.sin(ang)
+            extra.append(np.stack([X / p[0] + W / 2, Y / p[1] + H / 2], 1))
+        xy = np.concatenate([xy] + extra)
+        u, v, e, th = O.vafr_forward(acuity, W, H, p, G, xy)
+        back = O.vafr_inverse(acuity, W, H, p, G, u, v)
+        assert np.max(np.abs(back - xy)) < 1e-9
+
+
+def test_forward_map_orientation(acuity, O):
+    """theta is measured from +x (screen right) toward +y (screen down)."""
+    W, H = 1000, 1000
+    p = O.film_pitch(W, H, 90.0, 90.0)
+    G = O.gaze_film(W, H, p, 500.0, 500.0)
+    xy = np.array([[600.0, 500.0], [500.0, 600.0], [400.0, 500.0], [500.0, 400.0]])
+    _, _, e, th = O.vafr_forward(acuity, W, H, p, G, xy)
+    assert np.allclose(th, [0.0, 90.0, 180.0, 270.0])
+    # 100 px at pitch 2 tan(45)/1000 = 0.2 film units -> e = atan(0.2)
+    assert np.allclose(e, np.degrees(np.arctan(0.2)))
+
+
+def test_layout_independent_of_display(layout, O):
+    """Sec. 3.2.2 / Table 1: the LP layout and the angular offsets of its rays
+    do not depend on the display resolution or field of view."""
+    cam = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)
+    idx = np.arange(0, layout.n_texels, 997)
+    ref = None
+    for W, H, fov in ((640, 360, 100.0), (2560, 1440, 100.0), (11520, 6480, 100.0), (1920, 1080, 60.0)):
+        p = O.film_pitch(W, H, fov, fov)
+        G = O.gaze_film(W, H, p, W / 2, H / 2)
+        _, d = O.vafr_rays(layout, idx, G, cam)
+        if ref is None:
+            ref = d
+        assert np.array_equal(d, ref)
+
+
+def test_texel_rays_pass_through_their_lp_position(layout, O):
+    """Ray of texel (i, j) points at eccentricity e_i and polar angle
+    theta_ij = 360 (j + 1/2)/n_i around the gaze ray (Sec. 6.1 with the
+    layout's discretisation)."""
+    cam = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)
+    W, H = 1920, 1080
+    p = O.film_pitch(W, H, 100.0, 100.0)
+    G = O.gaze_film(W, H, p, 1000.0, 400.0)
+    rng = np.random.default_rng(14)
+    idx = rng.integers(0, layout.n_texels, 3000)
+    _, d = O.vafr_rays(layout, idx, G, cam)
+    X = d[:, 0].astype(float) / d[:, 2]
+    Y = -d[:, 1].astype(float) / d[:, 2]
+    col = np.searchsorted(layout.col_off, idx, side="right") - 1
+    row = idx - layout.col_off[col]
+    dx, dy = X - G[0], Y - G[1]
+    e = np.degrees(np.arctan(np.hypot(dx, dy)))
+    th = np.degrees(np.arctan2(dy, dx)) % 360.0
+    assert np.max(np.abs(e - layout.col_e[col])) < 1e-4
+    dth = (th - 360.0 * (row + 0.5) / layout.n_rows[col] + 180.0) % 360.0 - 180.0
+    assert np.max(np.abs(dth) * np.tan(np.radians(layout.col_e[col]))) < 1e-4
+
+
+def test_full_rays_hit_pixel_centres_and_field_edges(O):
+    """Pixel (x, y) -> film ((x + 1/2 - W/2) px, (y + 1/2 - H/2) py); the
+    outer edge of the display sits at tan(fov/2)."""
+    W, H = 640, 360
+    p = O.film_pitch(W, H, 100.0, 100.0)
+    assert abs(W * p[0] / 2 - math.tan(math.radians(50))) < 1e-12
+    assert abs(H * p[1] / 2 - math.tan(math.radians(50))) < 1e-12
+    cam = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)
+    pix = np.array([0, W - 1, (H - 1) * W, H * W - 1, 180 * W + 320])
+    _, d = O.full_rays(W, H, p, pix, cam)
+    x, y = pix % W, pix // W
+    assert np.allclose(d[:, 0] / d[:, 2], (x + 0.5 - W / 2) * p[0], rtol=1e-6)
+    assert np.allclose(-d[:, 1] / d[:, 2], (y + 0.5 - H / 2) * p[1], rtol=1e-6)
+
+
+def test_rays_use_the_camera_basis(O):
+    """dir = Px R - Py U + F for an arbitrary orthonormal basis."""
+    ang = 0.3
+    R = np.array([math.cos(ang), 0, -math.sin(ang)])
+    U = np.array([0.0, 1.0, 0.0])
+    F = np.cross(R, U)
+    cam = np.concatenate([[1, 2, 3], R, U, F]).astype(np.float32)
+    W, H = 200, 100
+    p = O.film_pitch(W, H, 90.0, 60.0)
+    pix = np.arange(0, W * H, 37)
+    org, d = O.full_rays(W, H, p, pix, cam)
+    Px = (pix % W + 0.5 - W / 2) * p[0]
+    Py = (pix // W + 0.5 - H / 2) * p[1]
+    Rf, Uf, Ff = (cam[3:6].astype(float), cam[6:9].astype(float), cam[9:12].astype(float))
+    want = Px[:, None] * Rf - Py[:, None] * Uf + Ff
+    assert np.allclose(d, want, rtol=1e-6, atol=1e-7)
+    assert np.all(org == cam[:3])
+
+
+# ---------------------------------------------------------------- LMFR ----
+
+def test_lmfr_sizes_match_table1(O, paper):
+    """Sec. 5.2 Table 1: LaFR(1.8)/LMFR(1.8) shade (W/1.8) x (H/1.8) pixels;
+    GT shades W x H.  Rounded buffer dims stay within 0.1% of the table."""
+    t = paper["table1_rays_per_eye"]
+    for name, (W, H) in t["resolutions"].items():
+        w, h = O.lmfr_dims(W, H, 1.8)
+        assert abs(W * H / 1.8 ** 2 / 1000.0 - t["LaFR_1.8_K"][name]) < 1.0
+        assert abs(w * h / 1000.0 - t["LaFR_1.8_K"][name]) / t["LaFR_1.8_K"][name] < 1e-3
+        assert abs(W * H / 2.2 ** 2 / 1000.0 - t["LaFR_2.2_K"][name]) < 1.0
+        assert W * H // 1000 == t["GT_K"][name]
+
+
+def test_lmfr_forward_extremes(O):
+    """Eq. (1) / Eq. (14): the farthest corner maps to u = w (z = 1); a point
+    within one pixel of the gaze maps to u = 0; v is the polar angle / 360 h."""
+    W, H = 1920, 1080
+    w, h = O.lmfr_dims(W, H, 1.8)
+    gx, gy = 500.0, 300.0
+    u, v = O.lmfr_forward(W, H, gx, gy, w, h, 4.0, np.array([[W, H], [gx + 0.5, gy], [gx, gy + 100.0]]))
+    assert abs(u[0] - w) < 1e-9
+    assert u[1] == 0.0
+    assert abs(v[2] - 0.25 * h) < 1e-9
+
+
+def test_lmfr_texel_rays_round_trip(O):
+    """The texel -> screen inverse of Eq. (1) and the forward map agree:
+    texel (i, j)'s ray passes through the point that maps to (i+1/2, j+1/2)."""
+    W, H = 1920, 1080
+    w, h = O.lmfr_dims(W, H, 1.8)
+    gx, gy = 700.25, 400.5
+    p = O.film_pitch(W, H, 100.0, 100.0)
+    cam = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)
+    rng = np.random.default_rng(15)
+    idx = rng.integers(0, w * h, 4000)
+    _, d = O.lmfr_rays(W, H, p, gx, gy, w, h, 4.0, idx, cam)
+    X = d[:, 0].astype(float) / d[:, 2]
+    Y = -d[:, 1].astype(float) / d[:, 2]
+    xy = np.stack([X / p[0] + W / 2, Y / p[1] + H / 2], 1)
+    u, v = O.lmfr_forward(W, H, gx, gy, w, h, 4.0, xy)
+    i, j = idx // h, idx % h
+    r = np.hypot(xy[:, 0] - gx, xy[:, 1] - gy)
+    ok = r > 2.0   # skip the 1-pixel clamp
+    assert np.max(np.abs(u[ok] - (i[ok] + 0.5))) < 2e-2
+    dv = (v - (j + 0.5) + h / 2) % h - h / 2
+    assert np.max(np.abs(dv[ok] * r[ok] / h)) < 1e-2
