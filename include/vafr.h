@@ -1,0 +1,218 @@
+/*
+ * vafr.h -- C ABI of the MI355X-native VaFR hot path.
+ *
+ * Visual-acuity-consistent foveated rendering ("Visual Acuity Consistent
+ * Foveated Rendering towards Retinal Resolution", Zhang, Gai, Li, arXiv
+ * 2503.23410): a constant-size log-polar (LP) buffer whose radial axis and
+ * shading rate follow the acuity model (Sec. 3.2, 3.3) is shaded with one
+ * ray-cast sample per texel (Sec. 6.1) and inverse-mapped onto every display
+ * pixel (Sec. 3.2.3).  The LMFR log-polar mapping (Sec. 3.1 Eq. (1), Sec. 4.1
+ * Eq. (14)) and a full-resolution ray cast are the same-GPU comparisons.
+ *
+ * Conventions
+ *  - Every call returns int: VAFR_OK (0) or a negative VAFR_E_* code; the
+ *    message of the last failure on the calling thread is vafr_last_error().
+ *    No C++ exception crosses the ABI.
+ *  - Handles (vafr_layout, vafr_scene) are owned by the library, immutable
+ *    after creation and safe to share across threads and streams; free them
+ *    with the matching *_destroy.
+ *  - Buffer arguments named *_dev are device pointers owned by the caller
+ *    (e.g. from torch tensors) on the device that is current at the call.
+ *    Host arrays are read during the call only.
+ *  - Per-frame calls are asynchronous on the caller's stream.  Only
+ *    vafr_scene_create and the first use of a layout on a device (table
+ *    upload) synchronise.
+ *  - Angles are in degrees.  Display pixel coordinates are continuous:
+ *    pixel (x, y) covers [x, x+1) x [y, y+1), x grows right, y grows down.
+ *  - Colours are linear FP32 RGBA (alpha = 1), no tone map.
+ */
+#ifndef VAFR_H
+#define VAFR_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VAFR_OK 0
+#define VAFR_E_ARG (-1)          /* invalid argument (checked before any launch) */
+#define VAFR_E_OOM (-2)          /* host or device allocation failed            */
+#define VAFR_E_HIP (-3)          /* a HIP runtime call failed / no device       */
+#define VAFR_E_UNSUPPORTED (-4)  /* valid request the library cannot serve      */
+#define VAFR_E_BUDGET (-5)       /* request exceeds a memory budget             */
+
+/* Message of the last failure on this thread ("" if none).  The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* vafr_last_error(void);
+
+/* ABI version: bumped on any incompatible change of this header. */
+int vafr_abi_version(void);
+
+/* ------------------------------------------------------------------ types */
+
+/* Display: resolution and full field of view (Sec. 3.2.1, Eq. (3) relates
+ * pixels to eccentricity through the film-plane pitch). */
+typedef struct {
+    int32_t width, height;
+    double fov_x_deg, fov_y_deg;   /* in (0, 180) */
+} vafr_display;
+
+/* Acuity pivots (Sec. 3.3): MAR 1/cpd is linear between consecutive
+ * (ecc_deg[k], cpd[k]); ecc_deg[0] must be 0 and strictly increasing;
+ * cpd > 0; 2 <= n_pivots <= 16; 0 < e_max_deg < 90.  Passing NULL for the
+ * acuity selects the paper's pivots {0,10,20,30,60} deg -> {40,10,6,5,4} cpd
+ * and e_max = 60 deg (Sec. 3.2.2). */
+typedef struct {
+    int32_t n_pivots;
+    const double* ecc_deg;
+    const double* cpd;
+    double e_max_deg;
+} vafr_acuity;
+
+/* Pinhole camera: eye position and an orthonormal basis; the film plane is
+ * at unit distance along forward, film y points along -up. */
+typedef struct {
+    float eye[3], right[3], up[3], forward[3];
+} vafr_camera;
+
+/* Gaze point in continuous display-pixel coordinates (may lie off screen). */
+typedef struct {
+    double x_px, y_px;
+} vafr_gaze;
+
+#define VAFR_SHADE_LAMBERT 0
+#define VAFR_SHADE_PATH 1
+
+/* Shading.  Lambert mode: miss -> background; hit -> albedo(id) *
+ * (ambient + light_rgb * max(0, n.l) * vis), one shadow ray when
+ * shadow_rays = 1.  Path mode: one sample, next-event estimation to the
+ * directional light at each vertex and `bounces` cosine-weighted
+ * continuation rays; random numbers are keyed by (seed, frame, view, texel).
+ * light_dir must be a unit vector pointing toward the light. */
+typedef struct {
+    float light_dir[3];
+    float light_rgb[3];
+    float ambient[3];
+    float background[3];
+    int32_t shadow_rays;   /* 0 or 1 */
+    int32_t mode;          /* VAFR_SHADE_LAMBERT or VAFR_SHADE_PATH */
+    int32_t bounces;       /* path mode: 0..8 */
+    uint32_t frame;        /* path mode key */
+    uint32_t view;         /* path mode key */
+    uint32_t pad_;
+    uint64_t seed;         /* path mode key */
+} vafr_shading;
+
+#define VAFR_LAYOUT_VAFR 0
+#define VAFR_LAYOUT_LMFR 1
+
+/* Layout dimensions.  VaFR: n_cols columns of n_rows[i] texels stored
+ * column-major and packed (texel k of column i is col_off[i] + j);
+ * LMFR: a dense n_cols x max_rows buffer, k = i * max_rows + j. */
+typedef struct {
+    int32_t kind;          /* VAFR_LAYOUT_VAFR or VAFR_LAYOUT_LMFR */
+    int32_t n_cols;
+    int32_t max_rows;
+    int32_t width, height; /* display the layout was made for */
+    int64_t n_texels;
+} vafr_dims;
+
+typedef struct vafr_layout_s* vafr_layout;
+typedef struct vafr_scene_s* vafr_scene;
+
+/* ----------------------------------------------------------------- layout */
+
+/* VaFR LP layout (Sec. 3.2.1-3.2.3, Sec. 3.3 Eq. (12)): FP64 segment
+ * constants of u(e) (Eq. (5)), ceil(u(e_max)) columns sampled at their
+ * centres, n_i = ceil(l(e_i)) rows (Eq. (9)) at polar angles
+ * 360 (j + 1/2)/n_i, and per texel the FP32 film-plane offset
+ * tan(e_i) (cos, sin) of its screen point from the gaze point.  The tables do
+ * not depend on the display; the display fixes the pixel pitch used by
+ * vafr_shade_lp / vafr_reconstruct.  Host-only; tables are uploaded to a
+ * device on first use there.  Errors: VAFR_E_ARG for an invalid display or
+ * acuity, VAFR_E_OOM. */
+int vafr_lp_layout(const vafr_display* display, const vafr_acuity* acuity, vafr_layout* out);
+
+/* LMFR comparison layout (Sec. 3.1 Eq. (1), Sec. 4.1 Eq. (14), Sec. 5.2):
+ * round(W/delta) x round(H/delta) texels, kernel K(z) = z^alpha.
+ * delta >= 1, alpha > 0. */
+int lmfr_lp_layout(const vafr_display* display, double delta, double alpha, vafr_layout* out);
+
+int vafr_layout_dims(vafr_layout layout, vafr_dims* out);
+
+/* Host views of the layout tables (valid until vafr_layout_destroy):
+ * n_rows[n_cols], col_off[n_cols + 1], texel_dxy[2 * n_texels] (VaFR only;
+ * NULL for LMFR).  These are the bit-exact contract of the layout. */
+int vafr_layout_tables(vafr_layout layout, const int32_t** n_rows, const int64_t** col_off,
+                       const float** texel_dxy);
+
+void vafr_layout_destroy(vafr_layout layout);
+
+/* ------------------------------------------------------------------ scene */
+
+/* Triangle scene: xyz[3 * n_verts] FP32 positions, tri[3 * n_tris] vertex
+ * indices; triangle ids are positions in tri[].  Builds a binned-SAH BVH on
+ * the host and, when a HIP device is present, uploads it to the current
+ * device (synchronous).  0 <= n_tris < 2^27.  Errors: VAFR_E_ARG for an
+ * index out of range or a non-finite vertex, VAFR_E_OOM, VAFR_E_HIP. */
+int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris, vafr_scene* out);
+
+typedef struct {
+    int64_t n_tris;
+    int64_t n_nodes;       /* internal nodes */
+    int64_t n_leaves;
+    int32_t max_depth;
+    int32_t on_device;     /* 1 if uploaded */
+    int64_t device_bytes;
+    double build_ms;
+} vafr_scene_info;
+
+int vafr_scene_get_info(vafr_scene scene, vafr_scene_info* out);
+
+/* Host copies of the BVH for structural checks: nodes[16 * n_nodes] as
+ * stored on the device (two child boxes lo/hi, two child references) and
+ * tri_order[n_tris] (original id of each stored triangle).  Either may be
+ * NULL. */
+int vafr_scene_export(vafr_scene scene, float* nodes, int32_t* tri_order);
+
+void vafr_scene_destroy(vafr_scene scene);
+
+/* ---------------------------------------------------------- per-frame work */
+
+/* Shade an LP buffer (Sec. 6.1): one ray per texel from the eye through
+ * the texel's screen point (gaze + offset), closest hit over the scene BVH
+ * with the FP32 watertight test (ties broken by the smaller triangle id),
+ * then the shading model.  lp_rgba_dev[4 * n_texels]; hit_id_dev[n_texels]
+ * (nullable) receives the primary hit triangle id or -1.  Works with a VaFR
+ * layout; lmfr_shade_lp is the same call for an LMFR layout. */
+int vafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
+                  vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
+
+int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
+                  vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
+
+/* Inverse map (Sec. 3.2.3, Eqs. (10)-(11)): every display pixel centre is
+ * mapped to (u, theta) and the LP buffer is sampled with a two-column,
+ * angle-consistent bilinear filter (u clamped to the first/last column
+ * centre, theta wrapping).  img_rgba_dev[4 * W * H], row-major. */
+int vafr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_dev, float* img_rgba_dev,
+                     hipStream_t stream);
+
+/* LMFR inverse map: Eq. (1) with K(z) = z^alpha, bilinear, u clamped,
+ * v wrapping. */
+int lmfr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_dev, float* img_rgba_dev,
+                     hipStream_t stream);
+
+/* Full-resolution ray cast (Sec. 5.2 "GT"): one ray per display pixel
+ * centre, shaded as vafr_shade_lp, written to img_rgba_dev[4 * W * H];
+ * hit_id_dev[W * H] nullable. */
+int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* display, const vafr_shading* shading,
+               float* img_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VAFR_H */

@@ -1,0 +1,323 @@
+// C ABI entry points: argument validation, handle management and the
+// per-frame launches.  Host arithmetic on the film geometry is FP64.
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "vafr_internal.h"
+
+namespace vafr {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(VAFR_E_HIP, "%s failed: %s", what, hipGetErrorString(e));
+}
+
+int check_camera(const vafr_camera* c) {
+    if (!c) return fail(VAFR_E_ARG, "camera is NULL");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c->eye[k]) || !std::isfinite(c->right[k]) || !std::isfinite(c->up[k]) ||
+            !std::isfinite(c->forward[k]))
+            return fail(VAFR_E_ARG, "camera has a non-finite component");
+    return VAFR_OK;
+}
+
+int check_shading(const vafr_shading* s) {
+    if (!s) return fail(VAFR_E_ARG, "shading is NULL");
+    if (s->mode != VAFR_SHADE_LAMBERT && s->mode != VAFR_SHADE_PATH) return fail(VAFR_E_ARG, "unknown shading mode");
+    if (s->shadow_rays != 0 && s->shadow_rays != 1) return fail(VAFR_E_ARG, "shadow_rays must be 0 or 1");
+    if (s->mode == VAFR_SHADE_PATH && (s->bounces < 0 || s->bounces > 8))
+        return fail(VAFR_E_ARG, "bounces must be in [0, 8]");
+    double l2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        if (!std::isfinite(s->light_dir[k]) || !std::isfinite(s->light_rgb[k]) || !std::isfinite(s->ambient[k]) ||
+            !std::isfinite(s->background[k]))
+            return fail(VAFR_E_ARG, "shading has a non-finite component");
+        l2 += (double)s->light_dir[k] * s->light_dir[k];
+    }
+    if (std::fabs(l2 - 1.0) > 1e-5) return fail(VAFR_E_ARG, "light_dir must be a unit vector");
+    return VAFR_OK;
+}
+
+int check_gaze(vafr_gaze g) {
+    if (!std::isfinite(g.x_px) || !std::isfinite(g.y_px)) return fail(VAFR_E_ARG, "gaze is not finite");
+    if (std::fabs(g.x_px) > 1e7 || std::fabs(g.y_px) > 1e7) return fail(VAFR_E_ARG, "gaze is out of range");
+    return VAFR_OK;
+}
+
+static int current_device(int* dev) {
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(VAFR_E_HIP, "no HIP device available");
+    VAFR_HIP(hipGetDevice(dev));
+    return VAFR_OK;
+}
+
+static int scene_dev(vafr_scene s, SceneDev* out) {
+    if (!s) return fail(VAFR_E_ARG, "scene is NULL");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    if (s->n_tris > 0 && s->device != dev)
+        return fail(VAFR_E_ARG, "scene lives on device %d, current device is %d", s->device, dev);
+    out->nodes = s->d_nodes;
+    out->tris = s->d_tris;
+    out->root = s->host.root;
+    return VAFR_OK;
+}
+
+static void fill_view_common(TraceView& v, const vafr_camera* cam, const vafr_shading* sh) {
+    std::memcpy(v.eye, cam->eye, sizeof(v.eye));
+    std::memcpy(v.right, cam->right, sizeof(v.right));
+    std::memcpy(v.up, cam->up, sizeof(v.up));
+    std::memcpy(v.fwd, cam->forward, sizeof(v.fwd));
+    std::memcpy(v.light_dir, sh->light_dir, sizeof(v.light_dir));
+    std::memcpy(v.light_rgb, sh->light_rgb, sizeof(v.light_rgb));
+    std::memcpy(v.ambient, sh->ambient, sizeof(v.ambient));
+    std::memcpy(v.background, sh->background, sizeof(v.background));
+    v.shade_mode = sh->mode;
+    v.shadow = sh->shadow_rays;
+    v.bounces = sh->mode == VAFR_SHADE_PATH ? sh->bounces : 0;
+    v.seed_lo = (uint32_t)sh->seed;
+    v.seed_hi = (uint32_t)(sh->seed >> 32);
+    v.frame = sh->frame;
+    v.view = sh->view;
+}
+
+// Gaze point on the film plane (unit focal length).
+static void gaze_film(const vafr_layout_s* L, vafr_gaze g, double* gx, double* gy) {
+    *gx = (g.x_px - 0.5 * L->disp.width) * L->px;
+    *gy = (g.y_px - 0.5 * L->disp.height) * L->py;
+}
+
+// LMFR's L (Sec. 3.1, Eq. (1)): log of the longest pixel distance from the
+// gaze point to a screen corner.
+static double lmfr_log_extent(const vafr_layout_s* L, vafr_gaze g) {
+    const double cx[4] = {0.0, (double)L->disp.width, 0.0, (double)L->disp.width};
+    const double cy[4] = {0.0, 0.0, (double)L->disp.height, (double)L->disp.height};
+    double best = 0.0;
+    for (int c = 0; c < 4; ++c) {
+        const double dx = cx[c] - g.x_px, dy = cy[c] - g.y_px;
+        const double d = std::sqrt(dx * dx + dy * dy);
+        if (d > best) best = d;
+    }
+    return std::log(best);
+}
+
+static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze,
+                           const vafr_shading* sh, vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (L->kind != want_kind)
+        return fail(VAFR_E_ARG, want_kind == VAFR_LAYOUT_VAFR ? "vafr_shade_lp needs a VaFR layout"
+                                                              : "lmfr_shade_lp needs an LMFR layout");
+    if (int rc = check_camera(cam)) return rc;
+    if (int rc = check_shading(sh)) return rc;
+    if (int rc = check_gaze(gaze)) return rc;
+    if (!lp) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
+    SceneDev sd;
+    if (int rc = scene_dev(scene, &sd)) return rc;
+    const LayoutDev* ld;
+    if (int rc = layout_device(L, &ld)) return rc;
+    TraceView v;
+    std::memset(&v, 0, sizeof(v));
+    fill_view_common(v, cam, sh);
+    v.n_items = L->n_texels;
+    gaze_film(L, gaze, &v.gx, &v.gy);
+    v.px = L->px;
+    v.py = L->py;
+    v.width = L->disp.width;
+    v.height = L->disp.height;
+    if (want_kind == VAFR_LAYOUT_VAFR) {
+        v.mode = kModeVafr;
+        v.dxy = ld->dxy;
+    } else {
+        v.mode = kModeLmfr;
+        v.lm_z = ld->lm_z;
+        v.lm_cs = ld->lm_cs;
+        v.lm_h = L->max_rows;
+        v.lm_L = lmfr_log_extent(L, gaze);
+        if (!(v.lm_L > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+    }
+    v.out_rgba = reinterpret_cast<float4*>(lp);
+    v.out_id = hit;
+    return launch_trace(sd, v, stream);
+}
+
+}  // namespace vafr
+
+using namespace vafr;
+
+extern "C" const char* vafr_last_error(void) { return g_err; }
+
+extern "C" int vafr_abi_version(void) { return 1; }
+
+extern "C" int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris,
+                                 vafr_scene* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_tris < 0 || n_verts < 0) return fail(VAFR_E_ARG, "negative count");
+    if (n_tris >= ((int64_t)1 << 27)) return fail(VAFR_E_UNSUPPORTED, "at most 2^27 - 1 triangles");
+    if (n_tris > 0 && (!xyz || !tri)) return fail(VAFR_E_ARG, "NULL scene arrays");
+    vafr_scene s = new (std::nothrow) vafr_scene_s;
+    if (!s) return fail(VAFR_E_OOM, "scene allocation failed");
+    s->n_tris = n_tris;
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc;
+    try {
+        rc = build_bvh(xyz, n_verts, tri, n_tris, &s->host);
+    } catch (const std::bad_alloc&) {
+        rc = fail(VAFR_E_OOM, "BVH build ran out of host memory");
+    }
+    s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rc) { delete s; return rc; }
+    if (s->host.max_depth > kMaxDepth) {
+        delete s;
+        return fail(VAFR_E_UNSUPPORTED, "BVH depth exceeds the traversal stack");
+    }
+    int n_dev = 0;
+    if (n_tris > 0 && hipGetDeviceCount(&n_dev) == hipSuccess && n_dev > 0) {
+        auto cleanup = [&](int code) { vafr_scene_destroy(s); return code; };
+        if (hipGetDevice(&s->device) != hipSuccess) return cleanup(fail(VAFR_E_HIP, "hipGetDevice failed"));
+        const size_t nb = sizeof(BvhNode) * s->host.nodes.size();
+        const size_t tb = sizeof(float4) * s->host.tris.size();
+        if (nb && hipMalloc(&s->d_nodes, nb) != hipSuccess) return cleanup(fail(VAFR_E_OOM, "hipMalloc of BVH nodes"));
+        if (hipMalloc(&s->d_tris, tb) != hipSuccess) return cleanup(fail(VAFR_E_OOM, "hipMalloc of triangles"));
+        if (nb && hipMemcpy(s->d_nodes, s->host.nodes.data(), nb, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(VAFR_E_HIP, "upload of BVH nodes failed"));
+        if (hipMemcpy(s->d_tris, s->host.tris.data(), tb, hipMemcpyHostToDevice) != hipSuccess)
+            return cleanup(fail(VAFR_E_HIP, "upload of triangles failed"));
+        s->device_bytes = (int64_t)(nb + tb);
+    }
+    *out = s;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_scene_get_info(vafr_scene s, vafr_scene_info* out) {
+    if (!s || !out) return fail(VAFR_E_ARG, "NULL argument");
+    out->n_tris = s->n_tris;
+    out->n_nodes = (int64_t)s->host.nodes.size();
+    out->n_leaves = s->host.n_leaves;
+    out->max_depth = s->host.max_depth;
+    out->on_device = s->d_tris != nullptr;
+    out->device_bytes = s->device_bytes;
+    out->build_ms = s->build_ms;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_scene_export(vafr_scene s, float* nodes, int32_t* tri_order) {
+    if (!s) return fail(VAFR_E_ARG, "scene is NULL");
+    if (nodes) std::memcpy(nodes, s->host.nodes.data(), sizeof(BvhNode) * s->host.nodes.size());
+    if (tri_order) std::memcpy(tri_order, s->host.order.data(), sizeof(int32_t) * s->host.order.size());
+    return VAFR_OK;
+}
+
+extern "C" void vafr_scene_destroy(vafr_scene s) {
+    if (!s) return;
+    if (s->device >= 0) {
+        int cur = -1;
+        const bool have = hipGetDevice(&cur) == hipSuccess;
+        if (hipSetDevice(s->device) == hipSuccess) {
+            (void)hipFree(s->d_nodes);
+            (void)hipFree(s->d_tris);
+        }
+        if (have) (void)hipSetDevice(cur);
+    }
+    delete s;
+}
+
+extern "C" int vafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                             vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
+    return shade_lp_common(VAFR_LAYOUT_VAFR, scene, cam, gaze, sh, L, lp, hit, stream);
+}
+
+extern "C" int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                             vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
+    return shade_lp_common(VAFR_LAYOUT_LMFR, scene, cam, gaze, sh, L, lp, hit, stream);
+}
+
+extern "C" int vafr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (L->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_ARG, "vafr_reconstruct needs a VaFR layout");
+    if (int rc = check_gaze(gaze)) return rc;
+    if (!lp || !img) return fail(VAFR_E_ARG, "NULL buffer");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    const LayoutDev* ld;
+    if (int rc = layout_device(L, &ld)) return rc;
+    ReconVafr r;
+    std::memset(&r, 0, sizeof(r));
+    r.seg = segments_f32(L->seg);
+    r.n_cols = L->n_cols;
+    r.width = L->disp.width;
+    r.height = L->disp.height;
+    r.px = (float)L->px;
+    r.py = (float)L->py;
+    double gx, gy;
+    gaze_film(L, gaze, &gx, &gy);
+    r.gx = (float)gx;
+    r.gy = (float)gy;
+    r.col = ld->col;
+    r.lp = reinterpret_cast<const float4*>(lp);
+    r.img = reinterpret_cast<float4*>(img);
+    return launch_reconstruct_vafr(r, stream);
+}
+
+extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (L->kind != VAFR_LAYOUT_LMFR) return fail(VAFR_E_ARG, "lmfr_reconstruct needs an LMFR layout");
+    if (int rc = check_gaze(gaze)) return rc;
+    if (!lp || !img) return fail(VAFR_E_ARG, "NULL buffer");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    const double Lg = lmfr_log_extent(L, gaze);
+    if (!(Lg > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+    ReconLmfr r;
+    std::memset(&r, 0, sizeof(r));
+    r.w = L->n_cols;
+    r.h = L->max_rows;
+    r.width = L->disp.width;
+    r.height = L->disp.height;
+    r.gx = (float)gaze.x_px;
+    r.gy = (float)gaze.y_px;
+    r.inv_L = (float)(1.0 / Lg);
+    r.alpha = (float)L->alpha;
+    r.lp = reinterpret_cast<const float4*>(lp);
+    r.img = reinterpret_cast<float4*>(img);
+    return launch_reconstruct_lmfr(r, stream);
+}
+
+extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* d, const vafr_shading* sh,
+                          float* img, int32_t* hit, hipStream_t stream) {
+    if (!d) return fail(VAFR_E_ARG, "display is NULL");
+    if (d->width <= 0 || d->height <= 0 || d->width > 65536 || d->height > 65536)
+        return fail(VAFR_E_ARG, "display size out of range");
+    if (!(d->fov_x_deg > 0.0 && d->fov_x_deg < 180.0) || !(d->fov_y_deg > 0.0 && d->fov_y_deg < 180.0))
+        return fail(VAFR_E_ARG, "field of view must lie in (0, 180) degrees");
+    if (int rc = check_camera(cam)) return rc;
+    if (int rc = check_shading(sh)) return rc;
+    if (!img) return fail(VAFR_E_ARG, "img_rgba_dev is NULL");
+    SceneDev sd;
+    if (int rc = scene_dev(scene, &sd)) return rc;
+    TraceView v;
+    std::memset(&v, 0, sizeof(v));
+    fill_view_common(v, cam, sh);
+    v.mode = kModeFull;
+    v.width = d->width;
+    v.height = d->height;
+    film_pitch(*d, &v.px, &v.py);
+    v.n_items = (int64_t)d->width * d->height;
+    v.out_rgba = reinterpret_cast<float4*>(img);
+    v.out_id = hit;
+    return launch_trace(sd, v, stream);
+}

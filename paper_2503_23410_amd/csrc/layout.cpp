@@ -1,0 +1,282 @@
+// Host side of the LP layouts: FP64 acuity segments, the VaFR constant-size
+// LP buffer (Sec. 3.2.1-3.2.3, Sec. 3.3) and the LMFR comparison buffer
+// (Sec. 3.1 Eq. (1), Sec. 4.1 Eq. (14)), plus their per-device upload.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "vafr_internal.h"
+
+namespace vafr {
+
+static constexpr double kDeg = M_PI / 180.0;
+
+// Pivots (e_k, f_k) -> linear MAR per segment (Sec. 3.3): omega(e_k) = 1/f_k,
+// omega(e_{k+1}) = 1/f_{k+1}.  u(0) = 0 and u is continuous at the pivots,
+// which fixes the constants c_k of Eq. (12).
+int build_segments(int n_piv, const double* ecc, const double* cpd, Segments* s) {
+    if (n_piv < 2 || n_piv > kMaxSeg + 1) return fail(VAFR_E_ARG, "n_pivots must be in [2, %d]", kMaxSeg + 1);
+    if (!ecc || !cpd) return fail(VAFR_E_ARG, "acuity arrays are NULL");
+    if (ecc[0] != 0.0) return fail(VAFR_E_ARG, "first pivot eccentricity must be 0");
+    for (int k = 0; k < n_piv; ++k) {
+        if (!std::isfinite(ecc[k]) || !std::isfinite(cpd[k]) || !(cpd[k] > 0.0))
+            return fail(VAFR_E_ARG, "pivot %d: acuity must be finite and > 0", k);
+        if (k && !(ecc[k] > ecc[k - 1])) return fail(VAFR_E_ARG, "pivot eccentricities must increase strictly");
+    }
+    Segments r;
+    r.n = n_piv - 1;
+    for (int k = 0; k < n_piv; ++k) r.e[k] = ecc[k];
+    for (int k = 0; k < r.n; ++k) {
+        const double mar0 = 1.0 / cpd[k], mar1 = 1.0 / cpd[k + 1];
+        r.m[k] = (mar1 - mar0) / (ecc[k + 1] - ecc[k]);
+        r.b[k] = mar0 - r.m[k] * ecc[k];
+    }
+    auto raw = [&](int k, double e) {
+        return r.m[k] == 0.0 ? 2.0 * e / r.b[k] : 2.0 * std::log(r.m[k] * e + r.b[k]) / r.m[k];
+    };
+    r.u[0] = 0.0;
+    for (int k = 0; k < r.n; ++k) {
+        r.c[k] = r.u[k] - raw(k, r.e[k]);
+        r.u[k + 1] = raw(k, r.e[k + 1]) + r.c[k];
+    }
+    *s = r;
+    return VAFR_OK;
+}
+
+static int seg_index_e(const Segments& s, double e) {
+    int k = 0;
+    while (k + 1 < s.n && e >= s.e[k + 1]) ++k;
+    return k;
+}
+
+static int seg_index_u(const Segments& s, double u) {
+    int k = 0;
+    while (k + 1 < s.n && u >= s.u[k + 1]) ++k;
+    return k;
+}
+
+// Eq. (5) on the segment holding e; the last segment extends past e_max.
+double seg_u(const Segments& s, double e) {
+    const int k = seg_index_e(s, e);
+    if (s.m[k] == 0.0) return 2.0 * e / s.b[k] + s.c[k];
+    return 2.0 * std::log(s.m[k] * e + s.b[k]) / s.m[k] + s.c[k];
+}
+
+// Eq. (10) on the segment holding u.
+double seg_e_of_u(const Segments& s, double u) {
+    const int k = seg_index_u(s, u);
+    if (s.m[k] == 0.0) return (u - s.c[k]) * s.b[k] * 0.5;
+    return (std::exp((u - s.c[k]) * s.m[k] * 0.5) - s.b[k]) / s.m[k];
+}
+
+// Eq. (9): l(e) = 360 sin(2e) / omega(e).
+double seg_l(const Segments& s, double e) {
+    const int k = seg_index_e(s, e);
+    return 360.0 * std::sin(2.0 * e * kDeg) / (s.m[k] * e + s.b[k]);
+}
+
+// Film plane at unit focal length; a pixel spans 2 tan(fov/2) / size.
+void film_pitch(const vafr_display& d, double* px, double* py) {
+    *px = 2.0 * std::tan(0.5 * d.fov_x_deg * kDeg) / d.width;
+    *py = 2.0 * std::tan(0.5 * d.fov_y_deg * kDeg) / d.height;
+}
+
+SegmentsF segments_f32(const Segments& s) {
+    SegmentsF f;
+    std::memset(&f, 0, sizeof(f));
+    f.n = s.n;
+    for (int k = 0; k <= s.n; ++k) f.e[k] = (float)s.e[k];
+    for (int k = 0; k < s.n; ++k) {
+        f.m[k] = (float)s.m[k];
+        f.b[k] = (float)s.b[k];
+        // u = (2/m) ln(omega) + c; for m == 0 the kernel uses u = (2/b) e + c.
+        f.two_over_m[k] = s.m[k] == 0.0 ? 0.0f : (float)(2.0 / s.m[k]);
+        f.c[k] = (float)s.c[k];
+    }
+    return f;
+}
+
+static int check_display(const vafr_display* d) {
+    if (!d) return fail(VAFR_E_ARG, "display is NULL");
+    if (d->width <= 0 || d->height <= 0 || d->width > 65536 || d->height > 65536)
+        return fail(VAFR_E_ARG, "display size %dx%d out of range [1, 65536]", d->width, d->height);
+    if (!(d->fov_x_deg > 0.0 && d->fov_x_deg < 180.0) || !(d->fov_y_deg > 0.0 && d->fov_y_deg < 180.0))
+        return fail(VAFR_E_ARG, "field of view must lie in (0, 180) degrees");
+    return VAFR_OK;
+}
+
+int layout_device(vafr_layout L, const LayoutDev** out) {
+    int dev = -1;
+    VAFR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(L->mu);
+    for (auto& d : L->dev)
+        if (d.device == dev) { *out = &d; return VAFR_OK; }
+    LayoutDev d;
+    d.device = dev;
+    if (L->kind == VAFR_LAYOUT_VAFR) {
+        std::vector<int2> col(L->n_cols);
+        for (int i = 0; i < L->n_cols; ++i) col[i] = make_int2(L->n_rows[i], (int)L->col_off[i]);
+        VAFR_HIP(hipMalloc(&d.col, sizeof(int2) * col.size()));
+        VAFR_HIP(hipMemcpy(d.col, col.data(), sizeof(int2) * col.size(), hipMemcpyHostToDevice));
+        VAFR_HIP(hipMalloc(&d.dxy, sizeof(float) * L->dxy.size()));
+        VAFR_HIP(hipMemcpy(d.dxy, L->dxy.data(), sizeof(float) * L->dxy.size(), hipMemcpyHostToDevice));
+    } else {
+        std::vector<double2> cs(L->max_rows);
+        for (int j = 0; j < L->max_rows; ++j) cs[j] = make_double2(L->lm_cos[j], L->lm_sin[j]);
+        VAFR_HIP(hipMalloc(&d.lm_z, sizeof(double) * L->lm_z.size()));
+        VAFR_HIP(hipMemcpy(d.lm_z, L->lm_z.data(), sizeof(double) * L->lm_z.size(), hipMemcpyHostToDevice));
+        VAFR_HIP(hipMalloc(&d.lm_cs, sizeof(double2) * cs.size()));
+        VAFR_HIP(hipMemcpy(d.lm_cs, cs.data(), sizeof(double2) * cs.size(), hipMemcpyHostToDevice));
+    }
+    L->dev.push_back(d);
+    *out = &L->dev.back();
+    return VAFR_OK;
+}
+
+}  // namespace vafr
+
+using namespace vafr;
+
+extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* acuity, vafr_layout* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_display(display)) return rc;
+    static const double kEcc[5] = {0.0, 10.0, 20.0, 30.0, 60.0};
+    static const double kCpd[5] = {40.0, 10.0, 6.0, 5.0, 4.0};
+    vafr_acuity def{5, kEcc, kCpd, 60.0};
+    const vafr_acuity* a = acuity ? acuity : &def;
+    if (!(a->e_max_deg > 0.0 && a->e_max_deg < 90.0)) return fail(VAFR_E_ARG, "e_max must lie in (0, 90)");
+    Segments seg;
+    if (int rc = build_segments(a->n_pivots, a->ecc_deg, a->cpd, &seg)) return rc;
+    // MAR must stay positive up to e_max (and a little beyond for corners).
+    for (int k = 0; k < seg.n; ++k) {
+        double hi = (k + 1 < seg.n) ? seg.e[k + 1] : std::max(seg.e[k + 1], a->e_max_deg) + 30.0;
+        if (!(seg.m[k] * seg.e[k] + seg.b[k] > 0.0) || !(seg.m[k] * hi + seg.b[k] > 0.0))
+            return fail(VAFR_E_ARG, "acuity model gives a non-positive MAR on segment %d", k);
+    }
+    vafr_layout L = new (std::nothrow) vafr_layout_s;
+    if (!L) return fail(VAFR_E_OOM, "layout allocation failed");
+    L->kind = VAFR_LAYOUT_VAFR;
+    L->disp = *display;
+    film_pitch(*display, &L->px, &L->py);
+    L->seg = seg;
+    L->e_max = a->e_max_deg;
+    // Columns sampled at their centres u = i + 1/2; rows = ceil(l(e_i)).
+    const double umax = seg_u(seg, a->e_max_deg);
+    L->n_cols = (int32_t)std::ceil(umax);
+    try {
+        L->n_rows.resize(L->n_cols);
+        L->col_off.resize(L->n_cols + 1);
+        int64_t off = 0;
+        std::vector<double> col_e(L->n_cols);
+        for (int32_t i = 0; i < L->n_cols; ++i) {
+            col_e[i] = seg_e_of_u(seg, i + 0.5);
+            const int32_t n = (int32_t)std::ceil(seg_l(seg, col_e[i]));
+            L->n_rows[i] = n < 1 ? 1 : n;
+            L->col_off[i] = off;
+            off += L->n_rows[i];
+            if (L->n_rows[i] > L->max_rows) L->max_rows = L->n_rows[i];
+        }
+        L->col_off[L->n_cols] = off;
+        L->n_texels = off;
+        if (off >= (int64_t)1 << 31) {
+            delete L;
+            return fail(VAFR_E_UNSUPPORTED, "layout with %lld texels exceeds 2^31", (long long)off);
+        }
+        // Film offset of each texel's screen point from the gaze point:
+        // radius tan(e_i) (Eq. (3) at unit focal length) along the row angle.
+        L->dxy.resize(2 * (size_t)off);
+        for (int32_t i = 0; i < L->n_cols; ++i) {
+            const double rho = std::tan(col_e[i] * kDeg);
+            const int32_t n = L->n_rows[i];
+            float* d = L->dxy.data() + 2 * L->col_off[i];
+            for (int32_t j = 0; j < n; ++j) {
+                const double th = (360.0 * (j + 0.5) / n) * kDeg;
+                d[2 * j] = (float)(rho * std::cos(th));
+                d[2 * j + 1] = (float)(rho * std::sin(th));
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        delete L;
+        return fail(VAFR_E_OOM, "layout tables allocation failed");
+    }
+    *out = L;
+    return VAFR_OK;
+}
+
+extern "C" int lmfr_lp_layout(const vafr_display* display, double delta, double alpha, vafr_layout* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_display(display)) return rc;
+    if (!(delta >= 1.0 && delta < 1e6)) return fail(VAFR_E_ARG, "delta must be >= 1");
+    if (!(alpha > 0.0 && alpha < 64.0)) return fail(VAFR_E_ARG, "alpha must be in (0, 64)");
+    vafr_layout L = new (std::nothrow) vafr_layout_s;
+    if (!L) return fail(VAFR_E_OOM, "layout allocation failed");
+    L->kind = VAFR_LAYOUT_LMFR;
+    L->disp = *display;
+    film_pitch(*display, &L->px, &L->py);
+    L->delta = delta;
+    L->alpha = alpha;
+    const int32_t w = (int32_t)std::lround(display->width / delta);
+    const int32_t h = (int32_t)std::lround(display->height / delta);
+    L->n_cols = w < 1 ? 1 : w;
+    L->max_rows = h < 1 ? 1 : h;
+    L->n_texels = (int64_t)L->n_cols * L->max_rows;
+    try {
+        L->n_rows.assign(L->n_cols, L->max_rows);
+        L->col_off.resize(L->n_cols + 1);
+        for (int32_t i = 0; i <= L->n_cols; ++i) L->col_off[i] = (int64_t)i * L->max_rows;
+        // Inverse of Eq. (1) with K(z) = z^alpha: column i sits at
+        // z = ((i + 1/2)/w)^(1/alpha); row j at theta = 360 (j + 1/2)/h.
+        L->lm_z.resize(L->n_cols);
+        for (int32_t i = 0; i < L->n_cols; ++i) L->lm_z[i] = std::pow((i + 0.5) / L->n_cols, 1.0 / alpha);
+        L->lm_cos.resize(L->max_rows);
+        L->lm_sin.resize(L->max_rows);
+        for (int32_t j = 0; j < L->max_rows; ++j) {
+            const double th = 360.0 * (j + 0.5) / L->max_rows;
+            L->lm_cos[j] = std::cos(th * kDeg);
+            L->lm_sin[j] = std::sin(th * kDeg);
+        }
+    } catch (const std::bad_alloc&) {
+        delete L;
+        return fail(VAFR_E_OOM, "layout tables allocation failed");
+    }
+    *out = L;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_layout_dims(vafr_layout L, vafr_dims* out) {
+    if (!L || !out) return fail(VAFR_E_ARG, "NULL argument");
+    out->kind = L->kind;
+    out->n_cols = L->n_cols;
+    out->max_rows = L->max_rows;
+    out->width = L->disp.width;
+    out->height = L->disp.height;
+    out->n_texels = L->n_texels;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_layout_tables(vafr_layout L, const int32_t** n_rows, const int64_t** col_off,
+                                  const float** texel_dxy) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (n_rows) *n_rows = L->n_rows.data();
+    if (col_off) *col_off = L->col_off.data();
+    if (texel_dxy) *texel_dxy = L->kind == VAFR_LAYOUT_VAFR ? L->dxy.data() : nullptr;
+    return VAFR_OK;
+}
+
+extern "C" void vafr_layout_destroy(vafr_layout L) {
+    if (!L) return;
+    int cur = -1;
+    bool have = hipGetDevice(&cur) == hipSuccess;
+    for (auto& d : L->dev) {
+        if (hipSetDevice(d.device) != hipSuccess) continue;
+        (void)hipFree(d.col);
+        (void)hipFree(d.dxy);
+        (void)hipFree(d.lm_z);
+        (void)hipFree(d.lm_cs);
+    }
+    if (have) (void)hipSetDevice(cur);
+    delete L;
+}

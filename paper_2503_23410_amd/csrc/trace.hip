@@ -1,0 +1,401 @@
+// Ray generation, BVH traversal, watertight closest hit and shading for the
+// LP buffer (Sec. 6.1: one ray per LP texel, closest-hit shading, miss
+// shader), the LMFR buffer and the full-resolution comparison.
+//
+// Build with -ffp-contract=off: the ray set-up and the triangle test below
+// are written operation by operation so that every rounding is stated, and
+// no multiply-add may be fused unless fmaf() says so.
+#include "vafr_internal.h"
+
+namespace vafr {
+namespace {
+
+constexpr int kBlock = 256;
+// Conservative slab test (Ize, "Robust BVH Ray Traversal", JCGT 2013): the
+// exit distance is scaled by 1 + 2 gamma_3 before the overlap test.
+constexpr float kExitScale = 1.0000004f;
+// Boxes are tested up to the current hit distance scaled by this factor,
+// which covers the rounding of a triangle's t relative to its box.
+constexpr float kHitSlack = 1.00001f;
+constexpr float kTiny = 1e-30f;
+
+struct RayPre {
+    float ox, oy, oz;
+    float dx, dy, dz;
+    float ix, iy, iz;       // 1/d with zero components replaced by +-kTiny
+    int kx, ky, kz;
+    float Sx, Sy, Sz;
+    bool valid;
+};
+
+__device__ __forceinline__ float sel3(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
+
+__device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx, float dy, float dz, RayPre& r) {
+    r.ox = ox; r.oy = oy; r.oz = oz;
+    r.dx = dx; r.dy = dy; r.dz = dz;
+    const float sx = dx == 0.0f ? copysignf(kTiny, dx) : dx;
+    const float sy = dy == 0.0f ? copysignf(kTiny, dy) : dy;
+    const float sz = dz == 0.0f ? copysignf(kTiny, dz) : dz;
+    r.ix = 1.0f / sx;
+    r.iy = 1.0f / sy;
+    r.iz = 1.0f / sz;
+    // Watertight set-up: the axis of largest |d| becomes z (first on ties);
+    // x, y follow cyclically and swap when d_z < 0.
+    int kz = 0;
+    float m = fabsf(dx);
+    if (fabsf(dy) > m) { kz = 1; m = fabsf(dy); }
+    if (fabsf(dz) > m) { kz = 2; }
+    int kx = kz == 2 ? 0 : kz + 1;
+    int ky = kx == 2 ? 0 : kx + 1;
+    const float dkz = sel3(kz, dx, dy, dz);
+    if (dkz < 0.0f) { const int t = kx; kx = ky; ky = t; }
+    r.kx = kx; r.ky = ky; r.kz = kz;
+    r.valid = dkz != 0.0f;
+    const float dkx = sel3(kx, dx, dy, dz), dky = sel3(ky, dx, dy, dz);
+    r.Sx = dkx / dkz;
+    r.Sy = dky / dkz;
+    r.Sz = 1.0f / dkz;
+}
+
+// FP32 watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013).
+// Returns true on a hit with t > 0 and writes t = T / det.
+__device__ __forceinline__ bool tri_hit(const RayPre& r, float4 v0, float4 v1, float4 v2, float& t_out) {
+    const float A0 = v0.x - r.ox, A1 = v0.y - r.oy, A2 = v0.z - r.oz;
+    const float B0 = v1.x - r.ox, B1 = v1.y - r.oy, B2 = v1.z - r.oz;
+    const float C0 = v2.x - r.ox, C1 = v2.y - r.oy, C2 = v2.z - r.oz;
+    const float Akz = sel3(r.kz, A0, A1, A2), Bkz = sel3(r.kz, B0, B1, B2), Ckz = sel3(r.kz, C0, C1, C2);
+    const float Ax = fmaf(-r.Sx, Akz, sel3(r.kx, A0, A1, A2));
+    const float Ay = fmaf(-r.Sy, Akz, sel3(r.ky, A0, A1, A2));
+    const float Bx = fmaf(-r.Sx, Bkz, sel3(r.kx, B0, B1, B2));
+    const float By = fmaf(-r.Sy, Bkz, sel3(r.ky, B0, B1, B2));
+    const float Cx = fmaf(-r.Sx, Ckz, sel3(r.kx, C0, C1, C2));
+    const float Cy = fmaf(-r.Sy, Ckz, sel3(r.ky, C0, C1, C2));
+    // Edge functions with plain products (a shared edge gets exactly
+    // negated values in its two triangles).
+    float U = Cx * By - Cy * Bx;
+    float V = Ax * Cy - Ay * Cx;
+    float W = Bx * Ay - By * Ax;
+    if (U == 0.0f || V == 0.0f || W == 0.0f) {
+        U = (float)((double)Cx * (double)By - (double)Cy * (double)Bx);
+        V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
+        W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
+    }
+    if ((U < 0.0f || V < 0.0f || W < 0.0f) && (U > 0.0f || V > 0.0f || W > 0.0f)) return false;
+    const float det = (U + V) + W;
+    if (det == 0.0f || !r.valid) return false;
+    const float Az = r.Sz * Akz, Bz = r.Sz * Bkz, Cz = r.Sz * Ckz;
+    const float T = (U * Az + V * Bz) + W * Cz;
+    const float t = T / det;
+    t_out = t;
+    return t > 0.0f;
+}
+
+// Two child boxes of a node against the ray over [0, tlim].
+__device__ __forceinline__ void box2(const RayPre& r, const float4 a, const float4 b, const float4 c, float tlim,
+                                     bool& h0, bool& h1, float& tn0, float& tn1) {
+    const float x0 = (a.x - r.ox) * r.ix, x1 = (a.y - r.ox) * r.ix;
+    const float y0 = (a.z - r.oy) * r.iy, y1 = (a.w - r.oy) * r.iy;
+    const float z0 = (c.x - r.oz) * r.iz, z1 = (c.y - r.oz) * r.iz;
+    tn0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+    const float tf0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tlim));
+    h0 = tn0 <= tf0 * kExitScale;
+    const float p0 = (b.x - r.ox) * r.ix, p1 = (b.y - r.ox) * r.ix;
+    const float q0 = (b.z - r.oy) * r.iy, q1 = (b.w - r.oy) * r.iy;
+    const float s0 = (c.z - r.oz) * r.iz, s1 = (c.w - r.oz) * r.iz;
+    tn1 = fmaxf(fmaxf(fminf(p0, p1), fminf(q0, q1)), fmaxf(fminf(s0, s1), 0.0f));
+    const float tf1 = fminf(fminf(fmaxf(p0, p1), fmaxf(q0, q1)), fminf(fmaxf(s0, s1), tlim));
+    h1 = tn1 <= tf1 * kExitScale;
+}
+
+// Closest hit: smallest (t, triangle id); returns the stored slot or -1.
+// stk points at this lane's column of the block's LDS stack (stride kBlock).
+__device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float& t_best, int& id_best) {
+    t_best = INFINITY;
+    id_best = -1;
+    int slot_best = -1;
+    int ref = sc.root;
+    if (ref == kEmptyRef) return -1;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
+            const float4 a = p[0], b = p[1], c = p[2];
+            const int4 d = reinterpret_cast<const int4*>(p)[3];
+            const float tlim = t_best * kHitSlack;
+            bool h0, h1;
+            float tn0, tn1;
+            box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
+            if (h0 && h1) {
+                const bool first0 = tn0 <= tn1;
+                stk[sp * kBlock] = first0 ? d.y : d.x;
+                ++sp;
+                ref = first0 ? d.x : d.y;
+                continue;
+            }
+            if (h0) { ref = d.x; continue; }
+            if (h1) { ref = d.y; continue; }
+        } else {
+            const int x = ~ref;
+            const int first = x >> 3, count = (x & 7) + 1;
+            const float4* tp = sc.tris + 3 * (size_t)first;
+            for (int q = 0; q < count; ++q) {
+                const float4 v0 = tp[3 * q], v1 = tp[3 * q + 1], v2 = tp[3 * q + 2];
+                float t;
+                if (tri_hit(r, v0, v1, v2, t)) {
+                    const int id = __float_as_int(v0.w);
+                    if (t < t_best || (t == t_best && id < id_best)) {
+                        t_best = t;
+                        id_best = id;
+                        slot_best = first + q;
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+    return slot_best;
+}
+
+// Any hit with t > 0 (shadow ray toward a directional light).
+__device__ bool any_hit(const SceneDev& sc, const RayPre& r, int* stk) {
+    int ref = sc.root;
+    if (ref == kEmptyRef) return false;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
+            const float4 a = p[0], b = p[1], c = p[2];
+            const int4 d = reinterpret_cast<const int4*>(p)[3];
+            bool h0, h1;
+            float tn0, tn1;
+            box2(r, a, b, c, INFINITY, h0, h1, tn0, tn1);
+            if (h0 && h1) {
+                const bool first0 = tn0 <= tn1;
+                stk[sp * kBlock] = first0 ? d.y : d.x;
+                ++sp;
+                ref = first0 ? d.x : d.y;
+                continue;
+            }
+            if (h0) { ref = d.x; continue; }
+            if (h1) { ref = d.y; continue; }
+        } else {
+            const int x = ~ref;
+            const int first = x >> 3, count = (x & 7) + 1;
+            const float4* tp = sc.tris + 3 * (size_t)first;
+            for (int q = 0; q < count; ++q) {
+                float t;
+                if (tri_hit(r, tp[3 * q], tp[3 * q + 1], tp[3 * q + 2], t)) return true;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+    return false;
+}
+
+// 32-bit hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
+// JCGT 9(3), 2020 (PCG output permutation of one LCG step).
+__device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
+    const uint32_t state = v * 747796405u + 2891336453u;
+    const uint32_t word = ((state >> ((state >> 28u) + 4u)) ^ state) * 277803737u;
+    return (word >> 22u) ^ word;
+}
+
+__device__ __forceinline__ float3 albedo_of(int id) {
+    const uint32_t h = pcg_hash((uint32_t)id);
+    return make_float3(0.2f + 0.7f * (float)(h & 255u) / 255.0f, 0.2f + 0.7f * (float)((h >> 8) & 255u) / 255.0f,
+                       0.2f + 0.7f * (float)((h >> 16) & 255u) / 255.0f);
+}
+
+// Geometric normal facing the ray and the offset origin of the next ray.
+__device__ __forceinline__ void hit_frame(const float4 v0, const float4 v1, const float4 v2, const RayPre& r, float t,
+                                          float3& n, float3& os) {
+    const float e1x = v1.x - v0.x, e1y = v1.y - v0.y, e1z = v1.z - v0.z;
+    const float e2x = v2.x - v0.x, e2y = v2.y - v0.y, e2z = v2.z - v0.z;
+    float nx = e1y * e2z - e1z * e2y;
+    float ny = e1z * e2x - e1x * e2z;
+    float nz = e1x * e2y - e1y * e2x;
+    const float l2 = (nx * nx + ny * ny) + nz * nz;
+    const float len = sqrtf(l2);
+    if (len > 0.0f) { nx = nx / len; ny = ny / len; nz = nz / len; }
+    const float nd = (nx * r.dx + ny * r.dy) + nz * r.dz;
+    if (nd > 0.0f) { nx = -nx; ny = -ny; nz = -nz; }
+    const float px = fmaf(t, r.dx, r.ox), py = fmaf(t, r.dy, r.oy), pz = fmaf(t, r.dz, r.oz);
+    const float mx = fmaxf(fmaxf(fabsf(px), fabsf(py)), fabsf(pz));
+    const float eps = 1e-4f * (1.0f + mx);
+    n = make_float3(nx, ny, nz);
+    os = make_float3(fmaf(eps, nx, px), fmaf(eps, ny, py), fmaf(eps, nz, pz));
+}
+
+__device__ __forceinline__ float rng01(const TraceView& v, uint32_t texel, uint32_t slot) {
+    uint32_t h = pcg_hash(v.seed_lo);
+    h = pcg_hash(h ^ v.seed_hi);
+    h = pcg_hash(h ^ v.frame);
+    h = pcg_hash(h ^ v.view);
+    h = pcg_hash(h ^ texel);
+    h = pcg_hash(h ^ slot);
+    return (float)(h >> 8) * (1.0f / 16777216.0f);
+}
+
+// Cosine-weighted direction about n: rejection-sampled disk point (up to 8
+// tries) lifted to the hemisphere, in the frame of Duff et al. (JCGT 2017).
+__device__ __forceinline__ float3 cosine_dir(const TraceView& v, float3 n, uint32_t texel, uint32_t bounce) {
+    float x = 0.0f, y = 0.0f;
+    for (uint32_t tr = 0; tr < 8; ++tr) {
+        const float r0 = rng01(v, texel, bounce * 32u + 2u * tr);
+        const float r1 = rng01(v, texel, bounce * 32u + 2u * tr + 1u);
+        const float xx = 2.0f * r0 - 1.0f, yy = 2.0f * r1 - 1.0f;
+        if (xx * xx + yy * yy < 1.0f) { x = xx; y = yy; break; }
+    }
+    const float zz = (1.0f - x * x) - y * y;
+    const float z = sqrtf(zz > 0.0f ? zz : 0.0f);
+    const float s = copysignf(1.0f, n.z);
+    const float a = -1.0f / (s + n.z);
+    const float b = n.x * n.y * a;
+    const float t1x = 1.0f + s * n.x * n.x * a, t1y = s * b, t1z = -s * n.x;
+    const float t2x = b, t2y = s + n.y * n.y * a, t2z = -n.y;
+    return make_float3((x * t1x + y * t2x) + z * n.x, (x * t1y + y * t2y) + z * n.y, (x * t1z + y * t2z) + z * n.z);
+}
+
+// Primary ray direction through film point (Px, Py): (Px R - Py U) + F,
+// formed in FP64 operation by operation and rounded to FP32 once.
+__device__ __forceinline__ void film_ray(const TraceView& v, double Px, double Py, RayPre& r) {
+    float d[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double a = Px * (double)v.right[k];
+        const double b = Py * (double)v.up[k];
+        const double s = a - b;
+        d[k] = (float)(s + (double)v.fwd[k]);
+    }
+    ray_setup(v.eye[0], v.eye[1], v.eye[2], d[0], d[1], d[2], r);
+}
+
+// Item -> (ray, output slot).  Returns false for padding items.
+__device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, RayPre& r, int64_t& out) {
+    if (v.mode == kModeVafr) {
+        const float2 o = v.dxy[k];
+        film_ray(v, v.gx + (double)o.x, v.gy + (double)o.y, r);
+        out = k;
+        return true;
+    }
+    if (v.mode == kModeLmfr) {
+        const int64_t i = k / v.lm_h, j = k - i * v.lm_h;
+        const double rad = exp(v.lm_L * v.lm_z[i]);
+        const double2 cs = v.lm_cs[j];
+        film_ray(v, v.gx + (rad * cs.x) * v.px, v.gy + (rad * cs.y) * v.py, r);
+        out = k;
+        return true;
+    }
+    // full resolution, 8 x 8 pixel tiles for coherent waves
+    const int tiles_x = (v.width + 7) >> 3;
+    const int64_t tile = k >> 6;
+    const int w = (int)(k & 63);
+    const int x = (int)(tile % tiles_x) * 8 + (w & 7);
+    const int y = (int)(tile / tiles_x) * 8 + (w >> 3);
+    if (x >= v.width || y >= v.height) return false;
+    film_ray(v, ((double)x + 0.5 - 0.5 * (double)v.width) * v.px, ((double)y + 0.5 - 0.5 * (double)v.height) * v.py,
+             r);
+    out = (int64_t)y * v.width + x;
+    return true;
+}
+
+__device__ float4 shade_lambert(const SceneDev& sc, const TraceView& v, const RayPre& r, int* stk, int& id_out) {
+    float t;
+    int id;
+    const int slot = closest_hit(sc, r, stk, t, id);
+    id_out = id;
+    if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
+    const float4* tp = sc.tris + 3 * (size_t)slot;
+    float3 n, os;
+    hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+    const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
+    float vis = 1.0f;
+    if (ndl > 0.0f && v.shadow) {
+        RayPre s;
+        ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
+        if (any_hit(sc, s, stk)) vis = 0.0f;
+    }
+    const float lam = ndl > 0.0f ? ndl : 0.0f;
+    const float3 a = albedo_of(id);
+    return make_float4(a.x * (v.ambient[0] + v.light_rgb[0] * lam * vis),
+                       a.y * (v.ambient[1] + v.light_rgb[1] * lam * vis),
+                       a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
+}
+
+__device__ float4 shade_path(const SceneDev& sc, const TraceView& v, RayPre r, uint32_t texel, int* stk,
+                             int& id_out) {
+    float3 thr = make_float3(1.0f, 1.0f, 1.0f);
+    float3 L = make_float3(0.0f, 0.0f, 0.0f);
+    id_out = -1;
+    for (int bnc = 0; bnc <= v.bounces; ++bnc) {
+        float t;
+        int id;
+        const int slot = closest_hit(sc, r, stk, t, id);
+        if (bnc == 0) id_out = id;
+        if (slot < 0) {
+            L.x += thr.x * v.background[0];
+            L.y += thr.y * v.background[1];
+            L.z += thr.z * v.background[2];
+            break;
+        }
+        const float4* tp = sc.tris + 3 * (size_t)slot;
+        float3 n, os;
+        hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+        const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
+        float vis = 0.0f;
+        if (ndl > 0.0f) {
+            RayPre s;
+            ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
+            vis = any_hit(sc, s, stk) ? 0.0f : 1.0f;
+        }
+        const float3 a = albedo_of(id);
+        thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
+        L.x += thr.x * (v.ambient[0] + v.light_rgb[0] * ndl * vis);
+        L.y += thr.y * (v.ambient[1] + v.light_rgb[1] * ndl * vis);
+        L.z += thr.z * (v.ambient[2] + v.light_rgb[2] * ndl * vis);
+        if (bnc == v.bounces) break;
+        const float3 w = cosine_dir(v, n, texel, (uint32_t)bnc);
+        ray_setup(os.x, os.y, os.z, w.x, w.y, w.z, r);
+    }
+    return make_float4(L.x, L.y, L.z, 1.0f);
+}
+
+__global__ __launch_bounds__(kBlock) void k_trace(const SceneDev sc, const TraceView v, int64_t n_items) {
+    __shared__ int stack[kMaxDepth * kBlock];
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n_items) return;
+    RayPre r;
+    int64_t out;
+    if (!make_item_ray(v, k, r, out)) return;
+    int* stk = stack + threadIdx.x;
+    int id;
+    float4 c;
+    if (v.shade_mode == VAFR_SHADE_PATH)
+        c = shade_path(sc, v, r, (uint32_t)out, stk, id);
+    else
+        c = shade_lambert(sc, v, r, stk, id);
+    v.out_rgba[out] = c;
+    if (v.out_id) v.out_id[out] = id;
+}
+
+}  // namespace
+
+int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream) {
+    int64_t n_items = v.n_items;
+    if (v.mode == kModeFull) {
+        const int64_t tx = (v.width + 7) / 8, ty = (v.height + 7) / 8;
+        n_items = tx * ty * 64;
+    }
+    if (n_items <= 0) return VAFR_OK;
+    const int64_t blocks = (n_items + kBlock - 1) / kBlock;
+    if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
+    hipLaunchKernelGGL(k_trace, dim3((unsigned)blocks), dim3(kBlock), 0, stream, sc, v, n_items);
+    VAFR_HIP(hipGetLastError());
+    return VAFR_OK;
+}
+
+}  // namespace vafr

@@ -1,0 +1,197 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "vafr.h"
+
+namespace vafr {
+
+// ------------------------------------------------------------------ errors
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define VAFR_HIP(call)                                      \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return ::vafr::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------- acuity segments
+// MAR omega(e) = m_k e + b_k on [e_k, e_{k+1}); u(e) = 2 ln(omega)/m_k + c_k.
+constexpr int kMaxSeg = 16;
+struct Segments {
+    int n = 0;
+    double e[kMaxSeg + 1] = {};
+    double m[kMaxSeg] = {};
+    double b[kMaxSeg] = {};
+    double c[kMaxSeg] = {};
+    double u[kMaxSeg + 1] = {};
+};
+
+// FP32 copy of the segment constants handed to the reconstruction kernel.
+struct SegmentsF {
+    int n;
+    float e[kMaxSeg + 1];
+    float m[kMaxSeg];
+    float b[kMaxSeg];
+    float two_over_m[kMaxSeg];
+    float c[kMaxSeg];
+};
+
+// Per-device copy of a layout's tables.
+struct LayoutDev {
+    int device = -1;
+    int2* col = nullptr;          // VaFR: (n_rows, col_off) per column
+    float2* dxy = nullptr;        // VaFR: film offset per texel
+    double* lm_z = nullptr;       // LMFR: z_i per column
+    double2* lm_cs = nullptr;     // LMFR: (cos, sin) of theta_j per row
+};
+
+}  // namespace vafr
+
+struct vafr_layout_s {
+    int kind = VAFR_LAYOUT_VAFR;
+    vafr_display disp{};
+    double px = 0, py = 0;               // film pitch per pixel (FP64)
+    // VaFR
+    vafr::Segments seg;
+    double e_max = 60.0;
+    int32_t n_cols = 0, max_rows = 0;
+    int64_t n_texels = 0;
+    std::vector<int32_t> n_rows;
+    std::vector<int64_t> col_off;
+    std::vector<float> dxy;
+    // LMFR
+    double delta = 0, alpha = 0;
+    std::vector<double> lm_z, lm_cos, lm_sin;
+    // device copies
+    std::mutex mu;
+    std::deque<vafr::LayoutDev> dev;   // stable addresses across push_back
+};
+
+namespace vafr {
+
+// ------------------------------------------------------------------ layout
+int build_segments(int n_piv, const double* ecc, const double* cpd, Segments* s);
+double seg_u(const Segments& s, double e);
+double seg_e_of_u(const Segments& s, double u);
+double seg_l(const Segments& s, double e);
+void film_pitch(const vafr_display& d, double* px, double* py);
+SegmentsF segments_f32(const Segments& s);
+// Upload (once per device) and return the tables of the current device.
+int layout_device(vafr_layout L, const LayoutDev** out);
+
+// -------------------------------------------------------------------- BVH
+// Device node: two child boxes and two child references (64 bytes).
+//   a = (lo0.x, hi0.x, lo0.y, hi0.y)  b = (lo1.x, hi1.x, lo1.y, hi1.y)
+//   c = (lo0.z, hi0.z, lo1.z, hi1.z)  d = (ref0, ref1, 0, 0)
+// ref >= 0: internal node index; ref < 0: leaf, ~ref = first << 3 | (count-1).
+struct alignas(16) BvhNode {
+    float4 a, b, c;
+    int4 d;
+};
+constexpr int kMaxLeaf = 4;
+constexpr int kMaxDepth = 32;   // traversal stack depth bound
+constexpr int32_t kEmptyRef = INT32_MIN;
+
+struct HostBvh {
+    std::vector<BvhNode> nodes;
+    std::vector<float4> tris;    // 3 float4 per stored triangle: v0|id, v1, v2
+    std::vector<int32_t> order;  // original id of each stored triangle
+    int32_t root = kEmptyRef;
+    int32_t max_depth = 0;
+    int64_t n_leaves = 0;
+};
+
+int build_bvh(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris, HostBvh* out);
+
+}  // namespace vafr
+
+struct vafr_scene_s {
+    vafr::HostBvh host;
+    int64_t n_tris = 0;
+    int device = -1;
+    vafr::BvhNode* d_nodes = nullptr;
+    float4* d_tris = nullptr;
+    int64_t device_bytes = 0;
+    double build_ms = 0;
+};
+
+namespace vafr {
+
+// ------------------------------------------------------------ trace kernels
+enum RayMode : int32_t { kModeVafr = 0, kModeLmfr = 1, kModeFull = 2 };
+
+// Everything one view's rays need; passed by value (kernel argument) or
+// stored in a device array for batched launches.
+struct TraceView {
+    int32_t mode;
+    int32_t shade_mode;     // VAFR_SHADE_*
+    int64_t n_items;
+    // camera
+    float eye[3], right[3], up[3], fwd[3];
+    // film geometry (FP64): gaze point on the film and pixel pitch
+    double gx, gy, px, py;
+    int32_t width, height;
+    // VaFR
+    const float2* dxy;
+    // LMFR
+    const double* lm_z;
+    const double2* lm_cs;
+    int32_t lm_h;
+    double lm_L;
+    // shading
+    float light_dir[3], light_rgb[3], ambient[3], background[3];
+    int32_t shadow;
+    int32_t bounces;
+    uint32_t seed_lo, seed_hi, frame, view;
+    // outputs
+    float4* out_rgba;
+    int32_t* out_id;
+};
+
+struct SceneDev {
+    const BvhNode* nodes;
+    const float4* tris;
+    int32_t root;
+};
+
+int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream);
+
+// ------------------------------------------------------- reconstruction
+struct ReconVafr {
+    SegmentsF seg;
+    int32_t n_cols;
+    int32_t width, height;
+    float px, py;       // pitch
+    float gx, gy;       // gaze on the film
+    const int2* col;    // (n_rows, col_off)
+    const float4* lp;
+    float4* img;
+};
+
+struct ReconLmfr {
+    int32_t w, h;
+    int32_t width, height;
+    float gx, gy;       // gaze in pixels
+    float inv_L;
+    float alpha;
+    const float4* lp;
+    float4* img;
+};
+
+int launch_reconstruct_vafr(const ReconVafr& r, hipStream_t stream);
+int launch_reconstruct_lmfr(const ReconLmfr& r, hipStream_t stream);
+
+// common validation helpers
+int check_camera(const vafr_camera* c);
+int check_shading(const vafr_shading* s);
+int check_gaze(vafr_gaze g);
+
+}  // namespace vafr

@@ -1,0 +1,305 @@
+"""ctypes binding of libvafr.so with the C names of include/vafr.h.
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device buffers are torch tensors (memory and streams only); if
+the native library is missing, loading fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvafr.so")
+
+VAFR_OK = 0
+VAFR_E_ARG = -1
+VAFR_E_OOM = -2
+VAFR_E_HIP = -3
+VAFR_E_UNSUPPORTED = -4
+VAFR_E_BUDGET = -5
+
+VAFR_SHADE_LAMBERT = 0
+VAFR_SHADE_PATH = 1
+VAFR_LAYOUT_VAFR = 0
+VAFR_LAYOUT_LMFR = 1
+
+# Symbols declared in include/vafr.h (checked by the CPU test suite).
+EXPORTS = (
+    "vafr_last_error", "vafr_abi_version", "vafr_lp_layout", "lmfr_lp_layout", "vafr_layout_dims",
+    "vafr_layout_tables", "vafr_layout_destroy", "vafr_scene_create", "vafr_scene_get_info",
+    "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
+    "lmfr_reconstruct", "full_shade",
+)
+
+
+class VafrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class vafr_display(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fov_x_deg", C.c_double), ("fov_y_deg", C.c_double)]
+
+
+class vafr_acuity(C.Structure):
+    _fields_ = [("n_pivots", C.c_int32), ("ecc_deg", C.POINTER(C.c_double)), ("cpd", C.POINTER(C.c_double)),
+                ("e_max_deg", C.c_double)]
+
+
+class vafr_camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("right", C.c_float * 3), ("up", C.c_float * 3), ("forward", C.c_float * 3)]
+
+
+class vafr_gaze(C.Structure):
+    _fields_ = [("x_px", C.c_double), ("y_px", C.c_double)]
+
+
+class vafr_shading(C.Structure):
+    _fields_ = [("light_dir", C.c_float * 3), ("light_rgb", C.c_float * 3), ("ambient", C.c_float * 3),
+                ("background", C.c_float * 3), ("shadow_rays", C.c_int32), ("mode", C.c_int32),
+                ("bounces", C.c_int32), ("frame", C.c_uint32), ("view", C.c_uint32), ("pad_", C.c_uint32),
+                ("seed", C.c_uint64)]
+
+
+class vafr_dims(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n_cols", C.c_int32), ("max_rows", C.c_int32), ("width", C.c_int32),
+                ("height", C.c_int32), ("n_texels", C.c_int64)]
+
+
+class vafr_scene_info(C.Structure):
+    _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("max_depth", C.c_int32),
+                ("on_device", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
+
+
+_lib = None
+_P = C.c_void_p
+
+
+def load():
+    """Load libvafr.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2503_23410_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    sig = {
+        "vafr_last_error": (C.c_char_p, []),
+        "vafr_abi_version": (C.c_int, []),
+        "vafr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.POINTER(vafr_acuity), C.POINTER(_P)]),
+        "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
+        "vafr_layout_dims": (C.c_int, [_P, C.POINTER(vafr_dims)]),
+        "vafr_layout_tables": (C.c_int, [_P, C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_int64)),
+                                         C.POINTER(C.POINTER(C.c_float))]),
+        "vafr_layout_destroy": (None, [_P]),
+        "vafr_scene_create": (C.c_int, [_P, C.c_int64, _P, C.c_int64, C.POINTER(_P)]),
+        "vafr_scene_get_info": (C.c_int, [_P, C.POINTER(vafr_scene_info)]),
+        "vafr_scene_export": (C.c_int, [_P, _P, _P]),
+        "vafr_scene_destroy": (None, [_P]),
+        "vafr_shade_lp": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P,
+                                    _P]),
+        "lmfr_shade_lp": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P,
+                                    _P]),
+        "vafr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
+        "lmfr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
+        "full_shade": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_display), C.POINTER(vafr_shading), _P,
+                                 _P, _P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().vafr_last_error().decode()
+
+
+def _check(rc):
+    if rc != VAFR_OK:
+        raise VafrError(rc, last_error())
+
+
+# ------------------------------------------------------------------ helpers
+
+def display(width, height, fov=(100.0, 100.0)):
+    return vafr_display(int(width), int(height), float(fov[0]), float(fov[1]))
+
+
+def camera(cam12):
+    """cam12 = eye, right, up, forward (12 floats)."""
+    c = np.asarray(cam12, np.float32).reshape(4, 3)
+    out = vafr_camera()
+    for f, row in zip(("eye", "right", "up", "forward"), c):
+        getattr(out, f)[:] = [float(x) for x in row]
+    return out
+
+
+def gaze(x, y):
+    return vafr_gaze(float(x), float(y))
+
+
+def shading(light_dir=(0.3, 1.0, -0.5), light_rgb=(1.0, 1.0, 1.0), ambient=(0.1, 0.1, 0.1),
+            background=(0.05, 0.05, 0.08), shadow=True, mode=VAFR_SHADE_LAMBERT, bounces=0, frame=0, view=0,
+            seed=0):
+    """Light direction is normalised in FP64 and rounded to FP32."""
+    ld = np.asarray(light_dir, np.float64)
+    ld = (ld / np.sqrt(np.dot(ld, ld))).astype(np.float32)
+    s = vafr_shading()
+    s.light_dir[:] = [float(x) for x in ld]
+    s.light_rgb[:] = [float(x) for x in np.float32(light_rgb)]
+    s.ambient[:] = [float(x) for x in np.float32(ambient)]
+    s.background[:] = [float(x) for x in np.float32(background)]
+    s.shadow_rays = 1 if shadow else 0
+    s.mode = int(mode)
+    s.bounces = int(bounces)
+    s.frame = int(frame)
+    s.view = int(view)
+    s.seed = int(seed)
+    return s
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ handles
+
+class Layout:
+    """Owns a vafr_layout handle (VaFR or LMFR)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        d = vafr_dims()
+        _check(load().vafr_layout_dims(self._h, C.byref(d)))
+        self.kind = d.kind
+        self.n_cols = d.n_cols
+        self.max_rows = d.max_rows
+        self.width = d.width
+        self.height = d.height
+        self.n_texels = d.n_texels
+
+    @classmethod
+    def vafr(cls, disp: vafr_display, ecc=None, cpd=None, e_max=60.0):
+        h = C.c_void_p()
+        if ecc is None:
+            _check(load().vafr_lp_layout(C.byref(disp), None, C.byref(h)))
+        else:
+            e = np.ascontiguousarray(ecc, np.float64)
+            f = np.ascontiguousarray(cpd, np.float64)
+            a = vafr_acuity(len(e), e.ctypes.data_as(C.POINTER(C.c_double)),
+                            f.ctypes.data_as(C.POINTER(C.c_double)), float(e_max))
+            _check(load().vafr_lp_layout(C.byref(disp), C.byref(a), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def lmfr(cls, disp: vafr_display, delta=1.8, alpha=4.0):
+        h = C.c_void_p()
+        _check(load().lmfr_lp_layout(C.byref(disp), float(delta), float(alpha), C.byref(h)))
+        return cls(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def tables(self):
+        """Copies of (n_rows, col_off, texel_dxy or None)."""
+        nr = C.POINTER(C.c_int32)()
+        co = C.POINTER(C.c_int64)()
+        dx = C.POINTER(C.c_float)()
+        _check(load().vafr_layout_tables(self._h, C.byref(nr), C.byref(co), C.byref(dx)))
+        n_rows = np.ctypeslib.as_array(nr, (self.n_cols,)).copy()
+        col_off = np.ctypeslib.as_array(co, (self.n_cols + 1,)).copy()
+        dxy = np.ctypeslib.as_array(dx, (2 * self.n_texels,)).copy() if dx else None
+        return n_rows, col_off, dxy
+
+    def close(self):
+        if self._h:
+            load().vafr_layout_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Scene:
+    """Owns a vafr_scene handle (host BVH + device copy when a GPU exists)."""
+
+    def __init__(self, verts, tris):
+        v = np.ascontiguousarray(verts, np.float32).reshape(-1, 3)
+        t = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
+        h = C.c_void_p()
+        _check(load().vafr_scene_create(v.ctypes.data_as(_P), v.shape[0], t.ctypes.data_as(_P), t.shape[0],
+                                        C.byref(h)))
+        self._h = h
+        self.n_tris = t.shape[0]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = vafr_scene_info()
+        _check(load().vafr_scene_get_info(self._h, C.byref(i)))
+        return {f: getattr(i, f) for f, _ in vafr_scene_info._fields_}
+
+    def export(self):
+        inf = self.info()
+        nodes = np.empty((inf["n_nodes"], 16), np.float32)
+        order = np.empty(self.n_tris, np.int32)
+        _check(load().vafr_scene_export(self._h, nodes.ctypes.data_as(_P), order.ctypes.data_as(_P)))
+        return nodes, order
+
+    def close(self):
+        if self._h:
+            load().vafr_scene_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- frame calls
+
+def vafr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
+    _check(load().vafr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),
+                                _dptr(hit_id), _stream(stream)))
+
+
+def lmfr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
+    _check(load().lmfr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),
+                                _dptr(hit_id), _stream(stream)))
+
+
+def vafr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
+    _check(load().vafr_reconstruct(layout.handle, gz, _dptr(lp_rgba), _dptr(img_rgba), _stream(stream)))
+
+
+def lmfr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
+    _check(load().lmfr_reconstruct(layout.handle, gz, _dptr(lp_rgba), _dptr(img_rgba), _stream(stream)))
+
+
+def full_shade(scene, cam, disp, sh, img_rgba, hit_id=None, stream=None):
+    _check(load().full_shade(scene.handle, C.byref(cam), C.byref(disp), C.byref(sh), _dptr(img_rgba),
+                             _dptr(hit_id), _stream(stream)))

@@ -1,0 +1,368 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Acceptance, per ray / texel / pixel:
+  - hit triangle ids identical on rays the oracle does not flag as near ties
+    (barycentric margin or relative t gap below 1e-6);
+  - flagged rays at most 1e-4 of the compared outputs (counted, reported);
+  - colours within 2e-3 absolute on unflagged outputs.
+The layout tables are bit-exact (checked on the CPU in test_library_host).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_23410_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+COLOR_TOL = 2e-3
+FLAG_FRAC = 1e-4
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env(O):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_23410_amd import vafr as V
+    V.load()
+    O.set_threads(16)
+    return torch, V
+
+
+def _gpu_lp(torch, V, scene, layout, gaze, cam, sh, lmfr=False):
+    lp = torch.empty((layout.n_texels, 4), device="cuda", dtype=torch.float32)
+    hid = torch.empty(layout.n_texels, device="cuda", dtype=torch.int32)
+    fn = V.lmfr_shade_lp if lmfr else V.vafr_shade_lp
+    fn(scene, V.camera(cam), V.gaze(*gaze), sh, layout, lp, hid)
+    torch.cuda.synchronize()
+    return lp, hid
+
+
+def _compare(name, g_rgba, g_id, o_rgba, o_id, flag):
+    unf = flag == 0
+    n = len(o_id)
+    mism = int(((g_id != o_id) & unf).sum())
+    nflag = int(flag.sum())
+    diff = np.abs(g_rgba - o_rgba).max(axis=1)
+    worst = float(diff[unf].max()) if unf.any() else 0.0
+    log(f"{name}: n={n} id_mismatch_unflagged={mism} flagged={nflag} ({nflag / max(n, 1):.2e}) "
+        f"max_colour_err={worst:.2e} hit_frac={(o_id >= 0).mean():.3f}")
+    assert mism == 0, f"{name}: {mism} unflagged hit-id mismatches"
+    assert nflag <= FLAG_FRAC * n + 1e-9, f"{name}: {nflag} flagged rays exceed 1e-4 of {n}"
+    assert worst <= COLOR_TOL, f"{name}: colour error {worst}"
+
+
+# ------------------------------------------------------------ config 1 ---
+
+@pytest.fixture(scope="module")
+def soup(env, O):
+    torch, V = env
+    v, f = I.soup_scene()
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+@pytest.mark.parametrize("shadow", [False, True])
+def test_cfg1_vafr_lp_all_texels(env, O, layout, soup, shadow):
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    L = V.Layout.vafr(V.display(W, H))
+    sh = V.shading(shadow=shadow)
+    gz = (320.0, 180.0)
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), sh)
+    o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz,
+                                             I.soup_camera(), O.shading_params(shadow=shadow))
+    _compare(f"cfg1 vafr shadow={shadow}", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+
+
+@pytest.mark.parametrize("gaze", [(320.0, 180.0), (0.0, 0.0), (639.5, 12.25), (-200.0, 500.0), (101.3, 333.7)])
+def test_cfg1_reconstruct_random_lp(env, O, layout, gaze):
+    torch, V = env
+    W, H = 640, 360
+    L = V.Layout.vafr(V.display(W, H))
+    lp_np = I.random_lp(layout.n_texels, seed=101)
+    lp = torch.from_numpy(lp_np).cuda()
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.vafr_reconstruct(L, V.gaze(*gaze), lp, img)
+    torch.cuda.synchronize()
+    p = O.film_pitch(W, H, *I.FOV)
+    G = O.gaze_film(W, H, p, *gaze)
+    ref, _ = O.vafr_reconstruct(layout, lp_np, W, H, p, G, np.arange(W * H))
+    err = np.abs(img.cpu().numpy() - ref).max()
+    log(f"cfg1 reconstruct gaze={gaze}: max_err={err:.2e}")
+    assert err <= COLOR_TOL
+
+
+def test_cfg1_end_to_end_image(env, O, layout, soup):
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    gz = (250.0, 140.0)
+    L = V.Layout.vafr(V.display(W, H))
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), V.shading())
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+    torch.cuda.synchronize()
+    o_lp, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz,
+                                           I.soup_camera(), O.shading_params())
+    p = O.film_pitch(W, H, *I.FOV)
+    ref, pf = O.vafr_reconstruct(layout, o_lp, W, H, p, O.gaze_film(W, H, p, *gz), np.arange(W * H), o_fl)
+    err = np.abs(img.cpu().numpy() - ref).max(axis=1)
+    log(f"cfg1 end-to-end: flagged_pixels={int(pf.sum())} max_err_unflagged={err[~pf].max():.2e}")
+    assert err[~pf].max() <= COLOR_TOL
+    assert pf.mean() <= 20 * FLAG_FRAC   # a flagged texel feeds several pixels
+
+
+def test_cfg1_full_res(env, O, soup):
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    hid = torch.empty(H * W, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(I.soup_camera()), V.display(W, H), V.shading(), img, hid)
+    torch.cuda.synchronize()
+    o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, np.arange(W * H), W, H, I.FOV, I.soup_camera(),
+                                             O.shading_params())
+    _compare("cfg1 full-res", img.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+
+
+def test_cfg1_lmfr(env, O, soup):
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    gz = (400.0, 100.0)
+    L = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), V.shading(), lmfr=True)
+    w, h = O.lmfr_dims(W, H, 1.8)
+    o_rgba, o_id, o_fl = O.shade_lmfr_texels(o_sc, np.arange(w * h), W, H, I.FOV, gz, w, h, 4.0, I.soup_camera(),
+                                             O.shading_params())
+    _compare("cfg1 lmfr", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+    # reconstruction of a random LMFR buffer
+    lp_np = I.random_lp(w * h, seed=202)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.lmfr_reconstruct(L, V.gaze(*gz), torch.from_numpy(lp_np).cuda(), img)
+    torch.cuda.synchronize()
+    ref, _ = O.lmfr_reconstruct(W, H, gz[0], gz[1], w, h, 4.0, lp_np, np.arange(W * H))
+    err = np.abs(img.cpu().numpy() - ref).max()
+    log(f"cfg1 lmfr reconstruct max_err={err:.2e}")
+    assert err <= COLOR_TOL
+
+
+# ------------------------------------------------------------ config 2 ---
+
+@pytest.fixture(scope="module")
+def terrain1m(env, O):
+    torch, V = env
+    v, f = I.make_scene("terrain1m")
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+def test_cfg2_vafr_lmfr_full(env, O, layout, terrain1m):
+    torch, V = env
+    g_sc, o_sc = terrain1m
+    W, H = 1920, 1080
+    cam = I.terrain_camera()
+    gazes = I.uniform_gaze(3, W, H, seed=20)
+    L = V.Layout.vafr(V.display(W, H))
+    LM = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
+    w, h = O.lmfr_dims(W, H, 1.8)
+    rng = np.random.default_rng(2)
+    for gz in gazes:
+        gz = (float(gz[0]), float(gz[1]))
+        lp, hid = _gpu_lp(torch, V, g_sc, L, gz, cam, V.shading())
+        o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz, cam,
+                                                 O.shading_params())
+        _compare(f"cfg2 vafr gaze={gz}", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+        # the image: GPU end to end against the oracle's LP reconstructed by the oracle
+        img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+        V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+        torch.cuda.synchronize()
+        pix = rng.integers(0, W * H, 200000)
+        p = O.film_pitch(W, H, *I.FOV)
+        ref, pf = O.vafr_reconstruct(layout, o_rgba, W, H, p, O.gaze_film(W, H, p, *gz), pix, o_fl)
+        err = np.abs(img.cpu().numpy()[pix] - ref).max(axis=1)
+        log(f"cfg2 image gaze={gz}: flagged_px={int(pf.sum())} max_err={err[~pf].max():.2e}")
+        assert err[~pf].max() <= COLOR_TOL
+        # LMFR, a quarter of its texels
+        lpl, hidl = _gpu_lp(torch, V, g_sc, LM, gz, cam, V.shading(), lmfr=True)
+        idx = np.sort(rng.choice(w * h, (w * h) // 4, replace=False))
+        ol_rgba, ol_id, ol_fl = O.shade_lmfr_texels(o_sc, idx, W, H, I.FOV, gz, w, h, 4.0, cam, O.shading_params())
+        _compare(f"cfg2 lmfr gaze={gz}", lpl.cpu().numpy()[idx], hidl.cpu().numpy()[idx], ol_rgba, ol_id, ol_fl)
+    # full resolution, one pixel in 16
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    hid = torch.empty(H * W, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(cam), V.display(W, H), V.shading(), img, hid)
+    torch.cuda.synchronize()
+    pix = np.sort(rng.choice(W * H, W * H // 16, replace=False))
+    o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, pix, W, H, I.FOV, cam, O.shading_params())
+    _compare("cfg2 full-res", img.cpu().numpy()[pix], hid.cpu().numpy()[pix], o_rgba, o_id, o_fl)
+
+
+def test_cfg2_reconstruct_random_lp_all_pixels(env, O, layout):
+    torch, V = env
+    W, H = 1920, 1080
+    L = V.Layout.vafr(V.display(W, H))
+    lp_np = I.random_lp(layout.n_texels, seed=303)
+    lp = torch.from_numpy(lp_np).cuda()
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    for gz in ((960.0, 540.0), (1900.0, 20.0)):
+        V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+        torch.cuda.synchronize()
+        p = O.film_pitch(W, H, *I.FOV)
+        ref, _ = O.vafr_reconstruct(layout, lp_np, W, H, p, O.gaze_film(W, H, p, *gz), np.arange(W * H))
+        err = np.abs(img.cpu().numpy() - ref).max()
+        log(f"cfg2 reconstruct gaze={gz}: max_err={err:.2e}")
+        assert err <= COLOR_TOL
+
+
+# ------------------------------------------------------------ config 3 ---
+
+def test_cfg3_binocular_8k_sampled(env, O, layout):
+    """Full size: 4,521,984 triangles, two eyes at 7680 x 4320, gaze from the
+    seeded trace.  Every LP texel of both eyes is compared; the display
+    images are compared on 300,000 sampled pixels per eye."""
+    torch, V = env
+    v, f = I.make_scene("terrain4m")
+    g_sc = V.Scene(v, f)
+    o_sc = O.Scene(v, f)
+    W, H = 7680, 4320
+    L = V.Layout.vafr(V.display(W, H))
+    trace = I.gaze_trace(40, W, H, seed=30)
+    gz = (float(trace[37, 0]), float(trace[37, 1]))
+    rng = np.random.default_rng(3)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    for eye, cam in enumerate(I.binocular_cameras()):
+        lp, hid = _gpu_lp(torch, V, g_sc, L, gz, cam, V.shading())
+        V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+        torch.cuda.synchronize()
+        o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz, cam,
+                                                 O.shading_params())
+        _compare(f"cfg3 eye={eye} vafr", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+        pix = rng.integers(0, W * H, 300000)
+        pix_t = torch.from_numpy(pix).cuda()
+        g_img = img[pix_t].cpu().numpy()
+        p = O.film_pitch(W, H, *I.FOV)
+        ref, pf = O.vafr_reconstruct(layout, o_rgba, W, H, p, O.gaze_film(W, H, p, *gz), pix, o_fl)
+        err = np.abs(g_img - ref).max(axis=1)
+        log(f"cfg3 eye={eye} image: flagged_px={int(pf.sum())} max_err={err[~pf].max():.2e}")
+        assert err[~pf].max() <= COLOR_TOL
+    # full resolution and LMFR on sampled outputs (left eye)
+    cam = I.binocular_cameras()[0]
+    hid = torch.empty(H * W, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(cam), V.display(W, H), V.shading(), img, hid)
+    torch.cuda.synchronize()
+    pix = np.sort(rng.choice(W * H, 100000, replace=False))
+    pix_t = torch.from_numpy(pix).cuda()
+    o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, pix, W, H, I.FOV, cam, O.shading_params())
+    _compare("cfg3 full-res", img[pix_t].cpu().numpy(), hid[pix_t].cpu().numpy(), o_rgba, o_id, o_fl)
+    del img
+    LM = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
+    w, h = O.lmfr_dims(W, H, 1.8)
+    lpl, hidl = _gpu_lp(torch, V, g_sc, LM, gz, cam, V.shading(), lmfr=True)
+    idx = np.sort(rng.choice(w * h, 200000, replace=False))
+    idx_t = torch.from_numpy(idx).cuda()
+    ol_rgba, ol_id, ol_fl = O.shade_lmfr_texels(o_sc, idx, W, H, I.FOV, gz, w, h, 4.0, cam, O.shading_params())
+    _compare("cfg3 lmfr", lpl[idx_t].cpu().numpy(), hidl[idx_t].cpu().numpy(), ol_rgba, ol_id, ol_fl)
+
+
+# ------------------------------------------------------------ edge cases ---
+
+def test_empty_scene_is_all_background(env, O):
+    torch, V = env
+    sc = V.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+    L = V.Layout.vafr(V.display(64, 48))
+    lp, hid = _gpu_lp(torch, V, sc, L, (10.0, 10.0), I.soup_camera(), V.shading())
+    assert torch.all(hid == -1)
+    bg = torch.tensor([0.05, 0.05, 0.08, 1.0], device="cuda")
+    assert torch.all(lp == bg)
+
+
+@pytest.mark.parametrize("W,H,gaze", [(1, 1, (0.5, 0.5)), (7, 5, (3.0, 2.0)), (65, 3, (-1000.0, 1e4)),
+                                      (130, 67, (129.9, 66.9))])
+def test_tiny_and_ragged_displays(env, O, layout, soup, W, H, gaze):
+    torch, V = env
+    g_sc, o_sc = soup
+    L = V.Layout.vafr(V.display(W, H))
+    lp_np = I.random_lp(layout.n_texels, seed=W * 1000 + H)
+    img = torch.full((H * W, 4), -7.0, device="cuda", dtype=torch.float32)
+    V.vafr_reconstruct(L, V.gaze(*gaze), torch.from_numpy(lp_np).cuda(), img)
+    torch.cuda.synchronize()
+    p = O.film_pitch(W, H, *I.FOV)
+    ref, _ = O.vafr_reconstruct(layout, lp_np, W, H, p, O.gaze_film(W, H, p, *gaze), np.arange(W * H))
+    assert np.abs(img.cpu().numpy() - ref).max() <= COLOR_TOL
+    # full-resolution tiles are padded to 8 x 8: only real pixels are written
+    out = torch.full((H * W + 64, 4), -7.0, device="cuda", dtype=torch.float32)
+    hid = torch.full((H * W + 64,), -9, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(I.soup_camera()), V.display(W, H), V.shading(), out, hid)
+    torch.cuda.synchronize()
+    assert torch.all(out[H * W:] == -7.0) and torch.all(hid[H * W:] == -9)
+    o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, np.arange(W * H), W, H, I.FOV, I.soup_camera(),
+                                             O.shading_params())
+    _compare(f"full {W}x{H}", out[:H * W].cpu().numpy(), hid[:H * W].cpu().numpy(), o_rgba, o_id, o_fl)
+
+
+def test_degenerate_and_coincident_triangles(env, O, layout):
+    """Zero-area triangles never hit; coincident duplicates resolve to the
+    smaller id; rays through shared edges of a closed mesh never miss."""
+    torch, V = env
+    sv, sf = I.icosphere(3)
+    sv = (sv * 0.8).astype(np.float32)
+    degen = np.array([[0, 0, 0.3], [0.05, 0.05, 0.3], [0.1, 0.1, 0.3]], np.float32)   # collinear, in view
+    verts = np.concatenate([sv, sv, degen])
+    tris = np.concatenate([sf, sf + len(sv), np.array([[2 * len(sv), 2 * len(sv) + 1, 2 * len(sv) + 2]])])
+    tris = tris.astype(np.int32)
+    g_sc, o_sc = V.Scene(verts, tris), O.Scene(verts, tris)
+    W, H = 256, 256
+    cam = np.array([0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1], np.float32)   # eye at the sphere centre
+    L = V.Layout.vafr(V.display(W, H))
+    lp, hid = _gpu_lp(torch, V, g_sc, L, (128.0, 128.0), cam, V.shading(shadow=False))
+    h = hid.cpu().numpy()
+    assert np.all(h >= 0) and np.all(h < len(sf))       # never the duplicate copy, never a miss
+    o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV,
+                                             (128.0, 128.0), cam, O.shading_params(shadow=False))
+    assert np.array_equal(h[o_fl == 0], o_id[o_fl == 0])
+
+
+def test_path_mode_matches_oracle(env, O, layout, terrain1m):
+    """Path-traced LP shading (1 sample, 2 bounces): identical primary ids and
+    colours within tolerance on texels whose whole path is unflagged."""
+    torch, V = env
+    g_sc, o_sc = terrain1m
+    W, H = 1920, 1080
+    gz = (700.0, 600.0)
+    cam = I.terrain_camera()
+    L = V.Layout.vafr(V.display(W, H))
+    sh = V.shading(mode=V.VAFR_SHADE_PATH, bounces=2, frame=5, view=3, seed=0x1234_5678_9ABC)
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, cam, sh)
+    idx = np.arange(0, layout.n_texels, 7)
+    p = O.film_pitch(W, H, *I.FOV)
+    org, d = O.vafr_rays(layout, idx, O.gaze_film(W, H, p, *gz), cam)
+    o_rgba, o_id, o_fl = o_sc.shade_path(org, d, idx, O.shading_params(), 0x1234_5678_9ABC, 5, 3, 2)
+    _compare("path mode", lp.cpu().numpy()[idx], hid.cpu().numpy()[idx], o_rgba, o_id, o_fl)
+
+
+def test_invalid_calls_raise_before_launch(env):
+    torch, V = env
+    v, f = I.soup_scene(16, seed=3)
+    sc = V.Scene(v, f)
+    L = V.Layout.vafr(V.display(64, 64))
+    LM = V.Layout.lmfr(V.display(64, 64))
+    lp = torch.empty((L.n_texels, 4), device="cuda")
+    with pytest.raises(V.VafrError):
+        V.vafr_shade_lp(sc, V.camera(I.soup_camera()), V.gaze(float("nan"), 0.0), V.shading(), L, lp)
+    with pytest.raises(V.VafrError):
+        V.vafr_shade_lp(sc, V.camera(I.soup_camera()), V.gaze(1.0, 1.0), V.shading(), LM, lp)
+    with pytest.raises(V.VafrError):
+        V.lmfr_reconstruct(L, V.gaze(1.0, 1.0), lp, lp)
+    bad = V.shading()
+    bad.light_dir[0] = 3.0
+    with pytest.raises(V.VafrError):
+        V.vafr_shade_lp(sc, V.camera(I.soup_camera()), V.gaze(1.0, 1.0), bad, L, lp)

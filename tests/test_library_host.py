@@ -1,0 +1,168 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+its host layout tables equal the oracle's bit for bit, it validates
+arguments, and its BVH is structurally sound.  No GPU compute here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2503_23410_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2503_23410_amd import vafr
+    vafr.load()
+    return vafr
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "vafr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", src, flags=re.M)
+    return {n for n in names if n not in ("if", "defined")}
+
+
+def test_library_exports_every_declared_symbol(V):
+    declared = _declared_functions()
+    assert declared == set(V.EXPORTS)
+    lib = V.load()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert lib.vafr_abi_version() == 1
+
+
+def test_vafr_layout_tables_bit_exact_with_oracle(V, O, layout):
+    for W, H in ((640, 360), (7680, 4320)):
+        L = V.Layout.vafr(V.display(W, H))
+        assert (L.n_cols, L.n_texels) == (layout.n_cols, layout.n_texels)
+        n_rows, col_off, dxy = L.tables()
+        assert np.array_equal(n_rows, layout.n_rows)
+        assert np.array_equal(col_off, layout.col_off)
+        assert np.array_equal(dxy.view(np.uint32), layout.dxy.view(np.uint32))
+        assert L.max_rows == layout.n_rows.max()
+
+
+def test_custom_acuity_layout_matches_oracle(V, O):
+    """Device-adapted pivots (Sec. 3.3: other curves are just other pivot
+    values) go through the same code; tables still match bit for bit."""
+    ecc, cpd = (0.0, 10.0, 20.0, 30.0, 60.0), (9.0, 9.0, 6.0, 5.0, 4.0)
+    L = V.Layout.vafr(V.display(1920, 1080), ecc, cpd, 60.0)
+    ref = O.Layout(O.Acuity(ecc, cpd), 60.0)
+    n_rows, col_off, dxy = L.tables()
+    assert np.array_equal(n_rows, ref.n_rows) and np.array_equal(col_off, ref.col_off)
+    assert np.array_equal(dxy.view(np.uint32), ref.dxy.view(np.uint32))
+    assert L.n_texels < 1061735 * 0.85   # capping f at 9 cpd removes work
+
+
+def test_lmfr_layout_dims_match_oracle(V, O):
+    for W, H in ((640, 360), (1920, 1080), (7680, 4320), (11520, 6480)):
+        L = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
+        assert (L.n_cols, L.max_rows) == O.lmfr_dims(W, H, 1.8)
+        assert L.kind == V.VAFR_LAYOUT_LMFR
+        n_rows, col_off, dxy = L.tables()
+        assert dxy is None and np.all(n_rows == L.max_rows)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(disp=(0, 100)), dict(disp=(100, -1)), dict(fov=(0.0, 90.0)), dict(fov=(90.0, 180.0)),
+    dict(ecc=(1.0, 10.0), cpd=(40.0, 10.0)), dict(ecc=(0.0, 10.0, 10.0), cpd=(40.0, 10.0, 5.0)),
+    dict(ecc=(0.0, 10.0), cpd=(40.0, 0.0)), dict(e_max=95.0), dict(ecc=(0.0, 10.0), cpd=(1.0, 2.0)),
+])
+def test_layout_argument_validation(V, bad):
+    disp = V.display(*(bad.get("disp", (640, 360))), fov=bad.get("fov", (100.0, 100.0)))
+    with pytest.raises(V.VafrError) as ei:
+        V.Layout.vafr(disp, bad.get("ecc", (0.0, 10.0, 20.0, 30.0, 60.0)), bad.get("cpd", (40.0, 10.0, 6.0, 5.0, 4.0)),
+                      bad.get("e_max", 60.0))
+    assert ei.value.code == V.VAFR_E_ARG
+    assert V.last_error()
+
+
+def test_lmfr_argument_validation(V):
+    for delta, alpha in ((0.5, 4.0), (1.8, 0.0), (float("nan"), 4.0)):
+        with pytest.raises(V.VafrError) as ei:
+            V.Layout.lmfr(V.display(640, 360), delta, alpha)
+        assert ei.value.code == V.VAFR_E_ARG
+
+
+def _check_bvh(V, verts, tris):
+    sc = V.Scene(verts, tris)
+    info = sc.info()
+    nodes, order = sc.export()
+    assert info["n_tris"] == tris.shape[0]
+    assert np.array_equal(np.sort(order), np.arange(tris.shape[0]))      # each triangle stored once
+    assert info["max_depth"] <= 32
+    refs = nodes[:, 12:14].view(np.int32) if nodes.size else np.zeros((0, 2), np.int32)
+    tv = verts[tris[order]]                                               # stored order, (n, 3, 3)
+    # every child box contains every triangle of its subtree
+    seen_nodes = np.zeros(len(nodes), bool)
+
+    def tri_range(ref):
+        if ref < 0:
+            x = ~ref
+            return [(x >> 3, (x & 7) + 1)]
+        seen_nodes[ref] = True
+        return tri_range(refs[ref, 0]) + tri_range(refs[ref, 1])
+
+    for ni in range(len(nodes)):
+        a, b, c = nodes[ni, 0:4], nodes[ni, 4:8], nodes[ni, 8:12]
+        boxes = [((a[0], a[2], c[0]), (a[1], a[3], c[1])), ((b[0], b[2], c[2]), (b[1], b[3], c[3]))]
+        for ch in range(2):
+            lo, hi = np.array(boxes[ch][0]), np.array(boxes[ch][1])
+            for first, cnt in tri_range(refs[ni, ch]):
+                pts = tv[first:first + cnt].reshape(-1, 3)
+                assert np.all(pts >= lo) and np.all(pts <= hi)
+        if ni > 2000:
+            break
+    return sc, info
+
+
+def test_bvh_structure_soup(V):
+    v, f = I.soup_scene()
+    sc, info = _check_bvh(V, v, f)
+    assert info["n_leaves"] >= 4096 // 4
+
+
+def test_bvh_structure_terrain_and_degenerate(V):
+    v, f = I.terrain_scene(48, 24, 8, seed=4)
+    _check_bvh(V, v, f)
+    # many identical triangles force the depth guard and median splits
+    tri = np.array([[0, 0, 1], [1, 0, 1], [0, 1, 1]], np.float32)
+    vv = np.tile(tri, (3000, 1))
+    ff = np.arange(9000, dtype=np.int32).reshape(-1, 3)
+    sc, info = _check_bvh(V, vv, ff)
+    assert info["max_depth"] <= 32
+
+
+def test_bvh_small_and_empty_scenes(V):
+    v, f = I.soup_scene(1, seed=1)
+    sc = V.Scene(v, f)
+    assert sc.info()["n_nodes"] == 0        # a single leaf at the root
+    v, f = I.soup_scene(3, seed=1)
+    _check_bvh(V, v, f)
+    sc0 = V.Scene(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32))
+    assert sc0.info()["n_tris"] == 0
+
+
+def test_scene_validation(V):
+    v, f = I.soup_scene(4, seed=1)
+    bad = f.copy()
+    bad[1, 2] = 99
+    with pytest.raises(V.VafrError) as ei:
+        V.Scene(v, bad)
+    assert ei.value.code == V.VAFR_E_ARG
+    vn = v.copy()
+    vn[2, 1] = np.nan
+    with pytest.raises(V.VafrError):
+        V.Scene(vn, f)
+
+
+def test_large_scene_bvh_builds_fast(V):
+    v, f = I.make_scene("terrain1m")
+    sc = V.Scene(v, f)
+    info = sc.info()
+    assert info["max_depth"] <= 32
+    assert info["build_ms"] < 30000
