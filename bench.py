@@ -1,0 +1,315 @@
+#!/usr/bin/env python3
+"""Benchmark of the VaFR hot path on one MI355X.
+
+One step = one binocular frame at 7680 x 4320 per eye (100 x 100 degree field
+of view): for each eye, shade the constant-size LP buffer (one primary ray and
+one shadow ray per texel against a 4,521,984-triangle scene) and inverse-map it
+onto the display.  The gaze of frame f comes from a seeded fixation/saccade
+trace.  The same GPU also runs the full-resolution ray cast and the LMFR(1.8)
+mapping for the speed-ups.  Inputs are synthetic and already resident in HBM
+when timing starts.
+
+Prints ONE JSON line (rank 0).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+W, H = 7680, 4320
+SCENE = "terrain4m"
+# Peak figures of the MI355X (published): HBM3E bandwidth, and the VALU lane
+# issue rate = 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one non-packed FP32
+# operation per lane per clock; 157.3 TFLOP/s counts packed FMA as 4 flops).
+HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+# Algorithmic FP32 operations of one unit of traversal work, counted from the
+# method's arithmetic:
+#  - one node visit tests two child boxes: per child 6 subtractions and 6
+#    multiplies for the slab distances, 6 min/max per axis, 4 min/max to
+#    combine axes and clamp, 1 multiply (conservative exit) and 1 compare;
+#    plus 1 compare to order the children -> 2 * 24 + 1 = 49
+#  - one watertight ray/triangle test: 9 subtractions (vertices - origin),
+#    6 FMAs (shear), 6 multiplies + 3 subtractions (edge functions), 2 adds
+#    (det), 3 multiplies (z scaling), 3 multiplies + 2 adds (T), 1 division,
+#    4 compares -> 39
+#  - ray set-up: 3 reciprocals, 3 divisions, 8 compares/selects -> 14
+OPS_NODE = 49
+OPS_TRI = 39
+OPS_RAY = 14
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def percentile(x, q):
+    return float(np.percentile(np.asarray(x, np.float64), q))
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("trace.hip", "reconstruct.hip"):
+        with open(os.path.join(ROOT, "paper_2503_23410_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kind):
+    """HBM traffic per launch measured with rocprofv3 --pmc (FETCH_SIZE,
+    WRITE_SIZE) for the current kernel sources, or None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kind)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed binocular VaFR frames")
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--compare-steps", type=int, default=0,
+                    help="frames for the full-resolution and LMFR comparisons (default: steps/20, >= 3)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true", help="skip full-resolution and LMFR runs")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(views would be sharded across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2503_23410_amd import inputs as I
+    from paper_2503_23410_amd import vafr as V
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    V.load()
+    steps, warm = args.steps, args.warmup
+    csteps = args.compare_steps or max(3, steps // 20)
+
+    t = time.time()
+    verts, tris = I.make_scene(SCENE)
+    log(f"scene {SCENE}: {tris.shape[0]} triangles generated in {time.time() - t:.1f}s")
+    scene = V.Scene(verts, tris)
+    info = scene.info()
+    log(f"BVH: {info['n_nodes']} nodes, depth {info['max_depth']}, built in {info['build_ms']:.0f} ms, "
+        f"{info['device_bytes'] / 1e6:.0f} MB on device")
+    disp = V.display(W, H, I.FOV)
+    L = V.Layout.vafr(disp)
+    LM = V.Layout.lmfr(disp, 1.8, 4.0)
+    cams = [V.camera(c) for c in I.binocular_cameras()]
+    sh = V.shading()
+    trace = I.gaze_trace(warm + max(steps, csteps), W, H, seed=30)
+    gazes = [V.gaze(float(x), float(y)) for x, y in trace]
+
+    lp = [torch.empty((L.n_texels, 4), device="cuda", dtype=torch.float32) for _ in range(2)]
+    img = [torch.empty((H * W, 4), device="cuda", dtype=torch.float32) for _ in range(2)]
+    stream = torch.cuda.current_stream()
+
+    def vafr_frame(f, ev=None):
+        g = gazes[f]
+        for e in range(2):
+            if ev is not None:
+                ev[2 * e].record(stream)
+            V.vafr_shade_lp(scene, cams[e], g, sh, L, lp[e], None, stream)
+            if ev is not None:
+                ev[2 * e + 1].record(stream)
+            V.vafr_reconstruct(L, g, lp[e], img[e], stream)
+        if ev is not None:
+            ev[4].record(stream)
+
+    # ------------------------------------------------------------ VaFR
+    for f in range(warm):
+        vafr_frame(f)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(steps):
+        vafr_frame(warm + f, evs[f])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frame_ms, trace_ms, recon_ms = [], [], []
+    for ev in evs:
+        frame_ms.append(ev[0].elapsed_time(ev[4]))
+        trace_ms += [ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])]
+        recon_ms += [ev[1].elapsed_time(ev[2]), ev[3].elapsed_time(ev[4])]
+    fps = steps / wall
+    log(f"VaFR: {fps:.1f} frames/s, frame p50 {percentile(frame_ms, 50):.3f} ms p99 {percentile(frame_ms, 99):.3f} ms;"
+        f" trace {np.mean(trace_ms):.3f} ms/eye, reconstruct {np.mean(recon_ms):.3f} ms/eye")
+
+    # work counts of the traversal (one frame, both eyes, gaze of frame warm)
+    counters = torch.zeros(4, device="cuda", dtype=torch.int64)
+    for e in range(2):
+        V.vafr_count_work(scene, cams[e], gazes[warm], sh, L, counters, stream)
+    torch.cuda.synchronize()
+    n_prim, n_shadow, n_nodes, n_tri = [int(x) for x in counters.cpu()]
+    ops_per_launch = (OPS_NODE * n_nodes + OPS_TRI * n_tri + OPS_RAY * (n_prim + n_shadow)) / 2.0
+    trace_s = float(np.mean(trace_ms)) / 1e3
+    achieved_gops = ops_per_launch / trace_s / 1e9
+    rays_per_s = (n_prim + n_shadow) / 2.0 / trace_s
+    recon_bytes = W * H * 16 + L.n_texels * 16
+    recon_s = float(np.mean(recon_ms)) / 1e3
+    recon_gbs = recon_bytes / recon_s / 1e9
+    log(f"work per eye: {n_prim // 2} primary + {n_shadow // 2} shadow rays, {n_nodes / (n_prim + n_shadow):.1f} "
+        f"node visits and {n_tri / (n_prim + n_shadow):.2f} triangle tests per ray; "
+        f"{rays_per_s / 1e9:.2f} Grays/s; reconstruct {recon_gbs:.0f} GB/s")
+
+    out = {}
+    # ------------------------------------------------------------ comparisons
+    if not args.no_compare:
+        # full resolution: one primary + shadow ray per display pixel, per eye
+        def full_frame(f, ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            for e in range(2):
+                V.full_shade(scene, cams[e], disp, sh, img[e], None, stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        full_frame(0)
+        torch.cuda.synchronize()
+        fev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(csteps)]
+        t0 = time.perf_counter()
+        for f in range(csteps):
+            full_frame(f, fev[f])
+        torch.cuda.synchronize()
+        full_fps = csteps / (time.perf_counter() - t0)
+        full_ms = [ev[0].elapsed_time(ev[1]) for ev in fev]
+        log(f"full resolution: {full_fps:.2f} frames/s (frame {np.mean(full_ms):.2f} ms)")
+        # LMFR(1.8)
+        lpl = torch.empty((LM.n_texels, 4), device="cuda", dtype=torch.float32)
+
+        def lmfr_frame(f, ev=None):
+            g = gazes[warm + f]
+            if ev is not None:
+                ev[0].record(stream)
+            for e in range(2):
+                V.lmfr_shade_lp(scene, cams[e], g, sh, LM, lpl, None, stream)
+                V.lmfr_reconstruct(LM, g, lpl, img[e], stream)
+            if ev is not None:
+                ev[1].record(stream)
+
+        lmfr_frame(0)
+        torch.cuda.synchronize()
+        lev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(csteps)]
+        t0 = time.perf_counter()
+        for f in range(csteps):
+            lmfr_frame(f, lev[f])
+        torch.cuda.synchronize()
+        lmfr_fps = csteps / (time.perf_counter() - t0)
+        lmfr_ms = [ev[0].elapsed_time(ev[1]) for ev in lev]
+        log(f"LMFR(1.8): {lmfr_fps:.2f} frames/s (frame {np.mean(lmfr_ms):.2f} ms)")
+        del lpl
+        out.update({
+            "fullres_fps": round(full_fps, 3), "fullres_frame_ms": round(float(np.mean(full_ms)), 3),
+            "lmfr_fps": round(lmfr_fps, 3), "lmfr_frame_ms": round(float(np.mean(lmfr_ms)), 3),
+            "speedup_vs_fullres": round(fps / full_fps, 2), "speedup_vs_lmfr": round(fps / lmfr_fps, 2),
+            "fullres_grays_per_s": round(2 * 2 * W * H * full_fps / 1e9, 3),
+        })
+
+    # ------------------------------------------------------------ CPU baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(verts, tris, trace[warm:], I)
+
+    del img, lp
+    traffic = load_traffic("k_trace")
+    result = {
+        "metric": "frames/s + p99 frame ms, binocular 7680x4320 VaFR vs full-res ray cast, 1 GPU",
+        "value": round(fps, 3),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": warm,
+        "ms_per_step": round(1e3 * wall / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "binocular VaFR frame: 2 x (LP shading of 1,063,314 texels with primary + shadow ray "
+                        "against 4,521,984 triangles, then inverse map to 7680x4320), 100x100 deg FOV, seeded "
+                        "gaze trace",
+            "display": [W, H], "eyes": 2, "triangles": int(tris.shape[0]), "lp_texels_per_eye": int(L.n_texels),
+            "scene": SCENE,
+        },
+        "p50_frame_ms": round(percentile(frame_ms, 50), 4),
+        "p99_frame_ms": round(percentile(frame_ms, 99), 4),
+        "trace_ms_per_eye": round(float(np.mean(trace_ms)), 4),
+        "reconstruct_ms_per_eye": round(float(np.mean(recon_ms)), 4),
+        "grays_per_s": round(rays_per_s / 1e9, 3),
+        "display_gpix_per_s": round(2 * W * H * fps / 1e9, 3),
+        "work_per_ray": {"node_visits": round(n_nodes / (n_prim + n_shadow), 2),
+                         "triangle_tests": round(n_tri / (n_prim + n_shadow), 2),
+                         "shadow_fraction": round(n_shadow / max(n_prim, 1), 3)},
+        "roofline": {"kernel": "k_trace", "bound": "alu", "achieved": round(achieved_gops, 1),
+                     "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
+                     "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": traffic},
+        "roofline_reconstruct": {"kernel": "k_recon_vafr", "bound": "hbm", "achieved": round(recon_gbs, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(recon_gbs / HBM_PEAK_GBS, 4),
+                                 "traffic": load_traffic("k_recon_vafr")},
+        "cpu_baseline": cpu,
+    }
+    result.update(out)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(verts, tris, gazes, I, n_frames=4):
+    """The oracle on the host cores, timed on whole binocular frames: both
+    eyes' LP buffers shaded in full and every display pixel reconstructed
+    (in bands of rows to bound memory), for n_frames gaze samples."""
+    import oracle as O
+    thr = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    O.set_threads(thr)
+    t = time.time()
+    osc = O.Scene(verts, tris)
+    log(f"oracle BVH built in {time.time() - t:.1f}s (not timed)")
+    lay = O.Layout()
+    p = O.film_pitch(W, H, *I.FOV)
+    band = H // 8
+    t_shade = t_recon = 0.0
+    for f in range(n_frames):
+        gaze = (float(gazes[f][0]), float(gazes[f][1]))
+        G = O.gaze_film(W, H, p, *gaze)
+        for cam in I.binocular_cameras():
+            t0 = time.perf_counter()
+            lp, _, _ = O.shade_vafr_texels(osc, lay, np.arange(lay.n_texels), W, H, I.FOV, gaze, cam,
+                                           O.shading_params())
+            t_shade += time.perf_counter() - t0
+            for y0 in range(0, H, band):
+                pix = np.arange(y0 * W, min(H, y0 + band) * W, dtype=np.int64)
+                t0 = time.perf_counter()
+                O.vafr_reconstruct(lay, lp, W, H, p, G, pix)
+                t_recon += time.perf_counter() - t0
+    total = t_shade + t_recon
+    used = O.get_threads()
+    log(f"oracle: {n_frames} binocular frames, shade {t_shade:.2f}s, reconstruct {t_recon:.2f}s -> "
+        f"{n_frames / total:.4f} frames/s on {used} threads")
+    return {"value": round(n_frames / total, 5), "unit": "frames/s", "cores": used, "kind": "oracle",
+            "sample": f"{n_frames} whole binocular frames of the same workload (2 x {lay.n_texels} LP texels "
+                      f"shaded with primary + shadow rays, 2 x {W}x{H} pixels reconstructed), gazes from the "
+                      f"same trace; oracle BVH build excluded; shade {t_shade:.2f}s, reconstruct {t_recon:.2f}s"}
+
+
+if __name__ == "__main__":
+    main()

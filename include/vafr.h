@@ -211,6 +211,16 @@ int lmfr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_de
 int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* display, const vafr_shading* shading,
                float* img_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
 
+/* ------------------------------------------------------------ diagnostics */
+
+/* Work counting for roofline reports: traces exactly the rays that
+ * vafr_shade_lp / lmfr_shade_lp would trace for this layout (kind taken from
+ * the layout) and atomically adds to counters_dev[4] (device, caller-zeroed
+ * unsigned 64-bit): primary rays, shadow rays, BVH node visits (each a test
+ * of two child boxes) and ray/triangle tests.  Writes no image. */
+int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
+                    vafr_layout layout, unsigned long long* counters_dev, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -116,7 +116,8 @@ static double lmfr_log_extent(const vafr_layout_s* L, vafr_gaze g) {
 }
 
 static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze,
-                           const vafr_shading* sh, vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
+                           const vafr_shading* sh, vafr_layout L, float* lp, int32_t* hit, hipStream_t stream,
+                           unsigned long long* counters = nullptr) {
     if (!L) return fail(VAFR_E_ARG, "layout is NULL");
     if (L->kind != want_kind)
         return fail(VAFR_E_ARG, want_kind == VAFR_LAYOUT_VAFR ? "vafr_shade_lp needs a VaFR layout"
@@ -124,7 +125,7 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     if (int rc = check_camera(cam)) return rc;
     if (int rc = check_shading(sh)) return rc;
     if (int rc = check_gaze(gaze)) return rc;
-    if (!lp) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
+    if (!lp && !counters) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
     SceneDev sd;
     if (int rc = scene_dev(scene, &sd)) return rc;
     const LayoutDev* ld;
@@ -151,7 +152,7 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     }
     v.out_rgba = reinterpret_cast<float4*>(lp);
     v.out_id = hit;
-    return launch_trace(sd, v, stream);
+    return launch_trace(sd, v, stream, counters);
 }
 
 }  // namespace vafr
@@ -320,4 +321,11 @@ extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_d
     v.out_rgba = reinterpret_cast<float4*>(img);
     v.out_id = hit;
     return launch_trace(sd, v, stream);
+}
+
+extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                               vafr_layout L, unsigned long long* counters_dev, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (!counters_dev) return fail(VAFR_E_ARG, "counters_dev is NULL");
+    return shade_lp_common(L->kind, scene, cam, gaze, sh, L, nullptr, nullptr, stream, counters_dev);
 }

@@ -107,9 +107,17 @@ __device__ __forceinline__ void box2(const RayPre& r, const float4 a, const floa
     h1 = tn1 <= tf1 * kExitScale;
 }
 
+// Per-lane work counters of the diagnostic pass (node visits = box-pair
+// tests, triangle tests).
+struct WorkCount {
+    uint32_t nodes = 0, tris = 0;
+};
+
 // Closest hit: smallest (t, triangle id); returns the stored slot or -1.
 // stk points at this lane's column of the block's LDS stack (stride kBlock).
-__device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float& t_best, int& id_best) {
+template <bool kCount>
+__device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
+                           WorkCount& wc) {
     t_best = INFINITY;
     id_best = -1;
     int slot_best = -1;
@@ -122,6 +130,7 @@ __device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float&
             const float4 a = p[0], b = p[1], c = p[2];
             const int4 d = reinterpret_cast<const int4*>(p)[3];
             const float tlim = t_best * kHitSlack;
+            if (kCount) ++wc.nodes;
             bool h0, h1;
             float tn0, tn1;
             box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
@@ -138,6 +147,7 @@ __device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float&
             const int x = ~ref;
             const int first = x >> 3, count = (x & 7) + 1;
             const float4* tp = sc.tris + 3 * (size_t)first;
+            if (kCount) wc.tris += count;
             for (int q = 0; q < count; ++q) {
                 const float4 v0 = tp[3 * q], v1 = tp[3 * q + 1], v2 = tp[3 * q + 2];
                 float t;
@@ -159,7 +169,8 @@ __device__ int closest_hit(const SceneDev& sc, const RayPre& r, int* stk, float&
 }
 
 // Any hit with t > 0 (shadow ray toward a directional light).
-__device__ bool any_hit(const SceneDev& sc, const RayPre& r, int* stk) {
+template <bool kCount>
+__device__ bool any_hit(const SceneDev& sc, const RayPre& r, int* stk, WorkCount& wc) {
     int ref = sc.root;
     if (ref == kEmptyRef) return false;
     int sp = 0;
@@ -168,6 +179,7 @@ __device__ bool any_hit(const SceneDev& sc, const RayPre& r, int* stk) {
             const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
             const float4 a = p[0], b = p[1], c = p[2];
             const int4 d = reinterpret_cast<const int4*>(p)[3];
+            if (kCount) ++wc.nodes;
             bool h0, h1;
             float tn0, tn1;
             box2(r, a, b, c, INFINITY, h0, h1, tn0, tn1);
@@ -186,6 +198,7 @@ __device__ bool any_hit(const SceneDev& sc, const RayPre& r, int* stk) {
             const float4* tp = sc.tris + 3 * (size_t)first;
             for (int q = 0; q < count; ++q) {
                 float t;
+                if (kCount) ++wc.tris;
                 if (tri_hit(r, tp[3 * q], tp[3 * q + 1], tp[3 * q + 2], t)) return true;
             }
         }
@@ -303,10 +316,12 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
     return true;
 }
 
-__device__ float4 shade_lambert(const SceneDev& sc, const TraceView& v, const RayPre& r, int* stk, int& id_out) {
+template <bool kCount>
+__device__ float4 shade_lambert(const SceneDev& sc, const TraceView& v, const RayPre& r, int* stk, int& id_out,
+                                WorkCount& wc, uint32_t& n_shadow) {
     float t;
     int id;
-    const int slot = closest_hit(sc, r, stk, t, id);
+    const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
     id_out = id;
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
     const float4* tp = sc.tris + 3 * (size_t)slot;
@@ -317,7 +332,8 @@ __device__ float4 shade_lambert(const SceneDev& sc, const TraceView& v, const Ra
     if (ndl > 0.0f && v.shadow) {
         RayPre s;
         ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
-        if (any_hit(sc, s, stk)) vis = 0.0f;
+        ++n_shadow;
+        if (any_hit<kCount>(sc, s, stk, wc)) vis = 0.0f;
     }
     const float lam = ndl > 0.0f ? ndl : 0.0f;
     const float3 a = albedo_of(id);
@@ -326,15 +342,16 @@ __device__ float4 shade_lambert(const SceneDev& sc, const TraceView& v, const Ra
                        a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
 }
 
+template <bool kCount>
 __device__ float4 shade_path(const SceneDev& sc, const TraceView& v, RayPre r, uint32_t texel, int* stk,
-                             int& id_out) {
+                             int& id_out, WorkCount& wc, uint32_t& n_shadow) {
     float3 thr = make_float3(1.0f, 1.0f, 1.0f);
     float3 L = make_float3(0.0f, 0.0f, 0.0f);
     id_out = -1;
     for (int bnc = 0; bnc <= v.bounces; ++bnc) {
         float t;
         int id;
-        const int slot = closest_hit(sc, r, stk, t, id);
+        const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
         if (bnc == 0) id_out = id;
         if (slot < 0) {
             L.x += thr.x * v.background[0];
@@ -350,7 +367,8 @@ __device__ float4 shade_path(const SceneDev& sc, const TraceView& v, RayPre r, u
         if (ndl > 0.0f) {
             RayPre s;
             ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
-            vis = any_hit(sc, s, stk) ? 0.0f : 1.0f;
+            ++n_shadow;
+            vis = any_hit<kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
         }
         const float3 a = albedo_of(id);
         thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
@@ -364,7 +382,11 @@ __device__ float4 shade_path(const SceneDev& sc, const TraceView& v, RayPre r, u
     return make_float4(L.x, L.y, L.z, 1.0f);
 }
 
-__global__ __launch_bounds__(kBlock) void k_trace(const SceneDev sc, const TraceView v, int64_t n_items) {
+// kCount: diagnostic pass that counts work into counters[0..3] = primary
+// rays, shadow rays, node visits, triangle tests, and writes no image.
+template <bool kCount>
+__global__ __launch_bounds__(kBlock) void k_trace(const SceneDev sc, const TraceView v, int64_t n_items,
+                                                  unsigned long long* counters) {
     __shared__ int stack[kMaxDepth * kBlock];
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n_items) return;
@@ -374,17 +396,26 @@ __global__ __launch_bounds__(kBlock) void k_trace(const SceneDev sc, const Trace
     int* stk = stack + threadIdx.x;
     int id;
     float4 c;
+    WorkCount wc;
+    uint32_t n_shadow = 0;
     if (v.shade_mode == VAFR_SHADE_PATH)
-        c = shade_path(sc, v, r, (uint32_t)out, stk, id);
+        c = shade_path<kCount>(sc, v, r, (uint32_t)out, stk, id, wc, n_shadow);
     else
-        c = shade_lambert(sc, v, r, stk, id);
+        c = shade_lambert<kCount>(sc, v, r, stk, id, wc, n_shadow);
+    if (kCount) {
+        atomicAdd(counters + 0, 1ull);
+        atomicAdd(counters + 1, (unsigned long long)n_shadow);
+        atomicAdd(counters + 2, (unsigned long long)wc.nodes);
+        atomicAdd(counters + 3, (unsigned long long)wc.tris);
+        return;
+    }
     v.out_rgba[out] = c;
     if (v.out_id) v.out_id[out] = id;
 }
 
 }  // namespace
 
-int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream) {
+int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream, unsigned long long* counters) {
     int64_t n_items = v.n_items;
     if (v.mode == kModeFull) {
         const int64_t tx = (v.width + 7) / 8, ty = (v.height + 7) / 8;
@@ -393,7 +424,10 @@ int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream) {
     if (n_items <= 0) return VAFR_OK;
     const int64_t blocks = (n_items + kBlock - 1) / kBlock;
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
-    hipLaunchKernelGGL(k_trace, dim3((unsigned)blocks), dim3(kBlock), 0, stream, sc, v, n_items);
+    if (counters)
+        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, sc, v, n_items, counters);
+    else
+        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, sc, v, n_items, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

@@ -162,7 +162,8 @@ struct SceneDev {
     int32_t root;
 };
 
-int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream);
+// counters != nullptr selects the diagnostic work-counting pass.
+int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream, unsigned long long* counters = nullptr);
 
 // ------------------------------------------------------- reconstruction
 struct ReconVafr {

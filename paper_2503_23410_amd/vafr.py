@@ -31,7 +31,7 @@ EXPORTS = (
     "vafr_last_error", "vafr_abi_version", "vafr_lp_layout", "lmfr_lp_layout", "vafr_layout_dims",
     "vafr_layout_tables", "vafr_layout_destroy", "vafr_scene_create", "vafr_scene_get_info",
     "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
-    "lmfr_reconstruct", "full_shade",
+    "lmfr_reconstruct", "full_shade", "vafr_count_work",
 )
 
 
@@ -108,6 +108,7 @@ def load():
         "lmfr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
         "full_shade": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_display), C.POINTER(vafr_shading), _P,
                                  _P, _P]),
+        "vafr_count_work": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -303,3 +304,10 @@ def lmfr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
 def full_shade(scene, cam, disp, sh, img_rgba, hit_id=None, stream=None):
     _check(load().full_shade(scene.handle, C.byref(cam), C.byref(disp), C.byref(sh), _dptr(img_rgba),
                              _dptr(hit_id), _stream(stream)))
+
+
+def vafr_count_work(scene, cam, gz, sh, layout, counters, stream=None):
+    """counters: int64 device tensor of 4 (primary rays, shadow rays, node
+    visits, triangle tests), accumulated."""
+    _check(load().vafr_count_work(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(counters),
+                                  _stream(stream)))
