@@ -142,10 +142,12 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     if (want_kind == VAFR_LAYOUT_VAFR) {
         v.mode = kModeVafr;
         v.dxy = ld->dxy;
+        v.ord = ld->ord;
     } else {
         v.mode = kModeLmfr;
         v.lm_z = ld->lm_z;
         v.lm_cs = ld->lm_cs;
+        v.lm_w = L->n_cols;
         v.lm_h = L->max_rows;
         v.lm_L = lmfr_log_extent(L, gaze);
         if (!(v.lm_L > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
@@ -258,8 +260,9 @@ extern "C" int vafr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, 
     if (int rc = layout_device(L, &ld)) return rc;
     ReconVafr r;
     std::memset(&r, 0, sizeof(r));
-    r.seg = segments_f32(L->seg);
     r.n_cols = L->n_cols;
+    r.rho_scale = (float)(kURhoN / L->rho_max);
+    r.u_of_rho = ld->u_of_rho;
     r.width = L->disp.width;
     r.height = L->disp.height;
     r.px = (float)L->px;
@@ -291,7 +294,7 @@ extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, 
     r.height = L->disp.height;
     r.gx = (float)gaze.x_px;
     r.gy = (float)gaze.y_px;
-    r.inv_L = (float)(1.0 / Lg);
+    r.inv_L = (float)(M_LN2 / Lg);     // the kernel takes log2
     r.alpha = (float)L->alpha;
     r.lp = reinterpret_cast<const float4*>(lp);
     r.img = reinterpret_cast<float4*>(img);

@@ -82,21 +82,6 @@ void film_pitch(const vafr_display& d, double* px, double* py) {
     *py = 2.0 * std::tan(0.5 * d.fov_y_deg * kDeg) / d.height;
 }
 
-SegmentsF segments_f32(const Segments& s) {
-    SegmentsF f;
-    std::memset(&f, 0, sizeof(f));
-    f.n = s.n;
-    for (int k = 0; k <= s.n; ++k) f.e[k] = (float)s.e[k];
-    for (int k = 0; k < s.n; ++k) {
-        f.m[k] = (float)s.m[k];
-        f.b[k] = (float)s.b[k];
-        // u = (2/m) ln(omega) + c; for m == 0 the kernel uses u = (2/b) e + c.
-        f.two_over_m[k] = s.m[k] == 0.0 ? 0.0f : (float)(2.0 / s.m[k]);
-        f.c[k] = (float)s.c[k];
-    }
-    return f;
-}
-
 static int check_display(const vafr_display* d) {
     if (!d) return fail(VAFR_E_ARG, "display is NULL");
     if (d->width <= 0 || d->height <= 0 || d->width > 65536 || d->height > 65536)
@@ -104,6 +89,38 @@ static int check_display(const vafr_display* d) {
     if (!(d->fov_x_deg > 0.0 && d->fov_x_deg < 180.0) || !(d->fov_y_deg > 0.0 && d->fov_y_deg < 180.0))
         return fail(VAFR_E_ARG, "field of view must lie in (0, 180) degrees");
     return VAFR_OK;
+}
+
+// Interleave the bits of two 16-bit integers (Morton / Z order).
+static uint32_t morton2(uint32_t x, uint32_t y) {
+    auto spread = [](uint32_t v) {
+        v &= 0xffff;
+        v = (v | (v << 8)) & 0x00ff00ff;
+        v = (v | (v << 4)) & 0x0f0f0f0f;
+        v = (v | (v << 2)) & 0x33333333;
+        v = (v | (v << 1)) & 0x55555555;
+        return v;
+    };
+    return spread(x) | (spread(y) << 1);
+}
+
+// Trace order: texels sorted by the Morton code of their screen offset from
+// the gaze point, so that the 64 rays of a wave leave through a compact patch
+// of the screen (column-major order would spread them along a long arc).
+static void build_trace_order(vafr_layout_s* L) {
+    const int64_t n = L->n_texels;
+    float R = 0.0f;
+    for (int64_t k = 0; k < 2 * n; ++k) R = std::max(R, std::fabs(L->dxy[k]));
+    const double scale = R > 0.0f ? 65535.0 / (2.0 * R) : 0.0;
+    std::vector<uint64_t> key(n);
+    for (int64_t k = 0; k < n; ++k) {
+        const uint32_t qx = (uint32_t)std::min(65535.0, (L->dxy[2 * k] + R) * scale);
+        const uint32_t qy = (uint32_t)std::min(65535.0, (L->dxy[2 * k + 1] + R) * scale);
+        key[k] = ((uint64_t)morton2(qx, qy) << 32) | (uint64_t)k;
+    }
+    std::sort(key.begin(), key.end());
+    L->ord.resize(n);
+    for (int64_t k = 0; k < n; ++k) L->ord[k] = (int32_t)(key[k] & 0xffffffffu);
 }
 
 int layout_device(vafr_layout L, const LayoutDev** out) {
@@ -119,8 +136,15 @@ int layout_device(vafr_layout L, const LayoutDev** out) {
         for (int i = 0; i < L->n_cols; ++i) col[i] = make_int2(L->n_rows[i], (int)L->col_off[i]);
         VAFR_HIP(hipMalloc(&d.col, sizeof(int2) * col.size()));
         VAFR_HIP(hipMemcpy(d.col, col.data(), sizeof(int2) * col.size(), hipMemcpyHostToDevice));
-        VAFR_HIP(hipMalloc(&d.dxy, sizeof(float) * L->dxy.size()));
-        VAFR_HIP(hipMemcpy(d.dxy, L->dxy.data(), sizeof(float) * L->dxy.size(), hipMemcpyHostToDevice));
+        std::vector<float2> dxy_ord(L->n_texels);
+        for (int64_t k = 0; k < L->n_texels; ++k)
+            dxy_ord[k] = make_float2(L->dxy[2 * (int64_t)L->ord[k]], L->dxy[2 * (int64_t)L->ord[k] + 1]);
+        VAFR_HIP(hipMalloc(&d.dxy, sizeof(float2) * dxy_ord.size()));
+        VAFR_HIP(hipMemcpy(d.dxy, dxy_ord.data(), sizeof(float2) * dxy_ord.size(), hipMemcpyHostToDevice));
+        VAFR_HIP(hipMalloc(&d.ord, sizeof(int32_t) * L->ord.size()));
+        VAFR_HIP(hipMemcpy(d.ord, L->ord.data(), sizeof(int32_t) * L->ord.size(), hipMemcpyHostToDevice));
+        VAFR_HIP(hipMalloc(&d.u_of_rho, sizeof(float) * L->u_of_rho.size()));
+        VAFR_HIP(hipMemcpy(d.u_of_rho, L->u_of_rho.data(), sizeof(float) * L->u_of_rho.size(), hipMemcpyHostToDevice));
     } else {
         std::vector<double2> cs(L->max_rows);
         for (int j = 0; j < L->max_rows; ++j) cs[j] = make_double2(L->lm_cos[j], L->lm_sin[j]);
@@ -196,6 +220,23 @@ extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* ac
                 d[2 * j] = (float)(rho * std::cos(th));
                 d[2 * j + 1] = (float)(rho * std::sin(th));
             }
+        }
+        build_trace_order(L);
+        // Radial table for the inverse map: u as a function of the film
+        // radius rho = tan(e) (Eqs. (3), (5)), clamped to the first and last
+        // column centres; beyond rho_max every pixel reads the last column.
+        const double u_hi = L->n_cols - 0.5;
+        L->rho_max = std::tan(seg_e_of_u(seg, u_hi) * kDeg);
+        std::vector<double> u(kURhoN + 1);
+        for (int k = 0; k <= kURhoN; ++k) {
+            const double rho = L->rho_max * k / kURhoN;
+            const double e = std::atan(rho) / kDeg;
+            u[k] = std::min(std::max(seg_u(seg, e), 0.5), u_hi);
+        }
+        L->u_of_rho.resize(2 * (kURhoN + 1));
+        for (int k = 0; k <= kURhoN; ++k) {
+            L->u_of_rho[2 * k] = (float)u[k];
+            L->u_of_rho[2 * k + 1] = k < kURhoN ? (float)(u[k + 1] - u[k]) : 0.0f;
         }
     } catch (const std::bad_alloc&) {
         delete L;
@@ -274,6 +315,8 @@ extern "C" void vafr_layout_destroy(vafr_layout L) {
         if (hipSetDevice(d.device) != hipSuccess) continue;
         (void)hipFree(d.col);
         (void)hipFree(d.dxy);
+        (void)hipFree(d.ord);
+        (void)hipFree(d.u_of_rho);
         (void)hipFree(d.lm_z);
         (void)hipFree(d.lm_cs);
     }

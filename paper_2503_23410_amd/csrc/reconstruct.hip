@@ -19,7 +19,6 @@ namespace {
 constexpr int kTileW = 64;
 constexpr int kTileH = 4;
 constexpr int kXcds = 8;
-constexpr float kRadToDeg = 57.29577951308232f;
 
 // Workgroup id -> (tile x, tile y) so that XCD q (= id mod 8) gets the q-th
 // contiguous eighth of the tiles in row-major order.
@@ -49,15 +48,35 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float t) {
     return make_float4(s * a.x + t * b.x, s * a.y + t * b.y, s * a.z + t * b.z, s * a.w + t * b.w);
 }
 
-__device__ __forceinline__ float theta_deg(float dx, float dy) {
-    float th = atan2f(dy, dx) * kRadToDeg;
-    return th < 0.0f ? th + 360.0f : th;
+// Polar angle of (dx, dy) in turns, [0, 1], measured from +x toward +y.
+// atan on [0, 1] is a degree-15 odd minimax polynomial (coefficients fitted
+// for this kernel; FP32 error below 1.4e-7 rad), extended by the octant
+// symmetries.
+__device__ __forceinline__ float angle_turns(float dx, float dy) {
+    const float ax = fabsf(dx), ay = fabsf(dy);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float a = mx > 0.0f ? mn * __builtin_amdgcn_rcpf(mx) : 0.0f;
+    const float z = a * a;
+    float p = -0.00405457f;
+    p = fmaf(p, z, 0.02186295f);
+    p = fmaf(p, z, -0.05591232f);
+    p = fmaf(p, z, 0.09642197f);
+    p = fmaf(p, z, -0.13908629f);
+    p = fmaf(p, z, 0.19946566f);
+    p = fmaf(p, z, -0.33329861f);
+    p = fmaf(p, z, 0.99999934f);
+    float r = p * a;                                          // [0, pi/4]
+    r = ay > ax ? 1.5707963267948966f - r : r;
+    r = dx < 0.0f ? 3.141592653589793f - r : r;
+    r = dy < 0.0f ? 6.283185307179586f - r : r;
+    return r * 0.15915494309189535f;
 }
 
-// Angular interpolation inside one column of n rows starting at off.
-__device__ __forceinline__ float4 column_sample(const float4* __restrict__ lp, int2 col, float th) {
+// Angular interpolation inside one column (n rows starting at off), at
+// angle `turns` (fraction of the full circle).
+__device__ __forceinline__ float4 column_sample(const float4* __restrict__ lp, int2 col, float turns) {
     const int n = col.x;
-    const float s = th * ((float)n * (1.0f / 360.0f)) - 0.5f;
+    const float s = fmaf(turns, (float)n, -0.5f);
     const float fs = floorf(s);
     const float t = s - fs;
     int j0 = (int)fs;
@@ -76,24 +95,21 @@ __global__ __launch_bounds__(kTileW* kTileH) void k_recon_vafr(const ReconVafr R
     const float X = ((float)x + 0.5f - 0.5f * (float)R.width) * R.px;
     const float Y = ((float)y + 0.5f - 0.5f * (float)R.height) * R.py;
     const float dx = X - R.gx, dy = Y - R.gy;
-    const float rho = sqrtf(dx * dx + dy * dy);
-    const float e = atanf(rho) * kRadToDeg;                 // Eq. (3)
-    const float th = theta_deg(dx, dy);
-    // Eq. (5) on the segment holding e (Eq. (12)); segment constants are
-    // uniform, so the scan reads them with scalar loads.
-    float m = R.seg.m[0], b = R.seg.b[0], tm = R.seg.two_over_m[0], c = R.seg.c[0];
-    for (int q = 1; q < R.seg.n; ++q) {
-        if (e >= R.seg.e[q]) { m = R.seg.m[q]; b = R.seg.b[q]; tm = R.seg.two_over_m[q]; c = R.seg.c[q]; }
-    }
-    float u = m != 0.0f ? tm * __logf(fmaf(m, e, b)) + c : 2.0f * e / b + c;
-    u = fminf(fmaxf(u, 0.5f), (float)R.n_cols - 0.5f);
+    const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
+    // u(e(rho)) (Eqs. (3), (5), (12)) from the FP64-built radial table,
+    // already clamped to the first and last column centres.
+    const float tq = fminf(rho * R.rho_scale, (float)kURhoN);
+    const int k = (int)tq;
+    const float2 uk = R.u_of_rho[k];
+    const float u = fmaf(tq - (float)k, uk.y, uk.x);
     const float a = u - 0.5f;
     int i0 = (int)a;
-    i0 = i0 > R.n_cols - 1 ? R.n_cols - 1 : i0;
+    i0 = i0 > R.n_cols - 1 ? R.n_cols - 1 : (i0 < 0 ? 0 : i0);
     const int i1 = i0 + 1 < R.n_cols ? i0 + 1 : R.n_cols - 1;
     const float w = a - (float)i0;
-    const float4 c0 = column_sample(R.lp, R.col[i0], th);
-    const float4 c1 = column_sample(R.lp, R.col[i1], th);
+    const float turns = angle_turns(dx, dy);
+    const float4 c0 = column_sample(R.lp, R.col[i0], turns);
+    const float4 c1 = column_sample(R.lp, R.col[i1], turns);
     store_px(R.img + (size_t)y * R.width + x, lerp4(c0, c1, w));
 }
 
@@ -106,9 +122,9 @@ __global__ __launch_bounds__(kTileW* kTileH) void k_recon_lmfr(const ReconLmfr R
     if (x >= R.width || y >= R.height) return;
     const float dx = (float)x + 0.5f - R.gx, dy = (float)y + 0.5f - R.gy;
     const float r = fmaxf(sqrtf(dx * dx + dy * dy), 1.0f);
-    const float z = __logf(r) * R.inv_L;                      // Eq. (1)
+    const float z = __log2f(r) * R.inv_L;                     // Eq. (1); inv_L = ln 2 / L
     float u = (R.alpha == 4.0f ? (z * z) * (z * z) : __powf(z, R.alpha)) * (float)R.w;   // Eq. (14)
-    const float v = theta_deg(dx, dy) * ((float)R.h * (1.0f / 360.0f));
+    const float v = angle_turns(dx, dy) * (float)R.h;
     u = fminf(fmaxf(u, 0.5f), (float)R.w - 0.5f);
     const float a = u - 0.5f;
     int i0 = (int)a;

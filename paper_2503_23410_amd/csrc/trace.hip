@@ -290,17 +290,24 @@ __device__ __forceinline__ void film_ray(const TraceView& v, double Px, double P
 // Item -> (ray, output slot).  Returns false for padding items.
 __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, RayPre& r, int64_t& out) {
     if (v.mode == kModeVafr) {
+        // trace order: compact screen patches per wave
         const float2 o = v.dxy[k];
         film_ray(v, v.gx + (double)o.x, v.gy + (double)o.y, r);
-        out = k;
+        out = v.ord[k];
         return true;
     }
     if (v.mode == kModeLmfr) {
-        const int64_t i = k / v.lm_h, j = k - i * v.lm_h;
+        // 8 x 8 tiles of (column, row) of the dense LMFR buffer
+        const int tiles_j = (v.lm_h + 7) >> 3;
+        const int64_t tile = k >> 6;
+        const int w = (int)(k & 63);
+        const int64_t i = (tile / tiles_j) * 8 + (w >> 3);
+        const int64_t j = (tile % tiles_j) * 8 + (w & 7);
+        if (i >= v.lm_w || j >= v.lm_h) return false;
         const double rad = exp(v.lm_L * v.lm_z[i]);
         const double2 cs = v.lm_cs[j];
         film_ray(v, v.gx + (rad * cs.x) * v.px, v.gy + (rad * cs.y) * v.py, r);
-        out = k;
+        out = i * v.lm_h + j;
         return true;
     }
     // full resolution, 8 x 8 pixel tiles for coherent waves
@@ -420,6 +427,9 @@ int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream, uns
     if (v.mode == kModeFull) {
         const int64_t tx = (v.width + 7) / 8, ty = (v.height + 7) / 8;
         n_items = tx * ty * 64;
+    } else if (v.mode == kModeLmfr) {
+        const int64_t ti = (v.lm_w + 7) / 8, tj = (v.lm_h + 7) / 8;
+        n_items = ti * tj * 64;
     }
     if (n_items <= 0) return VAFR_OK;
     const int64_t blocks = (n_items + kBlock - 1) / kBlock;

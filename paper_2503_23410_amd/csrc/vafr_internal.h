@@ -34,21 +34,16 @@ struct Segments {
     double u[kMaxSeg + 1] = {};
 };
 
-// FP32 copy of the segment constants handed to the reconstruction kernel.
-struct SegmentsF {
-    int n;
-    float e[kMaxSeg + 1];
-    float m[kMaxSeg];
-    float b[kMaxSeg];
-    float two_over_m[kMaxSeg];
-    float c[kMaxSeg];
-};
+// Size of the radial table u(rho) used by the reconstruction kernel.
+constexpr int kURhoN = 16384;
 
 // Per-device copy of a layout's tables.
 struct LayoutDev {
     int device = -1;
     int2* col = nullptr;          // VaFR: (n_rows, col_off) per column
-    float2* dxy = nullptr;        // VaFR: film offset per texel
+    float2* dxy = nullptr;        // VaFR: film offset per texel, in trace order
+    int32_t* ord = nullptr;       // VaFR: texel index of each trace-order slot
+    float2* u_of_rho = nullptr;   // VaFR: (u_k, u_{k+1} - u_k) at rho_k = k h, k <= kURhoN
     double* lm_z = nullptr;       // LMFR: z_i per column
     double2* lm_cs = nullptr;     // LMFR: (cos, sin) of theta_j per row
 };
@@ -67,6 +62,9 @@ struct vafr_layout_s {
     std::vector<int32_t> n_rows;
     std::vector<int64_t> col_off;
     std::vector<float> dxy;
+    std::vector<int32_t> ord;            // trace order (Morton order of the screen offsets)
+    double rho_max = 0;                  // film radius of the last column centre
+    std::vector<float> u_of_rho;         // 2 * (kURhoN + 1) floats
     // LMFR
     double delta = 0, alpha = 0;
     std::vector<double> lm_z, lm_cos, lm_sin;
@@ -83,7 +81,6 @@ double seg_u(const Segments& s, double e);
 double seg_e_of_u(const Segments& s, double u);
 double seg_l(const Segments& s, double e);
 void film_pitch(const vafr_display& d, double* px, double* py);
-SegmentsF segments_f32(const Segments& s);
 // Upload (once per device) and return the tables of the current device.
 int layout_device(vafr_layout L, const LayoutDev** out);
 
@@ -139,12 +136,13 @@ struct TraceView {
     // film geometry (FP64): gaze point on the film and pixel pitch
     double gx, gy, px, py;
     int32_t width, height;
-    // VaFR
+    // VaFR: item k traces texel ord[k] through film offset dxy[k]
     const float2* dxy;
+    const int32_t* ord;
     // LMFR
     const double* lm_z;
     const double2* lm_cs;
-    int32_t lm_h;
+    int32_t lm_w, lm_h;
     double lm_L;
     // shading
     float light_dir[3], light_rgb[3], ambient[3], background[3];
@@ -167,11 +165,12 @@ int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream, uns
 
 // ------------------------------------------------------- reconstruction
 struct ReconVafr {
-    SegmentsF seg;
     int32_t n_cols;
     int32_t width, height;
     float px, py;       // pitch
     float gx, gy;       // gaze on the film
+    float rho_scale;    // kURhoN / rho_max
+    const float2* u_of_rho;
     const int2* col;    // (n_rows, col_off)
     const float4* lp;
     float4* img;
@@ -181,7 +180,7 @@ struct ReconLmfr {
     int32_t w, h;
     int32_t width, height;
     float gx, gy;       // gaze in pixels
-    float inv_L;
+    float inv_L;        // ln 2 / L (the kernel uses log2)
     float alpha;
     const float4* lp;
     float4* img;
