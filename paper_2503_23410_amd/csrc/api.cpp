@@ -1,5 +1,7 @@
 // C ABI entry points: argument validation, handle management and the
 // per-frame launches.  Host arithmetic on the film geometry is FP64.
+#include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -65,16 +67,36 @@ static int current_device(int* dev) {
     return VAFR_OK;
 }
 
-static int scene_dev(vafr_scene s, SceneDev* out) {
+static int scene_into_view(vafr_scene s, TraceView* v) {
     if (!s) return fail(VAFR_E_ARG, "scene is NULL");
     int dev;
     if (int rc = current_device(&dev)) return rc;
     if (s->n_tris > 0 && s->device != dev)
         return fail(VAFR_E_ARG, "scene lives on device %d, current device is %d", s->device, dev);
-    out->nodes = s->d_nodes;
-    out->tris = s->d_tris;
-    out->root = s->host.root;
+    v->nodes = s->d_nodes;
+    v->tris = s->d_tris;
+    v->root = s->host.root;
     return VAFR_OK;
+}
+
+static std::atomic<int32_t> g_trace_chunk{0};
+
+// Items per workgroup: an explicit setting, or enough workgroups to fill
+// every CU about twice at the kernel's occupancy (5 workgroups per CU).
+int32_t trace_chunk(int64_t n_items) {
+    const int32_t forced = g_trace_chunk.load();
+    if (forced > 0) return forced;
+    static int n_cu = 0;
+    if (!n_cu) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        n_cu = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+                   ? prop.multiProcessorCount : 256;
+    }
+    const int64_t slots = (int64_t)n_cu * 5 * 2;
+    int64_t c = (n_items + slots - 1) / slots;
+    c = (c + 63) / 64 * 64;
+    return (int32_t)std::min<int64_t>(std::max<int64_t>(c, 256), 1 << 20);
 }
 
 static void fill_view_common(TraceView& v, const vafr_camera* cam, const vafr_shading* sh) {
@@ -126,12 +148,11 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     if (int rc = check_shading(sh)) return rc;
     if (int rc = check_gaze(gaze)) return rc;
     if (!lp && !counters) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
-    SceneDev sd;
-    if (int rc = scene_dev(scene, &sd)) return rc;
-    const LayoutDev* ld;
-    if (int rc = layout_device(L, &ld)) return rc;
     TraceView v;
     std::memset(&v, 0, sizeof(v));
+    if (int rc = scene_into_view(scene, &v)) return rc;
+    const LayoutDev* ld;
+    if (int rc = layout_device(L, &ld)) return rc;
     fill_view_common(v, cam, sh);
     v.n_items = L->n_texels;
     gaze_film(L, gaze, &v.gx, &v.gy);
@@ -154,7 +175,8 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     }
     v.out_rgba = reinterpret_cast<float4*>(lp);
     v.out_id = hit;
-    return launch_trace(sd, v, stream, counters);
+    v.n_items = trace_items_of(v);
+    return launch_trace(v, trace_chunk(v.n_items), stream, counters);
 }
 
 }  // namespace vafr
@@ -311,19 +333,18 @@ extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_d
     if (int rc = check_camera(cam)) return rc;
     if (int rc = check_shading(sh)) return rc;
     if (!img) return fail(VAFR_E_ARG, "img_rgba_dev is NULL");
-    SceneDev sd;
-    if (int rc = scene_dev(scene, &sd)) return rc;
     TraceView v;
     std::memset(&v, 0, sizeof(v));
+    if (int rc = scene_into_view(scene, &v)) return rc;
     fill_view_common(v, cam, sh);
     v.mode = kModeFull;
     v.width = d->width;
     v.height = d->height;
     film_pitch(*d, &v.px, &v.py);
-    v.n_items = (int64_t)d->width * d->height;
     v.out_rgba = reinterpret_cast<float4*>(img);
     v.out_id = hit;
-    return launch_trace(sd, v, stream);
+    v.n_items = trace_items_of(v);
+    return launch_trace(v, trace_chunk(v.n_items), stream);
 }
 
 extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
@@ -331,4 +352,11 @@ extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_ga
     if (!L) return fail(VAFR_E_ARG, "layout is NULL");
     if (!counters_dev) return fail(VAFR_E_ARG, "counters_dev is NULL");
     return shade_lp_common(L->kind, scene, cam, gaze, sh, L, nullptr, nullptr, stream, counters_dev);
+}
+
+extern "C" int vafr_set_trace_chunk(int32_t items_per_workgroup) {
+    if (items_per_workgroup != 0 && (items_per_workgroup < 256 || items_per_workgroup % 64 || items_per_workgroup > (1 << 20)))
+        return fail(VAFR_E_ARG, "items per workgroup must be 0 or a multiple of 64 in [256, 2^20]");
+    g_trace_chunk.store(items_per_workgroup);
+    return VAFR_OK;
 }

@@ -130,7 +130,11 @@ enum RayMode : int32_t { kModeVafr = 0, kModeLmfr = 1, kModeFull = 2 };
 struct TraceView {
     int32_t mode;
     int32_t shade_mode;     // VAFR_SHADE_*
-    int64_t n_items;
+    int64_t n_items;        // work items (padded to whole 8 x 8 tiles for tiled modes)
+    // scene
+    const BvhNode* nodes;
+    const float4* tris;
+    int32_t root;
     // camera
     float eye[3], right[3], up[3], fwd[3];
     // film geometry (FP64): gaze point on the film and pixel pitch
@@ -154,14 +158,14 @@ struct TraceView {
     int32_t* out_id;
 };
 
-struct SceneDev {
-    const BvhNode* nodes;
-    const float4* tris;
-    int32_t root;
-};
-
+// Work items of a view (padded to whole tiles for full-resolution / LMFR).
+int64_t trace_items_of(const TraceView& v);
+// Items per workgroup of a launch of n items (tuned value or heuristic).
+int32_t trace_chunk(int64_t n_items);
 // counters != nullptr selects the diagnostic work-counting pass.
-int launch_trace(const SceneDev& sc, const TraceView& v, hipStream_t stream, unsigned long long* counters = nullptr);
+int launch_trace(const TraceView& v, int32_t chunk, hipStream_t stream, unsigned long long* counters = nullptr);
+int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
+                       int32_t chunk, hipStream_t stream, unsigned long long* counters = nullptr);
 
 // ------------------------------------------------------- reconstruction
 struct ReconVafr {
