@@ -89,7 +89,6 @@ def main():
                     help="frames for the full-resolution and LMFR comparisons (default: steps/20, >= 3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip full-resolution and LMFR runs")
-    ap.add_argument("--trace-chunk", type=int, default=0, help="rays per traversal workgroup (0: library choice)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -103,7 +102,6 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     V.load()
-    V.vafr_set_trace_chunk(args.trace_chunk)
     steps, warm = args.steps, args.warmup
     csteps = args.compare_steps or max(3, steps // 20)
 

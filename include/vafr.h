@@ -221,12 +221,6 @@ int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* dis
 int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
                     vafr_layout layout, unsigned long long* counters_dev, hipStream_t stream);
 
-/* Tuning: work items (rays) per workgroup of the traversal kernel for the
- * per-view calls above; 0 restores the built-in choice (about two
- * workgroups per CU slot).  Process-wide; must be 0 or a multiple of 64 in
- * [256, 2^20]. */
-int vafr_set_trace_chunk(int32_t items_per_workgroup);
-
 #ifdef __cplusplus
 }
 #endif

@@ -79,26 +79,6 @@ static int scene_into_view(vafr_scene s, TraceView* v) {
     return VAFR_OK;
 }
 
-static std::atomic<int32_t> g_trace_chunk{0};
-
-// Items per workgroup: an explicit setting, or enough workgroups to fill
-// every CU about twice at the kernel's occupancy (5 workgroups per CU).
-int32_t trace_chunk(int64_t n_items) {
-    const int32_t forced = g_trace_chunk.load();
-    if (forced > 0) return forced;
-    static int n_cu = 0;
-    if (!n_cu) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        n_cu = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-                   ? prop.multiProcessorCount : 256;
-    }
-    const int64_t slots = (int64_t)n_cu * 5 * 2;
-    int64_t c = (n_items + slots - 1) / slots;
-    c = (c + 63) / 64 * 64;
-    return (int32_t)std::min<int64_t>(std::max<int64_t>(c, 256), 1 << 20);
-}
-
 static void fill_view_common(TraceView& v, const vafr_camera* cam, const vafr_shading* sh) {
     std::memcpy(v.eye, cam->eye, sizeof(v.eye));
     std::memcpy(v.right, cam->right, sizeof(v.right));
@@ -176,7 +156,7 @@ static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* c
     v.out_rgba = reinterpret_cast<float4*>(lp);
     v.out_id = hit;
     v.n_items = trace_items_of(v);
-    return launch_trace(v, trace_chunk(v.n_items), stream, counters);
+    return launch_trace(v, stream, counters);
 }
 
 }  // namespace vafr
@@ -344,7 +324,7 @@ extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_d
     v.out_rgba = reinterpret_cast<float4*>(img);
     v.out_id = hit;
     v.n_items = trace_items_of(v);
-    return launch_trace(v, trace_chunk(v.n_items), stream);
+    return launch_trace(v, stream);
 }
 
 extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
@@ -354,9 +334,3 @@ extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_ga
     return shade_lp_common(L->kind, scene, cam, gaze, sh, L, nullptr, nullptr, stream, counters_dev);
 }
 
-extern "C" int vafr_set_trace_chunk(int32_t items_per_workgroup) {
-    if (items_per_workgroup != 0 && (items_per_workgroup < 256 || items_per_workgroup % 64 || items_per_workgroup > (1 << 20)))
-        return fail(VAFR_E_ARG, "items per workgroup must be 0 or a multiple of 64 in [256, 2^20]");
-    g_trace_chunk.store(items_per_workgroup);
-    return VAFR_OK;
-}

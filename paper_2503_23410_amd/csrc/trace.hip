@@ -107,6 +107,108 @@ __device__ __forceinline__ void box2(const RayPre& r, const float4 a, const floa
     h1 = tn1 <= tf1 * kExitScale;
 }
 
+// Per-lane work counters of the diagnostic pass (node visits = box-pair
+// tests, triangle tests).
+struct WorkCount {
+    uint32_t nodes = 0, tris = 0;
+};
+
+// Closest hit: smallest (t, triangle id); returns the stored slot or -1.
+// stk points at this lane's column of the block's LDS stack (stride kBlock).
+template <bool kCount>
+__device__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
+                           WorkCount& wc) {
+    t_best = INFINITY;
+    id_best = -1;
+    int slot_best = -1;
+    int ref = sc.root;
+    if (ref == kEmptyRef) return -1;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
+            const float4 a = p[0], b = p[1], c = p[2];
+            const int4 d = reinterpret_cast<const int4*>(p)[3];
+            const float tlim = t_best * kHitSlack;
+            if (kCount) ++wc.nodes;
+            bool h0, h1;
+            float tn0, tn1;
+            box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
+            if (h0 && h1) {
+                const bool first0 = tn0 <= tn1;
+                stk[sp * kBlock] = first0 ? d.y : d.x;
+                ++sp;
+                ref = first0 ? d.x : d.y;
+                continue;
+            }
+            if (h0) { ref = d.x; continue; }
+            if (h1) { ref = d.y; continue; }
+        } else {
+            const int x = ~ref;
+            const int first = x >> 3, count = (x & 7) + 1;
+            const float4* tp = sc.tris + 3 * (size_t)first;
+            if (kCount) wc.tris += count;
+            for (int q = 0; q < count; ++q) {
+                const float4 v0 = tp[3 * q], v1 = tp[3 * q + 1], v2 = tp[3 * q + 2];
+                float t;
+                if (tri_hit(r, v0, v1, v2, t)) {
+                    const int id = __float_as_int(v0.w);
+                    if (t < t_best || (t == t_best && id < id_best)) {
+                        t_best = t;
+                        id_best = id;
+                        slot_best = first + q;
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+    return slot_best;
+}
+
+// Any hit with t > 0 (shadow ray toward a directional light).
+template <bool kCount>
+__device__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
+    int ref = sc.root;
+    if (ref == kEmptyRef) return false;
+    int sp = 0;
+    for (;;) {
+        if (ref >= 0) {
+            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
+            const float4 a = p[0], b = p[1], c = p[2];
+            const int4 d = reinterpret_cast<const int4*>(p)[3];
+            if (kCount) ++wc.nodes;
+            bool h0, h1;
+            float tn0, tn1;
+            box2(r, a, b, c, INFINITY, h0, h1, tn0, tn1);
+            if (h0 && h1) {
+                const bool first0 = tn0 <= tn1;
+                stk[sp * kBlock] = first0 ? d.y : d.x;
+                ++sp;
+                ref = first0 ? d.x : d.y;
+                continue;
+            }
+            if (h0) { ref = d.x; continue; }
+            if (h1) { ref = d.y; continue; }
+        } else {
+            const int x = ~ref;
+            const int first = x >> 3, count = (x & 7) + 1;
+            const float4* tp = sc.tris + 3 * (size_t)first;
+            for (int q = 0; q < count; ++q) {
+                float t;
+                if (kCount) ++wc.tris;
+                if (tri_hit(r, tp[3 * q], tp[3 * q + 1], tp[3 * q + 2], t)) return true;
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        ref = stk[sp * kBlock];
+    }
+    return false;
+}
+
 // 32-bit hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
 // JCGT 9(3), 2020 (PCG output permutation of one LCG step).
 __device__ __forceinline__ uint32_t pcg_hash(uint32_t v) {
@@ -221,221 +323,121 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
     return true;
 }
 
-enum LanePhase : int { kIdle = 0, kClosest = 1, kShadow = 2, kDone = 3 };
-
-// Rays of items [begin, end) of one view, traced by one workgroup.
-//
-// Each lane runs a small state machine (primary/bounce closest hit, then
-// shadow any-hit, then the next item) and every loop iteration performs one
-// unit of traversal work per active lane: one node visit (two child boxes),
-// one triangle test, or entering a leaf.  Idle lanes take the next item from
-// the workgroup's LDS queue head, so lanes do not wait for the slowest ray of
-// their wave and leaves do not serialise four triangle tests behind one lane.
-// kCount: diagnostic pass that counts work into counters[0..3] = primary
-// rays, shadow rays, node visits, triangle tests, and writes no image.
 template <bool kCount>
-__device__ __forceinline__ void trace_items(const TraceView& v, int64_t begin, int64_t end, int* stack, int* q_head,
-                                            unsigned long long* counters) {
-    const int lane = threadIdx.x & 63;
-    int* stk = stack + threadIdx.x;
-    if (threadIdx.x == 0) *q_head = 0;
-    __syncthreads();
-    const int n_local = (int)(end - begin);
-    const bool path = v.shade_mode == VAFR_SHADE_PATH;
+__device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, int& id_out, WorkCount& wc,
+                                uint32_t& n_shadow) {
+    const TraceView& sc = v;
+    float t;
+    int id;
+    const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
+    id_out = id;
+    if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
+    const float4* tp = sc.tris + 3 * (size_t)slot;
+    float3 n, os;
+    hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+    const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
+    float vis = 1.0f;
+    if (ndl > 0.0f && v.shadow) {
+        RayPre s;
+        ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
+        ++n_shadow;
+        if (any_hit<kCount>(sc, s, stk, wc)) vis = 0.0f;
+    }
+    const float lam = ndl > 0.0f ? ndl : 0.0f;
+    const float3 a = albedo_of(id);
+    return make_float4(a.x * (v.ambient[0] + v.light_rgb[0] * lam * vis),
+                       a.y * (v.ambient[1] + v.light_rgb[1] * lam * vis),
+                       a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
+}
 
-    int phase = kIdle;
-    int64_t out = 0;
-    RayPre r;
-    float t_best = INFINITY;
-    int id_best = -1, slot_best = -1;
-    int ref = kEmptyRef, tri = 0, tri_end = 0, sp = 0;
-    bool shadow_hit = false;
-    int bounce = 0, prim_id = -1;
-    float3 thr = make_float3(0.0f, 0.0f, 0.0f), L = make_float3(0.0f, 0.0f, 0.0f);
-    float ndl = 0.0f;
-    float3 nrm = make_float3(0.0f, 0.0f, 0.0f), os = make_float3(0.0f, 0.0f, 0.0f);
-    uint32_t c_prim = 0, c_shadow = 0, c_nodes = 0, c_tris = 0;
-
-    auto start_closest = [&]() {
-        t_best = INFINITY;
-        id_best = -1;
-        slot_best = -1;
-        ref = v.root;
-        tri = tri_end = 0;
-        sp = 0;
-        phase = kClosest;
-    };
-    auto start_shadow = [&]() {
-        ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], r);
-        ref = v.root;
-        tri = tri_end = 0;
-        sp = 0;
-        shadow_hit = false;
-        phase = kShadow;
-        if (kCount) ++c_shadow;
-    };
-    auto finish = [&](float4 c) {
-        if (!kCount) {
-            v.out_rgba[out] = c;
-            if (v.out_id) v.out_id[out] = prim_id;
+template <bool kCount>
+__device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
+                             uint32_t& n_shadow) {
+    const TraceView& sc = v;
+    float3 thr = make_float3(1.0f, 1.0f, 1.0f);
+    float3 L = make_float3(0.0f, 0.0f, 0.0f);
+    id_out = -1;
+    for (int bnc = 0; bnc <= v.bounces; ++bnc) {
+        float t;
+        int id;
+        const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
+        if (bnc == 0) id_out = id;
+        if (slot < 0) {
+            L.x += thr.x * v.background[0];
+            L.y += thr.y * v.background[1];
+            L.z += thr.z * v.background[2];
+            break;
         }
-        phase = kIdle;
-    };
-    // Close the shading vertex once visibility toward the light is known.
-    auto close_vertex = [&](float vis) {
-        if (!path) {
-            const float lam = ndl > 0.0f ? ndl : 0.0f;
-            finish(make_float4(thr.x * (v.ambient[0] + v.light_rgb[0] * lam * vis),
-                               thr.y * (v.ambient[1] + v.light_rgb[1] * lam * vis),
-                               thr.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f));
-            return;
+        const float4* tp = sc.tris + 3 * (size_t)slot;
+        float3 n, os;
+        hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+        const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
+        float vis = 0.0f;
+        if (ndl > 0.0f) {
+            RayPre s;
+            ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
+            ++n_shadow;
+            vis = any_hit<kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
         }
+        const float3 a = albedo_of(id);
+        thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
         L.x += thr.x * (v.ambient[0] + v.light_rgb[0] * ndl * vis);
         L.y += thr.y * (v.ambient[1] + v.light_rgb[1] * ndl * vis);
         L.z += thr.z * (v.ambient[2] + v.light_rgb[2] * ndl * vis);
-        if (bounce == v.bounces) {
-            finish(make_float4(L.x, L.y, L.z, 1.0f));
-            return;
-        }
-        const float3 w = cosine_dir(v, nrm, (uint32_t)out, (uint32_t)bounce);
+        if (bnc == v.bounces) break;
+        const float3 w = cosine_dir(v, n, texel, (uint32_t)bnc);
         ray_setup(os.x, os.y, os.z, w.x, w.y, w.z, r);
-        ++bounce;
-        start_closest();
-    };
-
-    for (;;) {
-        // -------------------------------------------------- refill idle lanes
-        const uint64_t idle = __ballot(phase == kIdle);
-        if (idle) {
-            const int leader = __ffsll((unsigned long long)idle) - 1;
-            int base = 0;
-            if (lane == leader) base = atomicAdd(q_head, __popcll(idle));
-            base = __shfl(base, leader);
-            if (phase == kIdle) {
-                const int mine = base + __popcll(idle & ((1ull << lane) - 1ull));
-                if (mine >= n_local) {
-                    phase = kDone;
-                } else if (make_item_ray(v, begin + mine, r, out)) {
-                    bounce = 0;
-                    prim_id = -1;
-                    thr = make_float3(1.0f, 1.0f, 1.0f);
-                    L = make_float3(0.0f, 0.0f, 0.0f);
-                    start_closest();
-                    if (kCount) ++c_prim;
-                }
-            }
-        }
-        if (__ballot(phase != kDone) == 0) break;
-        if (phase != kClosest && phase != kShadow) continue;
-
-        // ------------------------------------------------- one unit of work
-        if (tri < tri_end) {
-            const float4* tp = v.tris + 3 * (size_t)tri;
-            const float4 v0 = tp[0];
-            float t;
-            if (tri_hit(r, v0, tp[1], tp[2], t)) {
-                if (phase == kShadow) {
-                    shadow_hit = true;
-                    tri = tri_end;
-                    ref = kEmptyRef;
-                    sp = 0;
-                } else {
-                    const int id = __float_as_int(v0.w);
-                    if (t < t_best || (t == t_best && id < id_best)) {
-                        t_best = t;
-                        id_best = id;
-                        slot_best = tri;
-                    }
-                }
-            }
-            ++tri;
-            if (kCount) ++c_tris;
-        } else if (ref >= 0) {
-            const float4* p = reinterpret_cast<const float4*>(v.nodes + ref);
-            const float4 a = p[0], b = p[1], c = p[2];
-            const int4 d = reinterpret_cast<const int4*>(p)[3];
-            const float tlim = phase == kShadow ? INFINITY : t_best * kHitSlack;
-            bool h0, h1;
-            float tn0, tn1;
-            box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
-            if (h0 && h1) {
-                const bool first0 = tn0 <= tn1;
-                stk[sp * kBlock] = first0 ? d.y : d.x;
-                ++sp;
-                ref = first0 ? d.x : d.y;
-            } else if (h0) {
-                ref = d.x;
-            } else if (h1) {
-                ref = d.y;
-            } else {
-                ref = sp > 0 ? stk[--sp * kBlock] : kEmptyRef;
-            }
-            if (kCount) ++c_nodes;
-        } else if (ref != kEmptyRef) {
-            const int x = ~ref;
-            tri = x >> 3;
-            tri_end = tri + (x & 7) + 1;
-            ref = sp > 0 ? stk[--sp * kBlock] : kEmptyRef;
-        }
-        if (tri < tri_end || ref != kEmptyRef) continue;
-
-        // --------------------------------------------- traversal finished
-        if (phase == kShadow) {
-            close_vertex(shadow_hit ? 0.0f : 1.0f);
-            continue;
-        }
-        if (bounce == 0) prim_id = id_best;
-        if (slot_best < 0) {
-            if (path)
-                finish(make_float4(L.x + thr.x * v.background[0], L.y + thr.y * v.background[1],
-                                   L.z + thr.z * v.background[2], 1.0f));
-            else
-                finish(make_float4(v.background[0], v.background[1], v.background[2], 1.0f));
-            continue;
-        }
-        const float4* tp = v.tris + 3 * (size_t)slot_best;
-        hit_frame(tp[0], tp[1], tp[2], r, t_best, nrm, os);
-        ndl = (nrm.x * v.light_dir[0] + nrm.y * v.light_dir[1]) + nrm.z * v.light_dir[2];
-        const float3 alb = albedo_of(id_best);
-        thr = path ? make_float3(thr.x * alb.x, thr.y * alb.y, thr.z * alb.z) : alb;
-        if (ndl > 0.0f && (path || v.shadow))
-            start_shadow();
-        else
-            close_vertex(path ? 0.0f : 1.0f);
     }
+    return make_float4(L.x, L.y, L.z, 1.0f);
+}
+
+// One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
+// counts work into counters[0..3] = primary rays, shadow rays, node visits,
+// triangle tests, and writes no image.
+template <bool kCount>
+__device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
+    RayPre r;
+    int64_t out;
+    if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
+    int* stk = stack + threadIdx.x;
+    int id;
+    float4 c;
+    WorkCount wc;
+    uint32_t n_shadow = 0;
+    if (v.shade_mode == VAFR_SHADE_PATH)
+        c = shade_path<kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow);
+    else
+        c = shade_lambert<kCount>(v, r, stk, id, wc, n_shadow);
     if (kCount) {
-        atomicAdd(counters + 0, (unsigned long long)c_prim);
-        atomicAdd(counters + 1, (unsigned long long)c_shadow);
-        atomicAdd(counters + 2, (unsigned long long)c_nodes);
-        atomicAdd(counters + 3, (unsigned long long)c_tris);
+        atomicAdd(counters + 0, 1ull);
+        atomicAdd(counters + 1, (unsigned long long)n_shadow);
+        atomicAdd(counters + 2, (unsigned long long)wc.nodes);
+        atomicAdd(counters + 3, (unsigned long long)wc.tris);
+        return;
     }
+    v.out_rgba[out] = c;
+    if (v.out_id) v.out_id[out] = id;
 }
 
 template <bool kCount>
-__global__ __launch_bounds__(kBlock) void k_trace(const TraceView v, int32_t chunk, unsigned long long* counters) {
+__global__ __launch_bounds__(kBlock) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[kMaxDepth * kBlock];
-    __shared__ int q_head;
-    const int64_t begin = (int64_t)blockIdx.x * chunk;
-    const int64_t end = begin + chunk < v.n_items ? begin + chunk : v.n_items;
-    trace_items<kCount>(v, begin, end, stack, &q_head, counters);
+    trace_item<kCount>(v, (int64_t)blockIdx.x * kBlock + threadIdx.x, stack, counters);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
-// block_end[vid] (block_end is the running sum of per-view workgroups).
+// block_end[vid] (block_end is the running sum of per-view workgroups of
+// kBlock items each).
 template <bool kCount>
 __global__ __launch_bounds__(kBlock) void k_trace_batch(const TraceView* __restrict__ views,
                                                         const int32_t* __restrict__ block_end, int32_t n_views,
-                                                        int32_t chunk, unsigned long long* counters) {
+                                                        unsigned long long* counters) {
     __shared__ int stack[kMaxDepth * kBlock];
-    __shared__ int q_head;
     const int b = blockIdx.x;
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    const TraceView& v = views[vid];
-    const int64_t begin = (int64_t)(b - first) * chunk;
-    const int64_t end = begin + chunk < v.n_items ? begin + chunk : v.n_items;
-    trace_items<kCount>(v, begin, end, stack, &q_head, counters);
+    trace_item<kCount>(views[vid], (int64_t)(b - first) * kBlock + threadIdx.x, stack, counters);
 }
 
 }  // namespace
@@ -446,28 +448,29 @@ int64_t trace_items_of(const TraceView& v) {
     return v.n_items;
 }
 
-int launch_trace(const TraceView& v, int32_t chunk, hipStream_t stream, unsigned long long* counters) {
+int64_t trace_blocks_of(const TraceView& v) { return (v.n_items + kBlock - 1) / kBlock; }
+
+int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters) {
     if (v.n_items <= 0) return VAFR_OK;
-    if (chunk < kBlock || chunk % 64) return fail(VAFR_E_ARG, "chunk must be a multiple of 64 and >= %d", kBlock);
-    const int64_t blocks = (v.n_items + chunk - 1) / chunk;
+    const int64_t blocks = trace_blocks_of(v);
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
     if (counters)
-        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, chunk, counters);
+        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, counters);
     else
-        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, chunk, counters);
+        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int32_t chunk, hipStream_t stream, unsigned long long* counters) {
+                       hipStream_t stream, unsigned long long* counters) {
     if (blocks <= 0) return VAFR_OK;
     if (counters)
         hipLaunchKernelGGL(k_trace_batch<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, views_dev,
-                           block_end_dev, n_views, chunk, counters);
+                           block_end_dev, n_views, counters);
     else
         hipLaunchKernelGGL(k_trace_batch<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, views_dev,
-                           block_end_dev, n_views, chunk, counters);
+                           block_end_dev, n_views, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

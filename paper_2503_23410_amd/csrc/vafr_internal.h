@@ -160,12 +160,12 @@ struct TraceView {
 
 // Work items of a view (padded to whole tiles for full-resolution / LMFR).
 int64_t trace_items_of(const TraceView& v);
-// Items per workgroup of a launch of n items (tuned value or heuristic).
-int32_t trace_chunk(int64_t n_items);
+// Workgroups of one view's launch (one ray per thread).
+int64_t trace_blocks_of(const TraceView& v);
 // counters != nullptr selects the diagnostic work-counting pass.
-int launch_trace(const TraceView& v, int32_t chunk, hipStream_t stream, unsigned long long* counters = nullptr);
+int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters = nullptr);
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int32_t chunk, hipStream_t stream, unsigned long long* counters = nullptr);
+                       hipStream_t stream, unsigned long long* counters = nullptr);
 
 // ------------------------------------------------------- reconstruction
 struct ReconVafr {

@@ -31,7 +31,7 @@ EXPORTS = (
     "vafr_last_error", "vafr_abi_version", "vafr_lp_layout", "lmfr_lp_layout", "vafr_layout_dims",
     "vafr_layout_tables", "vafr_layout_destroy", "vafr_scene_create", "vafr_scene_get_info",
     "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
-    "lmfr_reconstruct", "full_shade", "vafr_count_work", "vafr_set_trace_chunk",
+    "lmfr_reconstruct", "full_shade", "vafr_count_work",
 )
 
 
@@ -109,7 +109,6 @@ def load():
         "full_shade": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_display), C.POINTER(vafr_shading), _P,
                                  _P, _P]),
         "vafr_count_work": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P]),
-        "vafr_set_trace_chunk": (C.c_int, [C.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -313,6 +312,3 @@ def vafr_count_work(scene, cam, gz, sh, layout, counters, stream=None):
     _check(load().vafr_count_work(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(counters),
                                   _stream(stream)))
 
-
-def vafr_set_trace_chunk(items_per_workgroup: int):
-    _check(load().vafr_set_trace_chunk(int(items_per_workgroup)))
