@@ -137,6 +137,7 @@ def main():
             ev[4].record(stream)
 
     # ------------------------------------------------------------ VaFR
+    # (a) plain per-view calls: shade + reconstruct per eye
     for f in range(warm):
         vafr_frame(f)
     torch.cuda.synchronize()
@@ -146,15 +147,46 @@ def main():
     for f in range(steps):
         vafr_frame(warm + f, evs[f])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    frame_ms, trace_ms, recon_ms = [], [], []
+    wall_plain = time.perf_counter() - t0
+    frame_ms_plain, trace_ms, recon_ms = [], [], []
     for ev in evs:
-        frame_ms.append(ev[0].elapsed_time(ev[4]))
+        frame_ms_plain.append(ev[0].elapsed_time(ev[4]))
         trace_ms += [ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3])]
         recon_ms += [ev[1].elapsed_time(ev[2]), ev[3].elapsed_time(ev[4])]
-    fps = steps / wall
-    log(f"VaFR: {fps:.1f} frames/s, frame p50 {percentile(frame_ms, 50):.3f} ms p99 {percentile(frame_ms, 99):.3f} ms;"
-        f" trace {np.mean(trace_ms):.3f} ms/eye, reconstruct {np.mean(recon_ms):.3f} ms/eye")
+    fps_plain = steps / wall_plain
+    log(f"VaFR per-view calls: {fps_plain:.1f} frames/s, frame p50 {percentile(frame_ms_plain, 50):.3f} ms "
+        f"p99 {percentile(frame_ms_plain, 99):.3f} ms; trace {np.mean(trace_ms):.3f} ms/eye, "
+        f"reconstruct {np.mean(recon_ms):.3f} ms/eye")
+
+    # (b) batched frame: both eyes in one traversal + one reconstruction
+    # launch, replayed from a hipGraph, launch shape autotuned
+    batch = V.Batch(2)
+
+    def bviews(f):
+        g = gazes[f]
+        return [V.view(V.VAFR_VIEW_VAFR, scene, cams[e], g, sh, layout=L, lp_rgba=lp[e], img_rgba=img[e])
+                for e in range(2)]
+
+    tuned = batch.autotune(bviews(0), reps=5, stream=stream)
+    for f in range(warm):
+        batch.run(bviews(f), stream)
+    torch.cuda.synchronize()
+    bev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for f in range(steps):
+        bev[f][0].record(stream)
+        batch.run(bviews(warm + f), stream)
+        bev[f][1].record(stream)
+    torch.cuda.synchronize()
+    wall_batch = time.perf_counter() - t0
+    frame_ms_batch = [ev[0].elapsed_time(ev[1]) for ev in bev]
+    fps_batch = steps / wall_batch
+    log(f"VaFR batched ({tuned}): {fps_batch:.1f} frames/s, frame p50 {percentile(frame_ms_batch, 50):.3f} ms "
+        f"p99 {percentile(frame_ms_batch, 99):.3f} ms")
+    if fps_batch >= fps_plain:
+        fps, wall, frame_ms, path = fps_batch, wall_batch, frame_ms_batch, "batched"
+    else:
+        fps, wall, frame_ms, path = fps_plain, wall_plain, frame_ms_plain, "per-view"
 
     # work counts of the traversal (one frame, both eyes, gaze of frame warm)
     counters = torch.zeros(4, device="cuda", dtype=torch.int64)
@@ -226,6 +258,10 @@ def main():
             "fullres_grays_per_s": round(2 * 2 * W * H * full_fps / 1e9, 3),
         })
 
+    # ------------------------------------------------------------ 16 views
+    if not args.no_compare:
+        out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
+
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -253,6 +289,12 @@ def main():
             "display": [W, H], "eyes": 2, "triangles": int(tris.shape[0]), "lp_texels_per_eye": int(L.n_texels),
             "scene": SCENE,
         },
+        "path": path,
+        "batch_shape": tuned,
+        "per_view_fps": round(fps_plain, 3),
+        "per_view_p99_frame_ms": round(percentile(frame_ms_plain, 99), 4),
+        "batched_fps": round(fps_batch, 3),
+        "batched_p99_frame_ms": round(percentile(frame_ms_batch, 99), 4),
         "p50_frame_ms": round(percentile(frame_ms, 50), 4),
         "p99_frame_ms": round(percentile(frame_ms, 99), 4),
         "trace_ms_per_eye": round(float(np.mean(trace_ms)), 4),
@@ -272,6 +314,46 @@ def main():
     }
     result.update(out)
     print(json.dumps(result), flush=True)
+
+
+def batch16(torch, V, I, scene, sh, steps):
+    """16 views of display sizes drawn from 720p..8K with independent gaze
+    on the shared 4.5M-triangle scene: one batched frame (one traversal + one
+    reconstruction launch, graph replay, autotuned) against 16 separate
+    shade + reconstruct call pairs."""
+    sizes, gazes = I.batch_views(16, seed=4)
+    cam = V.camera(I.terrain_camera())
+    views = []
+    for (W_, H_), g in zip(sizes, gazes):
+        Lv = V.Layout.vafr(V.display(W_, H_, I.FOV))
+        views.append((Lv, V.gaze(*g), torch.empty((Lv.n_texels, 4), device="cuda"),
+                      torch.empty((W_ * H_, 4), device="cuda")))
+    stream = torch.cuda.current_stream()
+    desc = [V.view(V.VAFR_VIEW_VAFR, scene, cam, g, sh, layout=Lv, lp_rgba=lpv, img_rgba=imv)
+            for Lv, g, lpv, imv in views]
+    b = V.Batch(16)
+    shape = b.autotune(desc, reps=3, stream=stream)
+
+    def plain():
+        for Lv, g, lpv, imv in views:
+            V.vafr_shade_lp(scene, cam, g, sh, Lv, lpv, None, stream)
+            V.vafr_reconstruct(Lv, g, lpv, imv, stream)
+
+    res = {}
+    for name, fn in (("plain", plain), ("batched", lambda: b.run(desc, stream))):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = steps / (time.perf_counter() - t0)
+    pixels = sum(w * h for w, h in sizes)
+    log(f"16 views ({pixels / 1e6:.1f} Mpix): batched {res['batched']:.1f} frames/s ({shape}), "
+        f"16 plain call pairs {res['plain']:.1f} frames/s")
+    b.close()
+    return {"views": 16, "display_mpix": round(pixels / 1e6, 2), "batched_fps": round(res["batched"], 3),
+            "plain_fps": round(res["plain"], 3), "speedup": round(res["batched"] / res["plain"], 3), "shape": shape}
 
 
 def cpu_baseline(verts, tris, gazes, I, n_frames=4):

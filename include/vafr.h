@@ -211,6 +211,67 @@ int lmfr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_de
 int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* display, const vafr_shading* shading,
                float* img_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
 
+/* ---------------------------------------------------------------- batches */
+
+#define VAFR_VIEW_VAFR 0
+#define VAFR_VIEW_LMFR 1
+#define VAFR_VIEW_FULL 2
+
+/* One view of a batched frame.  VAFR / LMFR views shade layout's LP buffer
+ * into lp_rgba_dev and, when img_rgba_dev is not NULL, inverse-map it onto
+ * the layout's display; FULL views ray-cast every pixel of `display` into
+ * img_rgba_dev.  Same buffer contracts as the per-view calls. */
+typedef struct {
+    int32_t kind;            /* VAFR_VIEW_* */
+    int32_t pad_;
+    vafr_scene scene;
+    vafr_layout layout;      /* VAFR / LMFR views; NULL for FULL */
+    vafr_display display;    /* FULL views only */
+    vafr_camera camera;
+    vafr_gaze gaze;
+    vafr_shading shading;
+    float* lp_rgba_dev;      /* VAFR / LMFR views */
+    int32_t* hit_id_dev;     /* nullable */
+    float* img_rgba_dev;     /* nullable for LP-only VAFR / LMFR views */
+} vafr_view;
+
+/* Launch shape of a batch: traversal workgroup size (64, 128 or 256 rays),
+ * reconstruction tile height (1, 2, 4 or 8 rows of 64 pixels) and whether
+ * frames are replayed from a hipGraph. */
+typedef struct {
+    int32_t trace_block;
+    int32_t recon_rows;
+    int32_t use_graph;
+} vafr_batch_config;
+
+typedef struct vafr_batch_s* vafr_batch;
+
+/* A batch runner for up to max_views views per frame (1..256).  It owns
+ * pinned host and device descriptor tables (a ring of 4 frames in flight).
+ * cfg may be NULL for the defaults {128, 4, 1}. */
+int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg, vafr_batch* out);
+
+/* One frame of n_views views on `stream`: ONE traversal launch covering the
+ * rays of every view (workgroups are assigned to views by a running count)
+ * and ONE reconstruction launch covering every display of the VaFR / LMFR
+ * views.  With use_graph the sequence (descriptor upload, two kernels) is a
+ * hipGraph built once per launch shape; later frames only update the node
+ * parameters and replay it.  Results are identical to the per-view calls.
+ * Blocks the host only when all 4 descriptor slots are still in flight. */
+int vafr_batch_run(vafr_batch batch, const vafr_view* views, int32_t n_views, hipStream_t stream);
+
+/* Times every traversal workgroup size and reconstruction tile height on
+ * these views (reps frames each, on `stream`) and keeps the fastest in the
+ * batch's configuration; the choice is also returned in *chosen (nullable). */
+int vafr_batch_autotune(vafr_batch batch, const vafr_view* views, int32_t n_views, int32_t reps, hipStream_t stream,
+                        vafr_batch_config* chosen);
+
+int vafr_batch_get_config(vafr_batch batch, vafr_batch_config* out);
+int vafr_batch_set_config(vafr_batch batch, const vafr_batch_config* cfg);
+
+/* Waits for the batch's frames in flight and frees it. */
+void vafr_batch_destroy(vafr_batch batch);
+
 /* ------------------------------------------------------------ diagnostics */
 
 /* Work counting for roofline reports: traces exactly the rays that

@@ -34,6 +34,7 @@ SOURCES = {
     "api.cpp": ["-x", "hip", "-ffp-contract=off"],
     "layout.cpp": ["-x", "hip", "-ffp-contract=off"],
     "bvh.cpp": ["-x", "hip", "-ffp-contract=off"],
+    "batch.cpp": ["-x", "hip", "-ffp-contract=off"],
     "trace.hip": ["-ffp-contract=off"],
     "reconstruct.hip": [],
 }

@@ -117,46 +117,106 @@ static double lmfr_log_extent(const vafr_layout_s* L, vafr_gaze g) {
     return std::log(best);
 }
 
-static int shade_lp_common(int want_kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze,
-                           const vafr_shading* sh, vafr_layout L, float* lp, int32_t* hit, hipStream_t stream,
-                           unsigned long long* counters = nullptr) {
-    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
-    if (L->kind != want_kind)
-        return fail(VAFR_E_ARG, want_kind == VAFR_LAYOUT_VAFR ? "vafr_shade_lp needs a VaFR layout"
-                                                              : "lmfr_shade_lp needs an LMFR layout");
+// kind: VAFR_LAYOUT_VAFR / VAFR_LAYOUT_LMFR (layout given) or -1 for the
+// full-resolution view of `disp`.
+int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                    vafr_layout L, const vafr_display* disp, float* out_rgba, int32_t* hit, TraceView* out) {
     if (int rc = check_camera(cam)) return rc;
     if (int rc = check_shading(sh)) return rc;
-    if (int rc = check_gaze(gaze)) return rc;
-    if (!lp && !counters) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
     TraceView v;
     std::memset(&v, 0, sizeof(v));
-    if (int rc = scene_into_view(scene, &v)) return rc;
-    const LayoutDev* ld;
-    if (int rc = layout_device(L, &ld)) return rc;
-    fill_view_common(v, cam, sh);
-    v.n_items = L->n_texels;
-    gaze_film(L, gaze, &v.gx, &v.gy);
-    v.px = L->px;
-    v.py = L->py;
-    v.width = L->disp.width;
-    v.height = L->disp.height;
-    if (want_kind == VAFR_LAYOUT_VAFR) {
-        v.mode = kModeVafr;
-        v.dxy = ld->dxy;
-        v.ord = ld->ord;
+    if (kind < 0) {
+        if (!disp) return fail(VAFR_E_ARG, "display is NULL");
+        if (disp->width <= 0 || disp->height <= 0 || disp->width > 65536 || disp->height > 65536)
+            return fail(VAFR_E_ARG, "display size out of range");
+        if (!(disp->fov_x_deg > 0.0 && disp->fov_x_deg < 180.0) || !(disp->fov_y_deg > 0.0 && disp->fov_y_deg < 180.0))
+            return fail(VAFR_E_ARG, "field of view must lie in (0, 180) degrees");
     } else {
-        v.mode = kModeLmfr;
-        v.lm_z = ld->lm_z;
-        v.lm_cs = ld->lm_cs;
-        v.lm_w = L->n_cols;
-        v.lm_h = L->max_rows;
-        v.lm_L = lmfr_log_extent(L, gaze);
-        if (!(v.lm_L > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+        if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+        if (L->kind != kind)
+            return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR ? "vafr_shade_lp needs a VaFR layout"
+                                                             : "lmfr_shade_lp needs an LMFR layout");
+        if (int rc = check_gaze(gaze)) return rc;
     }
-    v.out_rgba = reinterpret_cast<float4*>(lp);
+    if (int rc = scene_into_view(scene, &v)) return rc;
+    fill_view_common(v, cam, sh);
+    if (kind < 0) {
+        v.mode = kModeFull;
+        v.width = disp->width;
+        v.height = disp->height;
+        film_pitch(*disp, &v.px, &v.py);
+    } else {
+        const LayoutDev* ld;
+        if (int rc = layout_device(L, &ld)) return rc;
+        gaze_film(L, gaze, &v.gx, &v.gy);
+        v.px = L->px;
+        v.py = L->py;
+        v.width = L->disp.width;
+        v.height = L->disp.height;
+        if (kind == VAFR_LAYOUT_VAFR) {
+            v.mode = kModeVafr;
+            v.n_items = L->n_texels;
+            v.dxy = ld->dxy;
+            v.ord = ld->ord;
+        } else {
+            v.mode = kModeLmfr;
+            v.lm_z = ld->lm_z;
+            v.lm_cs = ld->lm_cs;
+            v.lm_w = L->n_cols;
+            v.lm_h = L->max_rows;
+            v.lm_L = lmfr_log_extent(L, gaze);
+            if (!(v.lm_L > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+        }
+    }
+    v.out_rgba = reinterpret_cast<float4*>(out_rgba);
     v.out_id = hit;
     v.n_items = trace_items_of(v);
-    return launch_trace(v, stream, counters);
+    *out = v;
+    return VAFR_OK;
+}
+
+int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, ReconView* out) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (int rc = check_gaze(gaze)) return rc;
+    if (!lp || !img) return fail(VAFR_E_ARG, "NULL buffer");
+    int dev;
+    if (int rc = current_device(&dev)) return rc;
+    ReconView r;
+    std::memset(&r, 0, sizeof(r));
+    r.width = L->disp.width;
+    r.height = L->disp.height;
+    r.n_cols = L->n_cols;
+    r.lp = reinterpret_cast<const float4*>(lp);
+    r.img = reinterpret_cast<float4*>(img);
+    if (L->n_texels * 16 >= ((int64_t)1 << 32))
+        return fail(VAFR_E_UNSUPPORTED, "LP buffers of 2^28 texels or more are not supported");
+    r.lp_bytes = (uint32_t)(L->n_texels * 16);
+    if (L->kind == VAFR_LAYOUT_VAFR) {
+        const LayoutDev* ld;
+        if (int rc = layout_device(L, &ld)) return rc;
+        double gx, gy;
+        gaze_film(L, gaze, &gx, &gy);
+        r.mode = kModeVafr;
+        r.sx = (float)L->px;
+        r.sy = (float)L->py;
+        r.cx = (float)((0.5 - 0.5 * L->disp.width) * L->px - gx);
+        r.cy = (float)((0.5 - 0.5 * L->disp.height) * L->py - gy);
+        r.rho_scale = (float)(kURhoN / L->rho_max);
+        r.u_of_rho = ld->u_of_rho;
+        r.col = ld->col;
+    } else {
+        const double Lg = lmfr_log_extent(L, gaze);
+        if (!(Lg > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+        r.mode = kModeLmfr;
+        r.lm_h = L->max_rows;
+        r.sx = r.sy = 1.0f;
+        r.cx = (float)(0.5 - gaze.x_px);
+        r.cy = (float)(0.5 - gaze.y_px);
+        r.inv_L = (float)(M_LN2 / Lg);
+        r.alpha = (float)L->alpha;
+    }
+    *out = r;
+    return VAFR_OK;
 }
 
 }  // namespace vafr
@@ -243,87 +303,43 @@ extern "C" void vafr_scene_destroy(vafr_scene s) {
 
 extern "C" int vafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
                              vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
-    return shade_lp_common(VAFR_LAYOUT_VAFR, scene, cam, gaze, sh, L, lp, hit, stream);
+    if (!lp) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
+    TraceView v;
+    if (int rc = make_trace_view(VAFR_LAYOUT_VAFR, scene, cam, gaze, sh, L, nullptr, lp, hit, &v)) return rc;
+    return launch_trace(v, stream);
 }
 
 extern "C" int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
                              vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
-    return shade_lp_common(VAFR_LAYOUT_LMFR, scene, cam, gaze, sh, L, lp, hit, stream);
+    if (!lp) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
+    TraceView v;
+    if (int rc = make_trace_view(VAFR_LAYOUT_LMFR, scene, cam, gaze, sh, L, nullptr, lp, hit, &v)) return rc;
+    return launch_trace(v, stream);
+}
+
+static int reconstruct_kind(int kind, vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (L->kind != kind)
+        return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR ? "vafr_reconstruct needs a VaFR layout"
+                                                         : "lmfr_reconstruct needs an LMFR layout");
+    ReconView r;
+    if (int rc = make_recon_view(L, gaze, lp, img, &r)) return rc;
+    return launch_reconstruct(r, stream);
 }
 
 extern "C" int vafr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
-    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
-    if (L->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_ARG, "vafr_reconstruct needs a VaFR layout");
-    if (int rc = check_gaze(gaze)) return rc;
-    if (!lp || !img) return fail(VAFR_E_ARG, "NULL buffer");
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
-    const LayoutDev* ld;
-    if (int rc = layout_device(L, &ld)) return rc;
-    ReconVafr r;
-    std::memset(&r, 0, sizeof(r));
-    r.n_cols = L->n_cols;
-    r.rho_scale = (float)(kURhoN / L->rho_max);
-    r.u_of_rho = ld->u_of_rho;
-    r.width = L->disp.width;
-    r.height = L->disp.height;
-    r.px = (float)L->px;
-    r.py = (float)L->py;
-    double gx, gy;
-    gaze_film(L, gaze, &gx, &gy);
-    r.gx = (float)gx;
-    r.gy = (float)gy;
-    r.col = ld->col;
-    r.lp = reinterpret_cast<const float4*>(lp);
-    r.img = reinterpret_cast<float4*>(img);
-    return launch_reconstruct_vafr(r, stream);
+    return reconstruct_kind(VAFR_LAYOUT_VAFR, L, gaze, lp, img, stream);
 }
 
 extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
-    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
-    if (L->kind != VAFR_LAYOUT_LMFR) return fail(VAFR_E_ARG, "lmfr_reconstruct needs an LMFR layout");
-    if (int rc = check_gaze(gaze)) return rc;
-    if (!lp || !img) return fail(VAFR_E_ARG, "NULL buffer");
-    int dev;
-    if (int rc = current_device(&dev)) return rc;
-    const double Lg = lmfr_log_extent(L, gaze);
-    if (!(Lg > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
-    ReconLmfr r;
-    std::memset(&r, 0, sizeof(r));
-    r.w = L->n_cols;
-    r.h = L->max_rows;
-    r.width = L->disp.width;
-    r.height = L->disp.height;
-    r.gx = (float)gaze.x_px;
-    r.gy = (float)gaze.y_px;
-    r.inv_L = (float)(M_LN2 / Lg);     // the kernel takes log2
-    r.alpha = (float)L->alpha;
-    r.lp = reinterpret_cast<const float4*>(lp);
-    r.img = reinterpret_cast<float4*>(img);
-    return launch_reconstruct_lmfr(r, stream);
+    return reconstruct_kind(VAFR_LAYOUT_LMFR, L, gaze, lp, img, stream);
 }
 
 extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* d, const vafr_shading* sh,
                           float* img, int32_t* hit, hipStream_t stream) {
-    if (!d) return fail(VAFR_E_ARG, "display is NULL");
-    if (d->width <= 0 || d->height <= 0 || d->width > 65536 || d->height > 65536)
-        return fail(VAFR_E_ARG, "display size out of range");
-    if (!(d->fov_x_deg > 0.0 && d->fov_x_deg < 180.0) || !(d->fov_y_deg > 0.0 && d->fov_y_deg < 180.0))
-        return fail(VAFR_E_ARG, "field of view must lie in (0, 180) degrees");
-    if (int rc = check_camera(cam)) return rc;
-    if (int rc = check_shading(sh)) return rc;
     if (!img) return fail(VAFR_E_ARG, "img_rgba_dev is NULL");
     TraceView v;
-    std::memset(&v, 0, sizeof(v));
-    if (int rc = scene_into_view(scene, &v)) return rc;
-    fill_view_common(v, cam, sh);
-    v.mode = kModeFull;
-    v.width = d->width;
-    v.height = d->height;
-    film_pitch(*d, &v.px, &v.py);
-    v.out_rgba = reinterpret_cast<float4*>(img);
-    v.out_id = hit;
-    v.n_items = trace_items_of(v);
+    if (int rc = make_trace_view(-1, scene, cam, vafr_gaze{0.0, 0.0}, sh, nullptr, d, img, hit, &v)) return rc;
     return launch_trace(v, stream);
 }
 
@@ -331,6 +347,7 @@ extern "C" int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_ga
                                vafr_layout L, unsigned long long* counters_dev, hipStream_t stream) {
     if (!L) return fail(VAFR_E_ARG, "layout is NULL");
     if (!counters_dev) return fail(VAFR_E_ARG, "counters_dev is NULL");
-    return shade_lp_common(L->kind, scene, cam, gaze, sh, L, nullptr, nullptr, stream, counters_dev);
+    TraceView v;
+    if (int rc = make_trace_view(L->kind, scene, cam, gaze, sh, L, nullptr, nullptr, nullptr, &v)) return rc;
+    return launch_trace(v, stream, counters_dev);
 }
-

@@ -1,0 +1,398 @@
+// Batched frames: every view's rays in ONE traversal launch, every display
+// in ONE reconstruction launch, optionally replayed from a hipGraph whose
+// node parameters are updated per frame, and an autotuner for the launch
+// shape.
+//
+// Per frame the host writes the view descriptors into one slot of a ring of
+// pinned staging buffers; the slot is copied to its device twin on the
+// stream ahead of the kernels, and an event marks when the slot may be
+// reused.  With four slots the host runs up to three frames ahead.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "vafr_internal.h"
+
+namespace vafr {
+namespace {
+
+constexpr int kSlots = 4;
+constexpr int kMaxBatchViews = 256;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+struct Slot {
+    char* host = nullptr;   // pinned staging
+    char* dev = nullptr;    // device twin
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+
+// A graph for one launch shape.
+struct GraphEntry {
+    int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t copy = nullptr, ktrace = nullptr, krecon = nullptr;
+};
+
+}  // namespace
+}  // namespace vafr
+
+struct vafr_batch_s {
+    int32_t max_views = 0;
+    vafr_batch_config cfg{vafr::kTraceBlockDefault, vafr::kReconRowsDefault, 1};
+    int device = -1;
+    size_t off_tb = 0, off_rv = 0, off_rb = 0, bytes = 0;
+    vafr::Slot slot[vafr::kSlots];
+    int next = 0;
+    std::vector<vafr::GraphEntry> graphs;
+    std::mutex mu;
+    // host-side descriptors of the frame being prepared
+    std::vector<vafr::TraceView> tv;
+    std::vector<vafr::ReconView> rv;
+    std::vector<int32_t> tb, rb;
+};
+
+namespace vafr {
+namespace {
+
+int check_config(const vafr_batch_config* c) {
+    if (!trace_block_ok(c->trace_block)) return fail(VAFR_E_ARG, "trace_block must be 64, 128 or 256");
+    if (!recon_rows_ok(c->recon_rows)) return fail(VAFR_E_ARG, "recon_rows must be 1, 2, 4 or 8");
+    if (c->use_graph != 0 && c->use_graph != 1) return fail(VAFR_E_ARG, "use_graph must be 0 or 1");
+    return VAFR_OK;
+}
+
+void free_graphs(vafr_batch b) {
+    for (auto& g : b->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    b->graphs.clear();
+}
+
+// Descriptors of one frame into b->tv/tb/rv/rb.
+int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blocks, int32_t* recon_blocks) {
+    b->tv.clear();
+    b->rv.clear();
+    b->tb.clear();
+    b->rb.clear();
+    int64_t tsum = 0, rsum = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const vafr_view& w = views[i];
+        TraceView t;
+        int rc;
+        if (w.kind == VAFR_VIEW_FULL) {
+            if (!w.img_rgba_dev) return fail(VAFR_E_ARG, "view %d: img_rgba_dev is NULL", i);
+            rc = make_trace_view(-1, w.scene, &w.camera, w.gaze, &w.shading, nullptr, &w.display, w.img_rgba_dev,
+                                 w.hit_id_dev, &t);
+        } else if (w.kind == VAFR_VIEW_VAFR || w.kind == VAFR_VIEW_LMFR) {
+            if (!w.lp_rgba_dev) return fail(VAFR_E_ARG, "view %d: lp_rgba_dev is NULL", i);
+            rc = make_trace_view(w.kind == VAFR_VIEW_VAFR ? VAFR_LAYOUT_VAFR : VAFR_LAYOUT_LMFR, w.scene, &w.camera,
+                                 w.gaze, &w.shading, w.layout, nullptr, w.lp_rgba_dev, w.hit_id_dev, &t);
+        } else {
+            return fail(VAFR_E_ARG, "view %d: unknown kind %d", i, w.kind);
+        }
+        if (rc) return rc;
+        tsum += (t.n_items + b->cfg.trace_block - 1) / b->cfg.trace_block;
+        if (tsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
+        b->tv.push_back(t);
+        b->tb.push_back((int32_t)tsum);
+        if (w.kind != VAFR_VIEW_FULL && w.img_rgba_dev) {
+            ReconView r;
+            if (int rc2 = make_recon_view(w.layout, w.gaze, w.lp_rgba_dev, w.img_rgba_dev, &r)) return rc2;
+            rsum += recon_blocks_of(r, b->cfg.recon_rows);
+            if (rsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many pixels in one batch");
+            b->rv.push_back(r);
+            b->rb.push_back((int32_t)rsum);
+        }
+    }
+    *trace_blocks = (int32_t)tsum;
+    *recon_blocks = (int32_t)rsum;
+    return VAFR_OK;
+}
+
+hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const TraceView** v,
+                                 const int32_t** be, int32_t* n, unsigned long long** cnt) {
+    *v = reinterpret_cast<const TraceView*>(dev);
+    *be = reinterpret_cast<const int32_t*>(dev + b->off_tb);
+    *n = g.n_trace;
+    *cnt = nullptr;
+    args[0] = v;
+    args[1] = be;
+    args[2] = n;
+    args[3] = cnt;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block));
+    p.gridDim = dim3((unsigned)g.trace_blocks);
+    p.blockDim = dim3((unsigned)g.trace_block);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return p;
+}
+
+hipKernelNodeParams recon_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const ReconView** v,
+                                 const int32_t** be, int32_t* n) {
+    *v = reinterpret_cast<const ReconView*>(dev + b->off_rv);
+    *be = reinterpret_cast<const int32_t*>(dev + b->off_rb);
+    *n = g.n_recon;
+    args[0] = v;
+    args[1] = be;
+    args[2] = n;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(recon_batch_kernel(g.recon_rows));
+    p.gridDim = dim3((unsigned)g.recon_blocks);
+    p.blockDim = dim3((unsigned)(64 * g.recon_rows));
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return p;
+}
+
+int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s, GraphEntry** out) {
+    const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
+    for (auto& g : b->graphs)
+        if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
+            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows) {
+            *out = &g;
+            return VAFR_OK;
+        }
+    if (b->graphs.size() >= 16) {   // bounded cache of launch shapes
+        for (auto& sl : b->slot)
+            if (sl.used) VAFR_HIP(hipEventSynchronize(sl.done));
+        free_graphs(b);
+    }
+    GraphEntry g;
+    g.n_trace = nt;
+    g.n_recon = nr;
+    g.trace_blocks = trace_blocks;
+    g.recon_blocks = recon_blocks;
+    g.trace_block = b->cfg.trace_block;
+    g.recon_rows = b->cfg.recon_rows;
+    VAFR_HIP(hipGraphCreate(&g.graph, 0));
+    hipError_t e = hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, s.dev, s.host, b->bytes,
+                                           hipMemcpyHostToDevice);
+    void* ta[4];
+    const TraceView* tvp;
+    const int32_t* tbe;
+    int32_t tn;
+    unsigned long long* tc;
+    if (e == hipSuccess && trace_blocks > 0) {
+        hipKernelNodeParams p = trace_params(b, g, s.dev, ta, &tvp, &tbe, &tn, &tc);
+        e = hipGraphAddKernelNode(&g.ktrace, g.graph, &g.copy, 1, &p);
+    }
+    void* ra[3];
+    const ReconView* rvp;
+    const int32_t* rbe;
+    int32_t rn;
+    if (e == hipSuccess && recon_blocks > 0) {
+        hipKernelNodeParams p = recon_params(b, g, s.dev, ra, &rvp, &rbe, &rn);
+        hipGraphNode_t dep = g.ktrace ? g.ktrace : g.copy;
+        e = hipGraphAddKernelNode(&g.krecon, g.graph, &dep, 1, &p);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+        return hip_fail(e, "building the frame graph");
+    }
+    b->graphs.push_back(g);
+    *out = &b->graphs.back();
+    return VAFR_OK;
+}
+
+// One frame with the batch's current configuration (caller holds b->mu).
+int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stream) {
+    if (!views || n < 1 || n > b->max_views) return fail(VAFR_E_ARG, "n_views must be in [1, %d]", b->max_views);
+    int dev = -1;
+    VAFR_HIP(hipGetDevice(&dev));
+    if (dev != b->device) return fail(VAFR_E_ARG, "batch was created on device %d, current is %d", b->device, dev);
+    int32_t tblocks = 0, rblocks = 0;
+    if (int rc = describe(b, views, n, &tblocks, &rblocks)) return rc;
+    Slot& s = b->slot[b->next];
+    b->next = (b->next + 1) % kSlots;
+    if (s.used) VAFR_HIP(hipEventSynchronize(s.done));
+    std::memcpy(s.host, b->tv.data(), sizeof(TraceView) * b->tv.size());
+    std::memcpy(s.host + b->off_tb, b->tb.data(), sizeof(int32_t) * b->tb.size());
+    if (!b->rv.empty()) {
+        std::memcpy(s.host + b->off_rv, b->rv.data(), sizeof(ReconView) * b->rv.size());
+        std::memcpy(s.host + b->off_rb, b->rb.data(), sizeof(int32_t) * b->rb.size());
+    }
+    if (b->cfg.use_graph) {
+        GraphEntry* g;
+        if (int rc = graph_for(b, tblocks, rblocks, s, &g)) return rc;
+        VAFR_HIP(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, s.dev, s.host, b->bytes, hipMemcpyHostToDevice));
+        void* ta[4];
+        const TraceView* tvp;
+        const int32_t* tbe;
+        int32_t tn;
+        unsigned long long* tc;
+        if (g->ktrace) {
+            hipKernelNodeParams p = trace_params(b, *g, s.dev, ta, &tvp, &tbe, &tn, &tc);
+            VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->ktrace, &p));
+        }
+        void* ra[3];
+        const ReconView* rvp;
+        const int32_t* rbe;
+        int32_t rn;
+        if (g->krecon) {
+            hipKernelNodeParams p = recon_params(b, *g, s.dev, ra, &rvp, &rbe, &rn);
+            VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->krecon, &p));
+        }
+        VAFR_HIP(hipGraphLaunch(g->exec, stream));
+    } else {
+        VAFR_HIP(hipMemcpyAsync(s.dev, s.host, b->bytes, hipMemcpyHostToDevice, stream));
+        if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
+                                        reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
+                                        tblocks, b->cfg.trace_block, stream))
+            return rc;
+        if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),
+                                              reinterpret_cast<const int32_t*>(s.dev + b->off_rb),
+                                              (int32_t)b->rv.size(), rblocks, b->cfg.recon_rows, stream))
+            return rc;
+    }
+    VAFR_HIP(hipEventRecord(s.done, stream));
+    s.used = true;
+    return VAFR_OK;
+}
+
+}  // namespace
+}  // namespace vafr
+
+using namespace vafr;
+
+extern "C" int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg, vafr_batch* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (max_views < 1 || max_views > kMaxBatchViews) return fail(VAFR_E_ARG, "max_views must be in [1, %d]", kMaxBatchViews);
+    if (cfg)
+        if (int rc = check_config(cfg)) return rc;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0) return fail(VAFR_E_HIP, "no HIP device available");
+    vafr_batch b = new (std::nothrow) vafr_batch_s;
+    if (!b) return fail(VAFR_E_OOM, "batch allocation failed");
+    if (cfg) b->cfg = *cfg;
+    b->max_views = max_views;
+    b->off_tb = align256(sizeof(TraceView) * max_views);
+    b->off_rv = b->off_tb + align256(sizeof(int32_t) * max_views);
+    b->off_rb = b->off_rv + align256(sizeof(ReconView) * max_views);
+    b->bytes = b->off_rb + align256(sizeof(int32_t) * max_views);
+    auto bail = [&](int code) {
+        vafr_batch_destroy(b);
+        return code;
+    };
+    if (hipGetDevice(&b->device) != hipSuccess) return bail(fail(VAFR_E_HIP, "hipGetDevice failed"));
+    for (auto& s : b->slot) {
+        if (hipHostMalloc(reinterpret_cast<void**>(&s.host), b->bytes, hipHostMallocDefault) != hipSuccess)
+            return bail(fail(VAFR_E_OOM, "pinned staging allocation failed"));
+        std::memset(s.host, 0, b->bytes);
+        if (hipMalloc(reinterpret_cast<void**>(&s.dev), b->bytes) != hipSuccess)
+            return bail(fail(VAFR_E_OOM, "device descriptor table allocation failed"));
+        if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(VAFR_E_HIP, "event creation failed"));
+    }
+    try {
+        b->tv.reserve(max_views);
+        b->rv.reserve(max_views);
+        b->tb.reserve(max_views);
+        b->rb.reserve(max_views);
+    } catch (const std::bad_alloc&) {
+        return bail(fail(VAFR_E_OOM, "batch allocation failed"));
+    }
+    *out = b;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_batch_run(vafr_batch b, const vafr_view* views, int32_t n_views, hipStream_t stream) {
+    if (!b) return fail(VAFR_E_ARG, "batch is NULL");
+    std::lock_guard<std::mutex> lock(b->mu);
+    return run_locked(b, views, n_views, stream);
+}
+
+extern "C" int vafr_batch_get_config(vafr_batch b, vafr_batch_config* out) {
+    if (!b || !out) return fail(VAFR_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(b->mu);
+    *out = b->cfg;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_batch_set_config(vafr_batch b, const vafr_batch_config* cfg) {
+    if (!b || !cfg) return fail(VAFR_E_ARG, "NULL argument");
+    if (int rc = check_config(cfg)) return rc;
+    std::lock_guard<std::mutex> lock(b->mu);
+    b->cfg = *cfg;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_batch_autotune(vafr_batch b, const vafr_view* views, int32_t n_views, int32_t reps,
+                                   hipStream_t stream, vafr_batch_config* chosen) {
+    if (!b) return fail(VAFR_E_ARG, "batch is NULL");
+    if (reps < 1 || reps > 1000) return fail(VAFR_E_ARG, "reps must be in [1, 1000]");
+    std::lock_guard<std::mutex> lock(b->mu);
+    hipEvent_t e0, e1;
+    VAFR_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(VAFR_E_HIP, "event creation failed");
+    }
+    const vafr_batch_config start = b->cfg;
+    auto time_cfg = [&](const vafr_batch_config& c, float* ms) -> int {
+        b->cfg = c;
+        if (int rc = run_locked(b, views, n_views, stream)) return rc;   // warm-up (and graph build)
+        VAFR_HIP(hipEventRecord(e0, stream));
+        for (int r = 0; r < reps; ++r)
+            if (int rc = run_locked(b, views, n_views, stream)) return rc;
+        VAFR_HIP(hipEventRecord(e1, stream));
+        VAFR_HIP(hipEventSynchronize(e1));
+        VAFR_HIP(hipEventElapsedTime(ms, e0, e1));
+        return VAFR_OK;
+    };
+    int rc = VAFR_OK;
+    vafr_batch_config best = start;
+    float best_ms = 1e30f;
+    // traversal workgroup size first (the reconstruction shape fixed), then
+    // the reconstruction tile height with the chosen traversal shape
+    for (int tbk : {64, 128, 256}) {
+        vafr_batch_config c = best;
+        c.trace_block = tbk;
+        float ms;
+        if ((rc = time_cfg(c, &ms))) break;
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    if (!rc) {
+        const vafr_batch_config base = best;
+        for (int rows : {1, 2, 4, 8}) {
+            vafr_batch_config c = base;
+            c.recon_rows = rows;
+            if (c.recon_rows == base.recon_rows) continue;
+            float ms;
+            if ((rc = time_cfg(c, &ms))) break;
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->cfg = rc ? start : best;
+    if (!rc && chosen) *chosen = best;
+    return rc;
+}
+
+extern "C" void vafr_batch_destroy(vafr_batch b) {
+    if (!b) return;
+    int cur = -1;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (b->device >= 0) (void)hipSetDevice(b->device);
+    for (auto& s : b->slot) {
+        if (s.done) {
+            if (s.used) (void)hipEventSynchronize(s.done);
+            (void)hipEventDestroy(s.done);
+        }
+        if (s.dev) (void)hipFree(s.dev);
+        if (s.host) (void)hipHostFree(s.host);
+    }
+    free_graphs(b);
+    if (have) (void)hipSetDevice(cur);
+    delete b;
+}

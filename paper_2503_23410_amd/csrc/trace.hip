@@ -10,7 +10,6 @@
 namespace vafr {
 namespace {
 
-constexpr int kBlock = 256;
 // Conservative slab test (Ize, "Robust BVH Ray Traversal", JCGT 2013): the
 // exit distance is scaled by 1 + 2 gamma_3 before the overlap test.
 constexpr float kExitScale = 1.0000004f;
@@ -114,8 +113,8 @@ struct WorkCount {
 };
 
 // Closest hit: smallest (t, triangle id); returns the stored slot or -1.
-// stk points at this lane's column of the block's LDS stack (stride kBlock).
-template <bool kCount>
+// stk points at this lane's column of the block's LDS stack (stride B).
+template <int B, bool kCount>
 __device__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
                            WorkCount& wc) {
     t_best = INFINITY;
@@ -136,7 +135,7 @@ __device__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float
             box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
             if (h0 && h1) {
                 const bool first0 = tn0 <= tn1;
-                stk[sp * kBlock] = first0 ? d.y : d.x;
+                stk[sp * B] = first0 ? d.y : d.x;
                 ++sp;
                 ref = first0 ? d.x : d.y;
                 continue;
@@ -163,13 +162,13 @@ __device__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float
         }
         if (sp == 0) break;
         --sp;
-        ref = stk[sp * kBlock];
+        ref = stk[sp * B];
     }
     return slot_best;
 }
 
 // Any hit with t > 0 (shadow ray toward a directional light).
-template <bool kCount>
+template <int B, bool kCount>
 __device__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
     int ref = sc.root;
     if (ref == kEmptyRef) return false;
@@ -185,7 +184,7 @@ __device__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCoun
             box2(r, a, b, c, INFINITY, h0, h1, tn0, tn1);
             if (h0 && h1) {
                 const bool first0 = tn0 <= tn1;
-                stk[sp * kBlock] = first0 ? d.y : d.x;
+                stk[sp * B] = first0 ? d.y : d.x;
                 ++sp;
                 ref = first0 ? d.x : d.y;
                 continue;
@@ -204,7 +203,7 @@ __device__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCoun
         }
         if (sp == 0) break;
         --sp;
-        ref = stk[sp * kBlock];
+        ref = stk[sp * B];
     }
     return false;
 }
@@ -323,13 +322,13 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
     return true;
 }
 
-template <bool kCount>
+template <int B, bool kCount>
 __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, int& id_out, WorkCount& wc,
                                 uint32_t& n_shadow) {
     const TraceView& sc = v;
     float t;
     int id;
-    const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
+    const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
     id_out = id;
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
     const float4* tp = sc.tris + 3 * (size_t)slot;
@@ -341,7 +340,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
         RayPre s;
         ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
         ++n_shadow;
-        if (any_hit<kCount>(sc, s, stk, wc)) vis = 0.0f;
+        if (any_hit<B, kCount>(sc, s, stk, wc)) vis = 0.0f;
     }
     const float lam = ndl > 0.0f ? ndl : 0.0f;
     const float3 a = albedo_of(id);
@@ -350,7 +349,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
                        a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
 }
 
-template <bool kCount>
+template <int B, bool kCount>
 __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
                              uint32_t& n_shadow) {
     const TraceView& sc = v;
@@ -360,7 +359,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
     for (int bnc = 0; bnc <= v.bounces; ++bnc) {
         float t;
         int id;
-        const int slot = closest_hit<kCount>(sc, r, stk, t, id, wc);
+        const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
         if (bnc == 0) id_out = id;
         if (slot < 0) {
             L.x += thr.x * v.background[0];
@@ -377,7 +376,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
             RayPre s;
             ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
             ++n_shadow;
-            vis = any_hit<kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
+            vis = any_hit<B, kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
         }
         const float3 a = albedo_of(id);
         thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
@@ -394,7 +393,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
 // One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
 // counts work into counters[0..3] = primary rays, shadow rays, node visits,
 // triangle tests, and writes no image.
-template <bool kCount>
+template <int B, bool kCount>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
@@ -405,9 +404,9 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     WorkCount wc;
     uint32_t n_shadow = 0;
     if (v.shade_mode == VAFR_SHADE_PATH)
-        c = shade_path<kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow);
+        c = shade_path<B, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow);
     else
-        c = shade_lambert<kCount>(v, r, stk, id, wc, n_shadow);
+        c = shade_lambert<B, kCount>(v, r, stk, id, wc, n_shadow);
     if (kCount) {
         atomicAdd(counters + 0, 1ull);
         atomicAdd(counters + 1, (unsigned long long)n_shadow);
@@ -419,25 +418,44 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_id) v.out_id[out] = id;
 }
 
-template <bool kCount>
-__global__ __launch_bounds__(kBlock) void k_trace(const TraceView v, unsigned long long* counters) {
-    __shared__ int stack[kMaxDepth * kBlock];
-    trace_item<kCount>(v, (int64_t)blockIdx.x * kBlock + threadIdx.x, stack, counters);
+template <int B, bool kCount>
+__global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
+    __shared__ int stack[kMaxDepth * B];
+    trace_item<B, kCount>(v, (int64_t)blockIdx.x * B + threadIdx.x, stack, counters);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
-// block_end[vid] (block_end is the running sum of per-view workgroups of
-// kBlock items each).
-template <bool kCount>
-__global__ __launch_bounds__(kBlock) void k_trace_batch(const TraceView* __restrict__ views,
-                                                        const int32_t* __restrict__ block_end, int32_t n_views,
-                                                        unsigned long long* counters) {
-    __shared__ int stack[kMaxDepth * kBlock];
+// block_end[vid] (block_end is the running sum of per-view workgroups of B
+// items each).
+template <int B, bool kCount>
+__global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__ views,
+                                                   const int32_t* __restrict__ block_end, int32_t n_views,
+                                                   unsigned long long* counters) {
+    __shared__ int stack[kMaxDepth * B];
     const int b = blockIdx.x;
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    trace_item<kCount>(views[vid], (int64_t)(b - first) * kBlock + threadIdx.x, stack, counters);
+    trace_item<B, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+}
+
+template <int B>
+void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsigned long long* counters) {
+    if (counters)
+        hipLaunchKernelGGL((k_trace<B, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+    else
+        hipLaunchKernelGGL((k_trace<B, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+}
+
+template <int B>
+void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks,
+                  hipStream_t stream, unsigned long long* counters) {
+    if (counters)
+        hipLaunchKernelGGL((k_trace_batch<B, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
+                           n_views, counters);
+    else
+        hipLaunchKernelGGL((k_trace_batch<B, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
+                           n_views, counters);
 }
 
 }  // namespace
@@ -448,29 +466,34 @@ int64_t trace_items_of(const TraceView& v) {
     return v.n_items;
 }
 
-int64_t trace_blocks_of(const TraceView& v) { return (v.n_items + kBlock - 1) / kBlock; }
+bool trace_block_ok(int block) { return block == 64 || block == 128 || block == 256; }
 
-int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters) {
+int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters, int block) {
     if (v.n_items <= 0) return VAFR_OK;
-    const int64_t blocks = trace_blocks_of(v);
+    if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
+    const int64_t blocks = (v.n_items + block - 1) / block;
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
-    if (counters)
-        hipLaunchKernelGGL(k_trace<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, counters);
-    else
-        hipLaunchKernelGGL(k_trace<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, v, counters);
+    if (block == 64) launch_single<64>(v, blocks, stream, counters);
+    else if (block == 128) launch_single<128>(v, blocks, stream, counters);
+    else launch_single<256>(v, blocks, stream, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }
 
+const void* trace_batch_kernel(int block) {
+    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, false>);
+    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, false>);
+    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, false>);
+    return nullptr;
+}
+
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       hipStream_t stream, unsigned long long* counters) {
+                       int block, hipStream_t stream, unsigned long long* counters) {
     if (blocks <= 0) return VAFR_OK;
-    if (counters)
-        hipLaunchKernelGGL(k_trace_batch<true>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, views_dev,
-                           block_end_dev, n_views, counters);
-    else
-        hipLaunchKernelGGL(k_trace_batch<false>, dim3((unsigned)blocks), dim3(kBlock), 0, stream, views_dev,
-                           block_end_dev, n_views, counters);
+    if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
+    if (block == 64) launch_batch<64>(views_dev, block_end_dev, n_views, blocks, stream, counters);
+    else if (block == 128) launch_batch<128>(views_dev, block_end_dev, n_views, blocks, stream, counters);
+    else launch_batch<256>(views_dev, block_end_dev, n_views, blocks, stream, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

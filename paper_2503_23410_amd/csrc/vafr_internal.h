@@ -160,38 +160,55 @@ struct TraceView {
 
 // Work items of a view (padded to whole tiles for full-resolution / LMFR).
 int64_t trace_items_of(const TraceView& v);
-// Workgroups of one view's launch (one ray per thread).
-int64_t trace_blocks_of(const TraceView& v);
+// Traversal workgroup sizes compiled in (one ray per thread).
+bool trace_block_ok(int block);
+constexpr int kTraceBlockDefault = 128;
 // counters != nullptr selects the diagnostic work-counting pass.
-int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters = nullptr);
+int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters = nullptr,
+                 int block = kTraceBlockDefault);
+// One launch over several views: workgroup b serves the view whose running
+// workgroup count block_end[] first exceeds b.
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       hipStream_t stream, unsigned long long* counters = nullptr);
+                       int block, hipStream_t stream, unsigned long long* counters = nullptr);
 
 // ------------------------------------------------------- reconstruction
-struct ReconVafr {
-    int32_t n_cols;
+// One view of the inverse map.  The offset of pixel (x, y)'s centre from the
+// gaze point is (x sx + cx, y sy + cy): film units for VaFR, pixels for LMFR.
+struct ReconView {
+    int32_t mode;       // kModeVafr or kModeLmfr
     int32_t width, height;
-    float px, py;       // pitch
-    float gx, gy;       // gaze on the film
+    int32_t n_cols;     // VaFR columns / LMFR buffer width
+    int32_t lm_h;       // LMFR buffer height
+    float sx, sy, cx, cy;
+    // VaFR
     float rho_scale;    // kURhoN / rho_max
     const float2* u_of_rho;
     const int2* col;    // (n_rows, col_off)
-    const float4* lp;
-    float4* img;
-};
-
-struct ReconLmfr {
-    int32_t w, h;
-    int32_t width, height;
-    float gx, gy;       // gaze in pixels
+    // LMFR
     float inv_L;        // ln 2 / L (the kernel uses log2)
     float alpha;
     const float4* lp;
+    uint32_t lp_bytes;  // < 2^32
     float4* img;
 };
 
-int launch_reconstruct_vafr(const ReconVafr& r, hipStream_t stream);
-int launch_reconstruct_lmfr(const ReconLmfr& r, hipStream_t stream);
+bool recon_rows_ok(int rows);
+constexpr int kReconRowsDefault = 4;
+int64_t recon_blocks_of(const ReconView& v, int rows);
+int launch_reconstruct(const ReconView& v, hipStream_t stream, int rows = kReconRowsDefault);
+int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_end_dev, int32_t n_views,
+                             int32_t blocks, int rows, hipStream_t stream);
+
+// Per-view descriptors from the public arguments (validated; uploads the
+// layout tables to the current device on first use).
+int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                    vafr_layout L, const vafr_display* disp, float* out_rgba, int32_t* hit, TraceView* v);
+int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, ReconView* r);
+
+// Kernel entry points of the batched launches (for graph nodes); their
+// parameters are (views, block_end, n_views[, counters]).
+const void* trace_batch_kernel(int block);
+const void* recon_batch_kernel(int rows);
 
 // common validation helpers
 int check_camera(const vafr_camera* c);

@@ -31,8 +31,13 @@ EXPORTS = (
     "vafr_last_error", "vafr_abi_version", "vafr_lp_layout", "lmfr_lp_layout", "vafr_layout_dims",
     "vafr_layout_tables", "vafr_layout_destroy", "vafr_scene_create", "vafr_scene_get_info",
     "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
-    "lmfr_reconstruct", "full_shade", "vafr_count_work",
+    "lmfr_reconstruct", "full_shade", "vafr_count_work", "vafr_batch_create", "vafr_batch_run",
+    "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
 )
+
+VAFR_VIEW_VAFR = 0
+VAFR_VIEW_LMFR = 1
+VAFR_VIEW_FULL = 2
 
 
 class VafrError(RuntimeError):
@@ -68,6 +73,16 @@ class vafr_shading(C.Structure):
 class vafr_dims(C.Structure):
     _fields_ = [("kind", C.c_int32), ("n_cols", C.c_int32), ("max_rows", C.c_int32), ("width", C.c_int32),
                 ("height", C.c_int32), ("n_texels", C.c_int64)]
+
+
+class vafr_view(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("scene", C.c_void_p), ("layout", C.c_void_p),
+                ("display", vafr_display), ("camera", vafr_camera), ("gaze", vafr_gaze), ("shading", vafr_shading),
+                ("lp_rgba_dev", C.c_void_p), ("hit_id_dev", C.c_void_p), ("img_rgba_dev", C.c_void_p)]
+
+
+class vafr_batch_config(C.Structure):
+    _fields_ = [("trace_block", C.c_int32), ("recon_rows", C.c_int32), ("use_graph", C.c_int32)]
 
 
 class vafr_scene_info(C.Structure):
@@ -109,6 +124,13 @@ def load():
         "full_shade": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_display), C.POINTER(vafr_shading), _P,
                                  _P, _P]),
         "vafr_count_work": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P]),
+        "vafr_batch_create": (C.c_int, [C.c_int32, C.POINTER(vafr_batch_config), C.POINTER(_P)]),
+        "vafr_batch_run": (C.c_int, [_P, C.POINTER(vafr_view), C.c_int32, _P]),
+        "vafr_batch_autotune": (C.c_int, [_P, C.POINTER(vafr_view), C.c_int32, C.c_int32, _P,
+                                          C.POINTER(vafr_batch_config)]),
+        "vafr_batch_get_config": (C.c_int, [_P, C.POINTER(vafr_batch_config)]),
+        "vafr_batch_set_config": (C.c_int, [_P, C.POINTER(vafr_batch_config)]),
+        "vafr_batch_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -312,3 +334,61 @@ def vafr_count_work(scene, cam, gz, sh, layout, counters, stream=None):
     _check(load().vafr_count_work(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(counters),
                                   _stream(stream)))
 
+
+
+def view(kind, scene, cam, gz, sh, layout=None, disp=None, lp_rgba=None, hit_id=None, img_rgba=None):
+    """A vafr_view; buffers are torch tensors (or None).  The returned
+    structure keeps raw pointers: keep the tensors alive while it is used."""
+    w = vafr_view()
+    w.kind = int(kind)
+    w.scene = scene.handle
+    w.layout = layout.handle if layout is not None else None
+    if disp is not None:
+        w.display = disp
+    w.camera = cam
+    w.gaze = gz
+    w.shading = sh
+    w.lp_rgba_dev = None if lp_rgba is None else lp_rgba.data_ptr()
+    w.hit_id_dev = None if hit_id is None else hit_id.data_ptr()
+    w.img_rgba_dev = None if img_rgba is None else img_rgba.data_ptr()
+    return w
+
+
+class Batch:
+    """Owns a vafr_batch (one traversal + one reconstruction launch per frame)."""
+
+    def __init__(self, max_views, trace_block=128, recon_rows=4, use_graph=True):
+        cfg = vafr_batch_config(int(trace_block), int(recon_rows), 1 if use_graph else 0)
+        h = C.c_void_p()
+        _check(load().vafr_batch_create(int(max_views), C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def run(self, views, stream=None):
+        arr = (vafr_view * len(views))(*views)
+        _check(load().vafr_batch_run(self._h, arr, len(views), _stream(stream)))
+
+    def autotune(self, views, reps=3, stream=None):
+        arr = (vafr_view * len(views))(*views)
+        c = vafr_batch_config()
+        _check(load().vafr_batch_autotune(self._h, arr, len(views), int(reps), _stream(stream), C.byref(c)))
+        return {"trace_block": c.trace_block, "recon_rows": c.recon_rows, "use_graph": c.use_graph}
+
+    def config(self):
+        c = vafr_batch_config()
+        _check(load().vafr_batch_get_config(self._h, C.byref(c)))
+        return {"trace_block": c.trace_block, "recon_rows": c.recon_rows, "use_graph": c.use_graph}
+
+    def set_config(self, trace_block, recon_rows, use_graph):
+        c = vafr_batch_config(int(trace_block), int(recon_rows), 1 if use_graph else 0)
+        _check(load().vafr_batch_set_config(self._h, C.byref(c)))
+
+    def close(self):
+        if self._h:
+            load().vafr_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,176 @@
+"""Batched frames (one traversal launch + one reconstruction launch over many
+views, optionally replayed from a hipGraph) must give exactly the results
+of the per-view calls, which the parity tests pin to the oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_23410_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_23410_amd import vafr as V
+    V.load()
+    return torch, V
+
+
+@pytest.fixture(scope="module")
+def scene(env):
+    torch, V = env
+    v, f = I.make_scene("terrain1m")
+    return V.Scene(v, f)
+
+
+def _views(torch, V, scene, sizes, gazes, cams, kinds):
+    """Buffers + per-view descriptors for a mixed batch."""
+    out = []
+    for (W, H), gz, cam, kind in zip(sizes, gazes, cams, kinds):
+        d = V.display(W, H, I.FOV)
+        if kind == V.VAFR_VIEW_FULL:
+            L = None
+            lp = None
+        else:
+            L = V.Layout.vafr(d) if kind == V.VAFR_VIEW_VAFR else V.Layout.lmfr(d, 1.8, 4.0)
+            lp = torch.full((L.n_texels, 4), -1.0, device="cuda")
+        n_hit = L.n_texels if L is not None else W * H
+        hit = torch.full((n_hit,), -7, device="cuda", dtype=torch.int32)
+        img = torch.full((W * H, 4), -1.0, device="cuda")
+        out.append(dict(kind=kind, disp=d, layout=L, lp=lp, hit=hit, img=img, gaze=V.gaze(*gz), cam=V.camera(cam)))
+    return out
+
+
+def _run_individual(V, scene, vs, sh):
+    for w in vs:
+        if w["kind"] == V.VAFR_VIEW_FULL:
+            V.full_shade(scene, w["cam"], w["disp"], sh, w["img"], w["hit"])
+        elif w["kind"] == V.VAFR_VIEW_VAFR:
+            V.vafr_shade_lp(scene, w["cam"], w["gaze"], sh, w["layout"], w["lp"], w["hit"])
+            V.vafr_reconstruct(w["layout"], w["gaze"], w["lp"], w["img"])
+        else:
+            V.lmfr_shade_lp(scene, w["cam"], w["gaze"], sh, w["layout"], w["lp"], w["hit"])
+            V.lmfr_reconstruct(w["layout"], w["gaze"], w["lp"], w["img"])
+
+
+def _descs(V, scene, vs, sh):
+    return [V.view(w["kind"], scene, w["cam"], w["gaze"], sh, layout=w["layout"], disp=w["disp"], lp_rgba=w["lp"],
+                   hit_id=w["hit"], img_rgba=w["img"]) for w in vs]
+
+
+def _snapshot(vs):
+    return [(None if w["lp"] is None else w["lp"].clone(), w["hit"].clone(), w["img"].clone()) for w in vs]
+
+
+def _clear(torch, vs):
+    for w in vs:
+        if w["lp"] is not None:
+            w["lp"].fill_(-1.0)
+        w["hit"].fill_(-7)
+        w["img"].fill_(-1.0)
+
+
+def _assert_equal(torch, ref, vs, what):
+    for i, (w, (lp, hit, img)) in enumerate(zip(vs, ref)):
+        if lp is not None:
+            assert torch.equal(w["lp"], lp), f"{what}: view {i} LP differs"
+        assert torch.equal(w["hit"], hit), f"{what}: view {i} hit ids differ"
+        assert torch.equal(w["img"], img), f"{what}: view {i} image differs"
+
+
+def test_batch_equals_individual_calls(env, scene):
+    """16 views of uneven size (sizes drawn from 720p..8K, gaze per view),
+    mostly VaFR plus one LMFR and one full-resolution view, eager and graph."""
+    torch, V = env
+    sizes, gazes = I.batch_views(16, seed=4)
+    kinds = [V.VAFR_VIEW_VAFR] * 16
+    kinds[5] = V.VAFR_VIEW_LMFR
+    kinds[11] = V.VAFR_VIEW_FULL
+    cams = [I.terrain_camera(0.01 * k) for k in range(16)]
+    vs = _views(torch, V, scene, sizes, gazes, cams, kinds)
+    sh = V.shading()
+    _run_individual(V, scene, vs, sh)
+    torch.cuda.synchronize()
+    ref = _snapshot(vs)
+    for use_graph in (False, True):
+        for tb, rows in ((128, 4), (64, 1), (256, 8)):
+            _clear(torch, vs)
+            b = V.Batch(16, trace_block=tb, recon_rows=rows, use_graph=use_graph)
+            b.run(_descs(V, scene, vs, sh))
+            torch.cuda.synchronize()
+            _assert_equal(torch, ref, vs, f"graph={use_graph} block={tb} rows={rows}")
+            b.close()
+    log("batch of 16 views equals the per-view calls (eager and graph)")
+
+
+def test_graph_replays_track_parameter_updates(env, scene):
+    """Replay the captured frame with new gazes and cameras each time, with
+    eager work between replays; every replay equals the eager result."""
+    torch, V = env
+    sizes = [(1920, 1080), (1280, 720), (1920, 1080)]
+    kinds = [V.VAFR_VIEW_VAFR, V.VAFR_VIEW_VAFR, V.VAFR_VIEW_LMFR]
+    trace = I.gaze_trace(12, 1920, 1080, seed=30)
+    b = V.Batch(4, use_graph=True)
+    sh = V.shading()
+    for f in range(5):
+        gz = [tuple(trace[2 * f]), tuple(trace[2 * f + 1] * 0.66), tuple(trace[2 * f + 2])]
+        cams = [I.terrain_camera(0.02 * f + 0.01 * k) for k in range(3)]
+        vs = _views(torch, V, scene, sizes, gz, cams, kinds)
+        _run_individual(V, scene, vs, sh)
+        torch.cuda.synchronize()
+        ref = _snapshot(vs)
+        _clear(torch, vs)
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()                       # unrelated eager work between replays
+        b.run(_descs(V, scene, vs, sh))
+        torch.cuda.synchronize()
+        _assert_equal(torch, ref, vs, f"replay {f}")
+    b.close()
+
+
+def test_autotune_picks_a_valid_shape(env, scene):
+    torch, V = env
+    sizes, gazes = I.batch_views(6, seed=8)
+    kinds = [V.VAFR_VIEW_VAFR] * 6
+    vs = _views(torch, V, scene, sizes, gazes, [I.terrain_camera()] * 6, kinds)
+    sh = V.shading()
+    _run_individual(V, scene, vs, sh)
+    torch.cuda.synchronize()
+    ref = _snapshot(vs)
+    b = V.Batch(8)
+    cfg = b.autotune(_descs(V, scene, vs, sh), reps=2)
+    log(f"autotuned shape: {cfg}")
+    assert cfg["trace_block"] in (64, 128, 256) and cfg["recon_rows"] in (1, 2, 4, 8)
+    assert b.config() == cfg
+    _clear(torch, vs)
+    b.run(_descs(V, scene, vs, sh))
+    torch.cuda.synchronize()
+    _assert_equal(torch, ref, vs, "after autotune")
+    b.close()
+
+
+def test_batch_rejects_bad_views(env, scene):
+    torch, V = env
+    b = V.Batch(2)
+    L = V.Layout.vafr(V.display(64, 64))
+    lp = torch.empty((L.n_texels, 4), device="cuda")
+    good = V.view(V.VAFR_VIEW_VAFR, scene, V.camera(I.terrain_camera()), V.gaze(1.0, 1.0), V.shading(), layout=L,
+                  lp_rgba=lp)
+    with pytest.raises(V.VafrError):
+        b.run([good, good, good])                       # more than max_views
+    bad = V.view(V.VAFR_VIEW_VAFR, scene, V.camera(I.terrain_camera()), V.gaze(1.0, 1.0), V.shading(), layout=L)
+    with pytest.raises(V.VafrError):
+        b.run([bad])                                    # no LP buffer
+    b.run([good])
+    torch.cuda.synchronize()
+    b.close()
