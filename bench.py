@@ -168,9 +168,11 @@ def main():
                 for e in range(2)]
 
     tuned = batch.autotune(bviews(0), reps=5, stream=stream)
+    batch.set_profiling(True)        # stage events inside the graph, read without host syncs
     for f in range(warm):
         batch.run(bviews(f), stream)
     torch.cuda.synchronize()
+    batch.set_profiling(True)        # reset the stage accumulators after warm-up
     bev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
     t0 = time.perf_counter()
     for f in range(steps):
@@ -180,9 +182,11 @@ def main():
     torch.cuda.synchronize()
     wall_batch = time.perf_counter() - t0
     frame_ms_batch = [ev[0].elapsed_time(ev[1]) for ev in bev]
+    (b_upload_ms, b_trace_ms, b_recon_ms), b_frames = batch.stage_ms()
     fps_batch = steps / wall_batch
     log(f"VaFR batched ({tuned}): {fps_batch:.1f} frames/s, frame p50 {percentile(frame_ms_batch, 50):.3f} ms "
-        f"p99 {percentile(frame_ms_batch, 99):.3f} ms")
+        f"p99 {percentile(frame_ms_batch, 99):.3f} ms; stages over {b_frames} frames: upload {b_upload_ms:.4f} ms, "
+        f"trace {b_trace_ms:.4f} ms, reconstruct {b_recon_ms:.4f} ms (both eyes)")
     if fps_batch >= fps_plain:
         fps, wall, frame_ms, path = fps_batch, wall_batch, frame_ms_batch, "batched"
     else:
@@ -194,12 +198,19 @@ def main():
         V.vafr_count_work(scene, cams[e], gazes[warm], sh, L, counters, stream)
     torch.cuda.synchronize()
     n_prim, n_shadow, n_nodes, n_tri = [int(x) for x in counters.cpu()]
-    ops_per_launch = (OPS_NODE * n_nodes + OPS_TRI * n_tri + OPS_RAY * (n_prim + n_shadow)) / 2.0
-    trace_s = float(np.mean(trace_ms)) / 1e3
+    ops_frame = OPS_NODE * n_nodes + OPS_TRI * n_tri + OPS_RAY * (n_prim + n_shadow)
+    recon_bytes_frame = 2 * (W * H * 16 + L.n_texels * 16)
+    if path == "batched":
+        # one traversal launch and one reconstruction launch per frame
+        k_trace, k_recon = "k_trace_batch", "k_recon_batch"
+        ops_per_launch, trace_s = ops_frame, b_trace_ms / 1e3
+        recon_bytes, recon_s = recon_bytes_frame, b_recon_ms / 1e3
+    else:
+        k_trace, k_recon = "k_trace", "k_recon"
+        ops_per_launch, trace_s = ops_frame / 2.0, float(np.mean(trace_ms)) / 1e3
+        recon_bytes, recon_s = recon_bytes_frame / 2.0, float(np.mean(recon_ms)) / 1e3
     achieved_gops = ops_per_launch / trace_s / 1e9
-    rays_per_s = (n_prim + n_shadow) / 2.0 / trace_s
-    recon_bytes = W * H * 16 + L.n_texels * 16
-    recon_s = float(np.mean(recon_ms)) / 1e3
+    rays_per_s = (n_prim + n_shadow) / (2.0 if path != "batched" else 1.0) / trace_s
     recon_gbs = recon_bytes / recon_s / 1e9
     log(f"work per eye: {n_prim // 2} primary + {n_shadow // 2} shadow rays, {n_nodes / (n_prim + n_shadow):.1f} "
         f"node visits and {n_tri / (n_prim + n_shadow):.2f} triangle tests per ray; "
@@ -268,7 +279,6 @@ def main():
         cpu = cpu_baseline(verts, tris, trace[warm:], I)
 
     del img, lp
-    traffic = load_traffic("k_trace")
     result = {
         "metric": "frames/s + p99 frame ms, binocular 7680x4320 VaFR vs full-res ray cast, 1 GPU",
         "value": round(fps, 3),
@@ -297,19 +307,23 @@ def main():
         "batched_p99_frame_ms": round(percentile(frame_ms_batch, 99), 4),
         "p50_frame_ms": round(percentile(frame_ms, 50), 4),
         "p99_frame_ms": round(percentile(frame_ms, 99), 4),
-        "trace_ms_per_eye": round(float(np.mean(trace_ms)), 4),
-        "reconstruct_ms_per_eye": round(float(np.mean(recon_ms)), 4),
+        "per_view_trace_ms_per_eye": round(float(np.mean(trace_ms)), 4),
+        "per_view_reconstruct_ms_per_eye": round(float(np.mean(recon_ms)), 4),
+        "batched_stage_ms": {"upload": round(b_upload_ms, 4), "trace": round(b_trace_ms, 4),
+                             "reconstruct": round(b_recon_ms, 4), "frames": b_frames},
         "grays_per_s": round(rays_per_s / 1e9, 3),
         "display_gpix_per_s": round(2 * W * H * fps / 1e9, 3),
         "work_per_ray": {"node_visits": round(n_nodes / (n_prim + n_shadow), 2),
                          "triangle_tests": round(n_tri / (n_prim + n_shadow), 2),
                          "shadow_fraction": round(n_shadow / max(n_prim, 1), 3)},
-        "roofline": {"kernel": "k_trace", "bound": "alu", "achieved": round(achieved_gops, 1),
+        "roofline": {"kernel": k_trace, "bound": "alu", "achieved": round(achieved_gops, 1),
                      "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
-                     "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": traffic},
-        "roofline_reconstruct": {"kernel": "k_recon_vafr", "bound": "hbm", "achieved": round(recon_gbs, 1),
+                     "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": load_traffic(k_trace),
+                     "launch_ms": round(trace_s * 1e3, 4), "ops_per_launch": int(ops_per_launch)},
+        "roofline_reconstruct": {"kernel": k_recon, "bound": "hbm", "achieved": round(recon_gbs, 1),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(recon_gbs / HBM_PEAK_GBS, 4),
-                                 "traffic": load_traffic("k_recon_vafr")},
+                                 "traffic": load_traffic(k_recon), "launch_ms": round(recon_s * 1e3, 4),
+                                 "bytes_per_launch": int(recon_bytes)},
         "cpu_baseline": cpu,
     }
     result.update(out)

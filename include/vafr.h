@@ -269,6 +269,16 @@ int vafr_batch_autotune(vafr_batch batch, const vafr_view* views, int32_t n_view
 int vafr_batch_get_config(vafr_batch batch, vafr_batch_config* out);
 int vafr_batch_set_config(vafr_batch batch, const vafr_batch_config* cfg);
 
+/* Stage timing: with profiling on, every frame records events around its
+ * descriptor upload, traversal launch and reconstruction launch (event-record
+ * nodes in graph mode); durations are read when a slot is reused, so timing
+ * adds no host synchronisation.  vafr_batch_stage_ms waits for the frames in
+ * flight and returns the mean (upload, traversal, reconstruction) durations
+ * in ms over all frames run since profiling was switched on (count in
+ * *frames, nullable).  vafr_batch_set_profiling resets the accumulators. */
+int vafr_batch_set_profiling(vafr_batch batch, int32_t on);
+int vafr_batch_stage_ms(vafr_batch batch, float* mean3, int64_t* frames);
+
 /* Waits for the batch's frames in flight and frees it. */
 void vafr_batch_destroy(vafr_batch batch);
 

@@ -27,6 +27,10 @@ struct Slot {
     char* dev = nullptr;    // device twin
     hipEvent_t done = nullptr;
     bool used = false;
+    // stage timing (when profiling): before upload, after upload, after
+    // traversal, after reconstruction
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool timed = false;
 };
 
 // A graph for one launch shape.
@@ -35,6 +39,8 @@ struct GraphEntry {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t copy = nullptr, ktrace = nullptr, krecon = nullptr;
+    bool timed = false;
+    hipGraphNode_t evn[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 }  // namespace
@@ -53,6 +59,9 @@ struct vafr_batch_s {
     std::vector<vafr::TraceView> tv;
     std::vector<vafr::ReconView> rv;
     std::vector<int32_t> tb, rb;
+    bool profiling = false;
+    double stage_sum[3] = {0, 0, 0};   // accumulated stage times (ms)
+    int64_t stage_frames = 0;
 };
 
 namespace vafr {
@@ -156,7 +165,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
     for (auto& g : b->graphs)
         if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
-            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows) {
+            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows && g.timed == b->profiling) {
             *out = &g;
             return VAFR_OK;
         }
@@ -172,9 +181,14 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     g.recon_blocks = recon_blocks;
     g.trace_block = b->cfg.trace_block;
     g.recon_rows = b->cfg.recon_rows;
+    g.timed = b->profiling;
     VAFR_HIP(hipGraphCreate(&g.graph, 0));
-    hipError_t e = hipGraphAddMemcpyNode1D(&g.copy, g.graph, nullptr, 0, s.dev, s.host, b->bytes,
-                                           hipMemcpyHostToDevice);
+    hipError_t e = hipSuccess;
+    if (g.timed) e = hipGraphAddEventRecordNode(&g.evn[0], g.graph, nullptr, 0, s.ev[0]);
+    if (e == hipSuccess)
+        e = hipGraphAddMemcpyNode1D(&g.copy, g.graph, g.evn[0] ? &g.evn[0] : nullptr, g.evn[0] ? 1 : 0, s.dev, s.host,
+                                    b->bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess && g.timed) e = hipGraphAddEventRecordNode(&g.evn[1], g.graph, &g.copy, 1, s.ev[1]);
     void* ta[4];
     const TraceView* tvp;
     const int32_t* tbe;
@@ -182,7 +196,12 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     unsigned long long* tc;
     if (e == hipSuccess && trace_blocks > 0) {
         hipKernelNodeParams p = trace_params(b, g, s.dev, ta, &tvp, &tbe, &tn, &tc);
-        e = hipGraphAddKernelNode(&g.ktrace, g.graph, &g.copy, 1, &p);
+        hipGraphNode_t dep = g.timed ? g.evn[1] : g.copy;
+        e = hipGraphAddKernelNode(&g.ktrace, g.graph, &dep, 1, &p);
+    }
+    if (e == hipSuccess && g.timed) {
+        hipGraphNode_t dep = g.ktrace ? g.ktrace : g.evn[1];
+        e = hipGraphAddEventRecordNode(&g.evn[2], g.graph, &dep, 1, s.ev[2]);
     }
     void* ra[3];
     const ReconView* rvp;
@@ -190,8 +209,12 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     int32_t rn;
     if (e == hipSuccess && recon_blocks > 0) {
         hipKernelNodeParams p = recon_params(b, g, s.dev, ra, &rvp, &rbe, &rn);
-        hipGraphNode_t dep = g.ktrace ? g.ktrace : g.copy;
+        hipGraphNode_t dep = g.timed ? g.evn[2] : (g.ktrace ? g.ktrace : g.copy);
         e = hipGraphAddKernelNode(&g.krecon, g.graph, &dep, 1, &p);
+    }
+    if (e == hipSuccess && g.timed) {
+        hipGraphNode_t dep = g.krecon ? g.krecon : g.evn[2];
+        e = hipGraphAddEventRecordNode(&g.evn[3], g.graph, &dep, 1, s.ev[3]);
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
     if (e != hipSuccess) {
@@ -200,6 +223,20 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     }
     b->graphs.push_back(g);
     *out = &b->graphs.back();
+    return VAFR_OK;
+}
+
+// Adds a finished timed frame's stage durations to the accumulators.
+int fold_slot(vafr_batch b, Slot& s) {
+    if (!s.used || !s.timed) return VAFR_OK;
+    VAFR_HIP(hipEventSynchronize(s.ev[3]));
+    for (int k = 0; k < 3; ++k) {
+        float ms = 0.0f;
+        VAFR_HIP(hipEventElapsedTime(&ms, s.ev[k], s.ev[k + 1]));
+        b->stage_sum[k] += ms;
+    }
+    ++b->stage_frames;
+    s.timed = false;
     return VAFR_OK;
 }
 
@@ -213,7 +250,10 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     if (int rc = describe(b, views, n, &tblocks, &rblocks)) return rc;
     Slot& s = b->slot[b->next];
     b->next = (b->next + 1) % kSlots;
-    if (s.used) VAFR_HIP(hipEventSynchronize(s.done));
+    if (s.used) {
+        VAFR_HIP(hipEventSynchronize(s.done));
+        if (int rc = fold_slot(b, s)) return rc;
+    }
     std::memcpy(s.host, b->tv.data(), sizeof(TraceView) * b->tv.size());
     std::memcpy(s.host + b->off_tb, b->tb.data(), sizeof(int32_t) * b->tb.size());
     if (!b->rv.empty()) {
@@ -224,6 +264,8 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         GraphEntry* g;
         if (int rc = graph_for(b, tblocks, rblocks, s, &g)) return rc;
         VAFR_HIP(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, s.dev, s.host, b->bytes, hipMemcpyHostToDevice));
+        if (g->timed)
+            for (int k = 0; k < 4; ++k) VAFR_HIP(hipGraphExecEventRecordNodeSetEvent(g->exec, g->evn[k], s.ev[k]));
         void* ta[4];
         const TraceView* tvp;
         const int32_t* tbe;
@@ -243,18 +285,23 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         }
         VAFR_HIP(hipGraphLaunch(g->exec, stream));
     } else {
+        if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[0], stream));
         VAFR_HIP(hipMemcpyAsync(s.dev, s.host, b->bytes, hipMemcpyHostToDevice, stream));
+        if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[1], stream));
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
                                         tblocks, b->cfg.trace_block, stream))
             return rc;
+        if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[2], stream));
         if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),
                                               reinterpret_cast<const int32_t*>(s.dev + b->off_rb),
                                               (int32_t)b->rv.size(), rblocks, b->cfg.recon_rows, stream))
             return rc;
+        if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[3], stream));
     }
     VAFR_HIP(hipEventRecord(s.done, stream));
     s.used = true;
+    s.timed = b->profiling;
     return VAFR_OK;
 }
 
@@ -292,6 +339,8 @@ extern "C" int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg
             return bail(fail(VAFR_E_OOM, "device descriptor table allocation failed"));
         if (hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
             return bail(fail(VAFR_E_HIP, "event creation failed"));
+        for (auto& ev : s.ev)
+            if (hipEventCreate(&ev) != hipSuccess) return bail(fail(VAFR_E_HIP, "event creation failed"));
     }
     try {
         b->tv.reserve(max_views);
@@ -379,6 +428,30 @@ extern "C" int vafr_batch_autotune(vafr_batch b, const vafr_view* views, int32_t
     return rc;
 }
 
+extern "C" int vafr_batch_set_profiling(vafr_batch b, int32_t on) {
+    if (!b) return fail(VAFR_E_ARG, "batch is NULL");
+    if (on != 0 && on != 1) return fail(VAFR_E_ARG, "on must be 0 or 1");
+    std::lock_guard<std::mutex> lock(b->mu);
+    for (auto& s : b->slot) {
+        if (s.used) VAFR_HIP(hipEventSynchronize(s.done));
+        s.timed = false;
+    }
+    b->profiling = on == 1;
+    b->stage_sum[0] = b->stage_sum[1] = b->stage_sum[2] = 0.0;
+    b->stage_frames = 0;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_batch_stage_ms(vafr_batch b, float* mean3, int64_t* frames) {
+    if (!b || !mean3) return fail(VAFR_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(b->mu);
+    for (auto& s : b->slot)
+        if (int rc = fold_slot(b, s)) return rc;
+    if (frames) *frames = b->stage_frames;
+    for (int k = 0; k < 3; ++k) mean3[k] = b->stage_frames ? (float)(b->stage_sum[k] / b->stage_frames) : 0.0f;
+    return VAFR_OK;
+}
+
 extern "C" void vafr_batch_destroy(vafr_batch b) {
     if (!b) return;
     int cur = -1;
@@ -389,6 +462,8 @@ extern "C" void vafr_batch_destroy(vafr_batch b) {
             if (s.used) (void)hipEventSynchronize(s.done);
             (void)hipEventDestroy(s.done);
         }
+        for (auto& ev : s.ev)
+            if (ev) (void)hipEventDestroy(ev);
         if (s.dev) (void)hipFree(s.dev);
         if (s.host) (void)hipHostFree(s.host);
     }

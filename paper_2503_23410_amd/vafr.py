@@ -33,6 +33,7 @@ EXPORTS = (
     "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
     "lmfr_reconstruct", "full_shade", "vafr_count_work", "vafr_batch_create", "vafr_batch_run",
     "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
+    "vafr_batch_set_profiling", "vafr_batch_stage_ms",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -131,6 +132,8 @@ def load():
         "vafr_batch_get_config": (C.c_int, [_P, C.POINTER(vafr_batch_config)]),
         "vafr_batch_set_config": (C.c_int, [_P, C.POINTER(vafr_batch_config)]),
         "vafr_batch_destroy": (None, [_P]),
+        "vafr_batch_set_profiling": (C.c_int, [_P, C.c_int32]),
+        "vafr_batch_stage_ms": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -381,6 +384,17 @@ class Batch:
     def set_config(self, trace_block, recon_rows, use_graph):
         c = vafr_batch_config(int(trace_block), int(recon_rows), 1 if use_graph else 0)
         _check(load().vafr_batch_set_config(self._h, C.byref(c)))
+
+    def set_profiling(self, on=True):
+        _check(load().vafr_batch_set_profiling(self._h, 1 if on else 0))
+
+    def stage_ms(self):
+        """Mean (upload, traversal, reconstruction) ms and the frame count
+        since profiling was switched on."""
+        a = (C.c_float * 3)()
+        n = C.c_int64()
+        _check(load().vafr_batch_stage_ms(self._h, a, C.byref(n)))
+        return tuple(a), n.value
 
     def close(self):
         if self._h:
