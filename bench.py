@@ -89,6 +89,8 @@ def main():
                     help="frames for the full-resolution and LMFR comparisons (default: steps/20, >= 3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true", help="skip full-resolution and LMFR runs")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of the served 8-headset workload per server configuration (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -273,6 +275,10 @@ def main():
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
 
+    # ------------------------------------------------------------ serving
+    if args.serve_seconds > 0:
+        out["serving"] = serving_bench(torch, V, I, scene, args.serve_seconds)
+
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
@@ -368,6 +374,52 @@ def batch16(torch, V, I, scene, sh, steps):
     b.close()
     return {"views": 16, "display_mpix": round(pixels / 1e6, 2), "batched_fps": round(res["batched"], 3),
             "plain_fps": round(res["plain"], 3), "speedup": round(res["batched"] / res["plain"], 3), "shape": shape}
+
+
+def serving_bench(torch, V, I, scene4m, seconds):
+    """8 headsets at 90 Hz with Poisson arrivals, binocular displays 2K x 3,
+    4K x 3, 8K x 2, even headsets on the 1.13M-triangle scene and odd ones on
+    the 4.52M-triangle scene, path-traced LP shading (1 sample, 2 bounces).
+    The continuous-batching server is compared with the same server limited
+    to one request per launch and one launch at a time (plain per-view
+    launches).  Latency = request submit -> both eyes' images ready."""
+    from paper_2503_23410_amd import serving
+    scene1m = V.Scene(*I.make_scene("terrain1m"))
+    sizes = [(2560, 1440)] * 3 + [(3840, 2160)] * 3 + [(7680, 4320)] * 2
+    layouts = {sz: V.Layout.vafr(V.display(sz[0], sz[1], I.FOV)) for sz in set(sizes)}
+    sh = V.shading(mode=V.VAFR_SHADE_PATH, bounces=2, seed=2025)
+    cl, cr = (V.camera(c) for c in I.binocular_cameras())
+    arrivals = serving.arrival_times(8, 90.0, seconds, seed_base=5)
+    gazes = [I.gaze_trace(int(seconds * 200) + 50, w, h, seed=40 + k) for k, (w, h) in enumerate(sizes)]
+    res = {"headsets": 8, "rate_hz": 90, "seconds": seconds, "requests": len(arrivals),
+           "displays": "2560x1440 x3, 3840x2160 x3, 7680x4320 x2 (binocular)", "shading": "path, 1 spp, 2 bounces"}
+    for name, kw in (("batched", dict(max_views_per_launch=16, max_inflight=4, n_streams=2)),
+                     ("plain", dict(max_views_per_launch=2, max_inflight=1, n_streams=1))):
+        srv = V.Server(max_queue=256, hbm_budget_bytes=64 << 30, **kw)
+        for k, sz in enumerate(sizes):
+            srv.add_headset(scene1m if k % 2 == 0 else scene4m, layouts[sz], cl, cr, sh)
+        # warm-up: one request per headset (buffers, graphs)
+        for k in range(8):
+            srv.submit(k, 10 ** 6 + k, V.gaze(sizes[k][0] / 2, sizes[k][1] / 2))
+        srv.wait_idle(120000)
+        for r in srv.poll():
+            if r["status"] == 0:
+                srv.release(r["slot"])
+        st0 = srv.stats()
+        recs, refused, wall = serving.run(srv, V, gazes, arrivals)
+        st = srv.stats()
+        lat = serving.latency_stats(recs)
+        launches = st["launches"] - st0["launches"]
+        entry = {"frames_per_s": round(lat["completed"] / wall, 2), "p50_ms": round(lat["p50_ms"], 3),
+                 "p99_ms": round(lat["p99_ms"], 3), "max_ms": round(lat["max_ms"], 3),
+                 "mean_queue_ms": round(lat["mean_queue_ms"], 3), "completed": lat["completed"],
+                 "refused": refused, "dropped": st["dropped"] - st0["dropped"],
+                 "deferred": st["deferred"] - st0["deferred"], "launches": launches,
+                 "requests_per_launch": round(lat["completed"] / max(launches, 1), 2)}
+        log(f"serving ({name}): {entry}")
+        res[name] = entry
+        srv.close()
+    return res
 
 
 def cpu_baseline(verts, tris, gazes, I, n_frames=4):

@@ -282,6 +282,85 @@ int vafr_batch_stage_ms(vafr_batch batch, float* mean3, int64_t* frames);
 /* Waits for the batch's frames in flight and frees it. */
 void vafr_batch_destroy(vafr_batch batch);
 
+/* ---------------------------------------------------------------- serving */
+
+typedef struct vafr_server_s* vafr_server;
+
+typedef struct {
+    int32_t max_views_per_launch;  /* views per batched launch (2 per request), 2..256 */
+    int32_t max_inflight;          /* launches on the device at once, 1..64 (<= 4 per stream avoids
+                                      host waits on descriptor slots) */
+    int32_t n_streams;             /* streams the launches are spread over, 1..8 */
+    int32_t max_queue;             /* waiting requests beyond which submissions are refused */
+    int64_t hbm_budget_bytes;      /* bound on per-request buffers (LP buffers + display images) */
+    vafr_batch_config batch;       /* launch shape of every batch */
+    int32_t simulate;              /* 1: no GPU; a launch of R Mrays (LP texels) and P Mpixels finishes
+                                      sim_ms_per_launch + R sim_ms_per_mray + P sim_ms_per_mpix after the
+                                      simulated device is free (capacity planning and policy tests) */
+    int32_t pad_;
+    double sim_ms_per_launch, sim_ms_per_mray, sim_ms_per_mpix;
+} vafr_server_config;
+
+/* A headset: resident scene and VaFR layout (display), one camera per eye
+ * and its shading (frame / view keys are set per request: frame from the
+ * request, view = 2 * headset + eye). */
+typedef struct {
+    vafr_scene scene;
+    vafr_layout layout;
+    vafr_camera camera[2];
+    vafr_shading shading;
+} vafr_headset;
+
+/* One binocular frame request: both eyes use the gaze display point. */
+typedef struct {
+    int32_t headset;
+    uint32_t frame;
+    vafr_gaze gaze;
+    double deadline_ms;            /* drop if not admitted within this time after submit; 0 = none */
+    uint64_t user_tag;
+} vafr_request;
+
+/* A finished request.  status VAFR_OK: the images (and LP buffers) of both
+ * eyes are ready at the device pointers, which stay valid until
+ * vafr_server_release(slot).  status VAFR_E_BUDGET: refused or dropped (no
+ * slot, nothing to release).  Times are ms on the server's clock. */
+typedef struct {
+    uint64_t user_tag;
+    int32_t headset;
+    uint32_t frame;
+    int32_t status;
+    int32_t slot;
+    double submit_ms, launch_ms, done_ms;
+    const float* img_rgba_dev[2];
+    const float* lp_rgba_dev[2];
+} vafr_result;
+
+typedef struct {
+    int64_t submitted, completed, refused, deferred, dropped, launches, views_launched, bytes_in_use;
+    int32_t waiting, inflight;
+} vafr_server_stats;
+
+/* Starts the dispatcher thread on the current device.  Requests are
+ * admitted in arrival order when a buffer set fits the budget (deferred
+ * otherwise); every free launch slot takes all admitted requests at the
+ * head of the queue (up to max_views_per_launch / 2) into one batched frame
+ * (vafr_batch_run) on the least busy stream, so requests that arrive while
+ * others run join the next launch.  Results equal those of the request
+ * rendered alone (kernels are per view and deterministic). */
+int vafr_server_create(const vafr_server_config* cfg, vafr_server* out);
+int vafr_server_add_headset(vafr_server server, const vafr_headset* headset, int32_t* id);
+/* Non-blocking; VAFR_E_BUDGET when the queue is full (counted as refused). */
+int vafr_server_submit(vafr_server server, const vafr_request* request);
+/* Up to max finished requests, oldest first; *n_out set to the count. */
+int vafr_server_poll(vafr_server server, vafr_result* out, int32_t max, int32_t* n_out);
+int vafr_server_release(vafr_server server, int32_t slot);
+/* Waits until nothing is queued or in flight (VAFR_E_BUDGET on timeout). */
+int vafr_server_wait_idle(vafr_server server, int32_t timeout_ms);
+int vafr_server_get_stats(vafr_server server, vafr_server_stats* out);
+/* Finishes in-flight work, drops requests that cannot be admitted, frees
+ * every buffer (results not yet released become invalid). */
+void vafr_server_destroy(vafr_server server);
+
 /* ------------------------------------------------------------ diagnostics */
 
 /* Work counting for roofline reports: traces exactly the rays that

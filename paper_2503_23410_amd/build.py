@@ -35,6 +35,7 @@ SOURCES = {
     "layout.cpp": ["-x", "hip", "-ffp-contract=off"],
     "bvh.cpp": ["-x", "hip", "-ffp-contract=off"],
     "batch.cpp": ["-x", "hip", "-ffp-contract=off"],
+    "server.cpp": ["-x", "hip", "-ffp-contract=off"],
     "trace.hip": ["-ffp-contract=off"],
     "reconstruct.hip": [],
 }

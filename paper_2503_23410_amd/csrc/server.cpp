@@ -1,0 +1,480 @@
+// Serving loop: per-headset frame requests carrying their gaze arrive at any
+// time; a dispatcher thread admits them against an HBM budget, batches every
+// admitted request into the next device launch as soon as a launch slot is
+// free (continuous batching: late requests join the next launch while
+// earlier launches still run), overlaps launches on several streams, and
+// reports completion with timestamps for latency statistics.
+//
+// Scenes, BVHs and layouts stay resident (the headsets reference them); the
+// per-request LP buffers and display images come from recycled buffer sets
+// whose total size is bounded by the budget.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "vafr_internal.h"
+
+namespace vafr {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct BufSet {
+    float* lp[2] = {nullptr, nullptr};
+    float* img[2] = {nullptr, nullptr};
+    size_t bytes = 0;
+    int64_t key = 0;   // (n_texels, pixels) class
+};
+
+struct Pending {
+    vafr_request req;
+    double submit_ms;
+    BufSet* bufs = nullptr;
+    bool deferred = false;
+};
+
+struct Launch {
+    std::vector<Pending> reqs;
+    hipEvent_t done = nullptr;
+    int stream = 0;
+    double launch_ms = 0;
+    double sim_done_ms = 0;   // simulated executor: completion time
+};
+
+}  // namespace
+}  // namespace vafr
+
+struct vafr_server_s {
+    vafr_server_config cfg{};
+    int device = -1;
+    std::chrono::steady_clock::time_point t0;
+    std::vector<vafr_headset> headsets;
+    std::vector<hipStream_t> streams;
+    std::vector<vafr_batch> batches;          // one per stream
+    std::vector<hipEvent_t> free_events;
+    // buffer pool
+    std::multimap<int64_t, vafr::BufSet*> free_sets;
+    std::vector<vafr::BufSet*> all_sets;
+    std::map<int32_t, vafr::BufSet*> leased;  // result slot -> buffers held by the caller
+    size_t bytes_in_use = 0;                  // allocated sets (free or not)
+    int32_t next_slot = 1;
+    // queues
+    std::deque<vafr::Pending> waiting;        // submitted, not yet launched
+    std::vector<vafr::Launch> inflight;
+    std::deque<vafr_result> done;
+    // stats
+    int64_t n_submitted = 0, n_completed = 0, n_refused = 0, n_deferred = 0, n_dropped = 0, n_launches = 0;
+    int64_t views_launched = 0;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool stop = false;
+    int error = VAFR_OK;
+    char error_msg[256] = "";
+    std::thread worker;
+    double sim_busy_until = 0;                // simulated executor: device timeline
+};
+
+namespace vafr {
+namespace {
+
+double now_ms(vafr_server s) { return std::chrono::duration<double, std::milli>(Clock::now() - s->t0).count(); }
+
+size_t set_bytes(const vafr_headset& h) {
+    const vafr_layout L = h.layout;
+    return 2 * (size_t)L->n_texels * 16 + 2 * (size_t)L->disp.width * L->disp.height * 16;
+}
+
+int64_t set_key(const vafr_headset& h) {
+    return h.layout->n_texels * ((int64_t)1 << 32) + (int64_t)h.layout->disp.width * h.layout->disp.height;
+}
+
+void free_set(BufSet* b) {
+    for (int e = 0; e < 2; ++e) {
+        (void)hipFree(b->lp[e]);
+        (void)hipFree(b->img[e]);
+    }
+    delete b;
+}
+
+// A buffer set for headset h within the budget, or nullptr (caller holds mu).
+BufSet* acquire_set(vafr_server s, const vafr_headset& h) {
+    const int64_t key = set_key(h);
+    auto it = s->free_sets.find(key);
+    if (it != s->free_sets.end()) {
+        BufSet* b = it->second;
+        s->free_sets.erase(it);
+        return b;
+    }
+    const size_t need = set_bytes(h);
+    // evict free sets of other shapes while that makes room
+    while (s->bytes_in_use + need > (size_t)s->cfg.hbm_budget_bytes && !s->free_sets.empty()) {
+        auto victim = s->free_sets.begin();
+        BufSet* v = victim->second;
+        s->free_sets.erase(victim);
+        s->bytes_in_use -= v->bytes;
+        s->all_sets.erase(std::find(s->all_sets.begin(), s->all_sets.end(), v));
+        if (s->cfg.simulate) delete v;
+        else free_set(v);
+    }
+    if (s->bytes_in_use + need > (size_t)s->cfg.hbm_budget_bytes) return nullptr;
+    BufSet* b = new (std::nothrow) BufSet;
+    if (!b) return nullptr;
+    b->bytes = need;
+    b->key = key;
+    bool ok = true;
+    for (int e = 0; e < 2 && ok && !s->cfg.simulate; ++e) {
+        ok = hipMalloc(&b->lp[e], (size_t)h.layout->n_texels * 16) == hipSuccess &&
+             hipMalloc(&b->img[e], (size_t)h.layout->disp.width * h.layout->disp.height * 16) == hipSuccess;
+    }
+    if (!ok) {
+        free_set(b);
+        return nullptr;
+    }
+    s->bytes_in_use += need;
+    s->all_sets.push_back(b);
+    return b;
+}
+
+void release_set(vafr_server s, BufSet* b) { s->free_sets.emplace(b->key, b); }
+
+void set_error(vafr_server s, int code, const char* msg) {
+    if (s->error == VAFR_OK) {
+        s->error = code;
+        std::snprintf(s->error_msg, sizeof(s->error_msg), "%s", msg);
+    }
+}
+
+// Launch one batched frame of the admitted requests at the queue head on
+// stream k (caller holds mu).
+void launch(vafr_server s, int k) {
+    Launch L;
+    L.stream = k;
+    const int max_req = std::max(1, s->cfg.max_views_per_launch / 2);
+    while (!s->waiting.empty() && (int)L.reqs.size() < max_req) {
+        Pending& p = s->waiting.front();
+        if (!p.bufs) break;                         // head not admitted yet: keep order
+        L.reqs.push_back(p);
+        s->waiting.pop_front();
+    }
+    if (L.reqs.empty()) return;
+    std::vector<vafr_view> views;
+    views.reserve(2 * L.reqs.size());
+    for (const Pending& p : L.reqs) {
+        const vafr_headset& h = s->headsets[p.req.headset];
+        for (int e = 0; e < 2; ++e) {
+            vafr_view v;
+            std::memset(&v, 0, sizeof(v));
+            v.kind = VAFR_VIEW_VAFR;
+            v.scene = h.scene;
+            v.layout = h.layout;
+            v.camera = h.camera[e];
+            v.gaze = p.req.gaze;
+            v.shading = h.shading;
+            v.shading.frame = p.req.frame;
+            v.shading.view = (uint32_t)(2 * p.req.headset + e);
+            v.lp_rgba_dev = p.bufs->lp[e];
+            v.img_rgba_dev = p.bufs->img[e];
+            views.push_back(v);
+        }
+    }
+    L.launch_ms = now_ms(s);
+    if (s->cfg.simulate) {
+        // cost model: fixed launch cost + rays (LP texels) + display pixels
+        double mray = 0, mpix = 0;
+        for (const Pending& p : L.reqs) {
+            const vafr_layout lay = s->headsets[p.req.headset].layout;
+            mray += 2e-6 * (double)lay->n_texels;
+            mpix += 2e-6 * (double)lay->disp.width * lay->disp.height;
+        }
+        const double start = std::max(L.launch_ms, s->sim_busy_until);
+        L.sim_done_ms = start + s->cfg.sim_ms_per_launch + s->cfg.sim_ms_per_mray * mray + s->cfg.sim_ms_per_mpix * mpix;
+        s->sim_busy_until = L.sim_done_ms;
+        ++s->n_launches;
+        s->views_launched += (int64_t)views.size();
+        s->inflight.push_back(std::move(L));
+        return;
+    }
+    int rc = vafr_batch_run(s->batches[k], views.data(), (int32_t)views.size(), s->streams[k]);
+    if (rc == VAFR_OK) {
+        L.done = s->free_events.back();
+        s->free_events.pop_back();
+        if (hipEventRecord(L.done, s->streams[k]) != hipSuccess) rc = VAFR_E_HIP;
+    }
+    if (rc != VAFR_OK) {
+        set_error(s, rc, vafr_last_error());
+        for (Pending& p : L.reqs) {
+            vafr_result r;
+            std::memset(&r, 0, sizeof(r));
+            r.user_tag = p.req.user_tag;
+            r.headset = p.req.headset;
+            r.frame = p.req.frame;
+            r.status = rc;
+            r.submit_ms = p.submit_ms;
+            r.launch_ms = r.done_ms = L.launch_ms;
+            release_set(s, p.bufs);
+            s->done.push_back(r);
+        }
+        if (L.done) s->free_events.push_back(L.done);
+        return;
+    }
+    ++s->n_launches;
+    s->views_launched += (int64_t)views.size();
+    s->inflight.push_back(std::move(L));
+}
+
+void worker_main(vafr_server s) {
+    if (!s->cfg.simulate) (void)hipSetDevice(s->device);
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+        // completions
+        for (size_t i = 0; i < s->inflight.size();) {
+            Launch& L = s->inflight[i];
+            const hipError_t q = s->cfg.simulate ? (now_ms(s) >= L.sim_done_ms ? hipSuccess : hipErrorNotReady)
+                                                 : hipEventQuery(L.done);
+            if (q == hipErrorNotReady) { ++i; continue; }
+            const double t = now_ms(s);
+            for (Pending& p : L.reqs) {
+                vafr_result r;
+                std::memset(&r, 0, sizeof(r));
+                r.user_tag = p.req.user_tag;
+                r.headset = p.req.headset;
+                r.frame = p.req.frame;
+                r.status = q == hipSuccess ? VAFR_OK : VAFR_E_HIP;
+                r.submit_ms = p.submit_ms;
+                r.launch_ms = L.launch_ms;
+                r.done_ms = t;
+                r.slot = s->next_slot++;
+                for (int e = 0; e < 2; ++e) {
+                    r.img_rgba_dev[e] = p.bufs->img[e];
+                    r.lp_rgba_dev[e] = p.bufs->lp[e];
+                }
+                s->leased[r.slot] = p.bufs;
+                s->done.push_back(r);
+                ++s->n_completed;
+            }
+            if (q != hipSuccess) set_error(s, VAFR_E_HIP, "a launched frame failed");
+            if (L.done) s->free_events.push_back(L.done);
+            s->inflight.erase(s->inflight.begin() + i);
+            s->cv.notify_all();
+        }
+        // admission: give buffers to waiting requests in arrival order;
+        // drop requests whose deadline already passed
+        const double t = now_ms(s);
+        for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+            if (it->req.deadline_ms > 0.0 && t - it->submit_ms > it->req.deadline_ms && !it->bufs) {
+                vafr_result r;
+                std::memset(&r, 0, sizeof(r));
+                r.user_tag = it->req.user_tag;
+                r.headset = it->req.headset;
+                r.frame = it->req.frame;
+                r.status = VAFR_E_BUDGET;
+                r.submit_ms = it->submit_ms;
+                r.launch_ms = r.done_ms = t;
+                s->done.push_back(r);
+                ++s->n_dropped;
+                it = s->waiting.erase(it);
+                s->cv.notify_all();
+                continue;
+            }
+            if (!it->bufs) {
+                it->bufs = acquire_set(s, s->headsets[it->req.headset]);
+                if (!it->bufs) {                              // wait for memory, keep order
+                    if (s->stop) {                            // draining: no memory will come back
+                        vafr_result r;
+                        std::memset(&r, 0, sizeof(r));
+                        r.user_tag = it->req.user_tag;
+                        r.headset = it->req.headset;
+                        r.frame = it->req.frame;
+                        r.status = VAFR_E_BUDGET;
+                        r.submit_ms = it->submit_ms;
+                        r.launch_ms = r.done_ms = t;
+                        s->done.push_back(r);
+                        ++s->n_dropped;
+                        it = s->waiting.erase(it);
+                        continue;
+                    }
+                    if (!it->deferred) { it->deferred = true; ++s->n_deferred; }
+                    break;
+                }
+            }
+            ++it;
+        }
+        // continuous batching: every free launch slot takes what is ready
+        while ((int)s->inflight.size() < s->cfg.max_inflight && !s->waiting.empty() && s->waiting.front().bufs) {
+            std::vector<int> busy(std::max<size_t>(1, s->streams.size()), 0);
+            for (auto& L : s->inflight) busy[L.stream]++;
+            const int k = (int)(std::min_element(busy.begin(), busy.end()) - busy.begin());
+            launch(s, k);
+        }
+        if (s->stop && s->waiting.empty() && s->inflight.empty()) break;
+        if (s->inflight.empty() && (s->waiting.empty() || !s->waiting.front().bufs) && !s->stop) {
+            s->cv.wait_for(lock, std::chrono::milliseconds(2));
+        } else {
+            lock.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(50));
+            lock.lock();
+        }
+    }
+}
+
+}  // namespace
+}  // namespace vafr
+
+using namespace vafr;
+
+extern "C" int vafr_server_create(const vafr_server_config* cfg, vafr_server* out) {
+    if (!out || !cfg) return fail(VAFR_E_ARG, "NULL argument");
+    *out = nullptr;
+    if (cfg->max_views_per_launch < 2 || cfg->max_views_per_launch > 256)
+        return fail(VAFR_E_ARG, "max_views_per_launch must be in [2, 256]");
+    if (cfg->max_inflight < 1 || cfg->max_inflight > 64) return fail(VAFR_E_ARG, "max_inflight must be in [1, 64]");
+    if (cfg->n_streams < 1 || cfg->n_streams > 8) return fail(VAFR_E_ARG, "n_streams must be in [1, 8]");
+    if (cfg->hbm_budget_bytes <= 0) return fail(VAFR_E_ARG, "hbm_budget_bytes must be positive");
+    if (cfg->max_queue < 1) return fail(VAFR_E_ARG, "max_queue must be positive");
+    if (cfg->simulate != 0 && cfg->simulate != 1) return fail(VAFR_E_ARG, "simulate must be 0 or 1");
+    if (cfg->simulate && (!(cfg->sim_ms_per_launch >= 0) || !(cfg->sim_ms_per_mray >= 0) || !(cfg->sim_ms_per_mpix >= 0)))
+        return fail(VAFR_E_ARG, "simulated costs must be >= 0");
+    int n_dev = 0;
+    if (!cfg->simulate && (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0))
+        return fail(VAFR_E_HIP, "no HIP device available");
+    vafr_server s = new (std::nothrow) vafr_server_s;
+    if (!s) return fail(VAFR_E_OOM, "server allocation failed");
+    s->cfg = *cfg;
+    s->t0 = Clock::now();
+    auto bail = [&](int code) {
+        vafr_server_destroy(s);
+        return code;
+    };
+    if (!cfg->simulate && hipGetDevice(&s->device) != hipSuccess) return bail(fail(VAFR_E_HIP, "hipGetDevice failed"));
+    for (int k = 0; k < cfg->n_streams && !cfg->simulate; ++k) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(VAFR_E_HIP, "stream creation failed"));
+        s->streams.push_back(st);
+        vafr_batch b;
+        if (int rc = vafr_batch_create(cfg->max_views_per_launch, &cfg->batch, &b)) return bail(rc);
+        s->batches.push_back(b);
+    }
+    for (int k = 0; k < cfg->max_inflight + 1 && !cfg->simulate; ++k) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(VAFR_E_HIP, "event creation failed"));
+        s->free_events.push_back(e);
+    }
+    s->worker = std::thread(worker_main, s);
+    *out = s;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_server_add_headset(vafr_server s, const vafr_headset* h, int32_t* id) {
+    if (!s || !h || !id) return fail(VAFR_E_ARG, "NULL argument");
+    if (!h->layout || (!h->scene && !s->cfg.simulate)) return fail(VAFR_E_ARG, "headset needs a scene and a layout");
+    if (h->layout->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_ARG, "headset layouts must be VaFR layouts");
+    for (int e = 0; e < 2; ++e)
+        if (int rc = check_camera(&h->camera[e])) return rc;
+    if (int rc = check_shading(&h->shading)) return rc;
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (set_bytes(*h) > (size_t)s->cfg.hbm_budget_bytes)
+        return fail(VAFR_E_BUDGET, "one frame of this headset does not fit the HBM budget");
+    s->headsets.push_back(*h);
+    *id = (int32_t)s->headsets.size() - 1;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_server_submit(vafr_server s, const vafr_request* r) {
+    if (!s || !r) return fail(VAFR_E_ARG, "NULL argument");
+    if (int rc = check_gaze(r->gaze)) return rc;
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stop) return fail(VAFR_E_ARG, "server is draining");
+    if (r->headset < 0 || r->headset >= (int32_t)s->headsets.size()) return fail(VAFR_E_ARG, "unknown headset");
+    ++s->n_submitted;
+    if ((int64_t)s->waiting.size() >= s->cfg.max_queue) {
+        ++s->n_refused;
+        return fail(VAFR_E_BUDGET, "request queue is full (%d waiting)", (int)s->waiting.size());
+    }
+    Pending p;
+    p.req = *r;
+    p.submit_ms = now_ms(s);
+    s->waiting.push_back(p);
+    s->cv.notify_all();
+    return VAFR_OK;
+}
+
+extern "C" int vafr_server_poll(vafr_server s, vafr_result* out, int32_t max, int32_t* n_out) {
+    if (!s || !n_out || (max > 0 && !out)) return fail(VAFR_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(s->mu);
+    int32_t n = 0;
+    while (n < max && !s->done.empty()) {
+        out[n++] = s->done.front();
+        s->done.pop_front();
+    }
+    *n_out = n;
+    if (s->error != VAFR_OK) return fail(s->error, "%s", s->error_msg);
+    return VAFR_OK;
+}
+
+extern "C" int vafr_server_release(vafr_server s, int32_t slot) {
+    if (!s) return fail(VAFR_E_ARG, "server is NULL");
+    std::lock_guard<std::mutex> lock(s->mu);
+    auto it = s->leased.find(slot);
+    if (it == s->leased.end()) return fail(VAFR_E_ARG, "unknown result slot %d", slot);
+    release_set(s, it->second);
+    s->leased.erase(it);
+    s->cv.notify_all();
+    return VAFR_OK;
+}
+
+extern "C" int vafr_server_wait_idle(vafr_server s, int32_t timeout_ms) {
+    if (!s) return fail(VAFR_E_ARG, "server is NULL");
+    std::unique_lock<std::mutex> lock(s->mu);
+    const bool idle = s->cv.wait_for(lock, std::chrono::milliseconds(timeout_ms < 0 ? 0 : timeout_ms),
+                                     [&] { return s->waiting.empty() && s->inflight.empty(); });
+    return idle ? VAFR_OK : fail(VAFR_E_BUDGET, "server still busy after %d ms", timeout_ms);
+}
+
+extern "C" int vafr_server_get_stats(vafr_server s, vafr_server_stats* out) {
+    if (!s || !out) return fail(VAFR_E_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lock(s->mu);
+    out->submitted = s->n_submitted;
+    out->completed = s->n_completed;
+    out->refused = s->n_refused;
+    out->deferred = s->n_deferred;
+    out->dropped = s->n_dropped;
+    out->launches = s->n_launches;
+    out->views_launched = s->views_launched;
+    out->bytes_in_use = (int64_t)s->bytes_in_use;
+    out->waiting = (int32_t)s->waiting.size();
+    out->inflight = (int32_t)s->inflight.size();
+    return VAFR_OK;
+}
+
+extern "C" void vafr_server_destroy(vafr_server s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto b : s->batches) vafr_batch_destroy(b);
+    for (auto st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (auto e : s->free_events) (void)hipEventDestroy(e);
+    for (auto& L : s->inflight)
+        if (L.done) (void)hipEventDestroy(L.done);
+    for (auto b : s->all_sets) {
+        if (s->cfg.simulate) delete b;
+        else free_set(b);
+    }
+    delete s;
+}

@@ -33,7 +33,9 @@ EXPORTS = (
     "vafr_scene_export", "vafr_scene_destroy", "vafr_shade_lp", "lmfr_shade_lp", "vafr_reconstruct",
     "lmfr_reconstruct", "full_shade", "vafr_count_work", "vafr_batch_create", "vafr_batch_run",
     "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
-    "vafr_batch_set_profiling", "vafr_batch_stage_ms",
+    "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
+    "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
+    "vafr_server_destroy",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -86,6 +88,34 @@ class vafr_batch_config(C.Structure):
     _fields_ = [("trace_block", C.c_int32), ("recon_rows", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class vafr_server_config(C.Structure):
+    _fields_ = [("max_views_per_launch", C.c_int32), ("max_inflight", C.c_int32), ("n_streams", C.c_int32),
+                ("max_queue", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("batch", vafr_batch_config),
+                ("simulate", C.c_int32), ("pad_", C.c_int32), ("sim_ms_per_launch", C.c_double),
+                ("sim_ms_per_mray", C.c_double), ("sim_ms_per_mpix", C.c_double)]
+
+
+class vafr_headset(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("layout", C.c_void_p), ("camera", vafr_camera * 2), ("shading", vafr_shading)]
+
+
+class vafr_request(C.Structure):
+    _fields_ = [("headset", C.c_int32), ("frame", C.c_uint32), ("gaze", vafr_gaze), ("deadline_ms", C.c_double),
+                ("user_tag", C.c_uint64)]
+
+
+class vafr_result(C.Structure):
+    _fields_ = [("user_tag", C.c_uint64), ("headset", C.c_int32), ("frame", C.c_uint32), ("status", C.c_int32),
+                ("slot", C.c_int32), ("submit_ms", C.c_double), ("launch_ms", C.c_double), ("done_ms", C.c_double),
+                ("img_rgba_dev", C.c_void_p * 2), ("lp_rgba_dev", C.c_void_p * 2)]
+
+
+class vafr_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("refused", C.c_int64), ("deferred", C.c_int64),
+                ("dropped", C.c_int64), ("launches", C.c_int64), ("views_launched", C.c_int64),
+                ("bytes_in_use", C.c_int64), ("waiting", C.c_int32), ("inflight", C.c_int32)]
+
+
 class vafr_scene_info(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("max_depth", C.c_int32),
                 ("on_device", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double)]
@@ -134,6 +164,14 @@ def load():
         "vafr_batch_destroy": (None, [_P]),
         "vafr_batch_set_profiling": (C.c_int, [_P, C.c_int32]),
         "vafr_batch_stage_ms": (C.c_int, [_P, C.POINTER(C.c_float), C.POINTER(C.c_int64)]),
+        "vafr_server_create": (C.c_int, [C.POINTER(vafr_server_config), C.POINTER(_P)]),
+        "vafr_server_add_headset": (C.c_int, [_P, C.POINTER(vafr_headset), C.POINTER(C.c_int32)]),
+        "vafr_server_submit": (C.c_int, [_P, C.POINTER(vafr_request)]),
+        "vafr_server_poll": (C.c_int, [_P, C.POINTER(vafr_result), C.c_int32, C.POINTER(C.c_int32)]),
+        "vafr_server_release": (C.c_int, [_P, C.c_int32]),
+        "vafr_server_wait_idle": (C.c_int, [_P, C.c_int32]),
+        "vafr_server_get_stats": (C.c_int, [_P, C.POINTER(vafr_server_stats)]),
+        "vafr_server_destroy": (None, [_P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -406,3 +444,98 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Owns a vafr_server: request loop with HBM-budget admission and
+    continuous batching (or its simulated executor when simulate=True)."""
+
+    def __init__(self, max_views_per_launch=16, max_inflight=3, n_streams=2, max_queue=64,
+                 hbm_budget_bytes=64 << 30, trace_block=128, recon_rows=4, use_graph=True, simulate=False,
+                 sim_ms_per_launch=0.05, sim_ms_per_mray=0.5, sim_ms_per_mpix=0.002):
+        cfg = vafr_server_config()
+        cfg.max_views_per_launch = int(max_views_per_launch)
+        cfg.max_inflight = int(max_inflight)
+        cfg.n_streams = int(n_streams)
+        cfg.max_queue = int(max_queue)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.batch = vafr_batch_config(int(trace_block), int(recon_rows), 1 if use_graph else 0)
+        cfg.simulate = 1 if simulate else 0
+        cfg.sim_ms_per_launch = float(sim_ms_per_launch)
+        cfg.sim_ms_per_mray = float(sim_ms_per_mray)
+        cfg.sim_ms_per_mpix = float(sim_ms_per_mpix)
+        h = C.c_void_p()
+        _check(load().vafr_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+        self._keep = []
+
+    def add_headset(self, scene, layout, cam_left, cam_right, sh):
+        hs = vafr_headset()
+        hs.scene = None if scene is None else scene.handle
+        hs.layout = layout.handle
+        hs.camera[0] = cam_left
+        hs.camera[1] = cam_right
+        hs.shading = sh
+        i = C.c_int32()
+        _check(load().vafr_server_add_headset(self._h, C.byref(hs), C.byref(i)))
+        self._keep += [scene, layout]
+        return i.value
+
+    def submit(self, headset, frame, gz, deadline_ms=0.0, tag=0):
+        """True if queued, False if refused (queue full)."""
+        r = vafr_request(int(headset), int(frame), gz, float(deadline_ms), int(tag))
+        rc = load().vafr_server_submit(self._h, C.byref(r))
+        if rc == VAFR_E_BUDGET:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_results=256):
+        arr = (vafr_result * max_results)()
+        n = C.c_int32()
+        _check(load().vafr_server_poll(self._h, arr, max_results, C.byref(n)))
+        out = []
+        for r in arr[:n.value]:
+            out.append({"tag": r.user_tag, "headset": r.headset, "frame": r.frame, "status": r.status,
+                        "slot": r.slot, "submit_ms": r.submit_ms, "launch_ms": r.launch_ms, "done_ms": r.done_ms,
+                        "img": (r.img_rgba_dev[0], r.img_rgba_dev[1]), "lp": (r.lp_rgba_dev[0], r.lp_rgba_dev[1])})
+        return out
+
+    def release(self, slot):
+        _check(load().vafr_server_release(self._h, int(slot)))
+
+    def wait_idle(self, timeout_ms=10000):
+        _check(load().vafr_server_wait_idle(self._h, int(timeout_ms)))
+
+    def stats(self):
+        st = vafr_server_stats()
+        _check(load().vafr_server_get_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in vafr_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            load().vafr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def copy_from_device(dst, src_ptr, nbytes=None):
+    """Copy nbytes from a raw device pointer (e.g. a served result) into the
+    torch tensor dst (device-to-device hipMemcpy)."""
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.restype = C.c_int
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    n = dst.numel() * dst.element_size() if nbytes is None else int(nbytes)
+    rc = _hip.hipMemcpy(C.c_void_p(dst.data_ptr()), C.c_void_p(src_ptr), n, 3)
+    if rc != 0:
+        raise VafrError(VAFR_E_HIP, f"hipMemcpy failed ({rc})")

@@ -1,0 +1,144 @@
+"""Serving-loop policy on the CPU: the server's simulated executor (launch
+cost from a model, no GPU) drives admission against the HBM budget,
+deferral, refusal, deadline drops and continuous batching."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2503_23410_amd import inputs as I
+from paper_2503_23410_amd import serving
+
+
+@pytest.fixture(scope="module")
+def V():
+    from paper_2503_23410_amd import vafr
+    vafr.load()
+    return vafr
+
+
+def _server(V, n_headsets=2, size=(1280, 720), **kw):
+    args = dict(max_views_per_launch=16, max_inflight=2, n_streams=1, max_queue=64, hbm_budget_bytes=8 << 30,
+                simulate=True, sim_ms_per_launch=0.2, sim_ms_per_mray=0.5, sim_ms_per_mpix=0.01)
+    args.update(kw)
+    s = V.Server(**args)
+    L = V.Layout.vafr(V.display(*size))
+    cam = V.camera(I.terrain_camera())
+    for _ in range(n_headsets):
+        s.add_headset(None, L, cam, cam, V.shading())
+    return s, L
+
+
+def _frame_bytes(L):
+    return 2 * L.n_texels * 16 + 2 * L.width * L.height * 16
+
+
+def _collect(s, n, timeout=10.0):
+    out = []
+    t0 = time.time()
+    while len(out) < n and time.time() - t0 < timeout:
+        out += s.poll()
+        time.sleep(0.001)
+    return out
+
+
+def test_light_load_completes_everything(V):
+    s, L = _server(V, n_headsets=4)
+    arr = serving.arrival_times(4, 90.0, 0.5, seed_base=5)
+    gazes = [I.gaze_trace(200, 1280, 720, seed=50 + h) for h in range(4)]
+    recs, refused, wall = serving.run(s, V, gazes, arr)
+    st = s.stats()
+    lat = serving.latency_stats(recs)
+    assert refused == 0 and st["refused"] == 0 and st["dropped"] == 0
+    assert lat["completed"] == len(arr) == st["completed"]
+    # one request costs 0.2 + 0.5 * 2.13 + 0.01 * 1.84 ~= 1.3 ms when alone
+    assert 1.0 < lat["p50_ms"] < 20.0
+    s.close()
+
+
+def test_continuous_batching_merges_late_arrivals(V):
+    """While one launch runs, requests that arrive join the NEXT launch
+    together instead of waiting for one launch each."""
+    s, L = _server(V, n_headsets=1, max_inflight=1, sim_ms_per_launch=30.0)
+    g = V.gaze(640.0, 360.0)
+    assert s.submit(0, 0, g)
+    time.sleep(0.005)                       # first launch is now running (30 ms)
+    for f in range(1, 7):
+        assert s.submit(0, f, g)
+    s.wait_idle(5000)
+    recs = _collect(s, 7)
+    st = s.stats()
+    assert st["completed"] == 7
+    assert st["launches"] == 2               # 1 + one batch of the 6 late arrivals
+    assert st["views_launched"] == 14
+    launches = sorted({round(r["launch_ms"], 6) for r in recs})
+    assert len(launches) == 2
+    s.close()
+
+
+def test_budget_defers_admission_until_release(V):
+    """With room for one frame's buffers, a second request waits (deferred)
+    until the first result is released."""
+    L = V.Layout.vafr(V.display(1280, 720))
+    s, _ = _server(V, n_headsets=1, hbm_budget_bytes=_frame_bytes(L) + 1024)
+    g = V.gaze(10.0, 10.0)
+    assert s.submit(0, 0, g) and s.submit(0, 1, g)
+    first = _collect(s, 1)
+    assert len(first) == 1 and first[0]["status"] == 0
+    time.sleep(0.05)
+    st = s.stats()
+    assert st["completed"] == 1 and st["waiting"] == 1 and st["deferred"] >= 1
+    s.release(first[0]["slot"])
+    second = _collect(s, 1)
+    assert len(second) == 1 and second[0]["status"] == 0 and second[0]["frame"] == 1
+    s.release(second[0]["slot"])
+    s.close()
+
+
+def test_deadline_drops_requests_that_cannot_be_admitted(V):
+    L = V.Layout.vafr(V.display(1280, 720))
+    s, _ = _server(V, n_headsets=1, hbm_budget_bytes=_frame_bytes(L) + 1024)
+    g = V.gaze(10.0, 10.0)
+    assert s.submit(0, 0, g)
+    first = _collect(s, 1)                      # held, never released: memory stays taken
+    assert s.submit(0, 1, g, deadline_ms=20.0)
+    late = _collect(s, 1)
+    assert len(late) == 1 and late[0]["status"] == V.VAFR_E_BUDGET
+    assert s.stats()["dropped"] == 1
+    s.release(first[0]["slot"])
+    s.close()
+
+
+def test_overload_refuses_when_queue_is_full(V):
+    """Device time per request well above the inter-arrival time: the queue
+    fills and further submissions are refused; p99 latency grows."""
+    s, L = _server(V, n_headsets=8, max_queue=8, max_inflight=1, sim_ms_per_launch=5.0, sim_ms_per_mray=10.0,
+                   max_views_per_launch=2)
+    arr = serving.arrival_times(8, 90.0, 0.4, seed_base=5)
+    gazes = [I.gaze_trace(100, 1280, 720, seed=60 + h) for h in range(8)]
+    recs, refused, wall = serving.run(s, V, gazes, arr)
+    st = s.stats()
+    assert refused > 0 and st["refused"] == refused
+    assert st["completed"] + refused == len(arr)
+    lat = serving.latency_stats(recs)
+    assert lat["p99_ms"] > 50.0
+    s.close()
+
+
+def test_headset_larger_than_budget_is_rejected(V):
+    s = V.Server(simulate=True, hbm_budget_bytes=1 << 20)
+    L = V.Layout.vafr(V.display(7680, 4320))
+    cam = V.camera(I.terrain_camera())
+    with pytest.raises(V.VafrError) as ei:
+        s.add_headset(None, L, cam, cam, V.shading())
+    assert ei.value.code == V.VAFR_E_BUDGET
+    with pytest.raises(V.VafrError):
+        s.submit(3, 0, V.gaze(0.0, 0.0))         # unknown headset
+    s.close()
+
+
+def test_server_config_validation(V):
+    for bad in (dict(max_views_per_launch=1), dict(max_inflight=0), dict(n_streams=9), dict(hbm_budget_bytes=0),
+                dict(max_queue=0), dict(sim_ms_per_mray=-1.0)):
+        with pytest.raises(V.VafrError):
+            V.Server(simulate=True, **bad)
