@@ -54,7 +54,16 @@ def run(server, V, gazes, arrivals, deadline_ms=0.0, on_result=None, poll_every_
             continue
         drain()
         time.sleep(min(poll_every_s, max(0.0, t - now)))
-    server.wait_idle(60000)
+    # keep releasing results until nothing is queued or in flight (leased
+    # buffers count against the budget, so waiting without draining could
+    # starve admission)
+    t_end = time.perf_counter() + 120.0
+    while time.perf_counter() < t_end:
+        drain()
+        st = server.stats()
+        if st["waiting"] == 0 and st["inflight"] == 0:
+            break
+        time.sleep(poll_every_s)
     drain()
     wall = time.perf_counter() - t0
     return recs, refused, wall
