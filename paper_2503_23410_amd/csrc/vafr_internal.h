@@ -94,7 +94,10 @@ struct alignas(16) BvhNode {
     int4 d;
 };
 constexpr int kMaxLeaf = 4;
-constexpr int kMaxDepth = 32;   // traversal stack depth bound
+#ifndef VAFR_MAX_DEPTH
+#define VAFR_MAX_DEPTH 32
+#endif
+constexpr int kMaxDepth = VAFR_MAX_DEPTH;   // BVH depth bound = traversal stack entries per lane
 constexpr int32_t kEmptyRef = INT32_MIN;
 
 struct HostBvh {

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libvafr.so")
+LIB_PATH = os.environ.get("VAFR_LIB", os.path.join(_PKG, "libvafr.so"))
 
 VAFR_OK = 0
 VAFR_E_ARG = -1
