@@ -167,6 +167,8 @@ typedef struct {
     int32_t on_device;     /* 1 if uploaded */
     int64_t device_bytes;
     double build_ms;
+    int32_t stack_entries; /* traversal stack entries per ray (LDS), > max_depth */
+    int32_t reserved;
 } vafr_scene_info;
 
 int vafr_scene_get_info(vafr_scene scene, vafr_scene_info* out);

@@ -76,6 +76,8 @@ static int scene_into_view(vafr_scene s, TraceView* v) {
     v->nodes = s->d_nodes;
     v->tris = s->d_tris;
     v->root = s->host.root;
+    v->stack = s->host.stack;
+    v->fma_origin_limit = s->host.fma_origin_limit;
     return VAFR_OK;
 }
 
@@ -246,7 +248,7 @@ extern "C" int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_
     }
     s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rc) { delete s; return rc; }
-    if (s->host.max_depth > kMaxDepth) {
+    if (s->host.max_depth > s->host.stack) {
         delete s;
         return fail(VAFR_E_UNSUPPORTED, "BVH depth exceeds the traversal stack");
     }
@@ -277,6 +279,8 @@ extern "C" int vafr_scene_get_info(vafr_scene s, vafr_scene_info* out) {
     out->on_device = s->d_tris != nullptr;
     out->device_bytes = s->device_bytes;
     out->build_ms = s->build_ms;
+    out->stack_entries = s->host.stack;
+    out->reserved = 0;
     return VAFR_OK;
 }
 

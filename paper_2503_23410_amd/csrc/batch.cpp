@@ -35,7 +35,7 @@ struct Slot {
 
 // A graph for one launch shape.
 struct GraphEntry {
-    int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0;
+    int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0, stack = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t copy = nullptr, ktrace = nullptr, krecon = nullptr;
@@ -58,6 +58,7 @@ struct vafr_batch_s {
     // host-side descriptors of the frame being prepared
     std::vector<vafr::TraceView> tv;
     std::vector<vafr::ReconView> rv;
+    int stack = vafr::kStackShort;   // stack class of the frame's traversal launch
     std::vector<int32_t> tb, rb;
     bool profiling = false;
     double stage_sum[3] = {0, 0, 0};   // accumulated stage times (ms)
@@ -89,6 +90,7 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     b->tb.clear();
     b->rb.clear();
     int64_t tsum = 0, rsum = 0;
+    b->stack = kStackShort;
     for (int32_t i = 0; i < n; ++i) {
         const vafr_view& w = views[i];
         TraceView t;
@@ -107,6 +109,7 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
         if (rc) return rc;
         tsum += (t.n_items + b->cfg.trace_block - 1) / b->cfg.trace_block;
         if (tsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
+        b->stack = std::max(b->stack, (int)t.stack);
         b->tv.push_back(t);
         b->tb.push_back((int32_t)tsum);
         if (w.kind != VAFR_VIEW_FULL && w.img_rgba_dev) {
@@ -134,7 +137,7 @@ hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, char* dev, v
     args[2] = n;
     args[3] = cnt;
     hipKernelNodeParams p{};
-    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block));
+    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack));
     p.gridDim = dim3((unsigned)g.trace_blocks);
     p.blockDim = dim3((unsigned)g.trace_block);
     p.sharedMemBytes = 0;
@@ -165,7 +168,8 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
     for (auto& g : b->graphs)
         if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
-            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows && g.timed == b->profiling) {
+            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows && g.stack == b->stack &&
+            g.timed == b->profiling) {
             *out = &g;
             return VAFR_OK;
         }
@@ -181,6 +185,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     g.recon_blocks = recon_blocks;
     g.trace_block = b->cfg.trace_block;
     g.recon_rows = b->cfg.recon_rows;
+    g.stack = b->stack;
     g.timed = b->profiling;
     VAFR_HIP(hipGraphCreate(&g.graph, 0));
     hipError_t e = hipSuccess;
@@ -290,7 +295,7 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[1], stream));
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
-                                        tblocks, b->cfg.trace_block, stream))
+                                        tblocks, b->cfg.trace_block, b->stack, stream))
             return rc;
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[2], stream));
         if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),

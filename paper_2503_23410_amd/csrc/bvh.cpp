@@ -63,6 +63,7 @@ struct Builder {
     std::atomic<int> threads_left{0};
     std::atomic<int> max_depth{0};
     std::atomic<int64_t> n_leaves{0};
+    int depth_limit = kStackLong;   // leaves stay at depth <= depth_limit - 1
 
     std::unique_ptr<TNode> build(int64_t first, int64_t n, int depth) {
         auto node = std::make_unique<TNode>();
@@ -81,7 +82,7 @@ struct Builder {
             return std::move(node);
         };
         if (n <= 1) return make_leaf();
-        const bool balance = depth + ceil_log2((n + kMaxLeaf - 1) / kMaxLeaf) >= kMaxDepth - 1;
+        const bool balance = depth + ceil_log2((n + kMaxLeaf - 1) / kMaxLeaf) >= depth_limit - 1;
         int64_t mid = -1;
         if (!balance) {
             // Binned SAH on all three axes: cost = 1 + (A_L n_L + A_R n_R)/A.
@@ -249,10 +250,17 @@ int build_bvh(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_t
     b.prims = prims.data();
     b.idx = idx.data();
     b.threads_left = (int)std::max(1u, std::thread::hardware_concurrency()) * 2;
+    out->stack = ceil_log2((n_tris + kMaxLeaf - 1) / kMaxLeaf) <= kShortStackLevels ? kStackShort : kStackLong;
+    b.depth_limit = out->stack;
     std::unique_ptr<TNode> root = b.build(0, n_tris, 0);
     out->max_depth = b.max_depth.load();
     out->n_leaves = b.n_leaves.load();
-    Packer pk{xyz, tri, idx.data(), 2e-5f * (1.0f + ext), out};
+    out->pad = 2e-5f * (1.0f + ext);
+    // fma(plane, 1/d, -o/d) moves a plane by at most 2^-24 |o|: keep that
+    // below pad / 8, and |o| small enough that o/d stays finite for the
+    // smallest substitute |d| of the traversal (1e-30).
+    out->fma_origin_limit = std::min(out->pad * 2097152.0f, 1.0e7f);
+    Packer pk{xyz, tri, idx.data(), out->pad, out};
     out->nodes.reserve(out->n_leaves);
     out->tris.reserve(3 * n_tris);
     out->order.reserve(n_tris);

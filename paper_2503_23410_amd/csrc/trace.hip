@@ -18,10 +18,25 @@ constexpr float kExitScale = 1.0000004f;
 constexpr float kHitSlack = 1.00001f;
 constexpr float kTiny = 1e-30f;
 
+// Scene arrays are read through global-address-space pointers: the loads
+// become global (not flat) loads, which wait on the vector-memory counter
+// only and do not serialise with the LDS stack traffic.
+typedef float NFloat4 __attribute__((ext_vector_type(4)));
+typedef int NInt2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 ldg4(const float4* p, size_t i) {
+    const NFloat4 v = ((const __attribute__((address_space(1))) NFloat4*)p)[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ int2 ldg_i2(const void* p) {
+    const NInt2 v = *(const __attribute__((address_space(1))) NInt2*)p;
+    return make_int2(v.x, v.y);
+}
+
 struct RayPre {
     float ox, oy, oz;
     float dx, dy, dz;
     float ix, iy, iz;       // 1/d with zero components replaced by +-kTiny
+    float oix, oiy, oiz;    // o * (1/d), rounded once (slab test in FMA form)
     int kx, ky, kz;
     float Sx, Sy, Sz;
     bool valid;
@@ -38,6 +53,9 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     r.ix = 1.0f / sx;
     r.iy = 1.0f / sy;
     r.iz = 1.0f / sz;
+    r.oix = ox * r.ix;
+    r.oiy = oy * r.iy;
+    r.oiz = oz * r.iz;
     // Watertight set-up: the axis of largest |d| becomes z (first on ties);
     // x, y follow cyclically and swap when d_z < 0.
     int kz = 0;
@@ -106,106 +124,149 @@ __device__ __forceinline__ void box2(const RayPre& r, const float4 a, const floa
     h1 = tn1 <= tf1 * kExitScale;
 }
 
+// The same test with each slab distance formed as fma(plane, 1/d, -o/d).
+// Against the exact distance to the plane this is the exact distance to a
+// plane moved by at most 2^-24 |o| (the rounding of o/d) times one more
+// relative rounding than the two of (plane - o) * (1/d) minus the one of
+// the subtraction, so kExitScale still covers the relative part.  The move
+// stays well inside the padding of every stored box as long as |o| is at
+// most TraceView::fma_origin_limit, which the caller checks per wave.
+__device__ __forceinline__ void box2_fma(const RayPre& r, const float4 a, const float4 b, const float4 c, float tlim,
+                                         bool& h0, bool& h1, float& tn0, float& tn1) {
+    const float x0 = fmaf(a.x, r.ix, -r.oix), x1 = fmaf(a.y, r.ix, -r.oix);
+    const float y0 = fmaf(a.z, r.iy, -r.oiy), y1 = fmaf(a.w, r.iy, -r.oiy);
+    const float z0 = fmaf(c.x, r.iz, -r.oiz), z1 = fmaf(c.y, r.iz, -r.oiz);
+    tn0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
+    const float tf0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tlim));
+    h0 = tn0 <= tf0 * kExitScale;
+    const float p0 = fmaf(b.x, r.ix, -r.oix), p1 = fmaf(b.y, r.ix, -r.oix);
+    const float q0 = fmaf(b.z, r.iy, -r.oiy), q1 = fmaf(b.w, r.iy, -r.oiy);
+    const float s0 = fmaf(c.z, r.iz, -r.oiz), s1 = fmaf(c.w, r.iz, -r.oiz);
+    tn1 = fmaxf(fmaxf(fminf(p0, p1), fminf(q0, q1)), fmaxf(fminf(s0, s1), 0.0f));
+    const float tf1 = fminf(fminf(fmaxf(p0, p1), fmaxf(q0, q1)), fminf(fmaxf(s0, s1), tlim));
+    h1 = tn1 <= tf1 * kExitScale;
+}
+
 // Per-lane work counters of the diagnostic pass (node visits = box-pair
 // tests, triangle tests).
 struct WorkCount {
     uint32_t nodes = 0, tris = 0;
 };
 
-// Closest hit: smallest (t, triangle id); returns the stored slot or -1.
+// Traversal loop shared by closest-hit and any-hit queries.
+//
+// Each step of the loop is wave-uniform: either a node step (lanes standing
+// on an internal node test its two child boxes) or a triangle step (lanes
+// holding a parked leaf test its triangles).  A lane parks the first leaf it
+// reaches and keeps descending from its stack; the wave switches to the
+// triangle step once kParkNum/kParkDen of its live lanes hold a parked leaf,
+// or when no lane can take a node step.  This speculative order (Aila and
+// Laine, "Understanding the efficiency of ray traversal on GPUs", HPG 2009)
+// keeps more of the 64 lanes busy in both steps than descending and testing
+// leaves in lock step.  Node steps taken before a parked leaf is tested use
+// a hit distance that is not yet the smallest, so they only ever visit more
+// boxes; the result is the same (t, id) minimum or the same any-hit bit.
+constexpr int kParkNum = 3, kParkDen = 4;
+
 // stk points at this lane's column of the block's LDS stack (stride B).
-template <int B, bool kCount>
-__device__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
-                           WorkCount& wc) {
+// Closest hit (kAny = false): smallest (t, triangle id); returns the stored
+// slot or -1.  Any hit with t > 0 (kAny = true): returns 1 or -1.
+template <int B, bool kAny, bool kCount, bool kFma>
+__device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
+                             WorkCount& wc) {
     t_best = INFINITY;
     id_best = -1;
+    float tlim = INFINITY;   // boxes are tested over [0, t_best * kHitSlack]
     int slot_best = -1;
-    int ref = sc.root;
-    if (ref == kEmptyRef) return -1;
+    int ref = sc.root;   // kEmptyRef: nothing left to visit
+    int parked = 0;      // parked leaf reference (< 0); 0 = none
     int sp = 0;
     for (;;) {
-        if (ref >= 0) {
-            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
-            const float4 a = p[0], b = p[1], c = p[2];
-            const int4 d = reinterpret_cast<const int4*>(p)[3];
-            const float tlim = t_best * kHitSlack;
-            if (kCount) ++wc.nodes;
-            bool h0, h1;
-            float tn0, tn1;
-            box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
-            if (h0 && h1) {
-                const bool first0 = tn0 <= tn1;
-                stk[sp * B] = first0 ? d.y : d.x;
-                ++sp;
-                ref = first0 ? d.x : d.y;
-                continue;
+        if (ref < 0 && ref != kEmptyRef && parked == 0) {
+            parked = ref;
+            ref = sp ? stk[--sp * B] : kEmptyRef;
+        }
+        const uint64_t live = __ballot(ref != kEmptyRef || parked != 0);
+        if (live == 0) break;
+        const uint64_t at_node = __ballot(ref >= 0);
+        const uint64_t holding = __ballot(parked != 0);
+        if (at_node != 0 && kParkDen * __popcll(holding) < kParkNum * __popcll(live)) {
+            if (ref >= 0) {
+                const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
+                const float4 a = ldg4(p, 0), b = ldg4(p, 1), c = ldg4(p, 2);
+                const int2 d = ldg_i2(p + 3);
+                if (kCount) ++wc.nodes;
+                bool h0, h1;
+                float tn0, tn1;
+                if (kFma) box2_fma(r, a, b, c, tlim, h0, h1, tn0, tn1);
+                else box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
+                if (h0 && h1) {
+                    const bool first0 = tn0 <= tn1;
+                    stk[sp * B] = first0 ? d.y : d.x;
+                    ++sp;
+                    ref = first0 ? d.x : d.y;
+                } else if (h0) {
+                    ref = d.x;
+                } else if (h1) {
+                    ref = d.y;
+                } else {
+                    ref = sp ? stk[--sp * B] : kEmptyRef;
+                }
             }
-            if (h0) { ref = d.x; continue; }
-            if (h1) { ref = d.y; continue; }
-        } else {
-            const int x = ~ref;
+            continue;
+        }
+        if (parked != 0) {
+            const int x = ~parked;
+            parked = 0;
             const int first = x >> 3, count = (x & 7) + 1;
             const float4* tp = sc.tris + 3 * (size_t)first;
             if (kCount) wc.tris += count;
             for (int q = 0; q < count; ++q) {
-                const float4 v0 = tp[3 * q], v1 = tp[3 * q + 1], v2 = tp[3 * q + 2];
+                const float4 v0 = ldg4(tp, 3 * q), v1 = ldg4(tp, 3 * q + 1), v2 = ldg4(tp, 3 * q + 2);
                 float t;
                 if (tri_hit(r, v0, v1, v2, t)) {
+                    if (kAny) {
+                        slot_best = 1;
+                        ref = kEmptyRef;
+                        break;
+                    }
                     const int id = __float_as_int(v0.w);
                     if (t < t_best || (t == t_best && id < id_best)) {
                         t_best = t;
                         id_best = id;
                         slot_best = first + q;
+                        tlim = t * kHitSlack;
                     }
                 }
             }
         }
-        if (sp == 0) break;
-        --sp;
-        ref = stk[sp * B];
     }
     return slot_best;
 }
 
-// Any hit with t > 0 (shadow ray toward a directional light).
+// The FMA slab test is taken when every lane's origin is within the
+// scene's limit (wave-uniform choice, so both loops run without divergence).
+template <int B, bool kAny, bool kCount>
+__device__ __forceinline__ int traverse(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
+                                        WorkCount& wc) {
+    const float om = fmaxf(fmaxf(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz));
+    const float oi = fmaxf(fmaxf(fabsf(r.oix), fabsf(r.oiy)), fabsf(r.oiz));
+    const bool fma_ok = om <= sc.fma_origin_limit && oi <= 3.0e38f;
+    if (__ballot(!fma_ok) == 0) return traverse_loop<B, kAny, kCount, true>(sc, r, stk, t_best, id_best, wc);
+    return traverse_loop<B, kAny, kCount, false>(sc, r, stk, t_best, id_best, wc);
+}
+
 template <int B, bool kCount>
-__device__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
-    int ref = sc.root;
-    if (ref == kEmptyRef) return false;
-    int sp = 0;
-    for (;;) {
-        if (ref >= 0) {
-            const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
-            const float4 a = p[0], b = p[1], c = p[2];
-            const int4 d = reinterpret_cast<const int4*>(p)[3];
-            if (kCount) ++wc.nodes;
-            bool h0, h1;
-            float tn0, tn1;
-            box2(r, a, b, c, INFINITY, h0, h1, tn0, tn1);
-            if (h0 && h1) {
-                const bool first0 = tn0 <= tn1;
-                stk[sp * B] = first0 ? d.y : d.x;
-                ++sp;
-                ref = first0 ? d.x : d.y;
-                continue;
-            }
-            if (h0) { ref = d.x; continue; }
-            if (h1) { ref = d.y; continue; }
-        } else {
-            const int x = ~ref;
-            const int first = x >> 3, count = (x & 7) + 1;
-            const float4* tp = sc.tris + 3 * (size_t)first;
-            for (int q = 0; q < count; ++q) {
-                float t;
-                if (kCount) ++wc.tris;
-                if (tri_hit(r, tp[3 * q], tp[3 * q + 1], tp[3 * q + 2], t)) return true;
-            }
-        }
-        if (sp == 0) break;
-        --sp;
-        ref = stk[sp * B];
-    }
-    return false;
+__device__ __forceinline__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best,
+                                           int& id_best, WorkCount& wc) {
+    return traverse<B, false, kCount>(sc, r, stk, t_best, id_best, wc);
+}
+
+template <int B, bool kCount>
+__device__ __forceinline__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
+    float t;
+    int id;
+    return traverse<B, true, kCount>(sc, r, stk, t, id, wc) >= 0;
 }
 
 // 32-bit hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
@@ -333,7 +394,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
     const float4* tp = sc.tris + 3 * (size_t)slot;
     float3 n, os;
-    hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+    hit_frame(ldg4(tp, 0), ldg4(tp, 1), ldg4(tp, 2), r, t, n, os);
     const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
     float vis = 1.0f;
     if (ndl > 0.0f && v.shadow) {
@@ -369,7 +430,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
         }
         const float4* tp = sc.tris + 3 * (size_t)slot;
         float3 n, os;
-        hit_frame(tp[0], tp[1], tp[2], r, t, n, os);
+        hit_frame(ldg4(tp, 0), ldg4(tp, 1), ldg4(tp, 2), r, t, n, os);
         const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
         float vis = 0.0f;
         if (ndl > 0.0f) {
@@ -418,20 +479,21 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_id) v.out_id[out] = id;
 }
 
-template <int B, bool kCount>
+// S = stack entries per lane (the scene's stack class).
+template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
-    __shared__ int stack[kMaxDepth * B];
+    __shared__ int stack[S * B];
     trace_item<B, kCount>(v, (int64_t)blockIdx.x * B + threadIdx.x, stack, counters);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
 // block_end[vid] (block_end is the running sum of per-view workgroups of B
-// items each).
-template <int B, bool kCount>
+// items each).  S covers the deepest scene of the batch.
+template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters) {
-    __shared__ int stack[kMaxDepth * B];
+    __shared__ int stack[S * B];
     const int b = blockIdx.x;
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
@@ -439,24 +501,50 @@ __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__
     trace_item<B, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
 }
 
-template <int B>
+template <int B, int S>
 void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsigned long long* counters) {
     if (counters)
-        hipLaunchKernelGGL((k_trace<B, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+        hipLaunchKernelGGL((k_trace<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
     else
-        hipLaunchKernelGGL((k_trace<B, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+        hipLaunchKernelGGL((k_trace<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
 }
 
-template <int B>
+template <int B, int S>
 void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks,
                   hipStream_t stream, unsigned long long* counters) {
     if (counters)
-        hipLaunchKernelGGL((k_trace_batch<B, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
+        hipLaunchKernelGGL((k_trace_batch<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
                            n_views, counters);
     else
-        hipLaunchKernelGGL((k_trace_batch<B, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
-                           n_views, counters);
+        hipLaunchKernelGGL((k_trace_batch<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
+                           block_end, n_views, counters);
 }
+
+template <int S>
+void launch_single_s(const TraceView& v, int64_t blocks, int block, hipStream_t stream,
+                     unsigned long long* counters) {
+    if (block == 64) launch_single<64, S>(v, blocks, stream, counters);
+    else if (block == 128) launch_single<128, S>(v, blocks, stream, counters);
+    else launch_single<256, S>(v, blocks, stream, counters);
+}
+
+template <int S>
+void launch_batch_s(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, int block,
+                    hipStream_t stream, unsigned long long* counters) {
+    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, stream, counters);
+    else if (block == 128) launch_batch<128, S>(views, block_end, n_views, blocks, stream, counters);
+    else launch_batch<256, S>(views, block_end, n_views, blocks, stream, counters);
+}
+
+template <int S>
+const void* batch_kernel_s(int block) {
+    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false>);
+    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false>);
+    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false>);
+    return nullptr;
+}
+
+bool stack_ok(int stack) { return stack == kStackShort || stack == kStackLong; }
 
 }  // namespace
 
@@ -471,29 +559,30 @@ bool trace_block_ok(int block) { return block == 64 || block == 128 || block == 
 int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* counters, int block) {
     if (v.n_items <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
+    if (!stack_ok(v.stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", v.stack);
     const int64_t blocks = (v.n_items + block - 1) / block;
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
-    if (block == 64) launch_single<64>(v, blocks, stream, counters);
-    else if (block == 128) launch_single<128>(v, blocks, stream, counters);
-    else launch_single<256>(v, blocks, stream, counters);
+    if (v.stack == kStackShort) launch_single_s<kStackShort>(v, blocks, block, stream, counters);
+    else launch_single_s<kStackLong>(v, blocks, block, stream, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }
 
-const void* trace_batch_kernel(int block) {
-    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, false>);
-    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, false>);
-    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, false>);
+const void* trace_batch_kernel(int block, int stack) {
+    if (stack == kStackShort) return batch_kernel_s<kStackShort>(block);
+    if (stack == kStackLong) return batch_kernel_s<kStackLong>(block);
     return nullptr;
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, hipStream_t stream, unsigned long long* counters) {
+                       int block, int stack, hipStream_t stream, unsigned long long* counters) {
     if (blocks <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
-    if (block == 64) launch_batch<64>(views_dev, block_end_dev, n_views, blocks, stream, counters);
-    else if (block == 128) launch_batch<128>(views_dev, block_end_dev, n_views, blocks, stream, counters);
-    else launch_batch<256>(views_dev, block_end_dev, n_views, blocks, stream, counters);
+    if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
+    if (stack == kStackShort)
+        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, stream, counters);
+    else
+        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, stream, counters);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

@@ -94,10 +94,15 @@ struct alignas(16) BvhNode {
     int4 d;
 };
 constexpr int kMaxLeaf = 4;
-#ifndef VAFR_MAX_DEPTH
-#define VAFR_MAX_DEPTH 32
-#endif
-constexpr int kMaxDepth = VAFR_MAX_DEPTH;   // BVH depth bound = traversal stack entries per lane
+// Traversal stack classes (entries per lane in LDS).  A tree of depth D needs
+// D entries; the builder keeps D below the class it picks for the scene.
+// The short class leaves room for more resident waves per CU (LDS per wave
+// = entries x 64 x 4 bytes), the long class admits every supported scene.
+constexpr int kStackShort = 24;
+constexpr int kStackLong = 32;
+// Scenes whose leaf count needs at most this many balanced levels get the
+// short class (two levels of slack for the SAH splits).
+constexpr int kShortStackLevels = kStackShort - 3;
 constexpr int32_t kEmptyRef = INT32_MIN;
 
 struct HostBvh {
@@ -106,6 +111,9 @@ struct HostBvh {
     std::vector<int32_t> order;  // original id of each stored triangle
     int32_t root = kEmptyRef;
     int32_t max_depth = 0;
+    int32_t stack = kStackShort; // traversal stack class (kStackShort or kStackLong)
+    float pad = 0.0f;            // absolute padding of every stored box
+    float fma_origin_limit = 0;  // origins up to this |component| move a slab plane by <= pad / 8
     int64_t n_leaves = 0;
 };
 
@@ -138,6 +146,8 @@ struct TraceView {
     const BvhNode* nodes;
     const float4* tris;
     int32_t root;
+    int32_t stack;          // stack class of the scene (entries per lane)
+    float fma_origin_limit; // largest |origin| component for the FMA slab test
     // camera
     float eye[3], right[3], up[3], fwd[3];
     // film geometry (FP64): gaze point on the film and pixel pitch
@@ -171,8 +181,9 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
                  int block = kTraceBlockDefault);
 // One launch over several views: workgroup b serves the view whose running
 // workgroup count block_end[] first exceeds b.
+// stack = the largest stack class among the views' scenes.
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, hipStream_t stream, unsigned long long* counters = nullptr);
+                       int block, int stack, hipStream_t stream, unsigned long long* counters = nullptr);
 
 // ------------------------------------------------------- reconstruction
 // One view of the inverse map.  The offset of pixel (x, y)'s centre from the
@@ -210,7 +221,7 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
 
 // Kernel entry points of the batched launches (for graph nodes); their
 // parameters are (views, block_end, n_views[, counters]).
-const void* trace_batch_kernel(int block);
+const void* trace_batch_kernel(int block, int stack);
 const void* recon_batch_kernel(int rows);
 
 // common validation helpers

@@ -94,7 +94,8 @@ def _check_bvh(V, verts, tris):
     nodes, order = sc.export()
     assert info["n_tris"] == tris.shape[0]
     assert np.array_equal(np.sort(order), np.arange(tris.shape[0]))      # each triangle stored once
-    assert info["max_depth"] <= 32
+    # the traversal stack holds one entry per level below the root
+    assert info["stack_entries"] in (24, 32) and info["max_depth"] <= info["stack_entries"] - 1
     refs = nodes[:, 12:14].view(np.int32) if nodes.size else np.zeros((0, 2), np.int32)
     tv = verts[tris[order]]                                               # stored order, (n, 3, 3)
     # every child box contains every triangle of its subtree
@@ -134,7 +135,7 @@ def test_bvh_structure_terrain_and_degenerate(V):
     vv = np.tile(tri, (3000, 1))
     ff = np.arange(9000, dtype=np.int32).reshape(-1, 3)
     sc, info = _check_bvh(V, vv, ff)
-    assert info["max_depth"] <= 32
+    assert info["stack_entries"] == 24 and info["max_depth"] <= 23
 
 
 def test_bvh_small_and_empty_scenes(V):
@@ -164,5 +165,27 @@ def test_large_scene_bvh_builds_fast(V):
     v, f = I.make_scene("terrain1m")
     sc = V.Scene(v, f)
     info = sc.info()
-    assert info["max_depth"] <= 32
+    assert info["stack_entries"] == 24 and info["max_depth"] <= 23
     assert info["build_ms"] < 30000
+
+
+@pytest.mark.slow
+def test_stack_class_follows_scene_size(V):
+    """Scenes of more than 2^23 triangles get the long stack class; the
+    depth bound holds for both classes, also under forced median splits."""
+    n = (1 << 23) + 4096
+    rng = np.random.default_rng(9)
+    c = rng.random((n, 3), dtype=np.float32) * 100.0
+    vv = np.repeat(c, 3, axis=0)
+    vv[1::3, 0] += 0.01
+    vv[2::3, 1] += 0.01
+    ff = np.arange(3 * n, dtype=np.int32).reshape(-1, 3)
+    sc = V.Scene(vv, ff)
+    info = sc.info()
+    assert info["stack_entries"] == 32 and info["max_depth"] <= 31
+    del sc, vv, ff
+    # identical triangles: no SAH split applies, every level is a median split
+    vv = np.tile(np.array([[0, 0, 1], [1, 0, 1], [0, 1, 1]], np.float32), ((1 << 21) + 17, 1))
+    ff = np.arange(vv.shape[0], dtype=np.int32).reshape(-1, 3)
+    info = V.Scene(vv, ff).info()
+    assert info["stack_entries"] == 24 and info["max_depth"] <= 23
