@@ -42,6 +42,8 @@ extern "C" {
 #define VAFR_E_HIP (-3)          /* a HIP runtime call failed / no device       */
 #define VAFR_E_UNSUPPORTED (-4)  /* valid request the library cannot serve      */
 #define VAFR_E_BUDGET (-5)       /* request exceeds a memory budget             */
+#define VAFR_E_LATE (-6)         /* request dropped: it could not complete by its
+                                    deadline, or a newer request replaced it   */
 
 /* Message of the last failure on this thread ("" if none).  The pointer
  * stays valid until the next failing call on the same thread. */
@@ -301,6 +303,11 @@ typedef struct {
                                       simulated device is free (capacity planning and policy tests) */
     int32_t pad_;
     double sim_ms_per_launch, sim_ms_per_mray, sim_ms_per_mpix;
+    double frame_budget_ms;        /* > 0: a request must complete within this many ms of its submission
+                                      (or within its own deadline_ms if that is smaller); 0 = none */
+    int32_t latest_only;           /* 1: a new request of a headset replaces that headset's requests
+                                      not yet launched (they finish with VAFR_E_LATE) */
+    int32_t pad2_;
 } vafr_server_config;
 
 /* A headset: resident scene and VaFR layout (display), one camera per eye
@@ -318,14 +325,18 @@ typedef struct {
     int32_t headset;
     uint32_t frame;
     vafr_gaze gaze;
-    double deadline_ms;            /* drop if not admitted within this time after submit; 0 = none */
+    double deadline_ms;            /* latest completion, ms after submit; 0 = none (frame_budget_ms of
+                                      the server applies if set) */
     uint64_t user_tag;
 } vafr_request;
 
 /* A finished request.  status VAFR_OK: the images (and LP buffers) of both
  * eyes are ready at the device pointers, which stay valid until
- * vafr_server_release(slot).  status VAFR_E_BUDGET: refused or dropped (no
- * slot, nothing to release).  Times are ms on the server's clock. */
+ * vafr_server_release(slot).  VAFR_E_LATE: dropped before launch because it
+ * could not complete by its deadline, or replaced by a newer request of the
+ * headset.  VAFR_E_BUDGET: dropped while draining without memory.  No slot
+ * and nothing to release for any error status.  Times are ms on the
+ * server's clock. */
 typedef struct {
     uint64_t user_tag;
     int32_t headset;
@@ -337,9 +348,12 @@ typedef struct {
     const float* lp_rgba_dev[2];
 } vafr_result;
 
+/* dropped counts every request finished with an error status; late and
+ * superseded count the VAFR_E_LATE drops by cause. */
 typedef struct {
     int64_t submitted, completed, refused, deferred, dropped, launches, views_launched, bytes_in_use;
     int32_t waiting, inflight;
+    int64_t late, superseded;
 } vafr_server_stats;
 
 /* Starts the dispatcher thread on the current device.  Requests are
@@ -348,7 +362,15 @@ typedef struct {
  * head of the queue (up to max_views_per_launch / 2) into one batched frame
  * (vafr_batch_run) on the least busy stream, so requests that arrive while
  * others run join the next launch.  Results equal those of the request
- * rendered alone (kernels are per view and deterministic). */
+ * rendered alone (kernels are per view and deterministic).
+ *
+ * Requests with a deadline go through a device-time model: a per-launch
+ * cost plus a cost per request of each headset, seeded from the headset's
+ * ray and pixel counts and corrected after every launch by its measured
+ * device time.  A launch takes requests from the queue head while the
+ * predicted end of the device's queued work plus the launch meets every
+ * included deadline; a request that cannot meet its deadline even in a
+ * launch of its own is dropped (VAFR_E_LATE). */
 int vafr_server_create(const vafr_server_config* cfg, vafr_server* out);
 int vafr_server_add_headset(vafr_server server, const vafr_headset* headset, int32_t* id);
 /* Non-blocking; VAFR_E_BUDGET when the queue is full (counted as refused). */

@@ -8,8 +8,17 @@
 // Scenes, BVHs and layouts stay resident (the headsets reference them); the
 // per-request LP buffers and display images come from recycled buffer sets
 // whose total size is bounded by the budget.
+//
+// Requests may carry a completion deadline (a VR frame is useless once its
+// display refresh has passed).  The dispatcher keeps a model of device time
+// -- a cost per launch plus a cost per request of each headset, corrected
+// after each launch by its measured duration -- and the predicted time at
+// which the device drains the work already launched.  A launch only takes
+// requests that the model says will finish in time; a request that cannot
+// finish in time even alone is dropped before it costs device time.
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstdio>
 #include <cstring>
@@ -37,16 +46,20 @@ struct BufSet {
 struct Pending {
     vafr_request req;
     double submit_ms;
+    double due_ms = INFINITY;   // completion deadline on the server clock
     BufSet* bufs = nullptr;
     bool deferred = false;
 };
 
 struct Launch {
     std::vector<Pending> reqs;
-    hipEvent_t done = nullptr;
+    hipEvent_t start = nullptr, done = nullptr;
     int stream = 0;
     double launch_ms = 0;
+    double pred_ms = 0;       // modelled device time of this launch
+    double pred_end_ms = 0;   // modelled completion on the server clock
     double sim_done_ms = 0;   // simulated executor: completion time
+    double sim_cost_ms = 0;   // simulated executor: device time of the launch
 };
 
 }  // namespace
@@ -72,7 +85,11 @@ struct vafr_server_s {
     std::deque<vafr_result> done;
     // stats
     int64_t n_submitted = 0, n_completed = 0, n_refused = 0, n_deferred = 0, n_dropped = 0, n_launches = 0;
-    int64_t views_launched = 0;
+    int64_t views_launched = 0, n_late = 0, n_superseded = 0;
+    // device-time model: launch cost + per-request cost of each headset
+    double est_launch_ms = 0;
+    std::vector<double> est_req_ms;
+    double pred_free_ms = 0;                  // modelled end of the launched work
     std::mutex mu;
     std::condition_variable cv;
     bool stop = false;
@@ -84,6 +101,11 @@ struct vafr_server_s {
 
 namespace vafr {
 namespace {
+
+// Launches are planned to end by this fraction of a request's budget: the
+// rest absorbs the spread of device times around the model and the delay
+// before the dispatcher sees a launch finish.
+constexpr double kPlanFraction = 0.9;
 
 double now_ms(vafr_server s) { return std::chrono::duration<double, std::milli>(Clock::now() - s->t0).count(); }
 
@@ -145,6 +167,37 @@ BufSet* acquire_set(vafr_server s, const vafr_headset& h) {
 
 void release_set(vafr_server s, BufSet* b) { s->free_sets.emplace(b->key, b); }
 
+// Finish a request that is not launched with an error status (caller holds
+// mu); its buffers go back to the pool.
+void finish_dropped(vafr_server s, Pending& p, int status, double t) {
+    vafr_result r;
+    std::memset(&r, 0, sizeof(r));
+    r.user_tag = p.req.user_tag;
+    r.headset = p.req.headset;
+    r.frame = p.req.frame;
+    r.status = status;
+    r.submit_ms = p.submit_ms;
+    r.launch_ms = r.done_ms = t;
+    if (p.bufs) release_set(s, p.bufs);
+    p.bufs = nullptr;
+    s->done.push_back(r);
+    ++s->n_dropped;
+    s->cv.notify_all();
+}
+
+// Initial device-time estimate of one request of headset h: rays traced for
+// both eyes' LP buffers and pixels written by both reconstructions, at rates
+// of the order the device sustains; corrected by measurement after launches.
+double initial_request_ms(const vafr_server_config& c, const vafr_headset& h) {
+    const double texels = 2.0 * (double)h.layout->n_texels;
+    const double pixels = 2.0 * (double)h.layout->disp.width * h.layout->disp.height;
+    if (c.simulate) return c.sim_ms_per_mray * texels * 1e-6 + c.sim_ms_per_mpix * pixels * 1e-6;
+    const double shadow = h.shading.shadow_rays ? 2.0 : 1.0;
+    const double rays_per_texel =
+        h.shading.mode == VAFR_SHADE_PATH ? shadow * (1.0 + (double)h.shading.bounces) : shadow;
+    return texels * rays_per_texel * 0.25e-6 + pixels * 0.004e-6;
+}
+
 void set_error(vafr_server s, int code, const char* msg) {
     if (s->error == VAFR_OK) {
         s->error = code;
@@ -158,13 +211,33 @@ void launch(vafr_server s, int k) {
     Launch L;
     L.stream = k;
     const int max_req = std::max(1, s->cfg.max_views_per_launch / 2);
+    const double t_now = now_ms(s);
+    const double free_at = std::max(t_now, s->pred_free_ms);
+    double cost = s->est_launch_ms, due = INFINITY;
     while (!s->waiting.empty() && (int)L.reqs.size() < max_req) {
         Pending& p = s->waiting.front();
         if (!p.bufs) break;                         // head not admitted yet: keep order
+        const double c = s->est_req_ms[p.req.headset];
+        if (free_at + cost + c > std::min(due, p.due_ms)) {
+            // Too late in this launch.  If it cannot finish in time in a
+            // launch of its own right after this one either, drop it now.
+            const double alone = (L.reqs.empty() ? free_at : free_at + cost) + s->est_launch_ms + c;
+            if (alone > p.due_ms) {
+                ++s->n_late;
+                finish_dropped(s, p, VAFR_E_LATE, t_now);
+                s->waiting.pop_front();
+                continue;
+            }
+            break;
+        }
+        cost += c;
+        due = std::min(due, p.due_ms);
         L.reqs.push_back(p);
         s->waiting.pop_front();
     }
     if (L.reqs.empty()) return;
+    L.pred_ms = cost;
+    L.pred_end_ms = free_at + cost;
     std::vector<vafr_view> views;
     views.reserve(2 * L.reqs.size());
     for (const Pending& p : L.reqs) {
@@ -195,14 +268,19 @@ void launch(vafr_server s, int k) {
             mpix += 2e-6 * (double)lay->disp.width * lay->disp.height;
         }
         const double start = std::max(L.launch_ms, s->sim_busy_until);
-        L.sim_done_ms = start + s->cfg.sim_ms_per_launch + s->cfg.sim_ms_per_mray * mray + s->cfg.sim_ms_per_mpix * mpix;
+        L.sim_cost_ms = s->cfg.sim_ms_per_launch + s->cfg.sim_ms_per_mray * mray + s->cfg.sim_ms_per_mpix * mpix;
+        L.sim_done_ms = start + L.sim_cost_ms;
         s->sim_busy_until = L.sim_done_ms;
+        s->pred_free_ms = L.pred_end_ms;
         ++s->n_launches;
         s->views_launched += (int64_t)views.size();
         s->inflight.push_back(std::move(L));
         return;
     }
-    int rc = vafr_batch_run(s->batches[k], views.data(), (int32_t)views.size(), s->streams[k]);
+    L.start = s->free_events.back();
+    s->free_events.pop_back();
+    int rc = hipEventRecord(L.start, s->streams[k]) == hipSuccess ? VAFR_OK : VAFR_E_HIP;
+    if (rc == VAFR_OK) rc = vafr_batch_run(s->batches[k], views.data(), (int32_t)views.size(), s->streams[k]);
     if (rc == VAFR_OK) {
         L.done = s->free_events.back();
         s->free_events.pop_back();
@@ -223,11 +301,36 @@ void launch(vafr_server s, int k) {
             s->done.push_back(r);
         }
         if (L.done) s->free_events.push_back(L.done);
+        s->free_events.push_back(L.start);
         return;
     }
+    s->pred_free_ms = L.pred_end_ms;
     ++s->n_launches;
     s->views_launched += (int64_t)views.size();
     s->inflight.push_back(std::move(L));
+}
+
+// After launch L finished at time t: correct the model by the ratio of
+// measured to modelled device time, and move the modelled end of the work
+// still in flight by the error.
+void learn(vafr_server s, const Launch& L, double t) {
+    double dur = L.pred_ms;
+    if (s->cfg.simulate) {
+        dur = L.sim_cost_ms;
+    } else {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, L.start, L.done) == hipSuccess && ms > 0.0f) dur = ms;
+    }
+    if (L.pred_ms > 0.0 && dur > 0.0) {
+        const double ratio = std::min(4.0, std::max(0.25, dur / L.pred_ms));
+        const double f = 0.7 + 0.3 * ratio;
+        s->est_launch_ms *= f;
+        for (const Pending& p : L.reqs) s->est_req_ms[p.req.headset] *= f;
+    }
+    const double shift = t - L.pred_end_ms;
+    for (Launch& o : s->inflight) o.pred_end_ms += shift;
+    s->pred_free_ms += shift;
+    if (s->inflight.size() <= 1) s->pred_free_ms = t;   // only L was in flight: the device is idle
 }
 
 void worker_main(vafr_server s) {
@@ -261,7 +364,9 @@ void worker_main(vafr_server s) {
                 ++s->n_completed;
             }
             if (q != hipSuccess) set_error(s, VAFR_E_HIP, "a launched frame failed");
+            learn(s, L, t);
             if (L.done) s->free_events.push_back(L.done);
+            if (L.start) s->free_events.push_back(L.start);
             s->inflight.erase(s->inflight.begin() + i);
             s->cv.notify_all();
         }
@@ -269,35 +374,17 @@ void worker_main(vafr_server s) {
         // drop requests whose deadline already passed
         const double t = now_ms(s);
         for (auto it = s->waiting.begin(); it != s->waiting.end();) {
-            if (it->req.deadline_ms > 0.0 && t - it->submit_ms > it->req.deadline_ms && !it->bufs) {
-                vafr_result r;
-                std::memset(&r, 0, sizeof(r));
-                r.user_tag = it->req.user_tag;
-                r.headset = it->req.headset;
-                r.frame = it->req.frame;
-                r.status = VAFR_E_BUDGET;
-                r.submit_ms = it->submit_ms;
-                r.launch_ms = r.done_ms = t;
-                s->done.push_back(r);
-                ++s->n_dropped;
+            if (t + s->est_launch_ms + s->est_req_ms[it->req.headset] > it->due_ms) {
+                ++s->n_late;
+                finish_dropped(s, *it, VAFR_E_LATE, t);
                 it = s->waiting.erase(it);
-                s->cv.notify_all();
                 continue;
             }
             if (!it->bufs) {
                 it->bufs = acquire_set(s, s->headsets[it->req.headset]);
                 if (!it->bufs) {                              // wait for memory, keep order
                     if (s->stop) {                            // draining: no memory will come back
-                        vafr_result r;
-                        std::memset(&r, 0, sizeof(r));
-                        r.user_tag = it->req.user_tag;
-                        r.headset = it->req.headset;
-                        r.frame = it->req.frame;
-                        r.status = VAFR_E_BUDGET;
-                        r.submit_ms = it->submit_ms;
-                        r.launch_ms = r.done_ms = t;
-                        s->done.push_back(r);
-                        ++s->n_dropped;
+                        finish_dropped(s, *it, VAFR_E_BUDGET, t);
                         it = s->waiting.erase(it);
                         continue;
                     }
@@ -342,6 +429,9 @@ extern "C" int vafr_server_create(const vafr_server_config* cfg, vafr_server* ou
     if (cfg->simulate != 0 && cfg->simulate != 1) return fail(VAFR_E_ARG, "simulate must be 0 or 1");
     if (cfg->simulate && (!(cfg->sim_ms_per_launch >= 0) || !(cfg->sim_ms_per_mray >= 0) || !(cfg->sim_ms_per_mpix >= 0)))
         return fail(VAFR_E_ARG, "simulated costs must be >= 0");
+    if (!(cfg->frame_budget_ms >= 0) || !std::isfinite(cfg->frame_budget_ms))
+        return fail(VAFR_E_ARG, "frame_budget_ms must be finite and >= 0");
+    if (cfg->latest_only != 0 && cfg->latest_only != 1) return fail(VAFR_E_ARG, "latest_only must be 0 or 1");
     int n_dev = 0;
     if (!cfg->simulate && (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0))
         return fail(VAFR_E_HIP, "no HIP device available");
@@ -349,6 +439,7 @@ extern "C" int vafr_server_create(const vafr_server_config* cfg, vafr_server* ou
     if (!s) return fail(VAFR_E_OOM, "server allocation failed");
     s->cfg = *cfg;
     s->t0 = Clock::now();
+    s->est_launch_ms = cfg->simulate ? cfg->sim_ms_per_launch : 0.03;
     auto bail = [&](int code) {
         vafr_server_destroy(s);
         return code;
@@ -363,10 +454,10 @@ extern "C" int vafr_server_create(const vafr_server_config* cfg, vafr_server* ou
         if (int rc = vafr_batch_create(cfg->max_views_per_launch, &cfg->batch, &b)) return bail(rc);
         s->batches.push_back(b);
     }
-    for (int k = 0; k < cfg->max_inflight + 1 && !cfg->simulate; ++k) {
+    // two timing events (start, done) per launch in flight, plus spares
+    for (int k = 0; k < 2 * (cfg->max_inflight + 1) && !cfg->simulate; ++k) {
         hipEvent_t e;
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
-            return bail(fail(VAFR_E_HIP, "event creation failed"));
+        if (hipEventCreate(&e) != hipSuccess) return bail(fail(VAFR_E_HIP, "event creation failed"));
         s->free_events.push_back(e);
     }
     s->worker = std::thread(worker_main, s);
@@ -385,6 +476,7 @@ extern "C" int vafr_server_add_headset(vafr_server s, const vafr_headset* h, int
     if (set_bytes(*h) > (size_t)s->cfg.hbm_budget_bytes)
         return fail(VAFR_E_BUDGET, "one frame of this headset does not fit the HBM budget");
     s->headsets.push_back(*h);
+    s->est_req_ms.push_back(initial_request_ms(s->cfg, *h));
     *id = (int32_t)s->headsets.size() - 1;
     return VAFR_OK;
 }
@@ -403,6 +495,17 @@ extern "C" int vafr_server_submit(vafr_server s, const vafr_request* r) {
     Pending p;
     p.req = *r;
     p.submit_ms = now_ms(s);
+    double budget = s->cfg.frame_budget_ms > 0.0 ? s->cfg.frame_budget_ms : INFINITY;
+    if (r->deadline_ms > 0.0) budget = std::min(budget, r->deadline_ms);
+    p.due_ms = p.submit_ms + kPlanFraction * budget;
+    if (s->cfg.latest_only) {
+        for (auto it = s->waiting.begin(); it != s->waiting.end();) {
+            if (it->req.headset != r->headset) { ++it; continue; }
+            ++s->n_superseded;
+            finish_dropped(s, *it, VAFR_E_LATE, p.submit_ms);
+            it = s->waiting.erase(it);
+        }
+    }
     s->waiting.push_back(p);
     s->cv.notify_all();
     return VAFR_OK;
@@ -453,6 +556,8 @@ extern "C" int vafr_server_get_stats(vafr_server s, vafr_server_stats* out) {
     out->bytes_in_use = (int64_t)s->bytes_in_use;
     out->waiting = (int32_t)s->waiting.size();
     out->inflight = (int32_t)s->inflight.size();
+    out->late = s->n_late;
+    out->superseded = s->n_superseded;
     return VAFR_OK;
 }
 
@@ -470,8 +575,10 @@ extern "C" void vafr_server_destroy(vafr_server s) {
         (void)hipStreamDestroy(st);
     }
     for (auto e : s->free_events) (void)hipEventDestroy(e);
-    for (auto& L : s->inflight)
+    for (auto& L : s->inflight) {
         if (L.done) (void)hipEventDestroy(L.done);
+        if (L.start) (void)hipEventDestroy(L.start);
+    }
     for (auto b : s->all_sets) {
         if (s->cfg.simulate) delete b;
         else free_set(b);

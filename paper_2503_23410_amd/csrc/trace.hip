@@ -22,14 +22,13 @@ constexpr float kTiny = 1e-30f;
 // become global (not flat) loads, which wait on the vector-memory counter
 // only and do not serialise with the LDS stack traffic.
 typedef float NFloat4 __attribute__((ext_vector_type(4)));
-typedef int NInt2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float4 ldg4(const float4* p, size_t i) {
     const NFloat4 v = ((const __attribute__((address_space(1))) NFloat4*)p)[i];
     return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ int2 ldg_i2(const void* p) {
-    const NInt2 v = *(const __attribute__((address_space(1))) NInt2*)p;
-    return make_int2(v.x, v.y);
+    const uint64_t v = *(const __attribute__((address_space(1))) uint64_t*)p;
+    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
 }
 
 struct RayPre {
@@ -479,11 +478,23 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_id) v.out_id[out] = id;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
+// permuted so that XCD q receives the q-th contiguous eighth of the items:
+// rays of one screen region then share their XCD's L2 for the BVH levels
+// near the leaves, instead of every L2 holding the whole screen's working
+// set.  Workgroup ids past the last multiple of 8 keep their place.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block(int b, int n) {
+    const int per = n / kXcds;
+    return b < per * kXcds ? (b % kXcds) * per + b / kXcds : b;
+}
+
 // S = stack entries per lane (the scene's stack class).
 template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[S * B];
-    trace_item<B, kCount>(v, (int64_t)blockIdx.x * B + threadIdx.x, stack, counters);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    trace_item<B, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
@@ -494,7 +505,7 @@ __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters) {
     __shared__ int stack[S * B];
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;

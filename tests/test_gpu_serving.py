@@ -142,3 +142,28 @@ def test_poisson_serving_smoke(env, rig):
     log(f"poisson smoke: {len(arr)} requests, {lat}, launches {st['launches']}, refused {refused}")
     assert refused == 0 and lat["completed"] == len(arr)
     s.close()
+
+
+def test_frame_budget_holds_on_device(env, rig):
+    """Four headsets requesting 240 frames/s each (beyond what the device
+    renders): with an 11.1 ms budget every served frame completes within it,
+    once the device-time model has seen a few launches; the rest is dropped
+    as late or replaced, and nothing waits in a growing queue."""
+    torch, V = env
+    s = _server(V, rig, max_inflight=2, n_streams=1, frame_budget_ms=11.1, latest_only=True)
+    gazes = [I.gaze_trace(600, h["layout"].width, h["layout"].height, seed=80 + k) for k, h in enumerate(rig["heads"])]
+    warm = serving.arrival_times(4, 240.0, 0.3, seed_base=11)       # the model learns the device times
+    serving.run(s, V, gazes, warm)
+    st0 = s.stats()
+    arr = serving.arrival_times(4, 240.0, 1.0, seed_base=21)
+    recs, refused, wall = serving.run(s, V, gazes, arr)
+    st = s.stats()
+    lat = serving.latency_stats(recs)
+    late, sup = st["late"] - st0["late"], st["superseded"] - st0["superseded"]
+    log(f"frame budget on device: {lat}, late={late} superseded={sup} refused={refused} "
+        f"launches={st['launches'] - st0['launches']}")
+    assert refused == 0
+    assert lat["completed"] + late + sup == len(arr)
+    assert lat["completed"] > 50
+    assert lat["p99_ms"] <= 11.1
+    s.close()

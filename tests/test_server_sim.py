@@ -103,8 +103,9 @@ def test_deadline_drops_requests_that_cannot_be_admitted(V):
     first = _collect(s, 1)                      # held, never released: memory stays taken
     assert s.submit(0, 1, g, deadline_ms=20.0)
     late = _collect(s, 1)
-    assert len(late) == 1 and late[0]["status"] == V.VAFR_E_BUDGET
-    assert s.stats()["dropped"] == 1
+    assert len(late) == 1 and late[0]["status"] == V.VAFR_E_LATE
+    st = s.stats()
+    assert st["dropped"] == 1 and st["late"] == 1
     s.release(first[0]["slot"])
     s.close()
 
@@ -125,6 +126,46 @@ def test_overload_refuses_when_queue_is_full(V):
     s.close()
 
 
+def test_frame_budget_bounds_latency_under_overload(V):
+    """8 headsets at 90 Hz against a device that needs about 3.9 ms per
+    request (2.8x overload): with an 11.1 ms frame budget and latest-frame
+    replacement, every served request completes within the budget (plus the
+    dispatcher's polling delay); the excess is dropped as late or replaced,
+    never queued."""
+    s, L = _server(V, n_headsets=8, max_queue=64, max_inflight=2, max_views_per_launch=16,
+                   sim_ms_per_launch=0.5, sim_ms_per_mray=1.6, sim_ms_per_mpix=0.0,
+                   frame_budget_ms=11.1, latest_only=True)
+    arr = serving.arrival_times(8, 90.0, 1.0, seed_base=5)
+    gazes = [I.gaze_trace(200, 1280, 720, seed=70 + h) for h in range(8)]
+    recs, refused, wall = serving.run(s, V, gazes, arr)
+    st = s.stats()
+    lat = serving.latency_stats(recs)
+    assert refused == 0
+    assert st["completed"] + st["late"] + st["superseded"] == len(arr)
+    assert st["late"] + st["superseded"] > 0.3 * len(arr)
+    assert lat["completed"] > 100
+    assert lat["max_ms"] < 11.1 + 4.0, lat
+    s.close()
+
+
+def test_latest_only_replaces_waiting_requests(V):
+    """While a 30 ms launch runs, three newer frames of the same headset
+    arrive; only the newest is rendered, the two before it are replaced."""
+    s, L = _server(V, n_headsets=1, max_inflight=1, sim_ms_per_launch=30.0, latest_only=True)
+    g = V.gaze(640.0, 360.0)
+    assert s.submit(0, 0, g)
+    time.sleep(0.005)
+    for f in (1, 2, 3):
+        assert s.submit(0, f, g)
+    s.wait_idle(5000)
+    recs = _collect(s, 4)
+    by_frame = {r["frame"]: r["status"] for r in recs}
+    assert by_frame == {0: 0, 1: V.VAFR_E_LATE, 2: V.VAFR_E_LATE, 3: 0}
+    st = s.stats()
+    assert st["superseded"] == 2 and st["completed"] == 2 and st["launches"] == 2
+    s.close()
+
+
 def test_headset_larger_than_budget_is_rejected(V):
     s = V.Server(simulate=True, hbm_budget_bytes=1 << 20)
     L = V.Layout.vafr(V.display(7680, 4320))
@@ -139,6 +180,7 @@ def test_headset_larger_than_budget_is_rejected(V):
 
 def test_server_config_validation(V):
     for bad in (dict(max_views_per_launch=1), dict(max_inflight=0), dict(n_streams=9), dict(hbm_budget_bytes=0),
-                dict(max_queue=0), dict(sim_ms_per_mray=-1.0)):
+                dict(max_queue=0), dict(sim_ms_per_mray=-1.0), dict(frame_budget_ms=-1.0),
+                dict(frame_budget_ms=float("inf"))):
         with pytest.raises(V.VafrError):
             V.Server(simulate=True, **bad)
