@@ -240,7 +240,8 @@ typedef struct {
 } vafr_view;
 
 /* Launch shape of a batch: traversal workgroup size (64, 128 or 256 rays),
- * reconstruction tile height (1, 2, 4 or 8 rows of 64 pixels) and whether
+ * display rows each reconstruction thread writes (1, 2, 4 or 8; a
+ * workgroup of 256 threads covers 64 x 4 recon_rows pixels) and whether
  * frames are replayed from a hipGraph. */
 typedef struct {
     int32_t trace_block;

@@ -157,7 +157,7 @@ hipKernelNodeParams recon_params(vafr_batch b, const GraphEntry& g, char* dev, v
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(recon_batch_kernel(g.recon_rows));
     p.gridDim = dim3((unsigned)g.recon_blocks);
-    p.blockDim = dim3((unsigned)(64 * g.recon_rows));
+    p.blockDim = dim3((unsigned)kReconThreads);
     p.sharedMemBytes = 0;
     p.kernelParams = args;
     p.extra = nullptr;

@@ -1,14 +1,22 @@
 // Inverse mapping of an LP buffer onto the display (Sec. 3.2.3,
-// Eqs. (10)-(11)), one thread per display pixel.
+// Eqs. (10)-(11)).
 //
-// A workgroup covers a tile of 64 x R display pixels; each wave covers 64
-// consecutive pixels of one row, so the 16-byte RGBA stores of a wave form one
-// contiguous 1 KiB segment; they are non-temporal because the image is
-// written once and not read back here.  The LP buffer (17 MB per VaFR view)
-// is read through the caches: a texel feeds tens of display pixels in the
-// periphery.  The kernel is bound by its arithmetic per pixel (measured), so
-// the forward map is reduced to one radial table lookup and one polynomial
-// angle evaluation.
+// A workgroup of 4 waves covers a tile of 64 x 4P display pixels; each wave
+// writes P rows of 64 consecutive pixels, so the 16-byte RGBA stores of a
+// wave form one contiguous 1 KiB segment per row; they are non-temporal
+// because the image is written once and not read back here.
+//
+// VaFR tiles stage their LP texels in LDS first.  Wave 0 bounds the tile's
+// footprint in the LP buffer -- the columns between the smallest and the
+// largest film radius of the tile and, in each column, the rows between the
+// smallest and the largest polar angle, with one texel of margin -- and the
+// workgroup copies those texels with row-contiguous loads; the four texels
+// of each pixel are then read from LDS.  A texel outside the staged region
+// (not expected, but the bound is computed in floating point) is read from
+// the LP buffer instead, so the result never depends on the bound.  Tiles
+// whose footprint exceeds the LDS budget -- those within a few degrees of
+// the gaze point, where one display pixel maps to about one texel or the
+// tile surrounds the gaze -- read every texel from the LP buffer.
 //
 // Workgroups are mapped XCD-aware: consecutive workgroup ids land on
 // different XCDs, so ids are permuted such that each XCD receives a
@@ -20,7 +28,12 @@ namespace vafr {
 namespace {
 
 constexpr int kTileW = 64;
+constexpr int kWaves = kReconThreads / 64;
 constexpr int kXcds = 8;
+// LDS budget of one tile: staged texels and staged columns (one per lane of
+// the wave that builds the column table).
+constexpr int kStageTexels = 1024;
+constexpr int kStageCols = 64;
 
 // Workgroup id (within one view) -> tile, so that XCD q (= id mod 8) gets the
 // q-th contiguous eighth of the tiles in row-major order.
@@ -31,8 +44,8 @@ __device__ __forceinline__ void xcd_tile(int id, int nbx, int nby, int& bx, int&
         const int per = n / kXcds;
         if (id < per * kXcds) t = (id % kXcds) * per + id / kXcds;
     }
-    bx = t % nbx;
     by = t / nbx;
+    bx = t - by * nbx;
 }
 
 // Buffer-resource access: 32-bit byte offsets from a uniform base keep the
@@ -86,13 +99,15 @@ __device__ __forceinline__ float angle_turns(float dx, float dy) {
     return r;
 }
 
-// Rows j0, j1 and weight t of angular interpolation in a column of n rows.
+// Rows j0, j1 = j0 + 1 (mod n) and weight t of angular interpolation in a
+// column of n rows, for turns in [0, 1]: s = turns n - 0.5 lies in
+// [-0.5, n - 0.5], so floor(s) is in [-1, n - 1] and only -1 wraps.
 __device__ __forceinline__ void column_rows(int n, float turns, int& j0, int& j1, float& t) {
     const float s = fmaf(turns, (float)n, -0.5f);
     const float fs = floorf(s);
     t = s - fs;
     j0 = (int)fs;
-    j0 = j0 < 0 ? j0 + n : (j0 >= n ? j0 - n : j0);
+    j0 = j0 < 0 ? j0 + n : j0;
     j1 = j0 + 1 == n ? 0 : j0 + 1;
 }
 
@@ -105,35 +120,90 @@ __device__ __forceinline__ float4 blend4(float4 a, float wa, float4 b, float wb,
                        fmaf(wd, d.w, fmaf(wc, c.w, fmaf(wb, b.w, wa * a.w))));
 }
 
-__device__ __forceinline__ float4 sample_vafr(const ReconView& v, float dx, float dy) {
-    const __amdgpu_buffer_rsrc_t lp = rsrc(v.lp, v.lp_bytes);
-    const __amdgpu_buffer_rsrc_t ut = rsrc(v.u_of_rho, (kURhoN + 1) * 8);
-    const __amdgpu_buffer_rsrc_t ct = rsrc(v.col, (uint32_t)v.n_cols * 8);
-    const float rho = __builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy));
-    // u(e(rho)) (Eqs. (3), (5), (12)) from the FP64-built radial table,
-    // already clamped to the first and last column centres.
+// Column coordinate a = u(e(rho)) - 0.5 (Eqs. (3), (5), (12)) from the
+// FP64-built radial table, already clamped to the first and last column
+// centres.
+__device__ __forceinline__ float column_coord(const ReconView& v, __amdgpu_buffer_rsrc_t ut, float rho) {
     const float tq = fminf(rho * v.rho_scale, (float)kURhoN);
     const int k = (int)tq;
     const v2u uk = ld2(ut, (uint32_t)k * 8u);
-    const float a = fmaf(tq - (float)k, __uint_as_float(uk.y), __uint_as_float(uk.x)) - 0.5f;
+    return fmaf(tq - (float)k, __uint_as_float(uk.y), __uint_as_float(uk.x)) - 0.5f;
+}
+
+// One staged column: LP offset and row count of the column, staged rows
+// j_start .. j_start + cnt - 1 (mod n) at LDS texels base .. base + cnt - 1.
+struct StageCol {
+    uint32_t off;
+    uint32_t n_cnt;     // n | cnt << 16
+    uint32_t js_base;   // j_start | base << 16
+};
+
+struct Stage {
+    float4 tex[kStageTexels];
+    StageCol col[kStageCols];
+    int base[kStageCols];   // first LDS texel of each staged column (ascending)
+    int i_lo, n_cols;       // staged columns i_lo .. i_lo + n_cols - 1 (n_cols = 0: nothing staged)
+    int total;              // staged texels
+};
+
+// Texel j of the column described by (off, n, j_start, cnt, base): from LDS
+// when staged, else from the LP buffer.
+__device__ __forceinline__ float4 texel(const Stage& st, __amdgpu_buffer_rsrc_t lp, uint32_t off, int n, int js,
+                                        int cnt, int base, int j) {
+    int rel = j - js;
+    rel = rel < 0 ? rel + n : rel;
+    if (rel < cnt) return st.tex[base + rel];
+    return ld4(lp, (off + (uint32_t)j) * 16u);
+}
+
+// Column i's (offset, rows, staged range): staged columns from LDS, others
+// from the column table with an empty staged range.
+__device__ __forceinline__ void column_of(const Stage& st, __amdgpu_buffer_rsrc_t ct, int i, uint32_t& off, int& n,
+                                          int& js, int& cnt, int& base) {
+    const int c = i - st.i_lo;
+    if ((unsigned)c < (unsigned)st.n_cols) {
+        const StageCol sc = st.col[c];
+        off = sc.off;
+        n = (int)(sc.n_cnt & 0xffffu);
+        cnt = (int)(sc.n_cnt >> 16);
+        js = (int)(sc.js_base & 0xffffu);
+        base = (int)(sc.js_base >> 16);
+    } else {
+        const v2u c2 = ld2(ct, (uint32_t)i * 8u);
+        n = (int)c2.x;
+        off = c2.y;
+        js = 0;
+        cnt = 0;
+        base = 0;
+    }
+}
+
+// Pixel at film offset (dx, dy) from the gaze point whose column coordinate
+// a = u - 0.5 is already known.
+__device__ __forceinline__ float4 sample_vafr(const ReconView& v, const Stage& st, __amdgpu_buffer_rsrc_t lp,
+                                              __amdgpu_buffer_rsrc_t ct, float dx, float dy, float a) {
     int i0 = (int)a;
     i0 = i0 > v.n_cols - 1 ? v.n_cols - 1 : (i0 < 0 ? 0 : i0);
     const int i1 = i0 + 1 < v.n_cols ? i0 + 1 : v.n_cols - 1;
     const float w = a - (float)i0;
     const float turns = angle_turns(dx, dy);
-    const v2u c0 = ld2(ct, (uint32_t)i0 * 8u), c1 = ld2(ct, (uint32_t)i1 * 8u);
+    uint32_t off0, off1;
+    int n0, js0, cnt0, base0, n1, js1, cnt1, base1;
+    column_of(st, ct, i0, off0, n0, js0, cnt0, base0);
+    column_of(st, ct, i1, off1, n1, js1, cnt1, base1);
     int j00, j01, j10, j11;
     float t0, t1;
-    column_rows((int)c0.x, turns, j00, j01, t0);
-    column_rows((int)c1.x, turns, j10, j11, t1);
-    const float4 A = ld4(lp, (c0.y + (uint32_t)j00) * 16u), B = ld4(lp, (c0.y + (uint32_t)j01) * 16u);
-    const float4 C = ld4(lp, (c1.y + (uint32_t)j10) * 16u), D = ld4(lp, (c1.y + (uint32_t)j11) * 16u);
+    column_rows(n0, turns, j00, j01, t0);
+    column_rows(n1, turns, j10, j11, t1);
+    const float4 A = texel(st, lp, off0, n0, js0, cnt0, base0, j00);
+    const float4 B = texel(st, lp, off0, n0, js0, cnt0, base0, j01);
+    const float4 C = texel(st, lp, off1, n1, js1, cnt1, base1, j10);
+    const float4 D = texel(st, lp, off1, n1, js1, cnt1, base1, j11);
     const float w0 = 1.0f - w;
     return blend4(A, w0 - w0 * t0, B, w0 * t0, C, w - w * t1, D, w * t1);
 }
 
-__device__ __forceinline__ float4 sample_lmfr(const ReconView& v, float dx, float dy) {
-    const __amdgpu_buffer_rsrc_t lp = rsrc(v.lp, v.lp_bytes);
+__device__ __forceinline__ float4 sample_lmfr(const ReconView& v, __amdgpu_buffer_rsrc_t lp, float dx, float dy) {
     const float r = fmaxf(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)), 1.0f);
     const float z = __log2f(r) * v.inv_L;                     // Eq. (1); inv_L = ln 2 / L
     float u = (v.alpha == 4.0f ? (z * z) * (z * z) : __powf(z, v.alpha)) * (float)v.n_cols;   // Eq. (14)
@@ -152,41 +222,196 @@ __device__ __forceinline__ float4 sample_lmfr(const ReconView& v, float dx, floa
                   ld4(lp, (o1 + j0) * 16u), w - w * t, ld4(lp, (o1 + j1) * 16u), w * t);
 }
 
-// Pixel tile `id` of view v: 64 x R pixels, one per thread.  M is the
-// mapping (kModeVafr / kModeLmfr) or -1 to read it from the view.
-template <int R, int M>
-__device__ __forceinline__ void recon_tile(const ReconView& v, int id) {
-    const int nbx = (v.width + kTileW - 1) / kTileW, nby = (v.height + R - 1) / R;
-    int bx, by;
-    xcd_tile(id, nbx, nby, bx, by);
-    const int x = bx * kTileW + (threadIdx.x & (kTileW - 1));
-    const int ty = threadIdx.x / kTileW;
-    const int y = by * R + ty;
-    if (x >= v.width || y >= v.height) return;
-    // offset of the pixel centre from the gaze point: film units for VaFR,
-    // pixels for LMFR (cx, cy hold the gaze and the half-pixel shift)
-    const float dx = fmaf((float)x, v.sx, v.cx), dy = fmaf((float)y, v.sy, v.cy);
-    const int mode = M >= 0 ? M : v.mode;
-    const float4 c = mode == kModeVafr ? sample_vafr(v, dx, dy) : sample_lmfr(v, dx, dy);
-    // the tile's rows start at a uniform base; offsets stay 32-bit
-    const __amdgpu_buffer_rsrc_t img = rsrc(v.img + (size_t)by * R * v.width, (uint32_t)(R * v.width) * 16u);
-    store_px(img, (uint32_t)(ty * v.width + x) * 16u, c);
+// Wave 0: the staged columns of the tile whose pixel centres span film
+// offsets [xl, xh] x [yl, yh] from the gaze point, written to st.col, and
+// st.i_lo / st.n_cols (n_cols = 0 when the footprint does not fit).
+__device__ void build_stage(const ReconView& v, Stage& st, __amdgpu_buffer_rsrc_t ut, __amdgpu_buffer_rsrc_t ct,
+                            float xl, float xh, float yl, float yh) {
+    const int lane = threadIdx.x;
+    int n_cols = 0, i_lo = 0, total = 0;
+    const bool around_gaze = xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f;
+    if (!around_gaze) {
+        // radius range: nearest point of the rectangle and farthest corner
+        const float qx = fminf(fmaxf(0.0f, xl), xh), qy = fminf(fmaxf(0.0f, yl), yh);
+        const float fx = fmaxf(fabsf(xl), fabsf(xh)), fy = fmaxf(fabsf(yl), fabsf(yh));
+        const float r_lo = __builtin_amdgcn_sqrtf(fmaf(qx, qx, qy * qy));
+        const float r_hi = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fy * fy));
+        const int c_lo = (int)column_coord(v, ut, r_lo) - 1;
+        const int c_hi = (int)column_coord(v, ut, r_hi) + 2;
+        i_lo = c_lo < 0 ? 0 : c_lo;
+        const int i_hi = c_hi > v.n_cols - 1 ? v.n_cols - 1 : c_hi;
+        n_cols = i_hi - i_lo + 1;
+        // angle range: the rectangle does not hold the gaze point, so the
+        // extreme angles are those of its corners (taken about the centre
+        // direction, which keeps the range unwrapped)
+        const float ref = angle_turns(0.5f * (xl + xh), 0.5f * (yl + yh));
+        float lo = 0.0f, hi = 0.0f;
+        const float cxs[4] = {xl, xh, xl, xh}, cys[4] = {yl, yl, yh, yh};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            float d = angle_turns(cxs[k], cys[k]) - ref;
+            d = d >= 0.5f ? d - 1.0f : (d < -0.5f ? d + 1.0f : d);
+            lo = fminf(lo, d);
+            hi = fmaxf(hi, d);
+        }
+        lo += ref;
+        hi += ref;
+        if (n_cols > kStageCols) n_cols = 0;
+        int cnt = 0, js = 0, n = 0;
+        uint32_t off = 0;
+        if (lane < n_cols) {
+            const v2u c2 = ld2(ct, (uint32_t)(i_lo + lane) * 8u);
+            n = (int)c2.x;
+            off = c2.y;
+            if (n > 0xffff) n_cols = 0;   // the packed column record holds 16-bit row counts
+            const int j_lo = (int)floorf(fmaf(lo, (float)n, -0.5f)) - 1;
+            const int j_hi = (int)floorf(fmaf(hi, (float)n, -0.5f)) + 2;
+            cnt = j_hi - j_lo + 1;
+            if (cnt >= n) {
+                cnt = n;
+                js = 0;
+            } else {
+                js = j_lo % n;
+                js = js < 0 ? js + n : js;
+            }
+        }
+        // exclusive prefix sum of the counts over the wave
+        int incl = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int o = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += o;
+        }
+        total = __shfl(incl, 63, 64);
+        if (total > kStageTexels || __ballot(n_cols == 0) != 0) n_cols = 0;
+        if (n_cols == 0) total = 0;
+        if (lane < n_cols) {
+            StageCol sc;
+            sc.off = off;
+            sc.n_cnt = (uint32_t)n | ((uint32_t)cnt << 16);
+            sc.js_base = (uint32_t)js | ((uint32_t)(incl - cnt) << 16);
+            st.col[lane] = sc;
+            st.base[lane] = incl - cnt;
+        }
+    }
+    if (lane == 0) {
+        st.i_lo = i_lo;
+        st.n_cols = n_cols;
+        st.total = total;
+    }
 }
 
-template <int R, int M>
-__global__ __launch_bounds__(kTileW* R) void k_recon(const ReconView v) {
-    recon_tile<R, M>(v, blockIdx.x);
+// Staged texel k: its column (binary search over the column bases) and its
+// LP offset.
+__device__ __forceinline__ uint32_t stage_source(const Stage& st, int k) {
+    int lo = 0, hi = st.n_cols - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st.base[mid] <= k) lo = mid;
+        else hi = mid - 1;
+    }
+    const StageCol sc = st.col[lo];
+    const int n = (int)(sc.n_cnt & 0xffffu), js = (int)(sc.js_base & 0xffffu);
+    int j = js + (k - st.base[lo]);
+    j = j >= n ? j - n : j;
+    return sc.off + (uint32_t)j;
+}
+
+// Thread t copies staged texels t, t + 256, ...: all of its loads are issued
+// before the first LDS write, so the copy costs one memory latency.
+__device__ __forceinline__ void fill_stage(Stage& st, __amdgpu_buffer_rsrc_t lp) {
+    constexpr int kPer = kStageTexels / kReconThreads;
+    const int total = st.total;
+    float4 t[kPer];
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        const int k = threadIdx.x + m * kReconThreads;
+        if (k < total) t[m] = ld4(lp, stage_source(st, k) * 16u);
+    }
+#pragma unroll
+    for (int m = 0; m < kPer; ++m) {
+        const int k = threadIdx.x + m * kReconThreads;
+        if (k < total) st.tex[k] = t[m];
+    }
+}
+
+// Tile `id` of view v: 64 x 4P pixels, P rows per wave.  M is the mapping
+// (kModeVafr / kModeLmfr) or -1 to read it from the view.
+template <int P, int M>
+__device__ __forceinline__ void recon_tile(const ReconView& v, int id, Stage& st) {
+    constexpr int kTileH = kWaves * P;
+    const int nbx = (v.width + kTileW - 1) / kTileW, nby = (v.height + kTileH - 1) / kTileH;
+    int bx, by;
+    xcd_tile(id, nbx, nby, bx, by);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int x = bx * kTileW + lane;
+    const int y0 = by * kTileH;
+    const int mode = M >= 0 ? M : v.mode;
+    const __amdgpu_buffer_rsrc_t lp = rsrc(v.lp, v.lp_bytes);
+    // the tile's rows start at a uniform base; offsets stay 32-bit
+    const int rows = v.height - y0 < kTileH ? v.height - y0 : kTileH;
+    const __amdgpu_buffer_rsrc_t img = rsrc(v.img + (size_t)y0 * v.width, (uint32_t)(rows * v.width) * 16u);
+    if (mode == kModeVafr) {
+        const __amdgpu_buffer_rsrc_t ut = rsrc(v.u_of_rho, (kURhoN + 1) * 8);
+        const __amdgpu_buffer_rsrc_t ct = rsrc(v.col, (uint32_t)v.n_cols * 8);
+        if (wave == 0) {
+            const int x_hi = bx * kTileW + kTileW - 1 < v.width - 1 ? bx * kTileW + kTileW - 1 : v.width - 1;
+            build_stage(v, st, ut, ct, fmaf((float)(bx * kTileW), v.sx, v.cx), fmaf((float)x_hi, v.sx, v.cx),
+                        fmaf((float)y0, v.sy, v.cy), fmaf((float)(y0 + rows - 1), v.sy, v.cy));
+        }
+        __syncthreads();
+        fill_stage(st, lp);
+        __syncthreads();
+        if (x >= v.width) return;
+        const float dx = fmaf((float)x, v.sx, v.cx);
+        // the radial table entries of all P pixels are loaded before the
+        // first store, so their latencies overlap
+        float tq[P];
+        v2u uk[P];
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const float dy = fmaf((float)(y0 + wave * P + r), v.sy, v.cy);
+            tq[r] = fminf(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)) * v.rho_scale, (float)kURhoN);
+            uk[r] = ld2(ut, (uint32_t)(int)tq[r] * 8u);
+        }
+#pragma unroll
+        for (int r = 0; r < P; ++r) {
+            const int ty = wave * P + r;
+            if (ty < rows) {
+                const float dy = fmaf((float)(y0 + ty), v.sy, v.cy);
+                const float k = (float)(int)tq[r];
+                const float a = fmaf(tq[r] - k, __uint_as_float(uk[r].y), __uint_as_float(uk[r].x)) - 0.5f;
+                store_px(img, (uint32_t)(ty * v.width + x) * 16u, sample_vafr(v, st, lp, ct, dx, dy, a));
+            }
+        }
+    } else {
+        if (x >= v.width) return;
+        const float dx = fmaf((float)x, v.sx, v.cx);
+        for (int r = 0; r < P; ++r) {
+            const int ty = wave * P + r;
+            if (ty >= rows) break;
+            const float dy = fmaf((float)(y0 + ty), v.sy, v.cy);
+            store_px(img, (uint32_t)(ty * v.width + x) * 16u, sample_lmfr(v, lp, dx, dy));
+        }
+    }
+}
+
+template <int P, int M>
+__global__ __launch_bounds__(kReconThreads) void k_recon(const ReconView v) {
+    __shared__ Stage st;
+    recon_tile<P, M>(v, blockIdx.x, st);
 }
 
 // Batched launch over several views (block_end: running tile counts).
-template <int R>
-__global__ __launch_bounds__(kTileW* R) void k_recon_batch(const ReconView* __restrict__ views,
-                                                         const int32_t* __restrict__ block_end, int32_t n_views) {
+template <int P>
+__global__ __launch_bounds__(kReconThreads) void k_recon_batch(const ReconView* __restrict__ views,
+                                                             const int32_t* __restrict__ block_end, int32_t n_views) {
+    __shared__ Stage st;
     const int b = blockIdx.x;
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    recon_tile<R, -1>(views[vid], b - first);
+    recon_tile<P, -1>(views[vid], b - first, st);
 }
 
 }  // namespace
@@ -194,27 +419,28 @@ __global__ __launch_bounds__(kTileW* R) void k_recon_batch(const ReconView* __re
 bool recon_rows_ok(int rows) { return rows == 1 || rows == 2 || rows == 4 || rows == 8; }
 
 int64_t recon_blocks_of(const ReconView& v, int rows) {
-    return (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + rows - 1) / rows);
+    const int tile_h = kWaves * rows;
+    return (int64_t)((v.width + kTileW - 1) / kTileW) * ((v.height + tile_h - 1) / tile_h);
 }
 
 int launch_reconstruct(const ReconView& v, hipStream_t stream, int rows) {
-    if (!recon_rows_ok(rows)) return fail(VAFR_E_ARG, "reconstruction tile height must be 1, 2, 4 or 8");
+    if (!recon_rows_ok(rows)) return fail(VAFR_E_ARG, "reconstruction rows per thread must be 1, 2, 4 or 8");
     const int64_t blocks = recon_blocks_of(v, rows);
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "display too large");
-    const dim3 g((unsigned)blocks);
+    const dim3 g((unsigned)blocks), t(kReconThreads);
     if (v.mode == kModeVafr) {
         switch (rows) {
-            case 1: hipLaunchKernelGGL((k_recon<1, kModeVafr>), g, dim3(kTileW * 1), 0, stream, v); break;
-            case 2: hipLaunchKernelGGL((k_recon<2, kModeVafr>), g, dim3(kTileW * 2), 0, stream, v); break;
-            case 4: hipLaunchKernelGGL((k_recon<4, kModeVafr>), g, dim3(kTileW * 4), 0, stream, v); break;
-            default: hipLaunchKernelGGL((k_recon<8, kModeVafr>), g, dim3(kTileW * 8), 0, stream, v); break;
+            case 1: hipLaunchKernelGGL((k_recon<1, kModeVafr>), g, t, 0, stream, v); break;
+            case 2: hipLaunchKernelGGL((k_recon<2, kModeVafr>), g, t, 0, stream, v); break;
+            case 4: hipLaunchKernelGGL((k_recon<4, kModeVafr>), g, t, 0, stream, v); break;
+            default: hipLaunchKernelGGL((k_recon<8, kModeVafr>), g, t, 0, stream, v); break;
         }
     } else {
         switch (rows) {
-            case 1: hipLaunchKernelGGL((k_recon<1, kModeLmfr>), g, dim3(kTileW * 1), 0, stream, v); break;
-            case 2: hipLaunchKernelGGL((k_recon<2, kModeLmfr>), g, dim3(kTileW * 2), 0, stream, v); break;
-            case 4: hipLaunchKernelGGL((k_recon<4, kModeLmfr>), g, dim3(kTileW * 4), 0, stream, v); break;
-            default: hipLaunchKernelGGL((k_recon<8, kModeLmfr>), g, dim3(kTileW * 8), 0, stream, v); break;
+            case 1: hipLaunchKernelGGL((k_recon<1, kModeLmfr>), g, t, 0, stream, v); break;
+            case 2: hipLaunchKernelGGL((k_recon<2, kModeLmfr>), g, t, 0, stream, v); break;
+            case 4: hipLaunchKernelGGL((k_recon<4, kModeLmfr>), g, t, 0, stream, v); break;
+            default: hipLaunchKernelGGL((k_recon<8, kModeLmfr>), g, t, 0, stream, v); break;
         }
     }
     VAFR_HIP(hipGetLastError());
@@ -234,13 +460,13 @@ const void* recon_batch_kernel(int rows) {
 int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_end_dev, int32_t n_views,
                              int32_t blocks, int rows, hipStream_t stream) {
     if (blocks <= 0) return VAFR_OK;
-    if (!recon_rows_ok(rows)) return fail(VAFR_E_ARG, "reconstruction tile height must be 1, 2, 4 or 8");
-    const dim3 g((unsigned)blocks);
+    if (!recon_rows_ok(rows)) return fail(VAFR_E_ARG, "reconstruction rows per thread must be 1, 2, 4 or 8");
+    const dim3 g((unsigned)blocks), t(kReconThreads);
     switch (rows) {
-        case 1: hipLaunchKernelGGL(k_recon_batch<1>, g, dim3(kTileW * 1), 0, stream, views_dev, block_end_dev, n_views); break;
-        case 2: hipLaunchKernelGGL(k_recon_batch<2>, g, dim3(kTileW * 2), 0, stream, views_dev, block_end_dev, n_views); break;
-        case 4: hipLaunchKernelGGL(k_recon_batch<4>, g, dim3(kTileW * 4), 0, stream, views_dev, block_end_dev, n_views); break;
-        default: hipLaunchKernelGGL(k_recon_batch<8>, g, dim3(kTileW * 8), 0, stream, views_dev, block_end_dev, n_views); break;
+        case 1: hipLaunchKernelGGL(k_recon_batch<1>, g, t, 0, stream, views_dev, block_end_dev, n_views); break;
+        case 2: hipLaunchKernelGGL(k_recon_batch<2>, g, t, 0, stream, views_dev, block_end_dev, n_views); break;
+        case 4: hipLaunchKernelGGL(k_recon_batch<4>, g, t, 0, stream, views_dev, block_end_dev, n_views); break;
+        default: hipLaunchKernelGGL(k_recon_batch<8>, g, t, 0, stream, views_dev, block_end_dev, n_views); break;
     }
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
