@@ -35,19 +35,21 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
 # Algorithmic FP32 operations of one unit of traversal work, counted from the
-# method's arithmetic:
-#  - one node visit tests two child boxes: per child 6 subtractions and 6
-#    multiplies for the slab distances, 6 min/max per axis, 4 min/max to
+# arithmetic the traversal performs:
+#  - one node visit tests two child boxes: per child 6 FMAs for the slab
+#    distances (plane * 1/d - o/d; the benchmark's eyes are within the range
+#    where this form is conservative), 6 min/max per axis, 4 min/max to
 #    combine axes and clamp, 1 multiply (conservative exit) and 1 compare;
-#    plus 1 compare to order the children -> 2 * 24 + 1 = 49
+#    plus 1 compare to order the children -> 2 * 18 + 1 = 37
 #  - one watertight ray/triangle test: 9 subtractions (vertices - origin),
 #    6 FMAs (shear), 6 multiplies + 3 subtractions (edge functions), 2 adds
 #    (det), 3 multiplies (z scaling), 3 multiplies + 2 adds (T), 1 division,
 #    4 compares -> 39
-#  - ray set-up: 3 reciprocals, 3 divisions, 8 compares/selects -> 14
-OPS_NODE = 49
+#  - ray set-up: 3 reciprocals, 3 multiplies (o/d), 3 divisions, 8
+#    compares/selects -> 17
+OPS_NODE = 37
 OPS_TRI = 39
-OPS_RAY = 14
+OPS_RAY = 17
 
 
 def log(msg):
