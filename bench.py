@@ -277,6 +277,7 @@ def main():
     # ------------------------------------------------------------ 16 views
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
+        out["layouts"] = layout_variants(torch, V, I, scene, sh, cams, gazes[warm:], max(20, csteps))
 
     # ------------------------------------------------------------ serving
     if args.serve_seconds > 0:
@@ -377,6 +378,49 @@ def batch16(torch, V, I, scene, sh, steps):
     b.close()
     return {"views": 16, "display_mpix": round(pixels / 1e6, 2), "batched_fps": round(res["batched"], 3),
             "plain_fps": round(res["plain"], 3), "speedup": round(res["batched"] / res["plain"], 3), "shape": shape}
+
+
+# Tangential-to-radial shading-rate ratio used to measure Eq. (19): 1 at the
+# fovea, falling linearly to 1/2 at 30 deg (the sensitivity ratio the paper
+# quotes there) and 1/2 beyond.
+ANISO_EXAMPLE = ((0.0, 30.0), (1.0, 0.5))
+
+
+def layout_variants(torch, V, I, scene, sh, cams, gazes, steps):
+    """Binocular 8K batched frames for the paper's layout and its variants:
+    device-adapted curves held at 9 and 18 cpd (Sec. 3.3) and an
+    anisotropic tangential rate (Eq. (19)).  Same scene, cameras and gaze
+    trace; launch shape fixed (trace 64, reconstruction 8 rows)."""
+    variants = {"standard": V.Layout.vafr(V.display(W, H, I.FOV))}
+    for cap in (9.0, 18.0):
+        e, c = V.acuity_capped(cap)
+        variants[f"cap{cap:g}cpd"] = V.Layout.vafr(V.display(W, H, I.FOV), e, c, 60.0)
+    variants["anisotropic"] = V.Layout.vafr(V.display(W, H, I.FOV), aniso=ANISO_EXAMPLE)
+    img = [torch.empty((H * W, 4), device="cuda") for _ in range(2)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, Lv in variants.items():
+        lp = [torch.empty((Lv.n_texels, 4), device="cuda") for _ in range(2)]
+        b = V.Batch(2, trace_block=64, recon_rows=8, use_graph=True)
+
+        def frame(f):
+            g = gazes[f % len(gazes)]
+            b.run([V.view(V.VAFR_VIEW_VAFR, scene, cams[e], g, sh, layout=Lv, lp_rgba=lp[e], img_rgba=img[e])
+                   for e in range(2)], stream)
+
+        for f in range(3):
+            frame(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(steps):
+            frame(f)
+        torch.cuda.synchronize()
+        fps = steps / (time.perf_counter() - t0)
+        res[name] = {"columns": Lv.n_cols, "texels_per_eye": Lv.n_texels, "fps": round(fps, 2)}
+        log(f"layout {name}: {Lv.n_cols} columns, {Lv.n_texels} texels per eye, {fps:.1f} frames/s")
+        b.close()
+        del lp
+    return res
 
 
 def serving_bench(torch, V, I, scene4m, seconds):

@@ -65,13 +65,32 @@ typedef struct {
  * (ecc_deg[k], cpd[k]); ecc_deg[0] must be 0 and strictly increasing;
  * cpd > 0; 2 <= n_pivots <= 16; 0 < e_max_deg < 90.  Passing NULL for the
  * acuity selects the paper's pivots {0,10,20,30,60} deg -> {40,10,6,5,4} cpd
- * and e_max = 60 deg (Sec. 3.2.2). */
+ * and e_max = 60 deg (Sec. 3.2.2), isotropic.
+ *
+ * Anisotropy (Sec. 9, Eq. (19)): the tangential shading rate is Delta(e)
+ * times the radial one, so column i gets ceil(Delta(e_i) l(e_i)) rows.
+ * Delta is linear between (aniso_ecc_deg[k], aniso_delta[k]) and constant
+ * before the first and after the last point; 0 <= n_aniso <= 16 (0: Delta =
+ * 1), eccentricities strictly increasing, 0 < delta <= 16. */
 typedef struct {
     int32_t n_pivots;
     const double* ecc_deg;
     const double* cpd;
     double e_max_deg;
+    int32_t n_aniso;
+    const double* aniso_ecc_deg;
+    const double* aniso_delta;
 } vafr_acuity;
+
+/* Device-adapted curve (Sec. 3.3): pivots of f_cap(e) = min(f(e), cap_cpd)
+ * for the pivot curve `in` (NULL: the paper's pivots).  The MAR of f_cap is
+ * max(1/f, 1/cap): each original pivot keeps its eccentricity with
+ * min(cpd, cap), and a pivot is inserted where a segment's MAR crosses
+ * 1/cap.  Writes *n_out <= max_out pivots to ecc_out / cpd_out (e_max and
+ * anisotropy of `in` are not copied).  Errors: VAFR_E_ARG for an invalid
+ * curve, cap <= 0 or max_out too small. */
+int vafr_acuity_capped(const vafr_acuity* in, double cap_cpd, double* ecc_out, double* cpd_out, int32_t max_out,
+                       int32_t* n_out);
 
 /* Pinhole camera: eye position and an orthonormal basis; the film plane is
  * at unit distance along forward, film y points along -up. */
@@ -128,7 +147,8 @@ typedef struct vafr_scene_s* vafr_scene;
 
 /* VaFR LP layout (Sec. 3.2.1-3.2.3, Sec. 3.3 Eq. (12)): FP64 segment
  * constants of u(e) (Eq. (5)), ceil(u(e_max)) columns sampled at their
- * centres, n_i = ceil(l(e_i)) rows (Eq. (9)) at polar angles
+ * centres, n_i = ceil(l(e_i)) rows (Eq. (9); ceil(Delta(e_i) l(e_i)) with
+ * anisotropy, Eq. (19)) at polar angles
  * 360 (j + 1/2)/n_i, and per texel the FP32 film-plane offset
  * tan(e_i) (cos, sin) of its screen point from the gaze point.  The tables do
  * not depend on the display; the display fixes the pixel pitch used by

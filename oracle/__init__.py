@@ -60,6 +60,9 @@ def _declare(L):
         "or_get_threads": (C.c_int, []),
         "or_acuity_size": (C.c_int, []),
         "or_acuity_init": (C.c_int, [_P, C.c_int, _P, _P]),
+        "or_acuity_set_aniso": (C.c_int, [_P, C.c_int, _P, _P]),
+        "or_delta": (_D, [_P, _D]),
+        "or_acuity_capped": (C.c_int, [C.c_int, _P, _P, _D, _P, _P, C.c_int]),
         "or_omega": (_D, [_P, _D]),
         "or_u": (_D, [_P, _D]),
         "or_e_of_u": (_D, [_P, _D]),
@@ -125,7 +128,9 @@ def get_threads() -> int:
 class Acuity:
     """Piecewise-linear MAR through acuity pivots (Sec. 3.3, Eq. (12))."""
 
-    def __init__(self, ecc=DEFAULT_ECC, cpd=DEFAULT_CPD):
+    def __init__(self, ecc=DEFAULT_ECC, cpd=DEFAULT_CPD, aniso=None):
+        """aniso: optional (ecc, delta) table of the tangential-to-radial
+        shading-rate ratio Delta(e) of Eq. (19)."""
         L = lib()
         self._buf = C.create_string_buffer(L.or_acuity_size())
         self.ecc = _arr(ecc, np.float64)
@@ -133,6 +138,11 @@ class Acuity:
         rc = L.or_acuity_init(self._buf, len(self.ecc), _ptr(self.ecc), _ptr(self.cpd))
         if rc != 0:
             raise ValueError("invalid acuity pivots")
+        if aniso is not None:
+            self.aniso_e = _arr(aniso[0], np.float64)
+            self.aniso_d = _arr(aniso[1], np.float64)
+            if L.or_acuity_set_aniso(self._buf, len(self.aniso_e), _ptr(self.aniso_e), _ptr(self.aniso_d)) != 0:
+                raise ValueError("invalid anisotropy table")
 
     @property
     def ptr(self):
@@ -158,6 +168,21 @@ class Acuity:
 
     def v(self, e, theta):
         return float(lib().or_v(self.ptr, float(e), float(theta)))
+
+    def delta(self, e):
+        return np.array([lib().or_delta(self.ptr, float(x)) for x in np.atleast_1d(e)])
+
+
+def acuity_capped(cap, ecc=DEFAULT_ECC, cpd=DEFAULT_CPD):
+    """Pivots of the device-adapted curve f_cap(e) = min(f(e), cap) (Sec. 3.3)."""
+    ecc = _arr(ecc, np.float64)
+    cpd = _arr(cpd, np.float64)
+    eo = np.empty(2 * len(ecc), np.float64)
+    co = np.empty(2 * len(ecc), np.float64)
+    n = lib().or_acuity_capped(len(ecc), _ptr(ecc), _ptr(cpd), float(cap), _ptr(eo), _ptr(co), len(eo))
+    if n < 0:
+        raise ValueError("invalid curve or cap")
+    return eo[:n].copy(), co[:n].copy()
 
 
 class Layout:

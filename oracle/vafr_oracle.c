@@ -69,6 +69,12 @@ typedef struct {
     double b[OR_MAX_SEG];         /* MAR intercept: omega_k(e) = m e + b     */
     double c[OR_MAX_SEG];         /* additive constant of u on segment k     */
     double u_piv[OR_MAX_SEG + 1]; /* u at each pivot                         */
+    /* Anisotropy, Eq. (19): tangential over radial shading rate Delta(e),
+     * linear between (aniso_e[k], aniso_d[k]), constant outside; n_aniso = 0
+     * means Delta = 1. */
+    int n_aniso;
+    double aniso_e[OR_MAX_SEG + 1];
+    double aniso_d[OR_MAX_SEG + 1];
 } or_acuity;
 
 int or_acuity_size(void) { return (int)sizeof(or_acuity); }
@@ -111,6 +117,55 @@ int or_acuity_init(or_acuity* a, int n_piv, const double* ecc, const double* cpd
         a->u_piv[k + 1] = seg_u_raw(a, k, a->e_piv[k + 1]) + a->c[k];
     }
     return 0;
+}
+
+/* Eq. (19) multiplies the tangential coordinate v by Delta(e).  The paper
+ * gives Delta no functional form; it is taken as a piecewise-linear table. */
+int or_acuity_set_aniso(or_acuity* a, int n, const double* ecc, const double* delta) {
+    if (n < 0 || n > OR_MAX_SEG + 1) return -1;
+    for (int k = 0; k < n; ++k) {
+        if (!(delta[k] > 0.0)) return -1;
+        if (k > 0 && !(ecc[k] > ecc[k - 1])) return -1;
+        a->aniso_e[k] = ecc[k];
+        a->aniso_d[k] = delta[k];
+    }
+    a->n_aniso = n;
+    return 0;
+}
+
+double or_delta(const or_acuity* a, double e) {
+    if (a->n_aniso == 0) return 1.0;
+    if (e <= a->aniso_e[0]) return a->aniso_d[0];
+    for (int k = 0; k + 1 < a->n_aniso; ++k) {
+        if (e < a->aniso_e[k + 1]) {
+            double t = (e - a->aniso_e[k]) / (a->aniso_e[k + 1] - a->aniso_e[k]);
+            return a->aniso_d[k] + t * (a->aniso_d[k + 1] - a->aniso_d[k]);
+        }
+    }
+    return a->aniso_d[a->n_aniso - 1];
+}
+
+/* Device-adapted curve (Sec. 3.3): the acuity f(e) is held at the display's
+ * limit, f_cap(e) = min(f(e), cap).  On each segment the MAR 1/f is linear,
+ * so 1/f_cap = max(MAR, 1/cap) is linear too except where MAR crosses 1/cap;
+ * that crossing becomes a new pivot.  Returns the number of pivots written
+ * (at most max_out) or -1. */
+int or_acuity_capped(int n, const double* ecc, const double* cpd, double cap, double* ecc_out, double* cpd_out,
+                     int max_out) {
+    if (n < 2 || !(cap > 0.0)) return -1;
+    int m = 0;
+#define OR_PUSH(E, F) do { if (m >= max_out) return -1; ecc_out[m] = (E); cpd_out[m] = (F); ++m; } while (0)
+    OR_PUSH(ecc[0], cpd[0] < cap ? cpd[0] : cap);
+    for (int k = 0; k + 1 < n; ++k) {
+        double w0 = 1.0 / cpd[k], w1 = 1.0 / cpd[k + 1], wc = 1.0 / cap;
+        if ((w0 - wc) * (w1 - wc) < 0.0) {
+            double e = ecc[k] + (wc - w0) / (w1 - w0) * (ecc[k + 1] - ecc[k]);
+            OR_PUSH(e, cap);
+        }
+        OR_PUSH(ecc[k + 1], cpd[k + 1] < cap ? cpd[k + 1] : cap);
+    }
+#undef OR_PUSH
+    return m;
 }
 
 /* Segment holding eccentricity e; the last segment extends past the last
@@ -176,13 +231,23 @@ void or_omega_many(const or_acuity* a, const double* e, int64_t n, double* out) 
  * rate never drops below the acuity model; row j sits at polar angle
  * theta_ij = 360 (j + 1/2) / n_i degrees so the rows tile the full circle.
  */
+/* Rows of a column at eccentricity e: the shading height l(e) of Eq. (9),
+ * times Delta(e) when the tangential rate is anisotropic (Eq. (19)),
+ * rounded up so that the tangential rate is never below the model. */
+static int32_t or_rows(const or_acuity* a, double e) {
+    double h = or_l(a, e);
+    if (a->n_aniso > 0) h = or_delta(a, e) * h;
+    int32_t n = (int32_t)ceil(h);
+    return n < 1 ? 1 : n;
+}
+
 int or_vafr_layout_dims(const or_acuity* a, double e_max, int32_t* n_cols, int64_t* n_texels) {
     double umax = or_u(a, e_max);
     int32_t nc = (int32_t)ceil(umax);
     int64_t tot = 0;
     for (int32_t i = 0; i < nc; ++i) {
         double e = or_e_of_u(a, i + 0.5);
-        tot += (int64_t)ceil(or_l(a, e));
+        tot += or_rows(a, e);
     }
     *n_cols = nc;
     *n_texels = tot;
@@ -202,7 +267,7 @@ int or_vafr_layout_fill(const or_acuity* a, double e_max, int32_t n_cols, int32_
     int64_t off = 0;
     for (int32_t i = 0; i < n_cols; ++i) {
         double e = or_e_of_u(a, i + 0.5);
-        int32_t n = (int32_t)ceil(or_l(a, e));
+        int32_t n = or_rows(a, e);
         n_rows[i] = n;
         col_off[i] = off;
         if (col_e) col_e[i] = e;

@@ -44,6 +44,19 @@ int build_segments(int n_piv, const double* ecc, const double* cpd, Segments* s)
     return VAFR_OK;
 }
 
+// Delta(e) of Eq. (19): linear between the table points, constant outside.
+static double aniso_delta(const vafr_layout_s& L, double e) {
+    const int n = (int)L.aniso_e.size();
+    if (n == 0) return 1.0;
+    if (e <= L.aniso_e[0]) return L.aniso_d[0];
+    for (int k = 0; k + 1 < n; ++k)
+        if (e < L.aniso_e[k + 1]) {
+            const double t = (e - L.aniso_e[k]) / (L.aniso_e[k + 1] - L.aniso_e[k]);
+            return L.aniso_d[k] + t * (L.aniso_d[k + 1] - L.aniso_d[k]);
+        }
+    return L.aniso_d[n - 1];
+}
+
 static int seg_index_e(const Segments& s, double e) {
     int k = 0;
     while (k + 1 < s.n && e >= s.e[k + 1]) ++k;
@@ -179,9 +192,25 @@ extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* ac
         if (!(seg.m[k] * seg.e[k] + seg.b[k] > 0.0) || !(seg.m[k] * hi + seg.b[k] > 0.0))
             return fail(VAFR_E_ARG, "acuity model gives a non-positive MAR on segment %d", k);
     }
+    if (acuity && acuity->n_aniso != 0) {
+        if (acuity->n_aniso < 0 || acuity->n_aniso > kMaxSeg + 1)
+            return fail(VAFR_E_ARG, "n_aniso must be in [0, %d]", kMaxSeg + 1);
+        if (!acuity->aniso_ecc_deg || !acuity->aniso_delta) return fail(VAFR_E_ARG, "anisotropy arrays are NULL");
+        for (int k = 0; k < acuity->n_aniso; ++k) {
+            const double e = acuity->aniso_ecc_deg[k], d = acuity->aniso_delta[k];
+            if (!std::isfinite(e) || !(d > 0.0 && d <= 16.0))
+                return fail(VAFR_E_ARG, "anisotropy point %d: eccentricity must be finite, delta in (0, 16]", k);
+            if (k && !(e > acuity->aniso_ecc_deg[k - 1]))
+                return fail(VAFR_E_ARG, "anisotropy eccentricities must increase strictly");
+        }
+    }
     vafr_layout L = new (std::nothrow) vafr_layout_s;
     if (!L) return fail(VAFR_E_OOM, "layout allocation failed");
     L->kind = VAFR_LAYOUT_VAFR;
+    if (acuity && acuity->n_aniso > 0) {
+        L->aniso_e.assign(acuity->aniso_ecc_deg, acuity->aniso_ecc_deg + acuity->n_aniso);
+        L->aniso_d.assign(acuity->aniso_delta, acuity->aniso_delta + acuity->n_aniso);
+    }
     L->disp = *display;
     film_pitch(*display, &L->px, &L->py);
     L->seg = seg;
@@ -196,7 +225,9 @@ extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* ac
         std::vector<double> col_e(L->n_cols);
         for (int32_t i = 0; i < L->n_cols; ++i) {
             col_e[i] = seg_e_of_u(seg, i + 0.5);
-            const int32_t n = (int32_t)std::ceil(seg_l(seg, col_e[i]));
+            double h = seg_l(seg, col_e[i]);
+            if (!L->aniso_e.empty()) h = aniso_delta(*L, col_e[i]) * h;
+            const int32_t n = (int32_t)std::ceil(h);
             L->n_rows[i] = n < 1 ? 1 : n;
             L->col_off[i] = off;
             off += L->n_rows[i];
@@ -322,4 +353,39 @@ extern "C" void vafr_layout_destroy(vafr_layout L) {
     }
     if (have) (void)hipSetDevice(cur);
     delete L;
+}
+
+extern "C" int vafr_acuity_capped(const vafr_acuity* in, double cap_cpd, double* ecc_out, double* cpd_out,
+                                  int32_t max_out, int32_t* n_out) {
+    if (!ecc_out || !cpd_out || !n_out) return fail(VAFR_E_ARG, "NULL output");
+    *n_out = 0;
+    static const double kEcc[5] = {0.0, 10.0, 20.0, 30.0, 60.0};
+    static const double kCpd[5] = {40.0, 10.0, 6.0, 5.0, 4.0};
+    const int n = in ? in->n_pivots : 5;
+    const double* ecc = in ? in->ecc_deg : kEcc;
+    const double* cpd = in ? in->cpd : kCpd;
+    Segments check;
+    if (int rc = build_segments(n, ecc, cpd, &check)) return rc;
+    if (!(cap_cpd > 0.0) || !std::isfinite(cap_cpd)) return fail(VAFR_E_ARG, "cap_cpd must be finite and > 0");
+    int32_t m = 0;
+    auto push = [&](double e, double f) {
+        if (m >= max_out) return false;
+        ecc_out[m] = e;
+        cpd_out[m] = f;
+        ++m;
+        return true;
+    };
+    // f_cap = min(f, cap) <=> MAR_cap = max(MAR, 1/cap); MAR is linear per
+    // segment, so the only new corner is where it crosses 1/cap.
+    const double mar_cap = 1.0 / cap_cpd;
+    bool ok = push(ecc[0], std::min(cpd[0], cap_cpd));
+    for (int k = 0; ok && k + 1 < n; ++k) {
+        const double m0 = 1.0 / cpd[k], m1 = 1.0 / cpd[k + 1];
+        if ((m0 - mar_cap) * (m1 - mar_cap) < 0.0)
+            ok = push(ecc[k] + (mar_cap - m0) / (m1 - m0) * (ecc[k + 1] - ecc[k]), cap_cpd);
+        if (ok) ok = push(ecc[k + 1], std::min(cpd[k + 1], cap_cpd));
+    }
+    if (!ok) return fail(VAFR_E_ARG, "max_out = %d is too small for the capped curve", max_out);
+    *n_out = m;
+    return VAFR_OK;
 }

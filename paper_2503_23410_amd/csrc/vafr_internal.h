@@ -57,6 +57,7 @@ struct vafr_layout_s {
     // VaFR
     vafr::Segments seg;
     double e_max = 60.0;
+    std::vector<double> aniso_e, aniso_d;   // Delta(e) table (empty: isotropic)
     int32_t n_cols = 0, max_rows = 0;
     int64_t n_texels = 0;
     std::vector<int32_t> n_rows;

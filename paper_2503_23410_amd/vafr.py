@@ -36,7 +36,7 @@ EXPORTS = (
     "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
     "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
     "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
-    "vafr_server_destroy",
+    "vafr_server_destroy", "vafr_acuity_capped",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -56,7 +56,8 @@ class vafr_display(C.Structure):
 
 class vafr_acuity(C.Structure):
     _fields_ = [("n_pivots", C.c_int32), ("ecc_deg", C.POINTER(C.c_double)), ("cpd", C.POINTER(C.c_double)),
-                ("e_max_deg", C.c_double)]
+                ("e_max_deg", C.c_double), ("n_aniso", C.c_int32), ("aniso_ecc_deg", C.POINTER(C.c_double)),
+                ("aniso_delta", C.POINTER(C.c_double))]
 
 
 class vafr_camera(C.Structure):
@@ -141,6 +142,8 @@ def load():
         "vafr_last_error": (C.c_char_p, []),
         "vafr_abi_version": (C.c_int, []),
         "vafr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.POINTER(vafr_acuity), C.POINTER(_P)]),
+        "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
         "vafr_layout_dims": (C.c_int, [_P, C.POINTER(vafr_dims)]),
         "vafr_layout_tables": (C.c_int, [_P, C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_int64)),
@@ -263,15 +266,23 @@ class Layout:
         self.n_texels = d.n_texels
 
     @classmethod
-    def vafr(cls, disp: vafr_display, ecc=None, cpd=None, e_max=60.0):
+    def vafr(cls, disp: vafr_display, ecc=None, cpd=None, e_max=60.0, aniso=None):
+        """ecc/cpd: acuity pivots (None: the paper's); aniso: optional
+        (ecc, delta) table of the tangential-to-radial rate Delta(e)."""
         h = C.c_void_p()
-        if ecc is None:
+        if ecc is None and aniso is None:
             _check(load().vafr_lp_layout(C.byref(disp), None, C.byref(h)))
         else:
+            if ecc is None:
+                ecc, cpd = (0.0, 10.0, 20.0, 30.0, 60.0), (40.0, 10.0, 6.0, 5.0, 4.0)
             e = np.ascontiguousarray(ecc, np.float64)
             f = np.ascontiguousarray(cpd, np.float64)
-            a = vafr_acuity(len(e), e.ctypes.data_as(C.POINTER(C.c_double)),
-                            f.ctypes.data_as(C.POINTER(C.c_double)), float(e_max))
+            dp = C.POINTER(C.c_double)
+            a = vafr_acuity(len(e), e.ctypes.data_as(dp), f.ctypes.data_as(dp), float(e_max), 0, None, None)
+            if aniso is not None:
+                ae = np.ascontiguousarray(aniso[0], np.float64)
+                ad = np.ascontiguousarray(aniso[1], np.float64)
+                a.n_aniso, a.aniso_ecc_deg, a.aniso_delta = len(ae), ae.ctypes.data_as(dp), ad.ctypes.data_as(dp)
             _check(load().vafr_lp_layout(C.byref(disp), C.byref(a), C.byref(h)))
         return cls(h)
 
@@ -349,6 +360,22 @@ class Scene:
 
 
 # --------------------------------------------------------------- frame calls
+
+def acuity_capped(cap_cpd, ecc=None, cpd=None):
+    """Pivots (ecc, cpd) of the device-adapted curve min(f(e), cap_cpd)."""
+    dp = C.POINTER(C.c_double)
+    a = None
+    if ecc is not None:
+        e = np.ascontiguousarray(ecc, np.float64)
+        f = np.ascontiguousarray(cpd, np.float64)
+        a = vafr_acuity(len(e), e.ctypes.data_as(dp), f.ctypes.data_as(dp), 60.0, 0, None, None)
+    eo = np.empty(32, np.float64)
+    co = np.empty(32, np.float64)
+    n = C.c_int32()
+    _check(load().vafr_acuity_capped(None if a is None else C.byref(a), float(cap_cpd), eo.ctypes.data_as(dp),
+                                     co.ctypes.data_as(dp), 32, C.byref(n)))
+    return eo[:n.value].copy(), co[:n.value].copy()
+
 
 def vafr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
     _check(load().vafr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),

@@ -206,6 +206,36 @@ def test_cfg2_vafr_lmfr_full(env, O, layout, terrain1m):
     _compare("cfg2 full-res", img.cpu().numpy()[pix], hid.cpu().numpy()[pix], o_rgba, o_id, o_fl)
 
 
+@pytest.mark.parametrize("cap,aniso", [(9.0, None), (18.0, ([0.0, 30.0], [1.0, 0.5]))])
+def test_device_curve_and_anisotropic_layouts(env, O, terrain1m, cap, aniso):
+    """Layouts of the device-adapted curves (Sec. 3.3) and of an anisotropic
+    tangential rate (Eq. (19)) go through the same kernels: every LP texel
+    against the oracle, and the reconstructed image on sampled pixels."""
+    torch, V = env
+    g_sc, o_sc = terrain1m
+    W, H = 1920, 1080
+    ecc, cpd = V.acuity_capped(cap)
+    L = V.Layout.vafr(V.display(W, H), ecc, cpd, 60.0, aniso=aniso)
+    ref_layout = O.Layout(O.Acuity(ecc, cpd, aniso=aniso), 60.0)
+    assert L.n_texels == ref_layout.n_texels
+    gz = (700.0, 420.0)
+    cam = I.terrain_camera()
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, cam, V.shading())
+    o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, ref_layout, np.arange(ref_layout.n_texels), W, H, I.FOV, gz, cam,
+                                             O.shading_params())
+    _compare(f"cap={cap} aniso={aniso is not None} vafr", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+    torch.cuda.synchronize()
+    pix = np.random.default_rng(5).integers(0, W * H, 200000)
+    p = O.film_pitch(W, H, *I.FOV)
+    ref, pf = O.vafr_reconstruct(ref_layout, o_rgba, W, H, p, O.gaze_film(W, H, p, *gz), pix, o_fl)
+    err = np.abs(img.cpu().numpy()[pix] - ref).max(axis=1)
+    log(f"cap={cap} aniso={aniso is not None} image: texels={L.n_texels} flagged_px={int(pf.sum())} "
+        f"max_err={err[~pf].max():.2e}")
+    assert err[~pf].max() <= COLOR_TOL
+
+
 def test_cfg2_reconstruct_random_lp_all_pixels(env, O, layout):
     torch, V = env
     W, H = 1920, 1080

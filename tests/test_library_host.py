@@ -58,6 +58,42 @@ def test_custom_acuity_layout_matches_oracle(V, O):
     assert L.n_texels < 1061735 * 0.85   # capping f at 9 cpd removes work
 
 
+@pytest.mark.parametrize("cap,aniso", [(9.0, None), (18.0, None), (None, ([0.0, 30.0], [1.0, 0.5])),
+                                       (9.0, ([0.0, 15.0, 45.0], [1.0, 0.6, 0.4])), (None, ([0.0, 60.0], [1.0, 1.0]))])
+def test_device_curve_and_anisotropic_layouts_match_oracle(V, O, cap, aniso):
+    """Device-adapted pivots (min(f, cap), Sec. 3.3) and the anisotropic row
+    counts of Eq. (19): the library's pivots and tables equal the oracle's
+    bit for bit."""
+    if cap is None:
+        ecc, cpd = O.DEFAULT_ECC, (40.0, 10.0, 6.0, 5.0, 4.0)
+    else:
+        ecc, cpd = V.acuity_capped(cap)
+        eo, co = O.acuity_capped(cap)
+        assert np.array_equal(ecc, eo) and np.array_equal(cpd, co)
+    L = V.Layout.vafr(V.display(1920, 1080), ecc, cpd, 60.0, aniso=aniso)
+    ref = O.Layout(O.Acuity(ecc, cpd, aniso=aniso), 60.0)
+    n_rows, col_off, dxy = L.tables()
+    assert (L.n_cols, L.n_texels) == (ref.n_cols, ref.n_texels)
+    assert np.array_equal(n_rows, ref.n_rows) and np.array_equal(col_off, ref.col_off)
+    assert np.array_equal(dxy.view(np.uint32), ref.dxy.view(np.uint32))
+
+
+@pytest.mark.parametrize("aniso", [([0.0, 0.0], [1.0, 1.0]), ([0.0, 30.0], [1.0, 0.0]), ([0.0], [17.0]),
+                                   ([0.0, float("nan")], [1.0, 1.0])])
+def test_anisotropy_validation(V, aniso):
+    with pytest.raises(V.VafrError) as ei:
+        V.Layout.vafr(V.display(640, 360), aniso=aniso)
+    assert ei.value.code == V.VAFR_E_ARG
+
+
+def test_capped_curve_validation(V):
+    for cap in (0.0, -1.0, float("inf")):
+        with pytest.raises(V.VafrError):
+            V.acuity_capped(cap)
+    with pytest.raises(V.VafrError):
+        V.acuity_capped(9.0, (1.0, 10.0), (40.0, 10.0))          # first pivot not at 0
+
+
 def test_lmfr_layout_dims_match_oracle(V, O):
     for W, H in ((640, 360), (1920, 1080), (7680, 4320), (11520, 6480)):
         L = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
