@@ -274,6 +274,10 @@ def main():
             "fullres_grays_per_s": round(2 * 2 * W * H * full_fps / 1e9, 3),
         })
 
+    # ------------------------------------------------------------ LP anti-aliasing
+    if not args.no_compare:
+        out["fxaa"] = fxaa_bench(torch, V, scene, cams, sh, L, gazes[warm:], max(20, csteps))
+
     # ------------------------------------------------------------ 16 views
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
@@ -378,6 +382,40 @@ def batch16(torch, V, I, scene, sh, steps):
     b.close()
     return {"views": 16, "display_mpix": round(pixels / 1e6, 2), "batched_fps": round(res["batched"], 3),
             "plain_fps": round(res["plain"], 3), "speedup": round(res["batched"] / res["plain"], 3), "shape": shape}
+
+
+def fxaa_bench(torch, V, scene, cams, sh, L, gazes, steps):
+    """LP anti-aliasing (Sec. 3.4) on the binocular 8K frame: kernel time per
+    eye, and per-view frames shade -> anti-alias -> inverse map."""
+    stream = torch.cuda.current_stream()
+    lp = [torch.empty((L.n_texels, 4), device="cuda") for _ in range(2)]
+    aa = [torch.empty((L.n_texels, 4), device="cuda") for _ in range(2)]
+    img = [torch.empty((H * W, 4), device="cuda") for _ in range(2)]
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+
+    def frame(f, timed=None):
+        g = gazes[f % len(gazes)]
+        for e in range(2):
+            V.vafr_shade_lp(scene, cams[e], g, sh, L, lp[e], None, stream)
+            if timed is not None and e == 0:
+                timed[0].record(stream)
+            V.vafr_fxaa_lp(L, lp[e], aa[e], stream)
+            if timed is not None and e == 0:
+                timed[1].record(stream)
+            V.vafr_reconstruct(L, g, aa[e], img[e], stream)
+
+    frame(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for f in range(steps):
+        frame(f, ev[f])
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    gbs = 2 * L.n_texels * 16 / (ms / 1e3) / 1e9
+    log(f"LP anti-aliasing: {ms * 1e3:.1f} us per eye ({gbs:.0f} GB/s of LP read + write); per-view frames with it "
+        f"{fps:.1f} frames/s")
+    return {"us_per_eye": round(ms * 1e3, 2), "lp_gbs": round(gbs, 1), "per_view_fps_with_fxaa": round(fps, 2)}
 
 
 # Tangential-to-radial shading-rate ratio used to measure Eq. (19): 1 at the

@@ -217,6 +217,21 @@ int vafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, cons
 int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
                   vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
 
+/* Anti-aliasing inside the LP buffer (Sec. 3.4: FXAA on the LP buffer before
+ * the inverse map).  FXAA's steps (Lottes 2009) on the polar grid: along the
+ * angle a texel's neighbours are the adjacent rows of its column (cyclic),
+ * along the radius the inner and outer columns sampled at its angle (linear
+ * in rows; columns clamp at the ends).  A texel whose luma range over itself
+ * and its four neighbours is below max(1/16, 1/8 of the largest luma) is
+ * copied; otherwise the edge normal follows the larger luma curvature, the
+ * ends of the edge are searched at offsets 1, 2, 3, 4, 6, 8 along it, and the
+ * texel is blended toward the neighbour across the edge by
+ * max(edge term, 0.75 x sub-texel term).  lp_in_dev and lp_out_dev hold
+ * 4 * n_texels floats of a VaFR layout and must not overlap.  Errors:
+ * VAFR_E_ARG (NULL or overlapping buffers), VAFR_E_UNSUPPORTED (LMFR
+ * layout), VAFR_E_HIP. */
+int vafr_fxaa_lp(vafr_layout layout, const float* lp_in_dev, float* lp_out_dev, hipStream_t stream);
+
 /* Inverse map (Sec. 3.2.3, Eqs. (10)-(11)): every display pixel centre is
  * mapped to (u, theta) and the LP buffer is sampled with a two-column,
  * angle-consistent bilinear filter (u clamped to the first/last column

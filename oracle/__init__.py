@@ -61,6 +61,7 @@ def _declare(L):
         "or_acuity_size": (C.c_int, []),
         "or_acuity_init": (C.c_int, [_P, C.c_int, _P, _P]),
         "or_acuity_set_aniso": (C.c_int, [_P, C.c_int, _P, _P]),
+        "or_fxaa_lp": (None, [C.c_int32, _P, _P, _P, _P, C.c_int64, _P]),
         "or_delta": (_D, [_P, _D]),
         "or_acuity_capped": (C.c_int, [C.c_int, _P, _P, _D, _P, _P, C.c_int]),
         "or_omega": (_D, [_P, _D]),
@@ -462,3 +463,14 @@ def shade_lmfr_texels(scene: Scene, idx, W, H, fov, gaze, w, h, alpha, cam, sh):
     p = film_pitch(W, H, *fov)
     org, d = lmfr_rays(W, H, p, gaze[0], gaze[1], w, h, alpha, idx, cam)
     return scene.shade(org, d, sh)
+
+
+def fxaa_lp(layout: Layout, lp, idx=None):
+    """FXAA-style anti-aliasing inside the LP buffer (Sec. 3.4) for texels
+    idx (all by default): RGBA per listed texel."""
+    lp = _arr(lp, np.float32).reshape(-1, 4)
+    idx = np.arange(layout.n_texels, dtype=np.int64) if idx is None else _arr(idx, np.int64)
+    out = np.empty((idx.size, 4), np.float32)
+    lib().or_fxaa_lp(layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(lp), _ptr(idx), idx.size,
+                     _ptr(out))
+    return out

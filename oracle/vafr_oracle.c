@@ -1200,3 +1200,189 @@ void or_lmfr_reconstruct(int32_t W, int32_t H, double gx, double gy, int32_t w, 
         if (pflag) pflag[q] = fl;
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* FXAA-style edge anti-aliasing inside the LP buffer (Sec. 3.4)            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The paper runs FXAA (Lottes, "FXAA", NVIDIA white paper 2009) on the LP
+ * buffer and gives no further detail.  On the ragged polar grid the steps
+ * of that method are taken as follows (every operation in FP32, in the order
+ * written, so that the library's kernel can agree bit for bit):
+ *
+ *  - a texel's neighbours along the angle are the adjacent rows of its own
+ *    column (cyclic); its neighbours along the radius are the inner and
+ *    outer columns sampled at the texel's angle, linear in the row
+ *    coordinate; diagonal neighbours are those columns at the angle one row
+ *    (of the texel's column) before and after.  Columns clamp at the ends.
+ *  - luma = 0.299 r + 0.587 g + 0.114 b.
+ *  - contrast test: the texel is left unchanged when the luma range over
+ *    itself and its four direct neighbours is below
+ *    max(FXAA_EDGE_MIN, FXAA_EDGE_REL * max luma).
+ *  - orientation: second differences of luma across the radius (summed over
+ *    the three angles, centre weighted 2) against those across the angle;
+ *    the larger decides the edge normal.
+ *  - the side of the edge is the neighbour along the normal with the larger
+ *    luma step; the edge line lies midway between the texel and that side.
+ *  - end search: along the edge line in both directions at offsets
+ *    FXAA_STEPS (in rows of the texel's column, or in columns), sampling the
+ *    mean luma of the two sides of the line, until it differs from the
+ *    line's mean at the texel by at least a quarter of the luma step;
+ *    an end not found is taken one step beyond the last offset.
+ *  - edge blend: 0.5 - d_near / (d_neg + d_pos) when the nearer end
+ *    continues the texel's side of the edge, else 0.
+ *  - sub-texel blend: smoothstep of |mean of neighbours - centre| / range
+ *    (direct neighbours weighted 2, diagonals 1, over 12), squared, times
+ *    FXAA_SUBPIX.
+ *  - output: centre + max(edge blend, sub-texel blend) x (side value -
+ *    centre), per channel.
+ */
+#define FXAA_EDGE_REL 0.125f
+#define FXAA_EDGE_MIN 0.0625f
+#define FXAA_SUBPIX 0.75f
+#define FXAA_NSTEP 6
+static const float FXAA_STEPS[FXAA_NSTEP] = {1.0f, 2.0f, 3.0f, 4.0f, 6.0f, 8.0f};
+
+typedef struct { float v[4]; } or_px;
+
+typedef struct {
+    int32_t n_cols;
+    const int32_t* n_rows;
+    const int64_t* col_off;
+    const float* lp;
+} or_lpgrid;
+
+static or_px fx_tex(const or_lpgrid* g, int32_t c, int64_t j) {
+    int64_t n = g->n_rows[c];
+    int64_t jj = j % n;
+    if (jj < 0) jj += n;
+    or_px p;
+    for (int k = 0; k < 4; ++k) p.v[k] = g->lp[4 * (g->col_off[c] + jj) + k];
+    return p;
+}
+
+static int32_t fx_clamp_col(const or_lpgrid* g, int32_t c) { return c < 0 ? 0 : (c >= g->n_cols ? g->n_cols - 1 : c); }
+
+/* Column c at angle t turns: linear between the rows around t n - 1/2. */
+static or_px fx_col(const or_lpgrid* g, int32_t c, float t) {
+    c = fx_clamp_col(g, c);
+    float s = t * (float)g->n_rows[c] - 0.5f;
+    float fs = floorf(s);
+    float w = s - fs;
+    int64_t j0 = (int64_t)fs;
+    or_px a = fx_tex(g, c, j0), b = fx_tex(g, c, j0 + 1), r;
+    for (int k = 0; k < 4; ++k) {
+        float d = b.v[k] - a.v[k];
+        r.v[k] = a.v[k] + w * d;
+    }
+    return r;
+}
+
+static float fx_luma(or_px p) {
+    float a = 0.299f * p.v[0];
+    float b = 0.587f * p.v[1];
+    float c = 0.114f * p.v[2];
+    return (a + b) + c;
+}
+
+static float fx_second(float a, float m, float b) {
+    float d = (a - m) + (b - m);
+    return fabsf(d);
+}
+
+static or_px fx_texel(const or_lpgrid* g, int32_t i, int32_t j) {
+    const int32_t n = g->n_rows[i];
+    const float t = ((float)j + 0.5f) / (float)n;
+    const float dt = 1.0f / (float)n;
+    const or_px M = fx_tex(g, i, j);
+    const float lM = fx_luma(M);
+    const float lU = fx_luma(fx_tex(g, i, (int64_t)j + 1));
+    const float lD = fx_luma(fx_tex(g, i, (int64_t)j - 1));
+    const or_px O = fx_col(g, i + 1, t), I = fx_col(g, i - 1, t);
+    const float lO = fx_luma(O), lI = fx_luma(I);
+    float lmax = fmaxf(fmaxf(fmaxf(lM, lU), fmaxf(lD, lO)), lI);
+    float lmin = fminf(fminf(fminf(lM, lU), fminf(lD, lO)), lI);
+    const float range = lmax - lmin;
+    if (range < fmaxf(FXAA_EDGE_MIN, lmax * FXAA_EDGE_REL)) return M;
+    const float lOU = fx_luma(fx_col(g, i + 1, t + dt)), lOD = fx_luma(fx_col(g, i + 1, t - dt));
+    const float lIU = fx_luma(fx_col(g, i - 1, t + dt)), lID = fx_luma(fx_col(g, i - 1, t - dt));
+    /* second differences across the radius (at three angles) and across the
+     * angle (at three radii) */
+    const float eR = (fx_second(lID, lD, lOD) + 2.0f * fx_second(lI, lM, lO)) + fx_second(lIU, lU, lOU);
+    const float eA = (fx_second(lID, lI, lIU) + 2.0f * fx_second(lD, lM, lU)) + fx_second(lOD, lO, lOU);
+    const int normal_radial = eR >= eA; /* luma changes across the radius: the edge runs along the angle */
+    const float lNeg = normal_radial ? lI : lD, lPos = normal_radial ? lO : lU;
+    const float gNeg = fabsf(lNeg - lM), gPos = fabsf(lPos - lM);
+    const int side = gPos >= gNeg ? 1 : -1;
+    const float lSide = side > 0 ? lPos : lNeg;
+    const float grad = fmaxf(gNeg, gPos);
+    const float lLine = 0.5f * (lM + lSide);
+    const float gScaled = 0.25f * grad;
+    float dist[2];
+    float lEnd[2];
+    for (int dir = 0; dir < 2; ++dir) {
+        const float sgn = dir == 0 ? -1.0f : 1.0f;
+        dist[dir] = FXAA_STEPS[FXAA_NSTEP - 1] + 1.0f;
+        lEnd[dir] = lLine;
+        for (int k = 0; k < FXAA_NSTEP; ++k) {
+            const float p = sgn * FXAA_STEPS[k];
+            float la, lb;
+            if (normal_radial) {
+                /* along the angle, between column i and column i + side */
+                const float tt = t + p * dt;
+                la = fx_luma(fx_col(g, i, tt));
+                lb = fx_luma(fx_col(g, i + side, tt));
+            } else {
+                /* along the radius, between angle t and t + side dt */
+                const int32_t c = i + (int32_t)p;
+                la = fx_luma(fx_col(g, c, t));
+                lb = fx_luma(fx_col(g, c, t + (float)side * dt));
+            }
+            const float l = 0.5f * (la + lb);
+            if (fabsf(l - lLine) >= gScaled) {
+                dist[dir] = FXAA_STEPS[k];
+                lEnd[dir] = l;
+                break;
+            }
+        }
+    }
+    const int near = dist[0] <= dist[1] ? 0 : 1;
+    const float dNear = dist[near];
+    const int centre_below = lM - lLine < 0.0f;
+    const int end_below = lEnd[near] - lLine < 0.0f;
+    const float edge = centre_below != end_below ? 0.5f - dNear / (dist[0] + dist[1]) : 0.0f;
+    const float lAvg = (2.0f * ((lU + lD) + (lI + lO)) + ((lIU + lID) + (lOU + lOD))) / 12.0f;
+    float s1 = fabsf(lAvg - lM) / range;
+    s1 = fminf(fmaxf(s1, 0.0f), 1.0f);
+    const float s2 = (-2.0f * s1 + 3.0f) * (s1 * s1);
+    const float sub = (s2 * s2) * FXAA_SUBPIX;
+    const float off = fmaxf(edge, sub);
+    or_px S = normal_radial ? fx_col(g, i + side, t) : fx_tex(g, i, (int64_t)j + side);
+    or_px r;
+    for (int k = 0; k < 4; ++k) {
+        float d = S.v[k] - M.v[k];
+        r.v[k] = M.v[k] + off * d;
+    }
+    return r;
+}
+
+/* FXAA over texels idx[0..n) of the LP buffer; out holds 4 floats per
+ * listed texel. */
+void or_fxaa_lp(int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, const float* lp, const int64_t* idx,
+                int64_t n, float* out) {
+    or_lpgrid g = {n_cols, n_rows, col_off, lp};
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t k = idx[q];
+        /* column of texel k */
+        int32_t lo = 0, hi = n_cols - 1;
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) / 2;
+            if (col_off[mid] <= k) lo = mid;
+            else hi = mid - 1;
+        }
+        or_px r = fx_texel(&g, lo, (int32_t)(k - col_off[lo]));
+        for (int c = 0; c < 4; ++c) out[4 * q + c] = r.v[c];
+    }
+}

@@ -38,6 +38,7 @@ SOURCES = {
     "server.cpp": ["-x", "hip", "-ffp-contract=off"],
     "trace.hip": ["-ffp-contract=off"],
     "reconstruct.hip": [],
+    "fxaa.hip": ["-ffp-contract=off"],
 }
 
 

@@ -339,6 +339,18 @@ extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, 
     return reconstruct_kind(VAFR_LAYOUT_LMFR, L, gaze, lp, img, stream);
 }
 
+extern "C" int vafr_fxaa_lp(vafr_layout L, const float* in, float* out, hipStream_t stream) {
+    if (!L) return fail(VAFR_E_ARG, "layout is NULL");
+    if (L->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_UNSUPPORTED, "LP anti-aliasing needs a VaFR layout");
+    if (!in || !out) return fail(VAFR_E_ARG, "LP buffer is NULL");
+    const uintptr_t a = reinterpret_cast<uintptr_t>(in), b = reinterpret_cast<uintptr_t>(out);
+    const uintptr_t bytes = (uintptr_t)L->n_texels * 16u;
+    if (a < b + bytes && b < a + bytes) return fail(VAFR_E_ARG, "input and output LP buffers overlap");
+    const LayoutDev* ld;
+    if (int rc = layout_device(L, &ld)) return rc;
+    return launch_fxaa(ld->col, L->n_cols, L->n_texels, in, out, stream);
+}
+
 extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* d, const vafr_shading* sh,
                           float* img, int32_t* hit, hipStream_t stream) {
     if (!img) return fail(VAFR_E_ARG, "img_rgba_dev is NULL");

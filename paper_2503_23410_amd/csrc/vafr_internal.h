@@ -217,6 +217,11 @@ int launch_reconstruct(const ReconView& v, hipStream_t stream, int rows = kRecon
 int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_end_dev, int32_t n_views,
                              int32_t blocks, int rows, hipStream_t stream);
 
+// LP anti-aliasing over all texels of a VaFR layout (col: per-column rows
+// and first texel on the device).
+int launch_fxaa(const int2* col_dev, int32_t n_cols, int64_t n_texels, const float* in, float* out,
+                hipStream_t stream);
+
 // Per-view descriptors from the public arguments (validated; uploads the
 // layout tables to the current device on first use).
 int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,

@@ -36,7 +36,7 @@ EXPORTS = (
     "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
     "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
     "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
-    "vafr_server_destroy", "vafr_acuity_capped",
+    "vafr_server_destroy", "vafr_acuity_capped", "vafr_fxaa_lp",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -142,6 +142,7 @@ def load():
         "vafr_last_error": (C.c_char_p, []),
         "vafr_abi_version": (C.c_int, []),
         "vafr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.POINTER(vafr_acuity), C.POINTER(_P)]),
+        "vafr_fxaa_lp": (C.c_int, [_P, _P, _P, _P]),
         "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
@@ -385,6 +386,10 @@ def vafr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None)
 def lmfr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
     _check(load().lmfr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),
                                 _dptr(hit_id), _stream(stream)))
+
+
+def vafr_fxaa_lp(layout, lp_in, lp_out, stream=None):
+    _check(load().vafr_fxaa_lp(layout.handle, _dptr(lp_in), _dptr(lp_out), _stream(stream)))
 
 
 def vafr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
