@@ -348,7 +348,7 @@ extern "C" int vafr_fxaa_lp(vafr_layout L, const float* in, float* out, hipStrea
     if (a < b + bytes && b < a + bytes) return fail(VAFR_E_ARG, "input and output LP buffers overlap");
     const LayoutDev* ld;
     if (int rc = layout_device(L, &ld)) return rc;
-    return launch_fxaa(ld->col, L->n_cols, L->n_texels, in, out, stream);
+    return launch_fxaa(ld->col, ld->blk_col, L->n_cols, L->n_texels, in, out, stream);
 }
 
 extern "C" int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* d, const vafr_shading* sh,

@@ -29,16 +29,21 @@ __constant__ float kStepAt[kSteps] = {1.0f, 2.0f, 3.0f, 4.0f, 6.0f, 8.0f};   // 
 
 struct FxaaView {
     const int2* col;     // (rows, first texel) per column
+    const int32_t* blk_col;   // column of the first texel of each workgroup
     int32_t n_cols;
     int64_t n_texels;
     const float4* in;
     float4* out;
 };
 
-__device__ __forceinline__ float4 texel_at(const FxaaView& v, int c, int j) {
-    const int2 cn = v.col[c];
-    int r = j % cn.x;
-    r = r < 0 ? r + cn.x : r;
+// Row j (any integer, cyclic) of the column with record cn = (rows, first
+// texel); the modulo is only taken when j leaves [0, rows).
+__device__ __forceinline__ float4 texel_of(const FxaaView& v, int2 cn, int j) {
+    int r = j;
+    if ((unsigned)r >= (unsigned)cn.x) {
+        r = j % cn.x;
+        r = r < 0 ? r + cn.x : r;
+    }
     return v.in[(int64_t)cn.y + r];
 }
 
@@ -46,15 +51,19 @@ __device__ __forceinline__ int clamp_col(const FxaaView& v, int c) {
     return c < 0 ? 0 : (c >= v.n_cols ? v.n_cols - 1 : c);
 }
 
-// Column c (clamped) at angle t turns, linear between rows.
-__device__ __forceinline__ float4 column_at(const FxaaView& v, int c, float t) {
-    c = clamp_col(v, c);
-    const float s = t * (float)v.col[c].x - 0.5f;
+// The column with record cn at angle t turns, linear between rows.
+__device__ __forceinline__ float4 column_of(const FxaaView& v, int2 cn, float t) {
+    const float s = t * (float)cn.x - 0.5f;
     const float fs = floorf(s);
     const float w = s - fs;
     const int j0 = (int)fs;
-    const float4 a = texel_at(v, c, j0), b = texel_at(v, c, j0 + 1);
+    const float4 a = texel_of(v, cn, j0), b = texel_of(v, cn, j0 + 1);
     return make_float4(a.x + w * (b.x - a.x), a.y + w * (b.y - a.y), a.z + w * (b.z - a.z), a.w + w * (b.w - a.w));
+}
+
+// Column c (clamped to the buffer) at angle t turns.
+__device__ __forceinline__ float4 column_at(const FxaaView& v, int c, float t) {
+    return column_of(v, v.col[clamp_col(v, c)], t);
 }
 
 __device__ __forceinline__ float luma(float4 p) { return (0.299f * p.x + 0.587f * p.y) + 0.114f * p.z; }
@@ -63,19 +72,21 @@ __device__ __forceinline__ float luma(float4 p) { return (0.299f * p.x + 0.587f 
 __device__ __forceinline__ float curvature(float a, float m, float b) { return fabsf((a - m) + (b - m)); }
 
 __device__ float4 fxaa_texel(const FxaaView& v, int i, int j) {
-    const int n = v.col[i].x;
+    // records of the texel's column and of its outer and inner neighbours
+    const int2 ci = v.col[i], co = v.col[clamp_col(v, i + 1)], cn = v.col[clamp_col(v, i - 1)];
+    const int n = ci.x;
     const float t = ((float)j + 0.5f) / (float)n;
     const float dt = 1.0f / (float)n;
-    const float4 M = texel_at(v, i, j);
+    const float4 M = texel_of(v, ci, j);
     const float lM = luma(M);
-    const float lU = luma(texel_at(v, i, j + 1)), lD = luma(texel_at(v, i, j - 1));
-    const float lO = luma(column_at(v, i + 1, t)), lI = luma(column_at(v, i - 1, t));
+    const float lU = luma(texel_of(v, ci, j + 1)), lD = luma(texel_of(v, ci, j - 1));
+    const float lO = luma(column_of(v, co, t)), lI = luma(column_of(v, cn, t));
     const float lmax = fmaxf(fmaxf(fmaxf(lM, lU), fmaxf(lD, lO)), lI);
     const float lmin = fminf(fminf(fminf(lM, lU), fminf(lD, lO)), lI);
     const float range = lmax - lmin;
     if (range < fmaxf(kEdgeMin, lmax * kEdgeRel)) return M;
-    const float lOU = luma(column_at(v, i + 1, t + dt)), lOD = luma(column_at(v, i + 1, t - dt));
-    const float lIU = luma(column_at(v, i - 1, t + dt)), lID = luma(column_at(v, i - 1, t - dt));
+    const float lOU = luma(column_of(v, co, t + dt)), lOD = luma(column_of(v, co, t - dt));
+    const float lIU = luma(column_of(v, cn, t + dt)), lID = luma(column_of(v, cn, t - dt));
     // luma curvature across the radius (three angles) and across the angle
     // (three radii), centre line weighted twice
     const float across_r = (curvature(lID, lD, lOD) + 2.0f * curvature(lI, lM, lO)) + curvature(lIU, lU, lOU);
@@ -98,8 +109,8 @@ __device__ float4 fxaa_texel(const FxaaView& v, int i, int j) {
             float la, lb;
             if (radial) {
                 const float tt = t + p * dt;
-                la = luma(column_at(v, i, tt));
-                lb = luma(column_at(v, i + side, tt));
+                la = luma(column_of(v, ci, tt));
+                lb = luma(column_of(v, side > 0 ? co : cn, tt));
             } else {
                 const int c = i + (int)p;
                 la = luma(column_at(v, c, t));
@@ -120,31 +131,30 @@ __device__ float4 fxaa_texel(const FxaaView& v, int i, int j) {
     const float s1 = fminf(fmaxf(fabsf(lAvg - lM) / range, 0.0f), 1.0f);
     const float s2 = (-2.0f * s1 + 3.0f) * (s1 * s1);
     const float off = fmaxf(edge, (s2 * s2) * kSubpix);
-    const float4 S = radial ? column_at(v, i + side, t) : texel_at(v, i, j + side);
+    const float4 S = radial ? column_of(v, side > 0 ? co : cn, t) : texel_of(v, ci, j + side);
     return make_float4(M.x + off * (S.x - M.x), M.y + off * (S.y - M.y), M.z + off * (S.z - M.z),
                        M.w + off * (S.w - M.w));
 }
 
-__global__ __launch_bounds__(256) void k_fxaa(const FxaaView v) {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(kTexelBlock) void k_fxaa(const FxaaView v) {
+    const int64_t k = (int64_t)blockIdx.x * kTexelBlock + threadIdx.x;
     if (k >= v.n_texels) return;
-    int lo = 0, hi = v.n_cols - 1;   // column of texel k: last column starting at or before k
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if ((int64_t)v.col[mid].y <= k) lo = mid;
-        else hi = mid - 1;
-    }
-    v.out[k] = fxaa_texel(v, lo, (int)(k - v.col[lo].y));
+    // column of texel k: from the workgroup's first column, walk forward
+    // (a workgroup spans several columns only near the centre of the grid)
+    int c = v.blk_col[blockIdx.x];
+    while (c + 1 < v.n_cols && (int64_t)v.col[c + 1].y <= k) ++c;
+    v.out[k] = fxaa_texel(v, c, (int)(k - v.col[c].y));
 }
 
 }  // namespace
 
-int launch_fxaa(const int2* col_dev, int32_t n_cols, int64_t n_texels, const float* in, float* out,
-                hipStream_t stream) {
+int launch_fxaa(const int2* col_dev, const int32_t* blk_col_dev, int32_t n_cols, int64_t n_texels, const float* in,
+                float* out, hipStream_t stream) {
     if (n_texels <= 0) return VAFR_OK;
-    FxaaView v{col_dev, n_cols, n_texels, reinterpret_cast<const float4*>(in), reinterpret_cast<float4*>(out)};
-    const int64_t blocks = (n_texels + 255) / 256;
-    hipLaunchKernelGGL(k_fxaa, dim3((unsigned)blocks), dim3(256), 0, stream, v);
+    FxaaView v{col_dev, blk_col_dev, n_cols, n_texels, reinterpret_cast<const float4*>(in),
+               reinterpret_cast<float4*>(out)};
+    const int64_t blocks = (n_texels + kTexelBlock - 1) / kTexelBlock;
+    hipLaunchKernelGGL(k_fxaa, dim3((unsigned)blocks), dim3(kTexelBlock), 0, stream, v);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

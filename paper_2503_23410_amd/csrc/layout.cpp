@@ -156,6 +156,14 @@ int layout_device(vafr_layout L, const LayoutDev** out) {
         VAFR_HIP(hipMemcpy(d.dxy, dxy_ord.data(), sizeof(float2) * dxy_ord.size(), hipMemcpyHostToDevice));
         VAFR_HIP(hipMalloc(&d.ord, sizeof(int32_t) * L->ord.size()));
         VAFR_HIP(hipMemcpy(d.ord, L->ord.data(), sizeof(int32_t) * L->ord.size(), hipMemcpyHostToDevice));
+        std::vector<int32_t> blk((L->n_texels + kTexelBlock - 1) / kTexelBlock);
+        for (int32_t c = 0, b = 0; b < (int32_t)blk.size(); ++b) {
+            const int64_t k = (int64_t)b * kTexelBlock;
+            while (c + 1 < L->n_cols && L->col_off[c + 1] <= k) ++c;
+            blk[b] = c;
+        }
+        VAFR_HIP(hipMalloc(&d.blk_col, sizeof(int32_t) * std::max<size_t>(1, blk.size())));
+        VAFR_HIP(hipMemcpy(d.blk_col, blk.data(), sizeof(int32_t) * blk.size(), hipMemcpyHostToDevice));
         VAFR_HIP(hipMalloc(&d.u_of_rho, sizeof(float) * L->u_of_rho.size()));
         VAFR_HIP(hipMemcpy(d.u_of_rho, L->u_of_rho.data(), sizeof(float) * L->u_of_rho.size(), hipMemcpyHostToDevice));
     } else {
@@ -347,6 +355,7 @@ extern "C" void vafr_layout_destroy(vafr_layout L) {
         (void)hipFree(d.col);
         (void)hipFree(d.dxy);
         (void)hipFree(d.ord);
+        (void)hipFree(d.blk_col);
         (void)hipFree(d.u_of_rho);
         (void)hipFree(d.lm_z);
         (void)hipFree(d.lm_cs);

@@ -43,6 +43,7 @@ struct LayoutDev {
     int2* col = nullptr;          // VaFR: (n_rows, col_off) per column
     float2* dxy = nullptr;        // VaFR: film offset per texel, in trace order
     int32_t* ord = nullptr;       // VaFR: texel index of each trace-order slot
+    int32_t* blk_col = nullptr;   // VaFR: column of texel 256 b (per-texel kernels' block start)
     float2* u_of_rho = nullptr;   // VaFR: (u_k, u_{k+1} - u_k) at rho_k = k h, k <= kURhoN
     double* lm_z = nullptr;       // LMFR: z_i per column
     double2* lm_cs = nullptr;     // LMFR: (cos, sin) of theta_j per row
@@ -219,8 +220,9 @@ int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_en
 
 // LP anti-aliasing over all texels of a VaFR layout (col: per-column rows
 // and first texel on the device).
-int launch_fxaa(const int2* col_dev, int32_t n_cols, int64_t n_texels, const float* in, float* out,
-                hipStream_t stream);
+constexpr int kTexelBlock = 256;   // texels per workgroup of per-texel kernels
+int launch_fxaa(const int2* col_dev, const int32_t* blk_col_dev, int32_t n_cols, int64_t n_texels, const float* in,
+                float* out, hipStream_t stream);
 
 // Per-view descriptors from the public arguments (validated; uploads the
 // layout tables to the current device on first use).
