@@ -278,6 +278,10 @@ def main():
     if not args.no_compare:
         out["fxaa"] = fxaa_bench(torch, V, scene, cams, sh, L, gazes[warm:], max(20, csteps))
 
+    # ------------------------------------------------------------ reprojection
+    if not args.no_compare:
+        out["rep"] = rep_bench(torch, V, scene, cams, sh, L, gazes[warm:], max(20, csteps))
+
     # ------------------------------------------------------------ 16 views
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
@@ -416,6 +420,54 @@ def fxaa_bench(torch, V, scene, cams, sh, L, gazes, steps):
     log(f"LP anti-aliasing: {ms * 1e3:.1f} us per eye ({gbs:.0f} GB/s of LP read + write); per-view frames with it "
         f"{fps:.1f} frames/s")
     return {"us_per_eye": round(ms * 1e3, 2), "lp_gbs": round(gbs, 1), "per_view_fps_with_fxaa": round(fps, 2)}
+
+
+def rep_bench(torch, V, scene, cams, sh, L, gazes, steps):
+    """Binocular reprojection (Sec. 5.1): per-view frames whose right eye is
+    reprojected from the left LP buffer (VaFR_Rep) against frames that shade
+    both eyes (VaFR_Dup), same scene, cameras and gaze trace; and the share
+    of right texels that received a left point."""
+    stream = torch.cuda.current_stream()
+    lp = [torch.empty((L.n_texels, 4), device="cuda") for _ in range(2)]
+    img = [torch.empty((H * W, 4), device="cuda") for _ in range(2)]
+    ws = torch.empty(V.rep_workspace_bytes(L), device="cuda", dtype=torch.uint8)
+    keys = ws[L.n_texels * 16:L.n_texels * 24].view(torch.int64)
+
+    def rep(f):
+        g = gazes[f % len(gazes)]
+        V.vafr_shade_lp_rep(scene, cams[0], cams[1], g, sh, L, lp[0], lp[1], ws, None, None, stream)
+        for e in range(2):
+            V.vafr_reconstruct(L, g, lp[e], img[e], stream)
+
+    def dup(f):
+        g = gazes[f % len(gazes)]
+        for e in range(2):
+            V.vafr_shade_lp(scene, cams[e], g, sh, L, lp[e], None, stream)
+            V.vafr_reconstruct(L, g, lp[e], img[e], stream)
+
+    res = {}
+    for name, fn in (("dup", dup), ("rep", rep)):
+        fn(0)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(steps)]
+        t0 = time.perf_counter()
+        for f in range(steps):
+            ev[f][0].record(stream)
+            fn(f)
+            ev[f][1].record(stream)
+        torch.cuda.synchronize()
+        fps = steps / (time.perf_counter() - t0)
+        res[name] = (fps, float(np.mean([a.elapsed_time(b) for a, b in ev])))
+    frac = []
+    for f in range(min(steps, 8)):
+        rep(f)
+        torch.cuda.synchronize()
+        frac.append(float((keys != -1).float().mean()))
+    log(f"reprojection: Rep {res['rep'][0]:.1f} frames/s ({res['rep'][1]:.3f} ms), Dup {res['dup'][0]:.1f} frames/s "
+        f"({res['dup'][1]:.3f} ms); right texels reprojected {np.mean(frac):.3f}")
+    return {"rep_fps": round(res["rep"][0], 2), "rep_frame_ms": round(res["rep"][1], 3),
+            "dup_fps": round(res["dup"][0], 2), "dup_frame_ms": round(res["dup"][1], 3),
+            "right_reprojected_frac": round(float(np.mean(frac)), 4), "per_view_path": True}
 
 
 # Tangential-to-radial shading-rate ratio used to measure Eq. (19): 1 at the

@@ -232,6 +232,31 @@ int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, cons
  * layout), VAFR_E_HIP. */
 int vafr_fxaa_lp(vafr_layout layout, const float* lp_in_dev, float* lp_out_dev, hipStream_t stream);
 
+/* Binocular reprojection (Sec. 5.1, VaFR_Rep): shades the left eye's LP
+ * buffer as vafr_shade_lp does, then builds the right eye's from it.  Each
+ * left texel whose primary ray hits carries its hit point
+ * p = fma(t, d, o) into the right eye: projected onto the right film plane
+ * (FP32: q = p - eye; x, y, z = dot(q, right / up / forward) summed left to
+ * right; film point (x / z, -(y / z)), z > 0), mapped to the LP cell holding
+ * it (FP64: radius -> eccentricity by Eq. (3), abscissa by Eqs. (5)/(12),
+ * column floor(u) if u < columns; row floor(theta / 360 n_i)).  The
+ * nearest point wins a cell (ties: lower left texel) and the right texel
+ * takes that left texel's colour and hit id; cells no point reached are
+ * ray-cast with the right camera (only those: they are listed first and
+ * traced as one compacted launch).  Both eyes use the gaze display point.
+ * workspace_dev: caller-owned device memory of vafr_rep_workspace_bytes()
+ * bytes (hit points, cell keys, list of unreached cells), 16-byte aligned, reused across calls
+ * on one stream (calls that overlap on one workspace race).  hit_left /
+ * hit_right are nullable.  The LP buffers, hit-id buffers and workspace
+ * must not overlap.  Errors: VAFR_E_ARG (NULL, overlapping or misaligned
+ * buffers, small workspace, invalid camera / shading / gaze), VAFR_E_UNSUPPORTED
+ * (LMFR layout), VAFR_E_HIP. */
+int vafr_rep_workspace_bytes(vafr_layout layout, int64_t* bytes);
+int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right, vafr_gaze gaze,
+                      const vafr_shading* shading, vafr_layout layout, float* lp_left_dev, float* lp_right_dev,
+                      int32_t* hit_left_dev, int32_t* hit_right_dev, void* workspace_dev, int64_t workspace_bytes,
+                      hipStream_t stream);
+
 /* Inverse map (Sec. 3.2.3, Eqs. (10)-(11)): every display pixel centre is
  * mapped to (u, theta) and the LP buffer is sampled with a two-column,
  * angle-consistent bilinear filter (u clamped to the first/last column

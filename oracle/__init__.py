@@ -62,6 +62,7 @@ def _declare(L):
         "or_acuity_init": (C.c_int, [_P, C.c_int, _P, _P]),
         "or_acuity_set_aniso": (C.c_int, [_P, C.c_int, _P, _P]),
         "or_fxaa_lp": (None, [C.c_int32, _P, _P, _P, _P, C.c_int64, _P]),
+        "or_rep_splat": (None, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
         "or_delta": (_D, [_P, _D]),
         "or_acuity_capped": (C.c_int, [C.c_int, _P, _P, _D, _P, _P, C.c_int]),
         "or_omega": (_D, [_P, _D]),
@@ -474,3 +475,34 @@ def fxaa_lp(layout: Layout, lp, idx=None):
     lib().or_fxaa_lp(layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(lp), _ptr(idx), idx.size,
                      _ptr(out))
     return out
+
+
+def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, sh):
+    """Binocular reprojection (Sec. 5.1, VaFR_Rep): the left LP buffer is
+    shaded; each left hit point is projected into the right eye's LP grid
+    (nearest point wins, then the lower left texel); right texels that
+    receive no point are ray cast.  Returns (left rgba, right rgba, src,
+    flags): src[r] = left texel whose colour the right texel takes, or -1
+    where it was ray cast; flags mark texels that may legitimately differ."""
+    idx = np.arange(layout.n_texels, dtype=np.int64)
+    p = film_pitch(W, H, *fov)
+    G = gaze_film(W, H, p, *gaze)
+    org, d = vafr_rays(layout, idx, G, cam_left)
+    left, lid, lfl = scene.shade(org, d, sh)
+    ids, t, _ = scene.closest(org, d)
+    src = np.empty(layout.n_texels, np.int64)
+    flag = np.empty(layout.n_texels, np.uint8)
+    c = _cam(cam_right)
+    lfl8 = np.ascontiguousarray(lfl, np.uint8)
+    lib().or_rep_splat(layout.acuity.ptr, layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(org),
+                       _ptr(d), _ptr(t), _ptr(ids), _ptr(lfl8), _ptr(G), _ptr(c), _ptr(src), _ptr(flag))
+    right = np.empty_like(left)
+    rfl = flag.astype(bool)
+    took = src >= 0
+    right[took] = left[src[took]]
+    holes = np.nonzero(~took)[0]
+    if holes.size:
+        h_rgba, _, h_fl = shade_vafr_texels(scene, layout, holes, W, H, fov, gaze, cam_right, sh)
+        right[holes] = h_rgba
+        rfl[holes] |= h_fl.astype(bool)
+    return left, right, src, rfl

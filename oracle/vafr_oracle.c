@@ -1386,3 +1386,139 @@ void or_fxaa_lp(int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, c
         for (int c = 0; c < 4; ++c) out[4 * q + c] = r.v[c];
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Binocular reprojection from the left LP buffer (VaFR_Rep, Sec. 5.1)      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The paper reprojects the left eye's LP buffer to the right eye instead of
+ * rendering the right eye again.  For ray casting this is taken as: every
+ * left texel whose primary ray hits a triangle carries its hit point
+ * p = fma(t, d, o) (FP32, as the hit frame forms it) into the right eye;
+ * the right texel whose LP cell holds the projection takes the left texel's
+ * colour, the nearest point winning (then the lower left texel index);
+ * right texels that receive nothing are ray cast as usual.
+ *
+ * Projection (FP32, in this order): q = p - eye_R; x = (q.R)... with
+ * dot products summed left to right; z must be > 0; film point
+ * (x / z, -(y / z)).  LP cell (FP64): offset from the gaze film point,
+ * rho = |offset|, e = atan(rho) (Eq. (3)), u = u(e) (Eq. (5), Eq. (12));
+ * column floor(u) (points with u >= number of columns are outside the
+ * buffer); angle theta in [0, 360), row floor(theta / 360 n_i) (Eqs. (7),
+ * (8): row j covers angles 360 j/n_i .. 360 (j + 1)/n_i).
+ *
+ * flag marks right texels whose result may legitimately differ from the
+ * GPU's: a candidate within 1e-9 of a cell boundary (it and the cell
+ * across the boundary are marked), a runner-up depth within relative 1e-6
+ * of the winner's, or a flagged left texel (near-tie hit; its cell and the
+ * cells around it are marked).  src[r] = winning left texel or -1.
+ */
+static int64_t rep_cell(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
+                        double dx, double dy, int64_t* nb) {
+    double rho = sqrt(dx * dx + dy * dy);
+    double e = atan(rho) / OR_DEG;
+    double u = or_u(a, e);
+    *nb = -1;
+    if (!(u < (double)n_cols)) return -1;
+    int32_t i = (int32_t)floor(u);
+    double th = atan2(dy, dx) / OR_DEG;
+    if (th < 0.0) th += 360.0;
+    double vv = th / 360.0 * (double)n_rows[i];
+    int32_t j = (int32_t)floor(vv);
+    if (j >= n_rows[i]) j = n_rows[i] - 1;
+    double fu = u - floor(u), fv = vv - floor(vv);
+    const double eps = 1e-9;
+    if (fu < eps && i > 0) {
+        int32_t jj = (int32_t)floor(th / 360.0 * (double)n_rows[i - 1]);
+        if (jj >= n_rows[i - 1]) jj = n_rows[i - 1] - 1;
+        *nb = col_off[i - 1] + jj;
+    } else if (fu > 1.0 - eps && i + 1 < n_cols) {
+        int32_t jj = (int32_t)floor(th / 360.0 * (double)n_rows[i + 1]);
+        if (jj >= n_rows[i + 1]) jj = n_rows[i + 1] - 1;
+        *nb = col_off[i + 1] + jj;
+    } else if (fv < eps) {
+        *nb = col_off[i] + (j == 0 ? n_rows[i] - 1 : j - 1);
+    } else if (fv > 1.0 - eps) {
+        *nb = col_off[i] + (j + 1 == n_rows[i] ? 0 : j + 1);
+    }
+    return col_off[i] + j;
+}
+
+void or_rep_splat(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
+                  const float* org, const float* dir, const float* t, const int32_t* hit_id, const uint8_t* lflag,
+                  const double* G, const float* cam_right, int64_t* src, uint8_t* flag) {
+    const int64_t n = col_off[n_cols];
+    uint64_t* best = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
+    float* second = (float*)malloc((size_t)n * sizeof(float));
+    for (int64_t r = 0; r < n; ++r) {
+        best[r] = UINT64_MAX;
+        second[r] = INFINITY;
+        flag[r] = 0;
+    }
+    const float* eye = cam_right;
+    const float* R = cam_right + 3;
+    const float* U = cam_right + 6;
+    const float* F = cam_right + 9;
+    for (int64_t k = 0; k < n; ++k) {
+        if (hit_id[k] < 0) continue;
+        float p[3], q[3];
+        for (int c = 0; c < 3; ++c) {
+            p[c] = fmaf(t[k], dir[3 * k + c], org[3 * k + c]);
+            q[c] = p[c] - eye[c];
+        }
+        float x = (q[0] * R[0] + q[1] * R[1]) + q[2] * R[2];
+        float y = (q[0] * U[0] + q[1] * U[1]) + q[2] * U[2];
+        float z = (q[0] * F[0] + q[1] * F[1]) + q[2] * F[2];
+        if (!(z > 0.0f)) continue;
+        float fx = x / z, fy = -(y / z);
+        int64_t nb;
+        int64_t r = rep_cell(a, n_cols, n_rows, col_off, (double)fx - G[0], (double)fy - G[1], &nb);
+        if (r < 0) continue;
+        if (nb >= 0) { flag[r] = 1; flag[nb] = 1; }
+        if (lflag && lflag[k]) {
+            flag[r] = 1;
+            /* the GPU's hit may be the other triangle of the tie: mark the
+             * neighbouring cells too */
+            int32_t i = 0;
+            while (i + 1 < n_cols && col_off[i + 1] <= r) ++i;
+            int32_t j = (int32_t)(r - col_off[i]);
+            flag[col_off[i] + (j + 1) % n_rows[i]] = 1;
+            flag[col_off[i] + (j + n_rows[i] - 1) % n_rows[i]] = 1;
+            for (int di = -1; di <= 1; di += 2) {
+                int32_t ii = i + di;
+                if (ii < 0 || ii >= n_cols) continue;
+                int64_t jj = (int64_t)((double)(j + 0.5) / n_rows[i] * n_rows[ii]);
+                if (jj >= n_rows[ii]) jj = n_rows[ii] - 1;
+                flag[col_off[ii] + jj] = 1;
+            }
+        }
+        uint32_t zb;
+        memcpy(&zb, &z, 4);
+        uint64_t key = ((uint64_t)zb << 32) | (uint64_t)(uint32_t)k;
+        if (key < best[r]) {
+            if (best[r] != UINT64_MAX) {
+                uint32_t ob = (uint32_t)(best[r] >> 32);
+                float oz;
+                memcpy(&oz, &ob, 4);
+                if (oz < second[r]) second[r] = oz;
+            }
+            best[r] = key;
+        } else if (z < second[r]) {
+            second[r] = z;
+        }
+    }
+    for (int64_t r = 0; r < n; ++r) {
+        if (best[r] == UINT64_MAX) {
+            src[r] = -1;
+            continue;
+        }
+        src[r] = (int64_t)(uint32_t)(best[r] & 0xffffffffu);
+        uint32_t zb = (uint32_t)(best[r] >> 32);
+        float z;
+        memcpy(&z, &zb, 4);
+        if (second[r] <= z * (1.0f + 1e-6f)) flag[r] = 1;
+    }
+    free(best);
+    free(second);
+}

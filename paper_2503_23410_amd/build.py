@@ -39,6 +39,7 @@ SOURCES = {
     "trace.hip": ["-ffp-contract=off"],
     "reconstruct.hip": [],
     "fxaa.hip": ["-ffp-contract=off"],
+    "reproject.hip": ["-ffp-contract=off"],
 }
 
 

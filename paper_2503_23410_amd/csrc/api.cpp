@@ -339,6 +339,66 @@ extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, 
     return reconstruct_kind(VAFR_LAYOUT_LMFR, L, gaze, lp, img, stream);
 }
 
+extern "C" int vafr_rep_workspace_bytes(vafr_layout L, int64_t* bytes) {
+    if (!L || !bytes) return fail(VAFR_E_ARG, "NULL argument");
+    if (L->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_UNSUPPORTED, "reprojection needs a VaFR layout");
+    // hit points, cell keys, hole list, hole count (padded to 16 bytes)
+    *bytes = L->n_texels * (int64_t)(sizeof(float4) + sizeof(unsigned long long) + sizeof(int32_t)) + 16;
+    return VAFR_OK;
+}
+
+extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right,
+                                 vafr_gaze gaze, const vafr_shading* sh, vafr_layout L, float* lp_left,
+                                 float* lp_right, int32_t* hit_left, int32_t* hit_right, void* ws, int64_t ws_bytes,
+                                 hipStream_t stream) {
+    int64_t need;
+    if (int rc = vafr_rep_workspace_bytes(L, &need)) return rc;
+    if (!lp_left || !lp_right) return fail(VAFR_E_ARG, "LP buffer is NULL");
+    if (!ws || ws_bytes < need)
+        return fail(VAFR_E_ARG, "workspace of %lld bytes needed, %lld given", (long long)need, (long long)ws_bytes);
+    if (reinterpret_cast<uintptr_t>(ws) % 16) return fail(VAFR_E_ARG, "workspace is not 16-byte aligned");
+    {
+        // the right eye reads the left buffers and the workspace while it
+        // writes its own: none of them may overlap
+        const uintptr_t lb = (uintptr_t)L->n_texels * 16u, ib = (uintptr_t)L->n_texels * 4u;
+        const struct { const void* p; uintptr_t n; } span[5] = {
+            {lp_left, lb}, {lp_right, lb}, {ws, (uintptr_t)need}, {hit_left, hit_left ? ib : 0},
+            {hit_right, hit_right ? ib : 0}};
+        for (int a = 0; a < 5; ++a)
+            for (int b = a + 1; b < 5; ++b) {
+                const uintptr_t pa = reinterpret_cast<uintptr_t>(span[a].p), pb = reinterpret_cast<uintptr_t>(span[b].p);
+                if (span[a].n && span[b].n && pa < pb + span[b].n && pb < pa + span[a].n)
+                    return fail(VAFR_E_ARG, "LP buffers, hit-id buffers and workspace must not overlap");
+            }
+    }
+    if (int rc = check_camera(cam_right)) return rc;
+    TraceView left, right;
+    if (int rc = make_trace_view(VAFR_LAYOUT_VAFR, scene, cam_left, gaze, sh, L, nullptr, lp_left, hit_left, &left))
+        return rc;
+    if (int rc = make_trace_view(VAFR_LAYOUT_VAFR, scene, cam_right, gaze, sh, L, nullptr, lp_right, hit_right, &right))
+        return rc;
+    const int64_t n = L->n_texels;
+    RepBuffers rb;
+    rb.points = reinterpret_cast<float4*>(ws);
+    rb.key = reinterpret_cast<unsigned long long*>(reinterpret_cast<float4*>(ws) + n);
+    rb.list = reinterpret_cast<int32_t*>(rb.key + n);
+    rb.count = rb.list + n;
+    rb.src_rgba = reinterpret_cast<const float4*>(lp_left);
+    rb.src_id = hit_left;
+    rb.out_rgba = reinterpret_cast<float4*>(lp_right);
+    rb.out_id = hit_right;
+    left.out_p = reinterpret_cast<float4*>(ws);
+    right.item_list = rb.list;
+    right.item_count = rb.count;
+    const LayoutDev* ld;
+    if (int rc = layout_device(L, &ld)) return rc;
+    if (int rc = launch_trace(left, stream)) return rc;
+    double gx, gy;
+    gaze_film(L, gaze, &gx, &gy);
+    if (int rc = launch_rep(*ld, *L, gx, gy, *cam_right, rb, stream)) return rc;
+    return launch_trace(right, stream);
+}
+
 extern "C" int vafr_fxaa_lp(vafr_layout L, const float* in, float* out, hipStream_t stream) {
     if (!L) return fail(VAFR_E_ARG, "layout is NULL");
     if (L->kind != VAFR_LAYOUT_VAFR) return fail(VAFR_E_UNSUPPORTED, "LP anti-aliasing needs a VaFR layout");

@@ -384,13 +384,15 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
 
 template <int B, bool kCount>
 __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, int& id_out, WorkCount& wc,
-                                uint32_t& n_shadow) {
+                                uint32_t& n_shadow, float4& p_out) {
     const TraceView& sc = v;
     float t;
     int id;
     const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
     id_out = id;
+    p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
+    p_out = make_float4(fmaf(t, r.dx, r.ox), fmaf(t, r.dy, r.oy), fmaf(t, r.dz, r.oz), 1.0f);
     const float4* tp = sc.tris + 3 * (size_t)slot;
     float3 n, os;
     hit_frame(ldg4(tp, 0), ldg4(tp, 1), ldg4(tp, 2), r, t, n, os);
@@ -411,16 +413,20 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
 
 template <int B, bool kCount>
 __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
-                             uint32_t& n_shadow) {
+                             uint32_t& n_shadow, float4& p_out) {
     const TraceView& sc = v;
     float3 thr = make_float3(1.0f, 1.0f, 1.0f);
     float3 L = make_float3(0.0f, 0.0f, 0.0f);
     id_out = -1;
+    p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int bnc = 0; bnc <= v.bounces; ++bnc) {
         float t;
         int id;
         const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
-        if (bnc == 0) id_out = id;
+        if (bnc == 0) {
+            id_out = id;
+            if (slot >= 0) p_out = make_float4(fmaf(t, r.dx, r.ox), fmaf(t, r.dy, r.oy), fmaf(t, r.dz, r.oz), 1.0f);
+        }
         if (slot < 0) {
             L.x += thr.x * v.background[0];
             L.y += thr.y * v.background[1];
@@ -457,16 +463,20 @@ template <int B, bool kCount>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
+    if (v.item_list) {
+        if (k >= *v.item_count) return;
+        k = v.item_list[k];
+    }
     if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
     int* stk = stack + threadIdx.x;
     int id;
-    float4 c;
+    float4 c, p;
     WorkCount wc;
     uint32_t n_shadow = 0;
     if (v.shade_mode == VAFR_SHADE_PATH)
-        c = shade_path<B, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow);
+        c = shade_path<B, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
     else
-        c = shade_lambert<B, kCount>(v, r, stk, id, wc, n_shadow);
+        c = shade_lambert<B, kCount>(v, r, stk, id, wc, n_shadow, p);
     if (kCount) {
         atomicAdd(counters + 0, 1ull);
         atomicAdd(counters + 1, (unsigned long long)n_shadow);
@@ -476,6 +486,7 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     }
     v.out_rgba[out] = c;
     if (v.out_id) v.out_id[out] = id;
+    if (v.out_p) v.out_p[out] = p;
 }
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
@@ -493,7 +504,7 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[S * B];
-    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int b = v.item_list ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
     trace_item<B, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
 

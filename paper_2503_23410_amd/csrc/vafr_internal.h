@@ -171,6 +171,12 @@ struct TraceView {
     // outputs
     float4* out_rgba;
     int32_t* out_id;
+    float4* out_p;          // nullable: primary hit point (w = 1) or zeros
+    // item list (nullable): thread q < *item_count traces item item_list[q];
+    // n_items bounds the list.  Workgroups keep their hardware order so that
+    // a short list still spreads over every XCD.
+    const int32_t* item_list;
+    const int32_t* item_count;
 };
 
 // Work items of a view (padded to whole tiles for full-resolution / LMFR).
@@ -217,6 +223,25 @@ int64_t recon_blocks_of(const ReconView& v, int rows);
 int launch_reconstruct(const ReconView& v, hipStream_t stream, int rows = kReconRowsDefault);
 int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_end_dev, int32_t n_views,
                              int32_t blocks, int rows, hipStream_t stream);
+
+// Binocular reprojection: clear the per-texel keys and splat the left hit
+// points into the right eye's LP cells.
+// Binocular reprojection into the right eye (per texel of a VaFR layout):
+// clears the cell keys and the hole count, splats the left hit points, then
+// copies each reached cell's winner (colour, hit id) into the right buffers
+// and lists the trace-order items of the cells nobody reached.
+struct RepBuffers {
+    const float4* points;         // left hit points (w = 1) or zeros
+    unsigned long long* key;      // per right texel
+    const float4* src_rgba;       // left LP buffer
+    const int32_t* src_id;        // nullable
+    float4* out_rgba;             // right LP buffer
+    int32_t* out_id;              // nullable
+    int32_t* list;                // hole items, trace order within a workgroup
+    int32_t* count;               // number of listed holes
+};
+int launch_rep(const LayoutDev& ld, const vafr_layout_s& L, double gx, double gy, const vafr_camera& right,
+               const RepBuffers& b, hipStream_t stream);
 
 // LP anti-aliasing over all texels of a VaFR layout (col: per-column rows
 // and first texel on the device).

@@ -36,7 +36,7 @@ EXPORTS = (
     "vafr_batch_autotune", "vafr_batch_get_config", "vafr_batch_set_config", "vafr_batch_destroy",
     "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
     "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
-    "vafr_server_destroy", "vafr_acuity_capped", "vafr_fxaa_lp",
+    "vafr_server_destroy", "vafr_acuity_capped", "vafr_fxaa_lp", "vafr_rep_workspace_bytes", "vafr_shade_lp_rep",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -143,6 +143,9 @@ def load():
         "vafr_abi_version": (C.c_int, []),
         "vafr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.POINTER(vafr_acuity), C.POINTER(_P)]),
         "vafr_fxaa_lp": (C.c_int, [_P, _P, _P, _P]),
+        "vafr_rep_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+        "vafr_shade_lp_rep": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_camera), vafr_gaze,
+                                        C.POINTER(vafr_shading), _P, _P, _P, _P, _P, _P, C.c_int64, _P]),
         "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
@@ -386,6 +389,22 @@ def vafr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None)
 def lmfr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
     _check(load().lmfr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),
                                 _dptr(hit_id), _stream(stream)))
+
+
+def rep_workspace_bytes(layout):
+    n = C.c_int64()
+    _check(load().vafr_rep_workspace_bytes(layout.handle, C.byref(n)))
+    return n.value
+
+
+def vafr_shade_lp_rep(scene, cam_left, cam_right, gz, sh, layout, lp_left, lp_right, workspace, hit_left=None,
+                      hit_right=None, stream=None):
+    """Left LP shaded, right LP reprojected from it (holes ray-cast);
+    workspace: a device tensor of at least rep_workspace_bytes(layout) bytes."""
+    _check(load().vafr_shade_lp_rep(scene.handle, C.byref(cam_left), C.byref(cam_right), gz, C.byref(sh),
+                                    layout.handle, _dptr(lp_left), _dptr(lp_right), _dptr(hit_left),
+                                    _dptr(hit_right), _dptr(workspace),
+                                    workspace.numel() * workspace.element_size(), _stream(stream)))
 
 
 def vafr_fxaa_lp(layout, lp_in, lp_out, stream=None):
