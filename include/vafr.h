@@ -248,14 +248,20 @@ int vafr_fxaa_lp(vafr_layout layout, const float* lp_in_dev, float* lp_out_dev, 
  * bytes (hit points, cell keys, list of unreached cells), 16-byte aligned, reused across calls
  * on one stream (calls that overlap on one workspace race).  hit_left /
  * hit_right are nullable.  The LP buffers, hit-id buffers and workspace
- * must not overlap.  Errors: VAFR_E_ARG (NULL, overlapping or misaligned
+ * must not overlap.  right_stream (nullable or equal to stream: one
+ * stream) receives the ray casting of the uncovered texels, ordered after
+ * the warp on stream; lp_right / hit_right are then complete in
+ * right_stream's order, lp_left / hit_left in stream's, and the workspace
+ * stays in use until right_stream's work is done.  A caller can so overlap
+ * that latency-bound pass with work on stream, such as the left eye's
+ * inverse map.  Errors: VAFR_E_ARG (NULL, overlapping or misaligned
  * buffers, small workspace, invalid camera / shading / gaze), VAFR_E_UNSUPPORTED
  * (LMFR layout), VAFR_E_HIP. */
 int vafr_rep_workspace_bytes(vafr_layout layout, int64_t* bytes);
 int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right, vafr_gaze gaze,
                       const vafr_shading* shading, vafr_layout layout, float* lp_left_dev, float* lp_right_dev,
                       int32_t* hit_left_dev, int32_t* hit_right_dev, void* workspace_dev, int64_t workspace_bytes,
-                      hipStream_t stream);
+                      hipStream_t stream, hipStream_t right_stream);
 
 /* Inverse map (Sec. 3.2.3, Eqs. (10)-(11)): every display pixel centre is
  * mapped to (u, theta) and the LP buffer is sampled with a two-column,

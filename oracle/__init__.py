@@ -62,7 +62,8 @@ def _declare(L):
         "or_acuity_init": (C.c_int, [_P, C.c_int, _P, _P]),
         "or_acuity_set_aniso": (C.c_int, [_P, C.c_int, _P, _P]),
         "or_fxaa_lp": (None, [C.c_int32, _P, _P, _P, _P, C.c_int64, _P]),
-        "or_rep_splat": (None, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+        "or_warp_triangles": (C.c_int64, [C.c_int32, _P, _P, _P, _P]),
+        "or_rep_warp": (None, [C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
         "or_delta": (_D, [_P, _D]),
         "or_acuity_capped": (C.c_int, [C.c_int, _P, _P, _D, _P, _P, C.c_int]),
         "or_omega": (_D, [_P, _D]),
@@ -477,32 +478,45 @@ def fxaa_lp(layout: Layout, lp, idx=None):
     return out
 
 
-def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, sh):
-    """Binocular reprojection (Sec. 5.1, VaFR_Rep): the left LP buffer is
-    shaded; each left hit point is projected into the right eye's LP grid
-    (nearest point wins, then the lower left texel); right texels that
-    receive no point are ray cast.  Returns (left rgba, right rgba, src,
-    flags): src[r] = left texel whose colour the right texel takes, or -1
-    where it was ray cast; flags mark texels that may legitimately differ."""
+def warp_triangles(layout: Layout):
+    """The grid triangles of forward grid warping (Sec. 5.1): (vertices
+    (m, 3) texel indices: previous, x, other; ids (m,))."""
+    m = int(lib().or_warp_triangles(layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), None, None))
+    v = np.empty((m, 3), np.int64)
+    ids = np.empty(m, np.int64)
+    lib().or_warp_triangles(layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(v), _ptr(ids))
+    return v, ids
+
+
+def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, sh, depth=None):
+    """Binocular reprojection (Sec. 5.1, VaFR_Rep) by forward grid warping:
+    the left LP buffer is shaded; its texels' hit points, as a grid of
+    triangles, are warped into the right eye's LP grid (nearest surface
+    wins, colours interpolated); right texels no triangle covers are ray
+    cast.  Returns (left rgba, right rgba, tri, flags, right ids):
+    tri[r] = winning grid triangle of right texel r, or -1 where it was ray
+    cast; flags mark texels that may legitimately differ.  depth: optional
+    float32 array that receives each warped texel's interpolated depth."""
     idx = np.arange(layout.n_texels, dtype=np.int64)
     p = film_pitch(W, H, *fov)
     G = gaze_film(W, H, p, *gaze)
     org, d = vafr_rays(layout, idx, G, cam_left)
     left, lid, lfl = scene.shade(org, d, sh)
     ids, t, _ = scene.closest(org, d)
-    src = np.empty(layout.n_texels, np.int64)
-    flag = np.empty(layout.n_texels, np.uint8)
-    c = _cam(cam_right)
+    n = layout.n_texels
+    right = np.zeros((n, 4), np.float32)
+    rid = np.full(n, -1, np.int32)
+    tri = np.empty(n, np.int64)
+    flag = np.empty(n, np.uint8)
     lfl8 = np.ascontiguousarray(lfl, np.uint8)
-    lib().or_rep_splat(layout.acuity.ptr, layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(org),
-                       _ptr(d), _ptr(t), _ptr(ids), _ptr(lfl8), _ptr(G), _ptr(c), _ptr(src), _ptr(flag))
-    right = np.empty_like(left)
+    lib().or_rep_warp(layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), _ptr(layout.dxy), _ptr(G),
+                      _ptr(org), _ptr(d), _ptr(t), _ptr(_arr(ids, np.int32)), _ptr(lfl8), _ptr(_arr(left, np.float32)),
+                      _ptr(_cam(cam_right)), _ptr(right), _ptr(rid), _ptr(tri), _ptr(depth), _ptr(flag))
     rfl = flag.astype(bool)
-    took = src >= 0
-    right[took] = left[src[took]]
-    holes = np.nonzero(~took)[0]
+    holes = np.nonzero(tri < 0)[0]
     if holes.size:
-        h_rgba, _, h_fl = shade_vafr_texels(scene, layout, holes, W, H, fov, gaze, cam_right, sh)
+        h_rgba, h_id, h_fl = shade_vafr_texels(scene, layout, holes, W, H, fov, gaze, cam_right, sh)
         right[holes] = h_rgba
+        rid[holes] = h_id
         rfl[holes] |= h_fl.astype(bool)
-    return left, right, src, rfl
+    return left, right, tri, rfl, rid

@@ -1386,81 +1386,139 @@ void or_fxaa_lp(int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, c
         for (int c = 0; c < 4; ++c) out[4 * q + c] = r.v[c];
     }
 }
-
 /* ------------------------------------------------------------------------ */
-/* Binocular reprojection from the left LP buffer (VaFR_Rep, Sec. 5.1)      */
+/* Binocular reprojection by forward grid warping of the left LP buffer     */
+/* (VaFR_Rep, Sec. 5.1)                                                     */
 /* ------------------------------------------------------------------------ */
 
 /*
- * The paper reprojects the left eye's LP buffer to the right eye instead of
- * rendering the right eye again.  For ray casting this is taken as: every
- * left texel whose primary ray hits a triangle carries its hit point
- * p = fma(t, d, o) (FP32, as the hit frame forms it) into the right eye;
- * the right texel whose LP cell holds the projection takes the left texel's
- * colour, the nearest point winning (then the lower left texel index);
- * right texels that receive nothing are ray cast as usual.
+ * The paper renders the right eye by warping the left eye's LP buffer as a
+ * grid (forward grid warping after Wissmann et al. 2020) instead of
+ * rendering it again.  For ray casting this is taken as follows.
  *
- * Projection (FP32, in this order): q = p - eye_R; x = (q.R)... with
- * dot products summed left to right; z must be > 0; film point
- * (x / z, -(y / z)).  LP cell (FP64): offset from the gaze film point,
- * rho = |offset|, e = atan(rho) (Eq. (3)), u = u(e) (Eq. (5), Eq. (12));
- * column floor(u) (points with u >= number of columns are outside the
- * buffer); angle theta in [0, 360), row floor(theta / 360 n_i) (Eqs. (7),
- * (8): row j covers angles 360 j/n_i .. 360 (j + 1)/n_i).
+ * Vertices.  Every left texel whose primary ray hits carries its hit point
+ * p = fma(t, d, o) (FP32, as the hit frame forms it).  Projected into the
+ * right eye (FP32, in this order): q = p - eye_R; x = q.R, y = q.U,
+ * z = q.F, each dot product summed left to right; film point
+ * (x / z, -(y / z)).  A vertex is valid when its ray hit, z > 0 and the
+ * film point is finite.
  *
- * flag marks right texels whose result may legitimately differ from the
- * GPU's: a candidate within 1e-9 of a cell boundary (it and the cell
- * across the boundary are marked), a runner-up depth within relative 1e-6
- * of the winner's, or a flagged left texel (near-tie hit; its cell and the
- * cells around it are marked).  src[r] = winning left texel or -1.
+ * Grid.  Texel (i, j) of column i (n_i rows) sits at angle (2j + 1) / (2 n_i)
+ * turns.  The band between columns s and s + 1 is triangulated by a zipper
+ * walk: the texels of both columns are merged by angle (on equal angles the
+ * inner column first), cyclically; each texel x met in that order closes
+ * the triangle (previous texel of x's column, x, last texel of the other
+ * column met before x -- the other column's last texel when none was).
+ * Triangle ids: 2 x + 1 for x in the inner column of the band, 2 x for x in
+ * the outer column.
+ *
+ * Discarded triangles (their area is left to ray casting): a vertex not
+ * valid; a depth jump, largest z > (1 + 1/10) x smallest z; a stretch, the
+ * right film bounding box's larger side above twice the larger side of the
+ * left film bounding box of the same texels; zero area.
+ *
+ * Coverage (FP64).  Right texel c's sample point is C = G + dxy[c] (the
+ * gaze film point plus its film offset, as its primary ray uses).  With
+ * E(P, Q; C) = (Q.x - P.x)(C.y - P.y) - (Q.y - P.y)(C.x - P.x), vertices
+ * V0 = previous, V1 = x, V2 = other, A = E(V0, V1; V2), e0 = E(V1, V2; C),
+ * e1 = E(V2, V0; C), e2 = E(V0, V1; C): C is covered when A != 0 and every
+ * e_k has A's sign or is zero.  b_k = e_k / A, s = b0/z0 + b1/z1 + b2/z2,
+ * depth = (float)(1 / s) (perspective-correct: 1/z is linear on the film).
+ * The covering triangle of least (depth bits, id) wins the texel.
+ *
+ * Colour.  w_k = (b_k / z_k) / s; rgba = w0 c0 + w1 c1 + w2 c2 (FP64, left to
+ * right, rounded to FP32); hit id of the vertex of largest w (first on
+ * ties).  Right texels no triangle covers are ray cast as usual.
+ *
+ * This function is the plain definition: the triangles are listed by the
+ * zipper walk and every texel is tested against the triangles of its bin on
+ * a uniform grid over the right film plane (no log-polar geometry).
+ *
+ * flag marks right texels whose result may legitimately differ: those whose
+ * sample point lies in the bounding box, widened by its size on every
+ * side, of the valid vertices of a triangle that uses a flagged left texel
+ * (near-tie hit, which another FP32 implementation may resolve to the other
+ * triangle).  tri[c] = winning triangle id or -1; depth_win[c] (nullable)
+ * its depth.
  */
-static int64_t rep_cell(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
-                        double dx, double dy, int64_t* nb) {
-    double rho = sqrt(dx * dx + dy * dy);
-    double e = atan(rho) / OR_DEG;
-    double u = or_u(a, e);
-    *nb = -1;
-    if (!(u < (double)n_cols)) return -1;
-    int32_t i = (int32_t)floor(u);
-    double th = atan2(dy, dx) / OR_DEG;
-    if (th < 0.0) th += 360.0;
-    double vv = th / 360.0 * (double)n_rows[i];
-    int32_t j = (int32_t)floor(vv);
-    if (j >= n_rows[i]) j = n_rows[i] - 1;
-    double fu = u - floor(u), fv = vv - floor(vv);
-    const double eps = 1e-9;
-    if (fu < eps && i > 0) {
-        int32_t jj = (int32_t)floor(th / 360.0 * (double)n_rows[i - 1]);
-        if (jj >= n_rows[i - 1]) jj = n_rows[i - 1] - 1;
-        *nb = col_off[i - 1] + jj;
-    } else if (fu > 1.0 - eps && i + 1 < n_cols) {
-        int32_t jj = (int32_t)floor(th / 360.0 * (double)n_rows[i + 1]);
-        if (jj >= n_rows[i + 1]) jj = n_rows[i + 1] - 1;
-        *nb = col_off[i + 1] + jj;
-    } else if (fv < eps) {
-        *nb = col_off[i] + (j == 0 ? n_rows[i] - 1 : j - 1);
-    } else if (fv > 1.0 - eps) {
-        *nb = col_off[i] + (j + 1 == n_rows[i] ? 0 : j + 1);
+#define OR_WARP_DEPTH_REL 0.1
+#define OR_WARP_STRETCH 2.0
+
+typedef struct {
+    int64_t v[3];      /* texels: previous, x, other */
+    int64_t id;
+} or_wtri;
+
+/* zipper walk of the band between columns s and s + 1; appends its
+ * triangles to out (2 n_s + 2 n_{s+1} entries reserved by the caller). */
+static int64_t warp_band(const int32_t* n_rows, const int64_t* col_off, int32_t s, or_wtri* out) {
+    const int64_t na = n_rows[s], nb = n_rows[s + 1];
+    const int64_t oa = col_off[s], ob = col_off[s + 1];
+    int64_t ka = 0, kb = 0, m = 0;
+    int64_t last_a = -1, last_b = -1;   /* last texel met in each column */
+    while (ka < na || kb < nb) {
+        int take_a;
+        if (ka >= na) take_a = 0;
+        else if (kb >= nb) take_a = 1;
+        else take_a = (2 * ka + 1) * nb <= (2 * kb + 1) * na;   /* inner first on ties */
+        if (take_a) {
+            const int64_t x = oa + ka;
+            out[m].v[0] = oa + (ka == 0 ? na - 1 : ka - 1);
+            out[m].v[1] = x;
+            out[m].v[2] = last_b >= 0 ? last_b : ob + nb - 1;
+            out[m].id = 2 * x + 1;
+            last_a = x;
+            ++ka;
+        } else {
+            const int64_t x = ob + kb;
+            out[m].v[0] = ob + (kb == 0 ? nb - 1 : kb - 1);
+            out[m].v[1] = x;
+            out[m].v[2] = last_a >= 0 ? last_a : oa + na - 1;
+            out[m].id = 2 * x;
+            last_b = x;
+            ++kb;
+        }
+        ++m;
     }
-    return col_off[i] + j;
+    return m;
 }
 
-void or_rep_splat(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
-                  const float* org, const float* dir, const float* t, const int32_t* hit_id, const uint8_t* lflag,
-                  const double* G, const float* cam_right, int64_t* src, uint8_t* flag) {
+/* All grid triangles, ordered by band; returns their number (the caller
+ * frees *tris). */
+int64_t or_warp_triangles(int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, int64_t* tri_v,
+                          int64_t* tri_id) {
     const int64_t n = col_off[n_cols];
-    uint64_t* best = (uint64_t*)malloc((size_t)n * sizeof(uint64_t));
-    float* second = (float*)malloc((size_t)n * sizeof(float));
-    for (int64_t r = 0; r < n; ++r) {
-        best[r] = UINT64_MAX;
-        second[r] = INFINITY;
-        flag[r] = 0;
-    }
+    or_wtri* t = (or_wtri*)malloc(sizeof(or_wtri) * (size_t)(2 * n + 1));
+    int64_t m = 0;
+    for (int32_t s = 0; s + 1 < n_cols; ++s) m += warp_band(n_rows, col_off, s, t + m);
+    if (tri_v)
+        for (int64_t k = 0; k < m; ++k) {
+            for (int c = 0; c < 3; ++c) tri_v[3 * k + c] = t[k].v[c];
+            tri_id[k] = t[k].id;
+        }
+    free(t);
+    return m;
+}
+
+static double warp_edge(const double* P, const double* Q, const double* Cp) {
+    return (Q[0] - P[0]) * (Cp[1] - P[1]) - (Q[1] - P[1]) * (Cp[0] - P[0]);
+}
+
+void or_rep_warp(int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, const float* dxy, const double* G,
+                 const float* org, const float* dir, const float* t, const int32_t* hit_id, const uint8_t* lflag,
+                 const float* rgba_left, const float* cam_right, float* rgba_right, int32_t* id_right,
+                 int64_t* tri_win, float* depth_win, uint8_t* flag) {
+    const int64_t n = col_off[n_cols];
     const float* eye = cam_right;
     const float* R = cam_right + 3;
     const float* U = cam_right + 6;
     const float* F = cam_right + 9;
+    /* vertices: right film point and depth */
+    double* fp = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+    float* zr = (float*)malloc(sizeof(float) * (size_t)n);
+    uint8_t* ok = (uint8_t*)malloc((size_t)n);
     for (int64_t k = 0; k < n; ++k) {
+        ok[k] = 0;
         if (hit_id[k] < 0) continue;
         float p[3], q[3];
         for (int c = 0; c < 3; ++c) {
@@ -1472,53 +1530,153 @@ void or_rep_splat(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, con
         float z = (q[0] * F[0] + q[1] * F[1]) + q[2] * F[2];
         if (!(z > 0.0f)) continue;
         float fx = x / z, fy = -(y / z);
-        int64_t nb;
-        int64_t r = rep_cell(a, n_cols, n_rows, col_off, (double)fx - G[0], (double)fy - G[1], &nb);
-        if (r < 0) continue;
-        if (nb >= 0) { flag[r] = 1; flag[nb] = 1; }
-        if (lflag && lflag[k]) {
-            flag[r] = 1;
-            /* the GPU's hit may be the other triangle of the tie: mark the
-             * neighbouring cells too */
-            int32_t i = 0;
-            while (i + 1 < n_cols && col_off[i + 1] <= r) ++i;
-            int32_t j = (int32_t)(r - col_off[i]);
-            flag[col_off[i] + (j + 1) % n_rows[i]] = 1;
-            flag[col_off[i] + (j + n_rows[i] - 1) % n_rows[i]] = 1;
-            for (int di = -1; di <= 1; di += 2) {
-                int32_t ii = i + di;
-                if (ii < 0 || ii >= n_cols) continue;
-                int64_t jj = (int64_t)((double)(j + 0.5) / n_rows[i] * n_rows[ii]);
-                if (jj >= n_rows[ii]) jj = n_rows[ii] - 1;
-                flag[col_off[ii] + jj] = 1;
+        if (!isfinite(fx) || !isfinite(fy)) continue;
+        fp[2 * k] = fx;
+        fp[2 * k + 1] = fy;
+        zr[k] = z;
+        ok[k] = 1;
+    }
+    /* triangles, kept ones with their right film boxes */
+    int64_t* tv = (int64_t*)malloc(sizeof(int64_t) * 3 * (size_t)(2 * n + 1));
+    int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (size_t)(2 * n + 1));
+    const int64_t m = or_warp_triangles(n_cols, n_rows, col_off, tv, tid);
+    uint8_t* keep = (uint8_t*)calloc((size_t)m, 1);
+    double* box = (double*)malloc(sizeof(double) * 4 * (size_t)m);   /* x0 y0 x1 y1 */
+    double gx0 = INFINITY, gy0 = INFINITY, gx1 = -INFINITY, gy1 = -INFINITY;
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t* v = tv + 3 * k;
+        if (!ok[v[0]] || !ok[v[1]] || !ok[v[2]]) continue;
+        float zmin = zr[v[0]], zmax = zr[v[0]];
+        for (int c = 1; c < 3; ++c) {
+            zmin = zr[v[c]] < zmin ? zr[v[c]] : zmin;
+            zmax = zr[v[c]] > zmax ? zr[v[c]] : zmax;
+        }
+        if ((double)zmax > (double)zmin * (1.0 + OR_WARP_DEPTH_REL)) continue;
+        double rx0 = INFINITY, ry0 = INFINITY, rx1 = -INFINITY, ry1 = -INFINITY;
+        double lx0 = INFINITY, ly0 = INFINITY, lx1 = -INFINITY, ly1 = -INFINITY;
+        for (int c = 0; c < 3; ++c) {
+            const double X = fp[2 * v[c]], Y = fp[2 * v[c] + 1];
+            const double LX = G[0] + (double)dxy[2 * v[c]], LY = G[1] + (double)dxy[2 * v[c] + 1];
+            rx0 = fmin(rx0, X); rx1 = fmax(rx1, X); ry0 = fmin(ry0, Y); ry1 = fmax(ry1, Y);
+            lx0 = fmin(lx0, LX); lx1 = fmax(lx1, LX); ly0 = fmin(ly0, LY); ly1 = fmax(ly1, LY);
+        }
+        const double ext_r = fmax(rx1 - rx0, ry1 - ry0), ext_l = fmax(lx1 - lx0, ly1 - ly0);
+        if (ext_r > OR_WARP_STRETCH * ext_l) continue;
+        if (warp_edge(fp + 2 * v[0], fp + 2 * v[1], fp + 2 * v[2]) == 0.0) continue;
+        keep[k] = 1;
+        box[4 * k] = rx0; box[4 * k + 1] = ry0; box[4 * k + 2] = rx1; box[4 * k + 3] = ry1;
+        gx0 = fmin(gx0, rx0); gy0 = fmin(gy0, ry0); gx1 = fmax(gx1, rx1); gy1 = fmax(gy1, ry1);
+    }
+    /* uniform bins over the kept boxes */
+    const int NB = 1024;
+    int64_t* cnt = (int64_t*)calloc((size_t)NB * NB + 1, sizeof(int64_t));
+    const double bw = (gx1 - gx0) / NB, bh = (gy1 - gy0) / NB;
+    const int have = gx0 < gx1 && gy0 < gy1;
+#define OR_BIN_X(X) ((int)fmin(NB - 1.0, fmax(0.0, floor(((X) - gx0) / bw))))
+#define OR_BIN_Y(Y) ((int)fmin(NB - 1.0, fmax(0.0, floor(((Y) - gy0) / bh))))
+    if (have)
+        for (int64_t k = 0; k < m; ++k) {
+            if (!keep[k]) continue;
+            for (int by = OR_BIN_Y(box[4 * k + 1]); by <= OR_BIN_Y(box[4 * k + 3]); ++by)
+                for (int bx = OR_BIN_X(box[4 * k]); bx <= OR_BIN_X(box[4 * k + 2]); ++bx) cnt[by * NB + bx + 1]++;
+        }
+    for (int64_t b = 0; b < (int64_t)NB * NB; ++b) cnt[b + 1] += cnt[b];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)NB * NB);
+    memcpy(fill, cnt, sizeof(int64_t) * (size_t)NB * NB);
+    int64_t* items = (int64_t*)malloc(sizeof(int64_t) * (size_t)(cnt[(int64_t)NB * NB] + 1));
+    if (have)
+        for (int64_t k = 0; k < m; ++k) {
+            if (!keep[k]) continue;
+            for (int by = OR_BIN_Y(box[4 * k + 1]); by <= OR_BIN_Y(box[4 * k + 3]); ++by)
+                for (int bx = OR_BIN_X(box[4 * k]); bx <= OR_BIN_X(box[4 * k + 2]); ++bx)
+                    items[fill[by * NB + bx]++] = k;
+        }
+    /* coverage and the winner of every right texel */
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int64_t c = 0; c < n; ++c) {
+        tri_win[c] = -1;
+        flag[c] = 0;
+        if (!have) continue;
+        const double Cp[2] = {G[0] + (double)dxy[2 * c], G[1] + (double)dxy[2 * c + 1]};
+        if (Cp[0] < gx0 || Cp[0] > gx1 || Cp[1] < gy0 || Cp[1] > gy1) continue;
+        const int64_t b = (int64_t)OR_BIN_Y(Cp[1]) * NB + OR_BIN_X(Cp[0]);
+        uint64_t best = UINT64_MAX;
+        int64_t best_k = -1;
+        double best_b[3] = {0, 0, 0}, best_s = 0;
+        for (int64_t q = cnt[b]; q < cnt[b + 1]; ++q) {
+            const int64_t k = items[q];
+            const int64_t* v = tv + 3 * k;
+            const double* V0 = fp + 2 * v[0];
+            const double* V1 = fp + 2 * v[1];
+            const double* V2 = fp + 2 * v[2];
+            const double A = warp_edge(V0, V1, V2);
+            const double e0 = warp_edge(V1, V2, Cp), e1 = warp_edge(V2, V0, Cp), e2 = warp_edge(V0, V1, Cp);
+            const int in = A > 0.0 ? (e0 >= 0.0 && e1 >= 0.0 && e2 >= 0.0) : (e0 <= 0.0 && e1 <= 0.0 && e2 <= 0.0);
+            if (!in) continue;
+            const double b0 = e0 / A, b1 = e1 / A, b2 = e2 / A;
+            const double s = (b0 / (double)zr[v[0]] + b1 / (double)zr[v[1]]) + b2 / (double)zr[v[2]];
+            const float depth = (float)(1.0 / s);
+            uint32_t zb;
+            memcpy(&zb, &depth, 4);
+            const uint64_t key = ((uint64_t)zb << 32) | (uint64_t)(uint32_t)tid[k];
+            if (key < best) {
+                best = key;
+                best_k = k;
+                best_b[0] = b0; best_b[1] = b1; best_b[2] = b2;
+                best_s = s;
             }
         }
-        uint32_t zb;
-        memcpy(&zb, &z, 4);
-        uint64_t key = ((uint64_t)zb << 32) | (uint64_t)(uint32_t)k;
-        if (key < best[r]) {
-            if (best[r] != UINT64_MAX) {
-                uint32_t ob = (uint32_t)(best[r] >> 32);
-                float oz;
-                memcpy(&oz, &ob, 4);
-                if (oz < second[r]) second[r] = oz;
+        if (best_k < 0) continue;
+        tri_win[c] = tid[best_k];
+        if (depth_win) {
+            const uint32_t zb = (uint32_t)(best >> 32);
+            memcpy(&depth_win[c], &zb, 4);
+        }
+        const int64_t* v = tv + 3 * best_k;
+        double w[3];
+        for (int q = 0; q < 3; ++q) w[q] = (best_b[q] / (double)zr[v[q]]) / best_s;
+        for (int ch = 0; ch < 4; ++ch)
+            rgba_right[4 * c + ch] = (float)((w[0] * (double)rgba_left[4 * v[0] + ch] +
+                                              w[1] * (double)rgba_left[4 * v[1] + ch]) +
+                                             w[2] * (double)rgba_left[4 * v[2] + ch]);
+        int top = 0;
+        if (w[1] > w[top]) top = 1;
+        if (w[2] > w[top]) top = 2;
+        id_right[c] = hit_id[v[top]];
+    }
+    /* flags around triangles that use a flagged left texel */
+    if (lflag && have)
+        for (int64_t k = 0; k < m; ++k) {
+            const int64_t* v = tv + 3 * k;
+            if (!lflag[v[0]] && !lflag[v[1]] && !lflag[v[2]]) continue;
+            double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY, lw = 0.0;
+            double lx0 = INFINITY, ly0 = INFINITY, lx1 = -INFINITY, ly1 = -INFINITY;
+            for (int c = 0; c < 3; ++c) {
+                const double LX = G[0] + (double)dxy[2 * v[c]], LY = G[1] + (double)dxy[2 * v[c] + 1];
+                lx0 = fmin(lx0, LX); lx1 = fmax(lx1, LX); ly0 = fmin(ly0, LY); ly1 = fmax(ly1, LY);
+                if (!ok[v[c]]) continue;
+                x0 = fmin(x0, fp[2 * v[c]]); x1 = fmax(x1, fp[2 * v[c]]);
+                y0 = fmin(y0, fp[2 * v[c] + 1]); y1 = fmax(y1, fp[2 * v[c] + 1]);
             }
-            best[r] = key;
-        } else if (z < second[r]) {
-            second[r] = z;
+            if (!(x0 <= x1)) continue;
+            lw = fmax(lx1 - lx0, ly1 - ly0);
+            const double wx = fmax(x1 - x0, lw), wy = fmax(y1 - y0, lw);
+            x0 -= wx; x1 += wx; y0 -= wy; y1 += wy;
+            for (int64_t c = 0; c < n; ++c) {
+                const double X = G[0] + (double)dxy[2 * c], Y = G[1] + (double)dxy[2 * c + 1];
+                if (X >= x0 && X <= x1 && Y >= y0 && Y <= y1) flag[c] = 1;
+            }
         }
-    }
-    for (int64_t r = 0; r < n; ++r) {
-        if (best[r] == UINT64_MAX) {
-            src[r] = -1;
-            continue;
-        }
-        src[r] = (int64_t)(uint32_t)(best[r] & 0xffffffffu);
-        uint32_t zb = (uint32_t)(best[r] >> 32);
-        float z;
-        memcpy(&z, &zb, 4);
-        if (second[r] <= z * (1.0f + 1e-6f)) flag[r] = 1;
-    }
-    free(best);
-    free(second);
+#undef OR_BIN_X
+#undef OR_BIN_Y
+    free(items);
+    free(fill);
+    free(cnt);
+    free(box);
+    free(keep);
+    free(tid);
+    free(tv);
+    free(ok);
+    free(zr);
+    free(fp);
 }

@@ -350,7 +350,7 @@ extern "C" int vafr_rep_workspace_bytes(vafr_layout L, int64_t* bytes) {
 extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right,
                                  vafr_gaze gaze, const vafr_shading* sh, vafr_layout L, float* lp_left,
                                  float* lp_right, int32_t* hit_left, int32_t* hit_right, void* ws, int64_t ws_bytes,
-                                 hipStream_t stream) {
+                                 hipStream_t stream, hipStream_t right_stream) {
     int64_t need;
     if (int rc = vafr_rep_workspace_bytes(L, &need)) return rc;
     if (!lp_left || !lp_right) return fail(VAFR_E_ARG, "LP buffer is NULL");
@@ -396,7 +396,16 @@ extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, 
     double gx, gy;
     gaze_film(L, gaze, &gx, &gy);
     if (int rc = launch_rep(*ld, *L, gx, gy, *cam_right, rb, stream)) return rc;
-    return launch_trace(right, stream);
+    if (!right_stream || right_stream == stream) return launch_trace(right, stream);
+    // the hole pass on right_stream, after the warp on stream (an event's
+    // state is captured by the wait, so it can be destroyed at once)
+    hipEvent_t ev;
+    VAFR_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(right_stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    VAFR_HIP(e);
+    return launch_trace(right, right_stream);
 }
 
 extern "C" int vafr_fxaa_lp(vafr_layout L, const float* in, float* out, hipStream_t stream) {

@@ -154,6 +154,8 @@ int layout_device(vafr_layout L, const LayoutDev** out) {
             dxy_ord[k] = make_float2(L->dxy[2 * (int64_t)L->ord[k]], L->dxy[2 * (int64_t)L->ord[k] + 1]);
         VAFR_HIP(hipMalloc(&d.dxy, sizeof(float2) * dxy_ord.size()));
         VAFR_HIP(hipMemcpy(d.dxy, dxy_ord.data(), sizeof(float2) * dxy_ord.size(), hipMemcpyHostToDevice));
+        VAFR_HIP(hipMalloc(&d.dxy_tex, sizeof(float) * L->dxy.size()));
+        VAFR_HIP(hipMemcpy(d.dxy_tex, L->dxy.data(), sizeof(float) * L->dxy.size(), hipMemcpyHostToDevice));
         VAFR_HIP(hipMalloc(&d.ord, sizeof(int32_t) * L->ord.size()));
         VAFR_HIP(hipMemcpy(d.ord, L->ord.data(), sizeof(int32_t) * L->ord.size(), hipMemcpyHostToDevice));
         std::vector<int32_t> blk((L->n_texels + kTexelBlock - 1) / kTexelBlock);
@@ -277,6 +279,22 @@ extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* ac
             L->u_of_rho[2 * k] = (float)u[k];
             L->u_of_rho[2 * k + 1] = k < kURhoN ? (float)(u[k + 1] - u[k]) : 0.0f;
         }
+        // Bound on |table - u(rho)| in columns for searches that must not
+        // miss a column: the interpolation error (sampled inside every
+        // interval), the table's FP32 rounding, and a film-radius error of
+        // 4e-7 times the steepest slope.
+        double err = 0.0, slope = 0.0;
+        for (int k = 0; k < kURhoN; ++k) {
+            const double du = (double)L->u_of_rho[2 * k + 1];
+            slope = std::max(slope, std::fabs(u[k + 1] - u[k]) * kURhoN / L->rho_max);
+            for (int q = 1; q < 5; ++q) {
+                const double f = 0.2 * q;
+                const double rho = L->rho_max * (k + f) / kURhoN;
+                const double ex = std::min(std::max(seg_u(seg, std::atan(rho) / kDeg), 0.5), u_hi);
+                err = std::max(err, std::fabs((double)L->u_of_rho[2 * k] + f * du - ex));
+            }
+        }
+        L->u_margin = 2.0 * err + 4e-7 * slope + 1e-3;
     } catch (const std::bad_alloc&) {
         delete L;
         return fail(VAFR_E_OOM, "layout tables allocation failed");
@@ -354,6 +372,7 @@ extern "C" void vafr_layout_destroy(vafr_layout L) {
         if (hipSetDevice(d.device) != hipSuccess) continue;
         (void)hipFree(d.col);
         (void)hipFree(d.dxy);
+        (void)hipFree(d.dxy_tex);
         (void)hipFree(d.ord);
         (void)hipFree(d.blk_col);
         (void)hipFree(d.u_of_rho);

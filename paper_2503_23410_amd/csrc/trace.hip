@@ -463,10 +463,6 @@ template <int B, bool kCount>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
-    if (v.item_list) {
-        if (k >= *v.item_count) return;
-        k = v.item_list[k];
-    }
     if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
     int* stk = stack + threadIdx.x;
     int id;
@@ -504,8 +500,20 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[S * B];
-    const int b = v.item_list ? (int)blockIdx.x : xcd_block(blockIdx.x, gridDim.x);
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     trace_item<B, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
+}
+
+// List mode: thread q < *item_count traces item item_list[q].  The grid is
+// sized for the longest list; workgroups past the count exit at once.
+// Workgroups keep their hardware order, so a short list still spreads over
+// every XCD.
+template <int B, int S>
+__global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
+    __shared__ int stack[S * B];
+    const int64_t q = (int64_t)blockIdx.x * B + threadIdx.x;
+    if (q >= *v.item_count) return;
+    trace_item<B, false>(v, v.item_list[q], stack, nullptr);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
@@ -525,7 +533,9 @@ __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__
 
 template <int B, int S>
 void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsigned long long* counters) {
-    if (counters)
+    if (v.item_list)
+        hipLaunchKernelGGL((k_trace_list<B, S>), dim3((unsigned)blocks), dim3(B), 0, stream, v);
+    else if (counters)
         hipLaunchKernelGGL((k_trace<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
     else
         hipLaunchKernelGGL((k_trace<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
@@ -583,6 +593,7 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
     if (!stack_ok(v.stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", v.stack);
     const int64_t blocks = (v.n_items + block - 1) / block;
+    if (v.item_list && counters) return fail(VAFR_E_UNSUPPORTED, "work counting does not take an item list");
     if (blocks > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one launch");
     if (v.stack == kStackShort) launch_single_s<kStackShort>(v, blocks, block, stream, counters);
     else launch_single_s<kStackLong>(v, blocks, block, stream, counters);

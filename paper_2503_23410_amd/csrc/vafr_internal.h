@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <deque>
 #include <mutex>
@@ -42,6 +43,7 @@ struct LayoutDev {
     int device = -1;
     int2* col = nullptr;          // VaFR: (n_rows, col_off) per column
     float2* dxy = nullptr;        // VaFR: film offset per texel, in trace order
+    float2* dxy_tex = nullptr;    // VaFR: film offset per texel, in texel order
     int32_t* ord = nullptr;       // VaFR: texel index of each trace-order slot
     int32_t* blk_col = nullptr;   // VaFR: column of texel 256 b (per-texel kernels' block start)
     float2* u_of_rho = nullptr;   // VaFR: (u_k, u_{k+1} - u_k) at rho_k = k h, k <= kURhoN
@@ -67,6 +69,7 @@ struct vafr_layout_s {
     std::vector<int32_t> ord;            // trace order (Morton order of the screen offsets)
     double rho_max = 0;                  // film radius of the last column centre
     std::vector<float> u_of_rho;         // 2 * (kURhoN + 1) floats
+    double u_margin = 1.0;               // bound on the table's error, in columns
     // LMFR
     double delta = 0, alpha = 0;
     std::vector<double> lm_z, lm_cos, lm_sin;
@@ -172,9 +175,8 @@ struct TraceView {
     float4* out_rgba;
     int32_t* out_id;
     float4* out_p;          // nullable: primary hit point (w = 1) or zeros
-    // item list (nullable): thread q < *item_count traces item item_list[q];
-    // n_items bounds the list.  Workgroups keep their hardware order so that
-    // a short list still spreads over every XCD.
+    // item list (nullable): the first *item_count entries of item_list are
+    // traced, one per thread; n_items bounds the list.
     const int32_t* item_list;
     const int32_t* item_count;
 };
@@ -226,13 +228,15 @@ int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_en
 
 // Binocular reprojection: clear the per-texel keys and splat the left hit
 // points into the right eye's LP cells.
-// Binocular reprojection into the right eye (per texel of a VaFR layout):
-// clears the cell keys and the hole count, splats the left hit points, then
-// copies each reached cell's winner (colour, hit id) into the right buffers
-// and lists the trace-order items of the cells nobody reached.
+// Binocular reprojection into the right eye (per texel of a VaFR layout) by
+// forward grid warping: clears the texel keys and the hole count, warps the
+// grid triangles of the left hit points (depth-ordered atomic minimum per
+// covered right texel), then writes each covered texel's interpolated
+// colour and hit id into the right buffers and lists the trace-order items
+// of the texels no triangle covered.
 struct RepBuffers {
     const float4* points;         // left hit points (w = 1) or zeros
-    unsigned long long* key;      // per right texel
+    unsigned long long* key;      // per right texel: depth bits << 32 | triangle id
     const float4* src_rgba;       // left LP buffer
     const int32_t* src_id;        // nullable
     float4* out_rgba;             // right LP buffer

@@ -145,7 +145,7 @@ def load():
         "vafr_fxaa_lp": (C.c_int, [_P, _P, _P, _P]),
         "vafr_rep_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
         "vafr_shade_lp_rep": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_camera), vafr_gaze,
-                                        C.POINTER(vafr_shading), _P, _P, _P, _P, _P, _P, C.c_int64, _P]),
+                                        C.POINTER(vafr_shading), _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]),
         "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
@@ -398,13 +398,16 @@ def rep_workspace_bytes(layout):
 
 
 def vafr_shade_lp_rep(scene, cam_left, cam_right, gz, sh, layout, lp_left, lp_right, workspace, hit_left=None,
-                      hit_right=None, stream=None):
-    """Left LP shaded, right LP reprojected from it (holes ray-cast);
-    workspace: a device tensor of at least rep_workspace_bytes(layout) bytes."""
+                      hit_right=None, stream=None, right_stream=None):
+    """Left LP shaded, right LP warped from it (uncovered texels ray-cast);
+    workspace: a device tensor of at least rep_workspace_bytes(layout) bytes.
+    right_stream: optional stream for the ray casting of the uncovered
+    texels (the right buffers are then complete in its order)."""
     _check(load().vafr_shade_lp_rep(scene.handle, C.byref(cam_left), C.byref(cam_right), gz, C.byref(sh),
                                     layout.handle, _dptr(lp_left), _dptr(lp_right), _dptr(hit_left),
                                     _dptr(hit_right), _dptr(workspace),
-                                    workspace.numel() * workspace.element_size(), _stream(stream)))
+                                    workspace.numel() * workspace.element_size(), _stream(stream),
+                                    None if right_stream is None else _stream(right_stream)))
 
 
 def vafr_fxaa_lp(layout, lp_in, lp_out, stream=None):
