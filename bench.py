@@ -35,19 +35,23 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
 # Algorithmic FP32 operations of one unit of traversal work, counted from the
-# arithmetic the traversal performs (see DESIGN.md):
-#  - one node visit tests two child boxes: per child 6 FMAs for the slab
-#    distances (plane * 1/d - o/d; the benchmark's eyes are within the range
-#    where this form is conservative), 6 min/max per axis, 4 min/max to
+# arithmetic the traversal performs:
+#  - one node visit tests four quantised child boxes: per node 6 selects
+#    (entry / exit plane codes by the ray's direction signs), 3 FMAs and 3
+#    multiplies (distance to the node origin, scale / d); per child 6 code
+#    conversions and 6 FMAs for the slab distances (the benchmark's eyes are
+#    within the range where this form is conservative), 4 min/max to
 #    combine axes and clamp, 1 multiply (conservative exit) and 1 compare;
-#    plus 1 compare to order the children -> 2 * 18 + 1 = 37
+#    then 3 adds (hit count), 4 selects (misses sort last) and a 5-exchange
+#    sorting network of (distance, reference) pairs, 1 compare + 4 selects
+#    each -> 12 + 4 * 18 + 3 + 4 + 25 = 116
 #  - one watertight ray/triangle test: 9 subtractions (vertices - origin),
 #    6 FMAs (shear), 6 multiplies + 3 subtractions (edge functions), 2 adds
 #    (det), 3 multiplies (z scaling), 3 multiplies + 2 adds (T), 1 division,
 #    4 compares -> 39
 #  - ray set-up: 3 reciprocals, 3 multiplies (o/d), 3 divisions, 8
 #    compares/selects -> 17
-OPS_NODE = 37
+OPS_NODE = 116
 OPS_TRI = 39
 OPS_RAY = 17
 
@@ -96,8 +100,9 @@ def main():
                     help="duration of the served 8-headset workload per server configuration (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(views would be sharded across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(views would be sharded across GPUs, each holding a replica of the scene, with no exchange).",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -183,20 +183,23 @@ int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_t* tri, int
 
 typedef struct {
     int64_t n_tris;
-    int64_t n_nodes;       /* internal nodes */
+    int64_t n_nodes;       /* internal (4-wide) nodes */
     int64_t n_leaves;
-    int32_t max_depth;
+    int32_t max_depth;     /* levels of the binary build tree below the root */
     int32_t on_device;     /* 1 if uploaded */
     int64_t device_bytes;
     double build_ms;
-    int32_t stack_entries; /* traversal stack entries per ray (LDS), > max_depth */
-    int32_t reserved;
+    int32_t stack_entries; /* traversal stack entries per ray in LDS (more spill to scratch) */
+    int32_t max_stack;     /* most entries a traversal can hold */
 } vafr_scene_info;
 
 int vafr_scene_get_info(vafr_scene scene, vafr_scene_info* out);
 
 /* Host copies of the BVH for structural checks: nodes[16 * n_nodes] as
- * stored on the device (two child boxes lo/hi, two child references) and
+ * stored on the device (per node: origin x, y, z and a word holding the
+ * three biased scale exponents and the child count; 8-bit plane codes of
+ * four child boxes, x-lo, x-hi, y-lo, y-hi, z-lo, z-hi, child c in byte c;
+ * two unused words; four child references) and
  * tri_order[n_tris] (original id of each stored triangle).  Either may be
  * NULL. */
 int vafr_scene_export(vafr_scene scene, float* nodes, int32_t* tri_order);

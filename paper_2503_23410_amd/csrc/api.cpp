@@ -248,7 +248,7 @@ extern "C" int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_
     }
     s->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rc) { delete s; return rc; }
-    if (s->host.max_depth > s->host.stack) {
+    if (s->host.max_depth > s->host.stack - 1 || s->host.max_stack > s->host.stack + kStackSpill) {
         delete s;
         return fail(VAFR_E_UNSUPPORTED, "BVH depth exceeds the traversal stack");
     }
@@ -280,7 +280,7 @@ extern "C" int vafr_scene_get_info(vafr_scene s, vafr_scene_info* out) {
     out->device_bytes = s->device_bytes;
     out->build_ms = s->build_ms;
     out->stack_entries = s->host.stack;
-    out->reserved = 0;
+    out->max_stack = s->host.max_stack;
     return VAFR_OK;
 }
 

@@ -1,6 +1,10 @@
 // Host BVH builder: binned SAH over triangle centroids, parallel over the
 // top-level subtrees, with a depth bound that keeps the GPU traversal stack
-// finite, then packed depth-first into 64-byte two-wide nodes.
+// finite, then collapsed into 4-wide nodes with 8-bit quantised child boxes
+// (64 bytes) packed depth-first.  A 4-wide node halves the node steps of a
+// ray against the binary tree and quantisation halves the bytes per node,
+// which is what the traversal's memory pipeline pays for; the collapse is
+// bounded so that the traversal stack still covers every pending sibling.
 //
 // Boxes are padded outward by a small absolute margin and rounded outward to
 // FP32, so the FP32 slab test on the GPU never rejects a box that holds a
@@ -46,6 +50,7 @@ struct TNode {
     Box box;
     std::unique_ptr<TNode> l, r;
     int64_t first = 0, count = 0;  // leaf range in idx[]
+    int h = 0;                     // internal levels below (0 for a leaf)
 };
 
 constexpr int kBins = 32;
@@ -154,6 +159,7 @@ struct Builder {
             node->l = build(first, mid, depth + 1);
             node->r = build(first + mid, n - mid, depth + 1);
         }
+        node->h = 1 + std::max(node->l->h, node->r->h);
         return node;
     }
 };
@@ -163,6 +169,7 @@ struct Packer {
     const int32_t* tri;
     const int64_t* idx;
     float pad;
+    int budget;          // stack entries per lane
     HostBvh* out;
 
     static float down(double v) {
@@ -202,25 +209,124 @@ struct Packer {
         }
     }
 
-    int32_t emit(const TNode* n) {
+    // Emits the subtree of binary node n as 4-wide nodes.  Up to four
+    // children are gathered by repeatedly opening the internal child of
+    // largest surface area.  `used` is the number of stack entries the
+    // traversal may hold on arrival (the sum of children - 1 over the
+    // ancestors); a node may gather k children only while
+    // used + (k - 1) + (the largest binary height among them) <= budget,
+    // so that two children always fit further down and no traversal
+    // pushes more than `budget` entries.
+    int32_t emit(const TNode* n, int used) {
         if (!n->l) return leaf_ref(n);
+        const TNode* ch[4] = {n->l.get(), n->r.get(), nullptr, nullptr};
+        int k = 2;
+        while (k < 4) {
+            int best = -1;
+            double best_a = -1.0;
+            for (int q = 0; q < k; ++q)
+                if (ch[q]->l && ch[q]->box.area() > best_a) {
+                    best = q;
+                    best_a = ch[q]->box.area();
+                }
+            if (best < 0) break;
+            int hmax = std::max(ch[best]->l->h, ch[best]->r->h);
+            for (int q = 0; q < k; ++q)
+                if (q != best) hmax = std::max(hmax, ch[q]->h);
+            if (used + k + hmax > budget) break;
+            const TNode* open = ch[best];
+            ch[best] = open->l.get();
+            ch[k++] = open->r.get();
+        }
         const int32_t me = (int32_t)out->nodes.size();
         out->nodes.push_back(BvhNode{});
-        float lo0[3], hi0[3], lo1[3], hi1[3];
-        child_box(n->l.get(), lo0, hi0);
-        child_box(n->r.get(), lo1, hi1);
-        const int32_t r0 = emit(n->l.get());
-        const int32_t r1 = emit(n->r.get());
+        const int below = used + k - 1;
+        out->max_stack = std::max(out->max_stack, below);
+        float lo[4][3], hi[4][3];
+        int32_t ref[4] = {kEmptyRef, kEmptyRef, kEmptyRef, kEmptyRef};
+        for (int q = 0; q < 4; ++q) {
+            for (int a = 0; a < 3; ++a) {   // an empty slot: [+inf, +inf], skipped by its reference
+                lo[q][a] = INFINITY;
+                hi[q][a] = INFINITY;
+            }
+            if (q < k) child_box(ch[q], lo[q], hi[q]);
+        }
+        for (int q = 0; q < k; ++q) ref[q] = emit(ch[q], below);
         BvhNode& b = out->nodes[me];
-        b.a = make_float4(lo0[0], hi0[0], lo0[1], hi0[1]);
-        b.b = make_float4(lo1[0], hi1[0], lo1[1], hi1[1]);
-        b.c = make_float4(lo0[2], hi0[2], lo1[2], hi1[2]);
-        b.d = make_int4(r0, r1, 0, 0);
+        float org[3];
+        uint32_t code_lo[3] = {0, 0, 0}, code_hi[3] = {0, 0, 0}, biased[3];
+        for (int a = 0; a < 3; ++a) {
+            float top = -INFINITY;
+            org[a] = INFINITY;
+            for (int q = 0; q < k; ++q) {
+                org[a] = std::min(org[a], lo[q][a]);
+                top = std::max(top, hi[q][a]);
+            }
+            uint8_t ql[4], qh[4];
+            biased[a] = quantise_axis(org[a], top, k, lo, hi, a, ql, qh);
+            for (int q = 0; q < 4; ++q) {
+                // empty slots keep codes 0 / 0; the traversal skips them by reference
+                code_lo[a] |= (uint32_t)(q < k ? ql[q] : 0) << (8 * q);
+                code_hi[a] |= (uint32_t)(q < k ? qh[q] : 0) << (8 * q);
+            }
+        }
+        uint32_t meta = biased[0] | biased[1] << 8 | biased[2] << 16 | (uint32_t)k << 24;
+        float meta_f;
+        std::memcpy(&meta_f, &meta, 4);
+        b.org = make_float4(org[0], org[1], org[2], meta_f);
+        b.q0 = make_uint4(code_lo[0], code_hi[0], code_lo[1], code_hi[1]);
+        b.q1 = make_uint4(code_lo[2], code_hi[2], 0u, 0u);
+        b.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
         return me;
+    }
+
+    // 8-bit codes of the children's planes on one axis, relative to origin
+    // o with the smallest power-of-two scale that spans up to `top`, each
+    // moved outward until fmaf(code, scale, o) lies outside the child's
+    // padded box.  Returns the scale's biased FP32 exponent.
+    static uint32_t quantise_axis(float o, float top, int k, const float lo[4][3], const float hi[4][3], int a,
+                                  uint8_t* ql, uint8_t* qh) {
+        const double span = (double)top - (double)o;
+        int e = -126;
+        if (span > 0.0) {
+            std::frexp(span / 255.0, &e);   // span / 255 <= 2^e
+            e = std::max(e - 1, -126);
+            while (std::ldexp(255.0, e) < span) ++e;
+        }
+        for (;; ++e) {
+            const float sc = std::ldexp(1.0f, e);
+            bool fits = true;
+            for (int q = 0; q < k && fits; ++q) {
+                double fl = std::floor(((double)lo[q][a] - o) / sc), fh = std::ceil(((double)hi[q][a] - o) / sc);
+                int cl = (int)std::min(std::max(fl, 0.0), 255.0), ch = (int)std::min(std::max(fh, 0.0), 255.0);
+                while (cl > 0 && std::fma((float)cl, sc, o) > lo[q][a]) --cl;
+                while (ch < 255 && std::fma((float)ch, sc, o) < hi[q][a]) ++ch;
+                if (std::fma((float)cl, sc, o) > lo[q][a] || std::fma((float)ch, sc, o) < hi[q][a]) fits = false;
+                ql[q] = (uint8_t)cl;
+                qh[q] = (uint8_t)ch;
+            }
+            if (fits) return (uint32_t)(e + 127);
+        }
     }
 };
 
 }  // namespace
+
+// Levels of 4-wide nodes on the longest root-to-leaf path.
+int wide_depth(const std::vector<BvhNode>& nodes, int32_t root) {
+    if (root < 0) return 0;
+    std::vector<std::pair<int32_t, int>> todo{{root, 1}};
+    int best = 0;
+    while (!todo.empty()) {
+        const auto [n, d] = todo.back();
+        todo.pop_back();
+        best = std::max(best, d);
+        const int4 r = nodes[n].ref;
+        for (int32_t c : {r.x, r.y, r.z, r.w})
+            if (c >= 0) todo.push_back({c, d + 1});
+    }
+    return best;
+}
 
 int build_bvh(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris, HostBvh* out) {
     *out = HostBvh();
@@ -244,6 +350,8 @@ int build_bvh(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_t
         }
         for (int k = 0; k < 3; ++k) p.c[k] = 0.5f * (p.lo[k] + p.hi[k]);
     }
+    // node scales stay at most 2^20, so code x scale / d never overflows
+    if (ext > 1.0e8f) return fail(VAFR_E_UNSUPPORTED, "scene coordinates beyond 1e8 are not supported");
     std::vector<int64_t> idx(n_tris);
     std::iota(idx.begin(), idx.end(), 0);
     Builder b;
@@ -259,12 +367,17 @@ int build_bvh(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_t
     // fma(plane, 1/d, -o/d) moves a plane by at most 2^-24 |o|: keep that
     // below pad / 8, and |o| small enough that o/d stays finite for the
     // smallest substitute |d| of the traversal (1e-30).
-    out->fma_origin_limit = std::min(out->pad * 2097152.0f, 1.0e7f);
-    Packer pk{xyz, tri, idx.data(), out->pad, out};
-    out->nodes.reserve(out->n_leaves);
+    // The quantised slab test forms fma(code, scale / d, (origin - o) / d);
+    // against the decoded plane its distance is that of a plane moved by at
+    // most 2^-24 (|o| + |origin - o| + |plane - o|) per axis, below pad / 8
+    // while every |o| component stays under pad 2^19 - ext.
+    out->fma_origin_limit = std::max(0.0f, std::min(out->pad * 524288.0f - ext, 1.0e7f));
+    Packer pk{xyz, tri, idx.data(), out->pad, out->stack + kStackSpill, out};
+    out->nodes.reserve(out->n_leaves / 2 + 1);
     out->tris.reserve(3 * n_tris);
     out->order.reserve(n_tris);
-    out->root = pk.emit(root.get());
+    out->root = pk.emit(root.get(), 0);
+    out->wide_depth = wide_depth(out->nodes, out->root);
     return VAFR_OK;
 }
 

@@ -26,9 +26,13 @@ __device__ __forceinline__ float4 ldg4(const float4* p, size_t i) {
     const NFloat4 v = ((const __attribute__((address_space(1))) NFloat4*)p)[i];
     return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ int2 ldg_i2(const void* p) {
-    const uint64_t v = *(const __attribute__((address_space(1))) uint64_t*)p;
-    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
+__device__ __forceinline__ uint4 ldg_u4(const void* p) {
+    const float4 v = ldg4(reinterpret_cast<const float4*>(p), 0);
+    return make_uint4(__float_as_uint(v.x), __float_as_uint(v.y), __float_as_uint(v.z), __float_as_uint(v.w));
+}
+__device__ __forceinline__ int4 ldg_i4(const void* p) {
+    const float4 v = ldg4(reinterpret_cast<const float4*>(p), 0);
+    return make_int4(__float_as_int(v.x), __float_as_int(v.y), __float_as_int(v.z), __float_as_int(v.w));
 }
 
 struct RayPre {
@@ -39,6 +43,7 @@ struct RayPre {
     int kx, ky, kz;
     float Sx, Sy, Sz;
     bool valid;
+    bool negx, negy, negz;  // 1/d component negative: the box's high plane is entered first
 };
 
 __device__ __forceinline__ float sel3(int k, float a, float b, float c) { return k == 0 ? a : (k == 1 ? b : c); }
@@ -55,6 +60,9 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     r.oix = ox * r.ix;
     r.oiy = oy * r.iy;
     r.oiz = oz * r.iz;
+    r.negx = r.ix < 0.0f;
+    r.negy = r.iy < 0.0f;
+    r.negz = r.iz < 0.0f;
     // Watertight set-up: the axis of largest |d| becomes z (first on ties);
     // x, y follow cyclically and swap when d_z < 0.
     int kz = 0;
@@ -106,44 +114,76 @@ __device__ __forceinline__ bool tri_hit(const RayPre& r, float4 v0, float4 v1, f
     return t > 0.0f;
 }
 
-// Two child boxes of a node against the ray over [0, tlim].
-__device__ __forceinline__ void box2(const RayPre& r, const float4 a, const float4 b, const float4 c, float tlim,
-                                     bool& h0, bool& h1, float& tn0, float& tn1) {
-    const float x0 = (a.x - r.ox) * r.ix, x1 = (a.y - r.ox) * r.ix;
-    const float y0 = (a.z - r.oy) * r.iy, y1 = (a.w - r.oy) * r.iy;
-    const float z0 = (c.x - r.oz) * r.iz, z1 = (c.y - r.oz) * r.iz;
-    tn0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
-    const float tf0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tlim));
-    h0 = tn0 <= tf0 * kExitScale;
-    const float p0 = (b.x - r.ox) * r.ix, p1 = (b.y - r.ox) * r.ix;
-    const float q0 = (b.z - r.oy) * r.iy, q1 = (b.w - r.oy) * r.iy;
-    const float s0 = (c.z - r.oz) * r.iz, s1 = (c.w - r.oz) * r.iz;
-    tn1 = fmaxf(fmaxf(fminf(p0, p1), fminf(q0, q1)), fmaxf(fminf(s0, s1), 0.0f));
-    const float tf1 = fminf(fminf(fmaxf(p0, p1), fmaxf(q0, q1)), fminf(fmaxf(s0, s1), tlim));
-    h1 = tn1 <= tf1 * kExitScale;
+// One child box against the ray over [0, tlim] from the distances to its
+// entry planes (nx, ny, nz) and exit planes (fx, fy, fz) along each axis:
+// tn = entry distance, the return value whether the box is hit.
+__device__ __forceinline__ bool slab(float nx, float fx, float ny, float fy, float nz, float fz, float tlim,
+                                     float& tn) {
+    tn = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+    const float tf = fminf(fminf(fx, fy), fminf(fz, tlim));
+    return tn <= tf * kExitScale;
 }
 
-// The same test with each slab distance formed as fma(plane, 1/d, -o/d).
-// Against the exact distance to the plane this is the exact distance to a
-// plane moved by at most 2^-24 |o| (the rounding of o/d) times one more
-// relative rounding than the two of (plane - o) * (1/d) minus the one of
-// the subtraction, so kExitScale still covers the relative part.  The move
-// stays well inside the padding of every stored box as long as |o| is at
-// most TraceView::fma_origin_limit, which the caller checks per wave.
-__device__ __forceinline__ void box2_fma(const RayPre& r, const float4 a, const float4 b, const float4 c, float tlim,
-                                         bool& h0, bool& h1, float& tn0, float& tn1) {
-    const float x0 = fmaf(a.x, r.ix, -r.oix), x1 = fmaf(a.y, r.ix, -r.oix);
-    const float y0 = fmaf(a.z, r.iy, -r.oiy), y1 = fmaf(a.w, r.iy, -r.oiy);
-    const float z0 = fmaf(c.x, r.iz, -r.oiz), z1 = fmaf(c.y, r.iz, -r.oiz);
-    tn0 = fmaxf(fmaxf(fminf(x0, x1), fminf(y0, y1)), fmaxf(fminf(z0, z1), 0.0f));
-    const float tf0 = fminf(fminf(fmaxf(x0, x1), fmaxf(y0, y1)), fminf(fmaxf(z0, z1), tlim));
-    h0 = tn0 <= tf0 * kExitScale;
-    const float p0 = fmaf(b.x, r.ix, -r.oix), p1 = fmaf(b.y, r.ix, -r.oix);
-    const float q0 = fmaf(b.z, r.iy, -r.oiy), q1 = fmaf(b.w, r.iy, -r.oiy);
-    const float s0 = fmaf(c.z, r.iz, -r.oiz), s1 = fmaf(c.w, r.iz, -r.oiz);
-    tn1 = fmaxf(fmaxf(fminf(p0, p1), fminf(q0, q1)), fmaxf(fminf(s0, s1), 0.0f));
-    const float tf1 = fminf(fminf(fmaxf(p0, p1), fmaxf(q0, q1)), fminf(fmaxf(s0, s1), tlim));
-    h1 = tn1 <= tf1 * kExitScale;
+// Byte c of a code word as a float (the compiler emits one byte-to-float
+// conversion for this pattern).
+__device__ __forceinline__ float code(uint32_t w, int c) { return (float)((w >> (8 * c)) & 0xffu); }
+
+// Slab distances of a node's quantised child boxes.  Per axis the node
+// gives origin g and scale s = 2^k; a plane with code q lies at g + q s.
+// Along an axis with 1/d >= 0 the low plane is the entry plane, otherwise
+// the high one: the distance is monotone in the code for either form below
+// (every rounding is monotone), so choosing the plane words by the sign of
+// 1/d gives exactly the min / max of the two distances.
+//
+// kFma: distance = fma(q, s/d, fma(g, 1/d, -o/d)).  s/d is exact (a power
+// of two times 1/d); the inner FMA is the distance to g moved by at most
+// 2^-24 |o| (the rounding of o/d) and rounded once; the outer rounds once
+// more.  Against the decoded plane this is the exact distance to a plane
+// moved by at most 2^-24 (|o| + |g - o| + |plane - o|), well inside the
+// padding of every stored box while every |o| component is at most
+// TraceView::fma_origin_limit (checked per wave by the caller); relative
+// roundings are covered by kExitScale.
+//
+// Otherwise each plane is decoded as fmaf(q, s, g), which the builder
+// checked lies outside the child's padded box, and tested in the
+// subtract-multiply form, conservative for any origin.
+template <bool kFma>
+__device__ __forceinline__ void node_slabs(const RayPre& r, const float4 org, const uint4 q0, const uint4 q1,
+                                           float tlim, float tn[4], bool hit[4]) {
+    const uint32_t meta = __float_as_uint(org.w);
+    const float sx = __uint_as_float((meta & 0xffu) << 23);
+    const float sy = __uint_as_float(((meta >> 8) & 0xffu) << 23);
+    const float sz = __uint_as_float(((meta >> 16) & 0xffu) << 23);
+    const uint32_t ex = r.negx ? q0.y : q0.x, xx = r.negx ? q0.x : q0.y;   // entry / exit plane codes
+    const uint32_t ey = r.negy ? q0.w : q0.z, xy = r.negy ? q0.z : q0.w;
+    const uint32_t ez = r.negz ? q1.y : q1.x, xz = r.negz ? q1.x : q1.y;
+    if (kFma) {
+        const float bx = fmaf(org.x, r.ix, -r.oix), by = fmaf(org.y, r.iy, -r.oiy), bz = fmaf(org.z, r.iz, -r.oiz);
+        const float tx = sx * r.ix, ty = sy * r.iy, tz = sz * r.iz;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            hit[c] = slab(fmaf(code(ex, c), tx, bx), fmaf(code(xx, c), tx, bx), fmaf(code(ey, c), ty, by),
+                          fmaf(code(xy, c), ty, by), fmaf(code(ez, c), tz, bz), fmaf(code(xz, c), tz, bz), tlim,
+                          tn[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            hit[c] = slab((fmaf(code(ex, c), sx, org.x) - r.ox) * r.ix, (fmaf(code(xx, c), sx, org.x) - r.ox) * r.ix,
+                          (fmaf(code(ey, c), sy, org.y) - r.oy) * r.iy, (fmaf(code(xy, c), sy, org.y) - r.oy) * r.iy,
+                          (fmaf(code(ez, c), sz, org.z) - r.oz) * r.iz, (fmaf(code(xz, c), sz, org.z) - r.oz) * r.iz,
+                          tlim, tn[c]);
+    }
+}
+
+// Orders two (distance, reference) pairs.
+__device__ __forceinline__ void cswap(float& ka, int& ra, float& kb, int& rb) {
+    const bool sw = kb < ka;
+    const float k = sw ? kb : ka;
+    const int rr = sw ? rb : ra;
+    kb = sw ? ka : kb;
+    rb = sw ? ra : rb;
+    ka = k;
+    ra = rr;
 }
 
 // Per-lane work counters of the diagnostic pass (node visits = box-pair
@@ -155,7 +195,8 @@ struct WorkCount {
 // Traversal loop shared by closest-hit and any-hit queries.
 //
 // Each step of the loop is wave-uniform: either a node step (lanes standing
-// on an internal node test its two child boxes) or a triangle step (lanes
+// on an internal node test its four child boxes, continue with the nearest
+// hit child and push the other hit children) or a triangle step (lanes
 // holding a parked leaf test its triangles).  A lane parks the first leaf it
 // reaches and keeps descending from its stack; the wave switches to the
 // triangle step once kParkNum/kParkDen of its live lanes hold a parked leaf,
@@ -170,11 +211,29 @@ constexpr int kParkNum = 3, kParkDen = 4;
 // stk points at this lane's column of the block's LDS stack (stride B).
 // Closest hit (kAny = false): smallest (t, triangle id); returns the stored
 // slot or -1.  Any hit with t > 0 (kAny = true): returns 1 or -1.
-template <int B, bool kAny, bool kCount, bool kFma>
+template <int B, int S, bool kAny, bool kCount, bool kFma>
 __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
                              WorkCount& wc) {
     t_best = INFINITY;
     id_best = -1;
+    // entries 0 .. S-1 in the lane's LDS column, the rest in scratch (the
+    // two kept in separate branches so that the common case stays an LDS
+    // access rather than a generic one; volatile keeps the rarely used
+    // spill area in memory instead of in registers)
+    volatile int spill[kStackSpill];
+    auto push = [&](int sp_, int v) {
+        if (sp_ < S) {
+            ((__attribute__((address_space(3))) int*)(stk))[sp_ * B] = v;
+        } else {
+            spill[sp_ - S] = v;
+        }
+    };
+    auto top = [&](int sp_) {
+        int v;
+        if (sp_ < S) v = ((__attribute__((address_space(3))) int*)(stk))[sp_ * B];
+        else v = spill[sp_ - S];
+        return v;
+    };
     float tlim = INFINITY;   // boxes are tested over [0, t_best * kHitSlack]
     int slot_best = -1;
     int ref = sc.root;   // kEmptyRef: nothing left to visit
@@ -183,7 +242,7 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
     for (;;) {
         if (ref < 0 && ref != kEmptyRef && parked == 0) {
             parked = ref;
-            ref = sp ? stk[--sp * B] : kEmptyRef;
+            ref = sp ? top(--sp) : kEmptyRef;
         }
         const uint64_t live = __ballot(ref != kEmptyRef || parked != 0);
         if (live == 0) break;
@@ -192,24 +251,45 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
         if (at_node != 0 && kParkDen * __popcll(holding) < kParkNum * __popcll(live)) {
             if (ref >= 0) {
                 const float4* p = reinterpret_cast<const float4*>(sc.nodes + ref);
-                const float4 a = ldg4(p, 0), b = ldg4(p, 1), c = ldg4(p, 2);
-                const int2 d = ldg_i2(p + 3);
+                const float4 org = ldg4(p, 0);
+                const uint4 q0 = ldg_u4(p + 1), q1 = ldg_u4(p + 2);
+                const int4 rf = ldg_i4(p + 3);
                 if (kCount) ++wc.nodes;
-                bool h0, h1;
-                float tn0, tn1;
-                if (kFma) box2_fma(r, a, b, c, tlim, h0, h1, tn0, tn1);
-                else box2(r, a, b, c, tlim, h0, h1, tn0, tn1);
-                if (h0 && h1) {
-                    const bool first0 = tn0 <= tn1;
-                    stk[sp * B] = first0 ? d.y : d.x;
-                    ++sp;
-                    ref = first0 ? d.x : d.y;
-                } else if (h0) {
-                    ref = d.x;
-                } else if (h1) {
-                    ref = d.y;
+                float tn[4];
+                bool hh[4];
+                node_slabs<kFma>(r, org, q0, q1, tlim, tn, hh);
+                // empty slots are skipped by their reference
+                const bool h0 = hh[0] && rf.x != kEmptyRef, h1 = hh[1] && rf.y != kEmptyRef;
+                const bool h2 = hh[2] && rf.z != kEmptyRef, h3 = hh[3] && rf.w != kEmptyRef;
+                float k0 = tn[0], k1 = tn[1], k2 = tn[2], k3 = tn[3];
+                const int n = (int)h0 + (int)h1 + (int)h2 + (int)h3;
+                if (n == 0) {
+                    ref = sp ? top(--sp) : kEmptyRef;
+                } else if (kAny) {
+                    // any hit needs no order: the first hit child next, the
+                    // other hit children pushed
+                    int nr = kEmptyRef;
+                    if (h0) nr = rf.x;
+                    if (h1) { if (nr != kEmptyRef) push(sp++, rf.y); else nr = rf.y; }
+                    if (h2) { if (nr != kEmptyRef) push(sp++, rf.z); else nr = rf.z; }
+                    if (h3) { if (nr != kEmptyRef) push(sp++, rf.w); else nr = rf.w; }
+                    ref = nr;
                 } else {
-                    ref = sp ? stk[--sp * B] : kEmptyRef;
+                    // nearest hit child next; the others pushed far first
+                    k0 = h0 ? k0 : INFINITY;
+                    k1 = h1 ? k1 : INFINITY;
+                    k2 = h2 ? k2 : INFINITY;
+                    k3 = h3 ? k3 : INFINITY;
+                    int r0 = rf.x, r1 = rf.y, r2 = rf.z, r3 = rf.w;
+                    cswap(k0, r0, k1, r1);
+                    cswap(k2, r2, k3, r3);
+                    cswap(k0, r0, k2, r2);
+                    cswap(k1, r1, k3, r3);
+                    cswap(k1, r1, k2, r2);
+                    if (n > 3) push(sp++, r3);
+                    if (n > 2) push(sp++, r2);
+                    if (n > 1) push(sp++, r1);
+                    ref = r0;
                 }
             }
             continue;
@@ -245,27 +325,27 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
 
 // The FMA slab test is taken when every lane's origin is within the
 // scene's limit (wave-uniform choice, so both loops run without divergence).
-template <int B, bool kAny, bool kCount>
+template <int B, int S, bool kAny, bool kCount>
 __device__ __forceinline__ int traverse(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
                                         WorkCount& wc) {
     const float om = fmaxf(fmaxf(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz));
     const float oi = fmaxf(fmaxf(fabsf(r.oix), fabsf(r.oiy)), fabsf(r.oiz));
     const bool fma_ok = om <= sc.fma_origin_limit && oi <= 3.0e38f;
-    if (__ballot(!fma_ok) == 0) return traverse_loop<B, kAny, kCount, true>(sc, r, stk, t_best, id_best, wc);
-    return traverse_loop<B, kAny, kCount, false>(sc, r, stk, t_best, id_best, wc);
+    if (__ballot(!fma_ok) == 0) return traverse_loop<B, S, kAny, kCount, true>(sc, r, stk, t_best, id_best, wc);
+    return traverse_loop<B, S, kAny, kCount, false>(sc, r, stk, t_best, id_best, wc);
 }
 
-template <int B, bool kCount>
+template <int B, int S, bool kCount>
 __device__ __forceinline__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best,
                                            int& id_best, WorkCount& wc) {
-    return traverse<B, false, kCount>(sc, r, stk, t_best, id_best, wc);
+    return traverse<B, S, false, kCount>(sc, r, stk, t_best, id_best, wc);
 }
 
-template <int B, bool kCount>
+template <int B, int S, bool kCount>
 __device__ __forceinline__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
     float t;
     int id;
-    return traverse<B, true, kCount>(sc, r, stk, t, id, wc) >= 0;
+    return traverse<B, S, true, kCount>(sc, r, stk, t, id, wc) >= 0;
 }
 
 // 32-bit hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
@@ -382,13 +462,13 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
     return true;
 }
 
-template <int B, bool kCount>
+template <int B, int S, bool kCount>
 __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, int& id_out, WorkCount& wc,
                                 uint32_t& n_shadow, float4& p_out) {
     const TraceView& sc = v;
     float t;
     int id;
-    const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
+    const int slot = closest_hit<B, S, kCount>(sc, r, stk, t, id, wc);
     id_out = id;
     p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
@@ -402,7 +482,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
         RayPre s;
         ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
         ++n_shadow;
-        if (any_hit<B, kCount>(sc, s, stk, wc)) vis = 0.0f;
+        if (any_hit<B, S, kCount>(sc, s, stk, wc)) vis = 0.0f;
     }
     const float lam = ndl > 0.0f ? ndl : 0.0f;
     const float3 a = albedo_of(id);
@@ -411,7 +491,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
                        a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
 }
 
-template <int B, bool kCount>
+template <int B, int S, bool kCount>
 __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
                              uint32_t& n_shadow, float4& p_out) {
     const TraceView& sc = v;
@@ -422,7 +502,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
     for (int bnc = 0; bnc <= v.bounces; ++bnc) {
         float t;
         int id;
-        const int slot = closest_hit<B, kCount>(sc, r, stk, t, id, wc);
+        const int slot = closest_hit<B, S, kCount>(sc, r, stk, t, id, wc);
         if (bnc == 0) {
             id_out = id;
             if (slot >= 0) p_out = make_float4(fmaf(t, r.dx, r.ox), fmaf(t, r.dy, r.oy), fmaf(t, r.dz, r.oz), 1.0f);
@@ -442,7 +522,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
             RayPre s;
             ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
             ++n_shadow;
-            vis = any_hit<B, kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
+            vis = any_hit<B, S, kCount>(sc, s, stk, wc) ? 0.0f : 1.0f;
         }
         const float3 a = albedo_of(id);
         thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
@@ -459,7 +539,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
 // One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
 // counts work into counters[0..3] = primary rays, shadow rays, node visits,
 // triangle tests, and writes no image.
-template <int B, bool kCount>
+template <int B, int S, bool kCount>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
@@ -470,9 +550,9 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     WorkCount wc;
     uint32_t n_shadow = 0;
     if (v.shade_mode == VAFR_SHADE_PATH)
-        c = shade_path<B, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
+        c = shade_path<B, S, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
     else
-        c = shade_lambert<B, kCount>(v, r, stk, id, wc, n_shadow, p);
+        c = shade_lambert<B, S, kCount>(v, r, stk, id, wc, n_shadow, p);
     if (kCount) {
         atomicAdd(counters + 0, 1ull);
         atomicAdd(counters + 1, (unsigned long long)n_shadow);
@@ -501,7 +581,7 @@ template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[S * B];
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    trace_item<B, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
 
 // List mode: thread q < *item_count traces item item_list[q].  The grid is
@@ -513,7 +593,7 @@ __global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
     __shared__ int stack[S * B];
     const int64_t q = (int64_t)blockIdx.x * B + threadIdx.x;
     if (q >= *v.item_count) return;
-    trace_item<B, false>(v, v.item_list[q], stack, nullptr);
+    trace_item<B, S, false>(v, v.item_list[q], stack, nullptr);
 }
 
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
@@ -528,7 +608,7 @@ __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    trace_item<B, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
 }
 
 template <int B, int S>

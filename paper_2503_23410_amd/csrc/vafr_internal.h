@@ -90,21 +90,37 @@ void film_pitch(const vafr_display& d, double* px, double* py);
 int layout_device(vafr_layout L, const LayoutDev** out);
 
 // -------------------------------------------------------------------- BVH
-// Device node: two child boxes and two child references (64 bytes).
-//   a = (lo0.x, hi0.x, lo0.y, hi0.y)  b = (lo1.x, hi1.x, lo1.y, hi1.y)
-//   c = (lo0.z, hi0.z, lo1.z, hi1.z)  d = (ref0, ref1, 0, 0)
-// ref >= 0: internal node index; ref < 0: leaf, ~ref = first << 3 | (count-1).
+// Device node: up to four child boxes, quantised, and four references
+// (64 bytes; the traversal is bound by the bytes its lanes load).
+//   org  = (origin.x, origin.y, origin.z, meta): the node's box corner; meta
+//          holds the biased FP32 exponents of the x, y, z scales in bytes
+//          0..2 (scale = 2^(byte - 127)) and the child count in byte 3.
+//   q0   = (lo.x, hi.x, lo.y, hi.y), q1 = (lo.z, hi.z, 0, 0): 8-bit plane
+//          codes, child c in byte c; plane = origin + code x scale.
+//   ref  = the four child references.
+// Every decoded plane, computed as fmaf(code, scale, origin), lies outside
+// the child's padded FP32 box (the builder checks each one).
+// ref >= 0: internal node index; ref == kEmptyRef: no child (skipped by its
+// reference); otherwise a leaf, ~ref = first << 3 | (count-1).
 struct alignas(16) BvhNode {
-    float4 a, b, c;
-    int4 d;
+    float4 org;
+    uint4 q0, q1;
+    int4 ref;
 };
+static_assert(sizeof(BvhNode) == 64, "quantised 4-wide nodes are 64 bytes");
 constexpr int kMaxLeaf = 4;
-// Traversal stack classes (entries per lane in LDS).  A tree of depth D needs
-// D entries; the builder keeps D below the class it picks for the scene.
-// The short class leaves room for more resident waves per CU (LDS per wave
-// = entries x 64 x 4 bytes), the long class admits every supported scene.
+// Traversal stack: a class of entries per lane in LDS, continued by
+// kStackSpill entries per lane in private (scratch) memory.  A node step
+// pushes the node's other hit children, so a traversal holds at most the
+// sum of (children - 1) over the ancestors of the current node; the binary
+// build tree is kept below depth class - 1 and its collapse into 4-wide
+// nodes keeps that sum within class + kStackSpill.  The spill entries are
+// rarely touched: most node steps hit one or two children.  The short class
+// leaves room for more resident waves per CU (LDS per wave = entries x 64 x
+// 4 bytes), the long class admits every supported scene.
 constexpr int kStackShort = 24;
 constexpr int kStackLong = 32;
+constexpr int kStackSpill = 24;
 // Scenes whose leaf count needs at most this many balanced levels get the
 // short class (two levels of slack for the SAH splits).
 constexpr int kShortStackLevels = kStackShort - 3;
@@ -115,10 +131,12 @@ struct HostBvh {
     std::vector<float4> tris;    // 3 float4 per stored triangle: v0|id, v1, v2
     std::vector<int32_t> order;  // original id of each stored triangle
     int32_t root = kEmptyRef;
-    int32_t max_depth = 0;
+    int32_t max_depth = 0;       // binary tree levels below the root
+    int32_t wide_depth = 0;      // 4-wide node levels
+    int32_t max_stack = 0;       // most stack entries a traversal can hold
     int32_t stack = kStackShort; // traversal stack class (kStackShort or kStackLong)
     float pad = 0.0f;            // absolute padding of every stored box
-    float fma_origin_limit = 0;  // origins up to this |component| move a slab plane by <= pad / 8
+    float fma_origin_limit = 0;  // origins up to this |component| move a slab plane by <= pad / 8 (fast form)
     int64_t n_leaves = 0;
 };
 

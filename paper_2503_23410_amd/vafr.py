@@ -123,7 +123,7 @@ class vafr_server_stats(C.Structure):
 class vafr_scene_info(C.Structure):
     _fields_ = [("n_tris", C.c_int64), ("n_nodes", C.c_int64), ("n_leaves", C.c_int64), ("max_depth", C.c_int32),
                 ("on_device", C.c_int32), ("device_bytes", C.c_int64), ("build_ms", C.c_double),
-                ("stack_entries", C.c_int32), ("reserved", C.c_int32)]
+                ("stack_entries", C.c_int32), ("max_stack", C.c_int32)]
 
 
 _lib = None

@@ -130,30 +130,67 @@ def _check_bvh(V, verts, tris):
     nodes, order = sc.export()
     assert info["n_tris"] == tris.shape[0]
     assert np.array_equal(np.sort(order), np.arange(tris.shape[0]))      # each triangle stored once
-    # the traversal stack holds one entry per level below the root
+    # binary build depth within the LDS class; the 4-wide collapse within
+    # the LDS class plus the 24 spill entries
     assert info["stack_entries"] in (24, 32) and info["max_depth"] <= info["stack_entries"] - 1
-    refs = nodes[:, 12:14].view(np.int32) if nodes.size else np.zeros((0, 2), np.int32)
+    assert info["max_stack"] <= info["stack_entries"] + 24
+    refs = nodes[:, 12:16].view(np.int32) if nodes.size else np.zeros((0, 4), np.int32)
+    meta = nodes[:, 3].view(np.uint32) if nodes.size else np.zeros(0, np.uint32)
+    kids = (meta >> 24).astype(np.int64)
     tv = verts[tris[order]]                                               # stored order, (n, 3, 3)
-    # every child box contains every triangle of its subtree
-    seen_nodes = np.zeros(len(nodes), bool)
+    empty = np.iinfo(np.int32).min
+    seen = np.zeros(len(nodes), int)
 
     def tri_range(ref):
         if ref < 0:
             x = ~ref
             return [(x >> 3, (x & 7) + 1)]
-        seen_nodes[ref] = True
-        return tri_range(refs[ref, 0]) + tri_range(refs[ref, 1])
+        seen[ref] += 1
+        out = []
+        for c in refs[ref]:
+            if c != empty:
+                out += tri_range(c)
+        return out
 
-    for ni in range(len(nodes)):
-        a, b, c = nodes[ni, 0:4], nodes[ni, 4:8], nodes[ni, 8:12]
-        boxes = [((a[0], a[2], c[0]), (a[1], a[3], c[1])), ((b[0], b[2], c[2]), (b[1], b[3], c[3]))]
-        for ch in range(2):
-            lo, hi = np.array(boxes[ch][0]), np.array(boxes[ch][1])
+    def planes(ni):
+        """Decoded child planes (4 children x (lo, hi) x 3 axes) as the
+        traversal's fallback computes them: fmaf(code, 2^(b - 127), origin)."""
+        codes = nodes[ni, 4:12].view(np.uint32)
+        out = np.zeros((4, 2, 3))
+        for a in range(3):
+            scale = np.ldexp(1.0, int((meta[ni] >> (8 * a)) & 255) - 127)
+            for c in range(4):
+                for side in range(2):
+                    q = (int(codes[2 * a + side]) >> (8 * c)) & 255
+                    out[c, side, a] = np.float32(np.float64(q) * scale + np.float64(nodes[ni, a]))
+        return out
+
+    # every triangle is reached exactly once from the root
+    if info["n_nodes"]:
+        ranges = tri_range(0)
+        covered = np.zeros(tris.shape[0], int)
+        for first, cnt in ranges:
+            covered[first:first + cnt] += 1
+        assert np.all(covered == 1) and np.all(seen == 1)
+    # stack bound: the sum of (children - 1) along any root-to-node path
+    worst = 0
+    todo = [(0, 0)] if info["n_nodes"] else []
+    while todo:
+        n, used = todo.pop()
+        below = used + kids[n] - 1
+        worst = max(worst, below)
+        todo += [(c, below) for c in refs[n] if c >= 0]
+    assert worst == info["max_stack"]
+    for ni in range(min(len(nodes), 2000)):
+        k = kids[ni]
+        assert 2 <= k <= 4
+        assert np.all(refs[ni, k:] == empty) and np.all(refs[ni, :k] != empty)
+        pl = planes(ni)
+        for ch in range(k):
+            lo, hi = pl[ch, 0], pl[ch, 1]
             for first, cnt in tri_range(refs[ni, ch]):
                 pts = tv[first:first + cnt].reshape(-1, 3)
                 assert np.all(pts >= lo) and np.all(pts <= hi)
-        if ni > 2000:
-            break
     return sc, info
 
 
