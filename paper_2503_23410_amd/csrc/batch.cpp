@@ -25,6 +25,7 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct Slot {
     char* host = nullptr;   // pinned staging
     char* dev = nullptr;    // device twin
+    int32_t* order = nullptr;   // planned dispatch order of this slot's traversal launch
     hipEvent_t done = nullptr;
     bool used = false;
     // stage timing (when profiling): before upload, after upload, after
@@ -38,7 +39,7 @@ struct GraphEntry {
     int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0, stack = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr, ktrace = nullptr, krecon = nullptr;
+    hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, krecon = nullptr;
     bool timed = false;
     hipGraphNode_t evn[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -63,6 +64,11 @@ struct vafr_batch_s {
     bool profiling = false;
     double stage_sum[3] = {0, 0, 0};   // accumulated stage times (ms)
     int64_t stage_frames = 0;
+    // longest-first dispatch: block durations of the last traversal launch
+    // (shared by the slots; only an ordering hint) and the capacity of it
+    // and of every slot's order buffer, in blocks
+    uint32_t* cost = nullptr;
+    int32_t plan_cap = 0;
 };
 
 namespace vafr {
@@ -126,16 +132,33 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     return VAFR_OK;
 }
 
-hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const TraceView** v,
-                                 const int32_t** be, int32_t* n, unsigned long long** cnt) {
-    *v = reinterpret_cast<const TraceView*>(dev);
-    *be = reinterpret_cast<const int32_t*>(dev + b->off_tb);
-    *n = g.n_trace;
-    *cnt = nullptr;
-    args[0] = v;
-    args[1] = be;
-    args[2] = n;
-    args[3] = cnt;
+// Kernel arguments of a batched traversal node; the pointed-to values must
+// outlive the call that consumes the parameters.
+struct TraceArgs {
+    const TraceView* v;
+    const int32_t* be;
+    int32_t n;
+    unsigned long long* cnt;
+    const int32_t* order;
+    uint32_t* cost;
+    void* p[6];
+};
+
+hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, const Slot& s, TraceArgs& a) {
+    a.v = reinterpret_cast<const TraceView*>(s.dev);
+    a.be = reinterpret_cast<const int32_t*>(s.dev + b->off_tb);
+    a.n = g.n_trace;
+    a.cnt = nullptr;
+    const bool planned = trace_plan_ok(g.trace_blocks);
+    a.order = planned ? s.order : nullptr;
+    a.cost = planned ? b->cost : nullptr;
+    a.p[0] = &a.v;
+    a.p[1] = &a.be;
+    a.p[2] = &a.n;
+    a.p[3] = &a.cnt;
+    a.p[4] = &a.order;
+    a.p[5] = &a.cost;
+    void** args = a.p;
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack));
     p.gridDim = dim3((unsigned)g.trace_blocks);
@@ -144,6 +167,56 @@ hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, char* dev, v
     p.kernelParams = args;
     p.extra = nullptr;
     return p;
+}
+
+struct PlanArgs {
+    uint32_t* cost;
+    int32_t* order;
+    int32_t blocks;
+    void* p[3];
+};
+
+hipKernelNodeParams plan_params(vafr_batch b, const GraphEntry& g, const Slot& s, PlanArgs& a) {
+    a.cost = b->cost;
+    a.order = s.order;
+    a.blocks = g.trace_blocks;
+    a.p[0] = &a.cost;
+    a.p[1] = &a.order;
+    a.p[2] = &a.blocks;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(trace_plan_kernel());
+    p.gridDim = dim3(8u);
+    p.blockDim = dim3(1024u);
+    p.sharedMemBytes = 0;
+    p.kernelParams = a.p;
+    p.extra = nullptr;
+    return p;
+}
+
+// Makes room for a traversal launch of `blocks` workgroups in the duration
+// buffer and in every slot's order buffer (waits for the slots in flight and
+// drops the graphs, which hold the old addresses, when it grows).
+int ensure_plan(vafr_batch b, int32_t blocks) {
+    if (blocks <= b->plan_cap) return VAFR_OK;
+    for (auto& sl : b->slot)
+        if (sl.used) VAFR_HIP(hipEventSynchronize(sl.done));
+    free_graphs(b);
+    const int32_t cap = std::max(blocks, 2 * b->plan_cap);
+    (void)hipFree(b->cost);
+    b->cost = nullptr;
+    for (auto& sl : b->slot) {
+        (void)hipFree(sl.order);
+        sl.order = nullptr;
+    }
+    b->plan_cap = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&b->cost), sizeof(uint32_t) * cap) != hipSuccess)
+        return fail(VAFR_E_OOM, "dispatch plan allocation failed");
+    VAFR_HIP(hipMemset(b->cost, 0, sizeof(uint32_t) * cap));
+    for (auto& sl : b->slot)
+        if (hipMalloc(reinterpret_cast<void**>(&sl.order), sizeof(int32_t) * cap) != hipSuccess)
+            return fail(VAFR_E_OOM, "dispatch plan allocation failed");
+    b->plan_cap = cap;
+    return VAFR_OK;
 }
 
 hipKernelNodeParams recon_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const ReconView** v,
@@ -194,15 +267,19 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
         e = hipGraphAddMemcpyNode1D(&g.copy, g.graph, g.evn[0] ? &g.evn[0] : nullptr, g.evn[0] ? 1 : 0, s.dev, s.host,
                                     b->bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess && g.timed) e = hipGraphAddEventRecordNode(&g.evn[1], g.graph, &g.copy, 1, s.ev[1]);
-    void* ta[4];
-    const TraceView* tvp;
-    const int32_t* tbe;
-    int32_t tn;
-    unsigned long long* tc;
+    TraceArgs ta;
+    PlanArgs pa;
     if (e == hipSuccess && trace_blocks > 0) {
-        hipKernelNodeParams p = trace_params(b, g, s.dev, ta, &tvp, &tbe, &tn, &tc);
         hipGraphNode_t dep = g.timed ? g.evn[1] : g.copy;
-        e = hipGraphAddKernelNode(&g.ktrace, g.graph, &dep, 1, &p);
+        if (trace_plan_ok(trace_blocks)) {
+            hipKernelNodeParams pp = plan_params(b, g, s, pa);
+            e = hipGraphAddKernelNode(&g.kplan, g.graph, &dep, 1, &pp);
+            dep = g.kplan;
+        }
+        if (e == hipSuccess) {
+            hipKernelNodeParams p = trace_params(b, g, s, ta);
+            e = hipGraphAddKernelNode(&g.ktrace, g.graph, &dep, 1, &p);
+        }
     }
     if (e == hipSuccess && g.timed) {
         hipGraphNode_t dep = g.ktrace ? g.ktrace : g.evn[1];
@@ -253,6 +330,10 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     if (dev != b->device) return fail(VAFR_E_ARG, "batch was created on device %d, current is %d", b->device, dev);
     int32_t tblocks = 0, rblocks = 0;
     if (int rc = describe(b, views, n, &tblocks, &rblocks)) return rc;
+    // launches too large to plan keep the fixed XCD order
+    const bool planned = trace_plan_ok(tblocks);
+    if (planned)
+        if (int rc = ensure_plan(b, tblocks)) return rc;
     Slot& s = b->slot[b->next];
     b->next = (b->next + 1) % kSlots;
     if (s.used) {
@@ -271,13 +352,14 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         VAFR_HIP(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, s.dev, s.host, b->bytes, hipMemcpyHostToDevice));
         if (g->timed)
             for (int k = 0; k < 4; ++k) VAFR_HIP(hipGraphExecEventRecordNodeSetEvent(g->exec, g->evn[k], s.ev[k]));
-        void* ta[4];
-        const TraceView* tvp;
-        const int32_t* tbe;
-        int32_t tn;
-        unsigned long long* tc;
+        TraceArgs ta;
+        PlanArgs pa;
         if (g->ktrace) {
-            hipKernelNodeParams p = trace_params(b, *g, s.dev, ta, &tvp, &tbe, &tn, &tc);
+            if (g->kplan) {
+                hipKernelNodeParams pp = plan_params(b, *g, s, pa);
+                VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->kplan, &pp));
+            }
+            hipKernelNodeParams p = trace_params(b, *g, s, ta);
             VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->ktrace, &p));
         }
         void* ra[3];
@@ -293,9 +375,12 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[0], stream));
         VAFR_HIP(hipMemcpyAsync(s.dev, s.host, b->bytes, hipMemcpyHostToDevice, stream));
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[1], stream));
+        if (planned)
+            if (int rc = launch_trace_plan(b->cost, s.order, tblocks, stream)) return rc;
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
-                                        tblocks, b->cfg.trace_block, b->stack, stream))
+                                        tblocks, b->cfg.trace_block, b->stack, stream, nullptr,
+                                        planned ? s.order : nullptr, planned ? b->cost : nullptr))
             return rc;
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[2], stream));
         if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),
@@ -470,8 +555,10 @@ extern "C" void vafr_batch_destroy(vafr_batch b) {
         for (auto& ev : s.ev)
             if (ev) (void)hipEventDestroy(ev);
         if (s.dev) (void)hipFree(s.dev);
+        if (s.order) (void)hipFree(s.order);
         if (s.host) (void)hipHostFree(s.host);
     }
+    if (b->cost) (void)hipFree(b->cost);
     free_graphs(b);
     if (have) (void)hipSetDevice(cur);
     delete b;

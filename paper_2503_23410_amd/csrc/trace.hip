@@ -599,16 +599,78 @@ __global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
 // Batched launch: workgroup b serves view vid with block_end[vid-1] <= b <
 // block_end[vid] (block_end is the running sum of per-view workgroups of B
 // items each).  S covers the deepest scene of the batch.
+// order (nullable): per XCD, the dispatch order of its workgroups'
+// blocks (see k_trace_plan); cost (nullable): each block's duration in
+// 100 MHz ticks, the larger of its waves', kept for the next frame's plan.
 template <int B, int S, bool kCount>
 __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
-                                                   unsigned long long* counters) {
+                                                   unsigned long long* counters, const int32_t* __restrict__ order,
+                                                   uint32_t* __restrict__ cost) {
     __shared__ int stack[S * B];
-    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t t0 = cost ? wall_clock64() : 0;
+    int b = xcd_block(blockIdx.x, gridDim.x);
+    const int per = gridDim.x / kXcds;
+    if (order && (int)blockIdx.x < per * kXcds) {
+        const int x = blockIdx.x % kXcds;
+        b = x * per + order[x * per + blockIdx.x / kXcds];
+    }
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
     trace_item<B, S, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+    if (cost && (threadIdx.x & 63) == 0) {
+        const uint64_t dt = wall_clock64() - t0;
+        atomicMax(cost + b, (uint32_t)(dt < 0xffffffffull ? dt : 0xffffffffull));
+    }
+}
+
+// Longest-first dispatch order of a batched traversal launch, from the
+// previous frame's block durations.  Workgroup x plans XCD x, which runs the
+// blocks x per .. x per + per - 1 (per = blocks / 8; the few blocks past
+// 8 per keep their place): the blocks are ranked into 32 classes of
+// duration (two per octave from 2.56 us up, longest first) by a counting
+// sort, and order[x per + p] is the p-th block of that ranking, so the
+// traversal starts the expensive screen regions first and the cheap ones
+// fill in behind them.  Each duration is read once and then cleared for the
+// frame being planned; the order is a permutation whatever the durations.
+constexpr int kPlanThreads = 1024;
+constexpr int kPlanMaxPer = 32768;
+constexpr int kPlanClasses = 32;
+
+__global__ __launch_bounds__(kPlanThreads) void k_trace_plan(uint32_t* __restrict__ cost, int32_t* __restrict__ order,
+                                                             int32_t blocks) {
+    __shared__ uint8_t cls[kPlanMaxPer];
+    __shared__ int hist[kPlanClasses], base[kPlanClasses];
+    const int per = blocks / kXcds;
+    const int x = blockIdx.x;
+    const int t = threadIdx.x;
+    if (t < kPlanClasses) hist[t] = 0;
+    __syncthreads();
+    for (int i = t; i < per; i += kPlanThreads) {
+        const uint32_t c = cost[x * per + i];
+        cost[x * per + i] = 0u;
+        // level = 2 log2(c) in half octaves from 2^8 ticks; longer is earlier
+        const uint32_t bits = __float_as_uint((float)c);
+        int lvl = c ? (int)(bits >> 22) - ((127 + 8) << 1) : 0;
+        lvl = lvl < 0 ? 0 : (lvl > kPlanClasses - 1 ? kPlanClasses - 1 : lvl);
+        const int k = kPlanClasses - 1 - lvl;
+        cls[i] = (uint8_t)k;
+        atomicAdd(&hist[k], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int k = 0; k < kPlanClasses; ++k) {
+            base[k] = acc;
+            acc += hist[k];
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < per; i += kPlanThreads) {
+        const int pos = atomicAdd(&base[cls[i]], 1);
+        order[x * per + pos] = i;
+    }
 }
 
 template <int B, int S>
@@ -623,13 +685,13 @@ void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsig
 
 template <int B, int S>
 void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks,
-                  hipStream_t stream, unsigned long long* counters) {
+                  hipStream_t stream, unsigned long long* counters, const int32_t* order, uint32_t* cost) {
     if (counters)
         hipLaunchKernelGGL((k_trace_batch<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
-                           n_views, counters);
+                           n_views, counters, order, cost);
     else
         hipLaunchKernelGGL((k_trace_batch<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
-                           block_end, n_views, counters);
+                           block_end, n_views, counters, order, cost);
 }
 
 template <int S>
@@ -642,10 +704,10 @@ void launch_single_s(const TraceView& v, int64_t blocks, int block, hipStream_t 
 
 template <int S>
 void launch_batch_s(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, int block,
-                    hipStream_t stream, unsigned long long* counters) {
-    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, stream, counters);
-    else if (block == 128) launch_batch<128, S>(views, block_end, n_views, blocks, stream, counters);
-    else launch_batch<256, S>(views, block_end, n_views, blocks, stream, counters);
+                    hipStream_t stream, unsigned long long* counters, const int32_t* order, uint32_t* cost) {
+    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
+    else if (block == 128) launch_batch<128, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
+    else launch_batch<256, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
 }
 
 template <int S>
@@ -688,14 +750,28 @@ const void* trace_batch_kernel(int block, int stack) {
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, hipStream_t stream, unsigned long long* counters) {
+                       int block, int stack, hipStream_t stream, unsigned long long* counters, const int32_t* order,
+                       uint32_t* cost) {
     if (blocks <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
     if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
+    if (order && !trace_plan_ok(blocks)) return fail(VAFR_E_ARG, "too many blocks for a planned launch");
     if (stack == kStackShort)
-        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, stream, counters);
+        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, stream, counters, order, cost);
     else
-        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, stream, counters);
+        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, stream, counters, order, cost);
+    VAFR_HIP(hipGetLastError());
+    return VAFR_OK;
+}
+
+bool trace_plan_ok(int32_t blocks) { return blocks / kXcds <= kPlanMaxPer; }
+
+const void* trace_plan_kernel() { return reinterpret_cast<const void*>(&k_trace_plan); }
+
+int launch_trace_plan(uint32_t* cost, int32_t* order, int32_t blocks, hipStream_t stream) {
+    if (blocks <= 0) return VAFR_OK;
+    if (!trace_plan_ok(blocks)) return fail(VAFR_E_ARG, "too many blocks for a planned launch");
+    hipLaunchKernelGGL(k_trace_plan, dim3(kXcds), dim3(kPlanThreads), 0, stream, cost, order, blocks);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

@@ -211,7 +211,16 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
 // workgroup count block_end[] first exceeds b.
 // stack = the largest stack class among the views' scenes.
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, hipStream_t stream, unsigned long long* counters = nullptr);
+                       int block, int stack, hipStream_t stream, unsigned long long* counters = nullptr,
+                       const int32_t* order = nullptr, uint32_t* cost = nullptr);
+// Longest-first dispatch order of a batched traversal launch of `blocks`
+// workgroups from the block durations the previous launch recorded in
+// cost[] (order: `blocks` entries, one planned permutation per XCD;
+// cost[] is cleared as it is read).  trace_plan_ok: whether a launch of
+// that size can be planned.
+bool trace_plan_ok(int32_t blocks);
+int launch_trace_plan(uint32_t* cost, int32_t* order, int32_t blocks, hipStream_t stream);
+const void* trace_plan_kernel();
 
 // ------------------------------------------------------- reconstruction
 // One view of the inverse map.  The offset of pixel (x, y)'s centre from the
