@@ -90,8 +90,9 @@ def load_traffic(kind):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200, help="timed binocular VaFR frames")
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=900,
+                    help="timed binocular VaFR frames (900 = 10 s of the 90 Hz gaze trace)")
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--compare-steps", type=int, default=0,
                     help="frames for the full-resolution and LMFR comparisons (default: steps/20, >= 3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

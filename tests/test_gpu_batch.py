@@ -138,6 +138,32 @@ def test_graph_replays_track_parameter_updates(env, scene):
     b.close()
 
 
+def test_planned_dispatch_keeps_results_over_frames(env, scene):
+    """From the second frame on, the batched traversal dispatches each XCD's
+    workgroups longest-first by the previous frame's durations; every frame
+    must still equal the per-view calls (each block traced exactly once),
+    eager and graph, with the gaze moving between frames."""
+    torch, V = env
+    sizes = [(3840, 2160), (3840, 2160)]
+    kinds = [V.VAFR_VIEW_VAFR, V.VAFR_VIEW_VAFR]
+    trace = I.gaze_trace(8, 3840, 2160, seed=31)
+    cl, cr = I.binocular_cameras()
+    sh = V.shading()
+    for use_graph in (False, True):
+        b = V.Batch(2, trace_block=128, recon_rows=8, use_graph=use_graph)
+        for f in range(4):
+            gz = [tuple(trace[f]), tuple(trace[f])]
+            vs = _views(torch, V, scene, sizes, gz, [cl, cr], kinds)
+            _run_individual(V, scene, vs, sh)
+            torch.cuda.synchronize()
+            ref = _snapshot(vs)
+            _clear(torch, vs)
+            b.run(_descs(V, scene, vs, sh))
+            torch.cuda.synchronize()
+            _assert_equal(torch, ref, vs, f"graph={use_graph} frame {f}")
+        b.close()
+
+
 def test_autotune_picks_a_valid_shape(env, scene):
     torch, V = env
     sizes, gazes = I.batch_views(6, seed=8)
