@@ -196,10 +196,10 @@ typedef struct {
 int vafr_scene_get_info(vafr_scene scene, vafr_scene_info* out);
 
 /* Host copies of the BVH for structural checks: nodes[16 * n_nodes] as
- * stored on the device (per node: origin x, y, z and a word holding the
- * three biased scale exponents and the child count; 8-bit plane codes of
- * four child boxes, x-lo, x-hi, y-lo, y-hi, z-lo, z-hi, child c in byte c;
- * two unused words; four child references) and
+ * stored on the device (per node: origin x, y, z, scale z; 8-bit plane
+ * codes of four child boxes, x-lo, x-hi, y-lo, y-hi, z-lo, z-hi, child c in
+ * byte c, then scale x, scale y (FP32 powers of two); four child references,
+ * INT32_MIN for an empty slot) and
  * tri_order[n_tris] (original id of each stored triangle).  Either may be
  * NULL. */
 int vafr_scene_export(vafr_scene scene, float* nodes, int32_t* tri_order);

@@ -270,12 +270,13 @@ struct Packer {
                 code_hi[a] |= (uint32_t)(q < k ? qh[q] : 0) << (8 * q);
             }
         }
-        uint32_t meta = biased[0] | biased[1] << 8 | biased[2] << 16 | (uint32_t)k << 24;
-        float meta_f;
-        std::memcpy(&meta_f, &meta, 4);
-        b.org = make_float4(org[0], org[1], org[2], meta_f);
+        // the scales as FP32 values (2^(biased - 127)), ready for the traversal
+        const uint32_t sbits[3] = {biased[0] << 23, biased[1] << 23, biased[2] << 23};
+        float sz;
+        std::memcpy(&sz, &sbits[2], 4);
+        b.org = make_float4(org[0], org[1], org[2], sz);
         b.q0 = make_uint4(code_lo[0], code_hi[0], code_lo[1], code_hi[1]);
-        b.q1 = make_uint4(code_lo[2], code_hi[2], 0u, 0u);
+        b.q1 = make_uint4(code_lo[2], code_hi[2], sbits[0], sbits[1]);
         b.ref = make_int4(ref[0], ref[1], ref[2], ref[3]);
         return me;
     }

@@ -150,10 +150,7 @@ __device__ __forceinline__ float code(uint32_t w, int c) { return (float)((w >> 
 template <bool kFma>
 __device__ __forceinline__ void node_slabs(const RayPre& r, const float4 org, const uint4 q0, const uint4 q1,
                                            float tlim, float tn[4], bool hit[4]) {
-    const uint32_t meta = __float_as_uint(org.w);
-    const float sx = __uint_as_float((meta & 0xffu) << 23);
-    const float sy = __uint_as_float(((meta >> 8) & 0xffu) << 23);
-    const float sz = __uint_as_float(((meta >> 16) & 0xffu) << 23);
+    const float sx = __uint_as_float(q1.z), sy = __uint_as_float(q1.w), sz = org.w;
     const uint32_t ex = r.negx ? q0.y : q0.x, xx = r.negx ? q0.x : q0.y;   // entry / exit plane codes
     const uint32_t ey = r.negy ? q0.w : q0.z, xy = r.negy ? q0.z : q0.w;
     const uint32_t ez = r.negz ? q1.y : q1.x, xz = r.negz ? q1.x : q1.y;

@@ -92,11 +92,11 @@ int layout_device(vafr_layout L, const LayoutDev** out);
 // -------------------------------------------------------------------- BVH
 // Device node: up to four child boxes, quantised, and four references
 // (64 bytes; the traversal is bound by the bytes its lanes load).
-//   org  = (origin.x, origin.y, origin.z, meta): the node's box corner; meta
-//          holds the biased FP32 exponents of the x, y, z scales in bytes
-//          0..2 (scale = 2^(byte - 127)) and the child count in byte 3.
-//   q0   = (lo.x, hi.x, lo.y, hi.y), q1 = (lo.z, hi.z, 0, 0): 8-bit plane
-//          codes, child c in byte c; plane = origin + code x scale.
+//   org  = (origin.x, origin.y, origin.z, scale.z): the node's box corner
+//          and the z scale;
+//   q0   = (lo.x, hi.x, lo.y, hi.y), q1 = (lo.z, hi.z, scale.x, scale.y):
+//          8-bit plane codes, child c in byte c, and the x and y scales;
+//          every scale is a power of two, plane = origin + code x scale.
 //   ref  = the four child references.
 // Every decoded plane, computed as fmaf(code, scale, origin), lies outside
 // the child's padded FP32 box (the builder checks each one).

@@ -135,8 +135,7 @@ def _check_bvh(V, verts, tris):
     assert info["stack_entries"] in (24, 32) and info["max_depth"] <= info["stack_entries"] - 1
     assert info["max_stack"] <= info["stack_entries"] + 24
     refs = nodes[:, 12:16].view(np.int32) if nodes.size else np.zeros((0, 4), np.int32)
-    meta = nodes[:, 3].view(np.uint32) if nodes.size else np.zeros(0, np.uint32)
-    kids = (meta >> 24).astype(np.int64)
+    kids = (refs != np.iinfo(np.int32).min).sum(axis=1) if nodes.size else np.zeros(0, np.int64)
     tv = verts[tris[order]]                                               # stored order, (n, 3, 3)
     empty = np.iinfo(np.int32).min
     seen = np.zeros(len(nodes), int)
@@ -154,11 +153,13 @@ def _check_bvh(V, verts, tris):
 
     def planes(ni):
         """Decoded child planes (4 children x (lo, hi) x 3 axes) as the
-        traversal's fallback computes them: fmaf(code, 2^(b - 127), origin)."""
+        traversal's fallback computes them: fmaf(code, scale, origin)."""
         codes = nodes[ni, 4:12].view(np.uint32)
+        scales = (float(nodes[ni, 10]), float(nodes[ni, 11]), float(nodes[ni, 3]))
         out = np.zeros((4, 2, 3))
         for a in range(3):
-            scale = np.ldexp(1.0, int((meta[ni] >> (8 * a)) & 255) - 127)
+            scale = scales[a]
+            assert scale > 0 and np.frexp(scale)[0] == 0.5          # a power of two
             for c in range(4):
                 for side in range(2):
                     q = (int(codes[2 * a + side]) >> (8 * c)) & 255
