@@ -203,7 +203,7 @@ struct WorkCount {
 // leaves in lock step.  Node steps taken before a parked leaf is tested use
 // a hit distance that is not yet the smallest, so they only ever visit more
 // boxes; the result is the same (t, id) minimum or the same any-hit bit.
-constexpr int kParkNum = 3, kParkDen = 4;
+constexpr int kParkNum = 5, kParkDen = 8;
 
 // stk points at this lane's column of the block's LDS stack (stride B).
 // Closest hit (kAny = false): smallest (t, triangle id); returns the stored
