@@ -461,7 +461,7 @@ void vafr_server_destroy(vafr_server server);
  * vafr_shade_lp / lmfr_shade_lp would trace for this layout (kind taken from
  * the layout) and atomically adds to counters_dev[4] (device, caller-zeroed
  * unsigned 64-bit): primary rays, shadow rays, BVH node visits (each a test
- * of two child boxes) and ray/triangle tests.  Writes no image. */
+ * of a node's four child boxes) and ray/triangle tests.  Writes no image. */
 int vafr_count_work(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
                     vafr_layout layout, unsigned long long* counters_dev, hipStream_t stream);
 

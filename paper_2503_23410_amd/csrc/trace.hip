@@ -183,8 +183,8 @@ __device__ __forceinline__ void cswap(float& ka, int& ra, float& kb, int& rb) {
     ra = rr;
 }
 
-// Per-lane work counters of the diagnostic pass (node visits = box-pair
-// tests, triangle tests).
+// Per-lane work counters of the diagnostic pass (node visits, each a test
+// of a node's four child boxes; triangle tests).
 struct WorkCount {
     uint32_t nodes = 0, tris = 0;
 };

@@ -114,8 +114,8 @@ constexpr int kMaxLeaf = 4;
 // pushes the node's other hit children, so a traversal holds at most the
 // sum of (children - 1) over the ancestors of the current node; the binary
 // build tree is kept below depth class - 1 and its collapse into 4-wide
-// nodes keeps that sum within class + kStackSpill.  The spill entries are
-// rarely touched: most node steps hit one or two children.  The short class
+// nodes keeps that sum within class + kStackSpill.  Only traversals deeper
+// than the class touch the spill entries.  The short class
 // leaves room for more resident waves per CU (LDS per wave = entries x 64 x
 // 4 bytes), the long class admits every supported scene.
 constexpr int kStackShort = 24;
