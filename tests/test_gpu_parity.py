@@ -424,3 +424,34 @@ def test_invalid_calls_raise_before_launch(env):
     bad.light_dir[0] = 3.0
     with pytest.raises(V.VafrError):
         V.vafr_shade_lp(sc, V.camera(I.soup_camera()), V.gaze(1.0, 1.0), bad, L, lp)
+
+
+def test_deep_stack_scene_matches_oracle(env, O):
+    """2^18 identical triangles covering the view: every ray hits every box
+    and every triangle at the same t, so the traversal pushes three
+    siblings at most levels and its stack runs past the 24 LDS entries into
+    the scratch continuation (the builder's bound for this tree is above
+    40 entries); the closest hit must still be the lowest id."""
+    torch, V = env
+    n = 1 << 18
+    tri = np.array([[-8, -8, 1.0], [8, -8, 1.0], [0, 8, 1.0]], np.float32)
+    verts = np.tile(tri, (n, 1))
+    tris = np.arange(3 * n, dtype=np.int32).reshape(-1, 3)
+    sc = V.Scene(verts, tris)
+    assert sc.info()["max_stack"] > 40
+    W, H = 8, 8
+    img = torch.empty((W * H, 4), device="cuda")
+    hid = torch.empty(W * H, device="cuda", dtype=torch.int32)
+    V.full_shade(sc, V.camera(I.soup_camera()), V.display(W, H), V.shading(), img, hid)
+    torch.cuda.synchronize()
+    osc = O.Scene(verts, tris)
+    o_rgba, o_id, o_fl = O.shade_full_pixels(osc, np.arange(W * H), W, H, I.FOV, I.soup_camera(), O.shading_params())
+    g_id = hid.cpu().numpy()
+    # every hit is an exact tie in t, which the oracle flags; both sides
+    # break it by the lowest id, so ids and colours must agree on all rays
+    assert (o_id >= 0).sum() > 8 and np.all(o_id[o_id >= 0] == 0)
+    err = np.abs(img.cpu().numpy() - o_rgba).max()
+    log(f"deep stack: {int((o_id >= 0).sum())} hits of {W * H}, max_stack {sc.info()['max_stack']}, "
+        f"colour err {err:.2e}")
+    assert np.array_equal(g_id, o_id)
+    assert err <= COLOR_TOL
