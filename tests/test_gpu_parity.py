@@ -303,6 +303,54 @@ def test_cfg3_binocular_8k_sampled(env, O, layout):
     _compare("cfg3 lmfr", lpl[idx_t].cpu().numpy(), hidl[idx_t].cpu().numpy(), ol_rgba, ol_id, ol_fl)
 
 
+def test_retinal_display_sampled(env, O, layout, terrain1m):
+    """The largest display the paper measures, 11520 x 6480 per eye (Table 1,
+    retinal column).  The LP buffer keeps its 1,063,314 texels, which are
+    all compared.  The inverse map writes 74.6M pixels (a 1.19 GB image, the
+    last tile row ragged: 6480 = 202 x 32 + 16), checked on sampled pixels
+    plus the whole last row and column, for an off-centre gaze.  Full
+    resolution and LMFR(1.8) (6400 x 3600 texels) on sampled outputs."""
+    torch, V = env
+    g_sc, o_sc = terrain1m
+    W, H = 11520, 6480
+    L = V.Layout.vafr(V.display(W, H))
+    assert L.n_texels == layout.n_texels
+    cam = I.terrain_camera()
+    gz = (0.62 * W, 0.31 * H)
+    rng = np.random.default_rng(11)
+    lp, hid = _gpu_lp(torch, V, g_sc, L, gz, cam, V.shading())
+    o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz, cam,
+                                             O.shading_params())
+    _compare("retinal vafr", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.vafr_reconstruct(L, V.gaze(*gz), lp, img)
+    torch.cuda.synchronize()
+    edge = np.concatenate([(H - 1) * W + np.arange(W), np.arange(H) * W + (W - 1)])
+    pix = np.unique(np.concatenate([rng.integers(0, W * H, 300000), edge]))
+    pix_t = torch.from_numpy(pix).cuda()
+    p = O.film_pitch(W, H, *I.FOV)
+    ref, pf = O.vafr_reconstruct(layout, o_rgba, W, H, p, O.gaze_film(W, H, p, *gz), pix, o_fl)
+    err = np.abs(img[pix_t].cpu().numpy() - ref).max(axis=1)
+    log(f"retinal image: n={len(pix)} flagged_px={int(pf.sum())} max_err={err[~pf].max():.2e}")
+    assert err[~pf].max() <= COLOR_TOL
+    hidf = torch.empty(H * W, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(cam), V.display(W, H), V.shading(), img, hidf)
+    torch.cuda.synchronize()
+    pix = np.unique(np.concatenate([rng.integers(0, W * H, 60000), edge[::7]]))
+    pix_t = torch.from_numpy(pix).cuda()
+    of_rgba, of_id, of_fl = O.shade_full_pixels(o_sc, pix, W, H, I.FOV, cam, O.shading_params())
+    _compare("retinal full-res", img[pix_t].cpu().numpy(), hidf[pix_t].cpu().numpy(), of_rgba, of_id, of_fl)
+    del img, hidf
+    LM = V.Layout.lmfr(V.display(W, H), 1.8, 4.0)
+    w, h = O.lmfr_dims(W, H, 1.8)
+    assert (w, h) == (6400, 3600)
+    lpl, hidl = _gpu_lp(torch, V, g_sc, LM, gz, cam, V.shading(), lmfr=True)
+    idx = np.unique(rng.integers(0, w * h, 150000))
+    idx_t = torch.from_numpy(idx).cuda()
+    ol_rgba, ol_id, ol_fl = O.shade_lmfr_texels(o_sc, idx, W, H, I.FOV, gz, w, h, 4.0, cam, O.shading_params())
+    _compare("retinal lmfr", lpl[idx_t].cpu().numpy(), hidl[idx_t].cpu().numpy(), ol_rgba, ol_id, ol_fl)
+
+
 # ------------------------------------------------------------ edge cases ---
 
 def test_empty_scene_is_all_background(env, O):
