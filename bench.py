@@ -297,6 +297,7 @@ def main():
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
         out["layouts"] = layout_variants(torch, V, I, scene, sh, cams, gazes[warm:], max(20, csteps))
+        out["resolutions"] = resolution_sweep(torch, V, I, scene, sh, cams, max(60, 10 * csteps), max(2, csteps))
 
     # ------------------------------------------------------------ serving
     if args.serve_seconds > 0:
@@ -504,6 +505,56 @@ def rep_bench(torch, V, scene, cams, sh, L, gazes, steps):
 # fovea, falling linearly to 1/2 at 30 deg (the sensitivity ratio the paper
 # quotes there) and 1/2 beyond.
 ANISO_EXAMPLE = ((0.0, 30.0), (1.0, 0.5))
+
+
+def resolution_sweep(torch, V, I, scene, sh, cams, steps, full_steps):
+    """Binocular frames at the display sizes of Table 1 (2K, 4K, 6K, 8K and
+    retinal 11520 x 6480 per eye): batched VaFR (same LP buffer at every
+    size; launch shape fixed at trace 128, reconstruction 8 rows) against
+    the full-resolution ray cast (one primary + shadow ray per pixel).  Each
+    size uses the seeded gaze trace scaled to its display."""
+    sizes = [(2560, 1440), (3840, 2160), (5760, 3240), (7680, 4320), (11520, 6480)]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for Wd, Hd in sizes:
+        disp = V.display(Wd, Hd, I.FOV)
+        Ld = V.Layout.vafr(disp)
+        tr = I.gaze_trace(steps + 10, Wd, Hd, seed=30)
+        gz = [V.gaze(float(x), float(y)) for x, y in tr]
+        lp = [torch.empty((Ld.n_texels, 4), device="cuda") for _ in range(2)]
+        img = [torch.empty((Hd * Wd, 4), device="cuda") for _ in range(2)]
+        b = V.Batch(2, trace_block=128, recon_rows=8, use_graph=True)
+
+        def frame(f):
+            b.run([V.view(V.VAFR_VIEW_VAFR, scene, cams[e], gz[f], sh, layout=Ld, lp_rgba=lp[e], img_rgba=img[e])
+                   for e in range(2)], stream)
+
+        for f in range(5):
+            frame(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(steps):
+            frame(5 + f % (len(gz) - 5))
+        torch.cuda.synchronize()
+        vafr_fps = steps / (time.perf_counter() - t0)
+        b.close()
+        for e in range(2):
+            V.full_shade(scene, cams[e], disp, sh, img[e], None, stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for f in range(full_steps):
+            for e in range(2):
+                V.full_shade(scene, cams[e], disp, sh, img[e], None, stream)
+        torch.cuda.synchronize()
+        full_fps = full_steps / (time.perf_counter() - t0)
+        key = f"{Wd}x{Hd}"
+        res[key] = {"vafr_fps": round(vafr_fps, 2), "fullres_fps": round(full_fps, 3),
+                    "speedup_vs_fullres": round(vafr_fps / full_fps, 2), "lp_texels_per_eye": Ld.n_texels,
+                    "fullres_rays_per_eye": Wd * Hd}
+        log(f"resolution {key}: VaFR {vafr_fps:.1f} frames/s, full resolution {full_fps:.2f} frames/s "
+            f"({vafr_fps / full_fps:.1f}x)")
+        del lp, img
+    return res
 
 
 def layout_variants(torch, V, I, scene, sh, cams, gazes, steps):
