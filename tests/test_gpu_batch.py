@@ -200,3 +200,50 @@ def test_batch_rejects_bad_views(env, scene):
     b.run([good])
     torch.cuda.synchronize()
     b.close()
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_random_batches_equal_individual_calls(env, scene, case):
+    """Seeded random batches: 1-12 views of random kind (VaFR, LMFR, full
+    resolution), display size (1-900 px per side), gaze (on and off
+    screen), camera and scene (the terrain and a small soup in one batch),
+    one shading per batch (Lambert, no shadows, or path mode), random launch
+    shape, eager or graph.  Each batch runs twice (the second run follows
+    the dispatch plan the first one recorded) and must equal the per-view
+    calls bit for bit."""
+    torch, V = env
+    rng = np.random.default_rng(900 + case)
+    sv, sf = I.soup_scene()
+    soup = V.Scene(sv, sf)
+    n = int(rng.integers(1, 13))
+    kinds = [int(rng.choice([V.VAFR_VIEW_VAFR, V.VAFR_VIEW_LMFR, V.VAFR_VIEW_FULL], p=[0.6, 0.2, 0.2]))
+             for _ in range(n)]
+    sizes = [(int(rng.integers(1, 901)), int(rng.integers(1, 901))) for _ in range(n)]
+    gazes = [(float(rng.uniform(-0.2, 1.2) * w), float(rng.uniform(-0.2, 1.2) * h)) for w, h in sizes]
+    cams = [I.terrain_camera(float(rng.uniform(-0.05, 0.05))) for _ in range(n)]
+    scenes = [scene if rng.uniform() < 0.7 else soup for _ in range(n)]
+    mode = case % 3
+    if mode == 2:
+        sh = V.shading(mode=V.VAFR_SHADE_PATH, bounces=int(rng.integers(0, 3)), frame=case, seed=77 + case)
+    else:
+        sh = V.shading(shadow=mode == 0)
+    vs = _views(torch, V, scene, sizes, gazes, cams, kinds)
+    for w, sc in zip(vs, scenes):
+        w["scene"] = sc
+    for w in vs:
+        _run_individual(V, w["scene"], [w], sh)
+    torch.cuda.synchronize()
+    ref = _snapshot(vs)
+    tb = int(rng.choice([64, 128, 256]))
+    rows = int(rng.choice([1, 2, 4, 8]))
+    use_graph = bool(rng.integers(0, 2))
+    b = V.Batch(12, trace_block=tb, recon_rows=rows, use_graph=use_graph)
+    descs = [V.view(w["kind"], w["scene"], w["cam"], w["gaze"], sh, layout=w["layout"], disp=w["disp"],
+                    lp_rgba=w["lp"], hit_id=w["hit"], img_rgba=w["img"]) for w in vs]
+    for rep in range(2):
+        _clear(torch, vs)
+        b.run(descs)
+        torch.cuda.synchronize()
+        _assert_equal(torch, ref, vs, f"case {case} run {rep} (views {n}, block {tb}, rows {rows}, graph {use_graph})")
+    b.close()
+    log(f"random batch {case}: {n} views {kinds} mode {mode} block {tb} rows {rows} graph {use_graph}: equal")
