@@ -109,3 +109,26 @@ def test_fxaa_rejects_bad_calls(env):
     with pytest.raises(V.VafrError) as ei:
         V.vafr_fxaa_lp(LM, lp, torch.zeros_like(lp))
     assert ei.value.code == V.VAFR_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("cap,aniso", [(9.0, None), (None, ([0.0, 30.0], [1.0, 0.5])),
+                                       (18.0, ([0.0, 10.0, 40.0], [1.0, 0.8, 0.4]))])
+def test_fxaa_on_capped_and_anisotropic_layouts(env, O, cap, aniso):
+    """The anti-aliasing reads neighbours across columns of different row
+    counts; layouts of the device-adapted curves and of anisotropic
+    tangential rates change those counts: every texel against the oracle."""
+    torch, V = env
+    if cap is None:
+        ecc, cpd = [0.0, 10.0, 20.0, 30.0, 60.0], [40.0, 10.0, 6.0, 5.0, 4.0]
+    else:
+        ecc, cpd = V.acuity_capped(cap)
+    L = V.Layout.vafr(V.display(1280, 720), ecc, cpd, 60.0, aniso=aniso)
+    ref_layout = O.Layout(O.Acuity(ecc, cpd, aniso=aniso), 60.0)
+    assert L.n_texels == ref_layout.n_texels
+    r = I.random_lp(L.n_texels, seed=405)
+    g = _fxaa_gpu(torch, V, L, r)
+    o = O.fxaa_lp(ref_layout, r)
+    err = np.abs(g - o).max()
+    log(f"fxaa cap={cap} aniso={aniso}: texels={L.n_texels} max_err={err:.2e} "
+        f"changed={np.mean(np.any(o != r, axis=1)):.3f}")
+    assert err <= COLOR_TOL
