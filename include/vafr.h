@@ -328,10 +328,14 @@ int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg, vafr_batc
 /* One frame of n_views views on `stream`: ONE traversal launch covering the
  * rays of every view (workgroups are assigned to views by a running count)
  * and ONE reconstruction launch covering every display of the VaFR / LMFR
- * views.  With use_graph the sequence (descriptor upload, two kernels) is a
- * hipGraph built once per launch shape; later frames only update the node
- * parameters and replay it.  Results are identical to the per-view calls.
- * Blocks the host only when all 4 descriptor slots are still in flight. */
+ * views.  Path-mode views with two or more bounces trace bounces 0-1 in the
+ * traversal launch and queue the paths still alive; one more launch
+ * finishes the queued paths, one per thread (the batch allocates the queue,
+ * 64 bytes per ray of those views, per descriptor slot on first use).  With
+ * use_graph the sequence (descriptor upload, kernels) is a hipGraph built
+ * once per launch shape; later frames only update the node parameters and
+ * replay it.  Results are identical to the per-view calls.  Blocks the host
+ * only when all 4 descriptor slots are still in flight. */
 int vafr_batch_run(vafr_batch batch, const vafr_view* views, int32_t n_views, hipStream_t stream);
 
 /* Times every traversal workgroup size and reconstruction tile height on

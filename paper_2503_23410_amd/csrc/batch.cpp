@@ -1,7 +1,9 @@
 // Batched frames: every view's rays in ONE traversal launch, every display
 // in ONE reconstruction launch, optionally replayed from a hipGraph whose
 // node parameters are updated per frame, and an autotuner for the launch
-// shape.
+// shape.  Path-mode views with two or more bounces run their later bounces
+// in a second traversal pass over the paths still alive (a compacted queue
+// per view), so that the waves of that pass are full of live paths.
 //
 // Per frame the host writes the view descriptors into one slot of a ring of
 // pinned staging buffers; the slot is copied to its device twin on the
@@ -26,6 +28,8 @@ struct Slot {
     char* host = nullptr;   // pinned staging
     char* dev = nullptr;    // device twin
     int32_t* order = nullptr;   // planned dispatch order of this slot's traversal launch
+    float4* queue = nullptr;    // live paths of the two-pass path-mode views (4 float4 each)
+    int64_t queue_cap = 0;      // capacity in paths
     hipEvent_t done = nullptr;
     bool used = false;
     // stage timing (when profiling): before upload, after upload, after
@@ -37,9 +41,10 @@ struct Slot {
 // A graph for one launch shape.
 struct GraphEntry {
     int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0, stack = 0;
+    int queue_blocks = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, krecon = nullptr;
+    hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, kqueue = nullptr, krecon = nullptr;
     bool timed = false;
     hipGraphNode_t evn[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -51,7 +56,10 @@ struct vafr_batch_s {
     int32_t max_views = 0;
     vafr_batch_config cfg{vafr::kTraceBlockDefault, vafr::kReconRowsDefault, 1};
     int device = -1;
-    size_t off_tb = 0, off_rv = 0, off_rb = 0, bytes = 0;
+    // staging layout: TraceView[], traversal block ends, ReconView[],
+    // reconstruction block ends, queue-pass block ends, queue counters (the
+    // counters stay zero on the host, so every upload clears them)
+    size_t off_tb = 0, off_rv = 0, off_rb = 0, off_qb = 0, off_qc = 0, bytes = 0;
     vafr::Slot slot[vafr::kSlots];
     int next = 0;
     std::vector<vafr::GraphEntry> graphs;
@@ -60,7 +68,9 @@ struct vafr_batch_s {
     std::vector<vafr::TraceView> tv;
     std::vector<vafr::ReconView> rv;
     int stack = vafr::kStackShort;   // stack class of the frame's traversal launch
-    std::vector<int32_t> tb, rb;
+    std::vector<int32_t> tb, rb, qb;
+    std::vector<int64_t> qoff;       // first queue entry of each view
+    int64_t queue_items = 0;         // queue entries the frame needs
     bool profiling = false;
     double stage_sum[3] = {0, 0, 0};   // accumulated stage times (ms)
     int64_t stage_frames = 0;
@@ -90,12 +100,16 @@ void free_graphs(vafr_batch b) {
 }
 
 // Descriptors of one frame into b->tv/tb/rv/rb.
-int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blocks, int32_t* recon_blocks) {
+int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blocks, int32_t* recon_blocks,
+             int32_t* queue_blocks) {
     b->tv.clear();
     b->rv.clear();
     b->tb.clear();
     b->rb.clear();
-    int64_t tsum = 0, rsum = 0;
+    b->qb.clear();
+    b->qoff.clear();
+    b->queue_items = 0;
+    int64_t tsum = 0, rsum = 0, qsum = 0;
     b->stack = kStackShort;
     for (int32_t i = 0; i < n; ++i) {
         const vafr_view& w = views[i];
@@ -116,6 +130,16 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
         tsum += (t.n_items + b->cfg.trace_block - 1) / b->cfg.trace_block;
         if (tsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
         b->stack = std::max(b->stack, (int)t.stack);
+        // path mode with two or more bounces: two passes (queue pointers
+        // are filled in per slot)
+        b->qoff.push_back(b->queue_items);
+        if (t.shade_mode == VAFR_SHADE_PATH && t.bounces > kPathSplitBounce) {
+            t.pt_split = kPathSplitBounce;
+            b->queue_items += t.n_items;
+            qsum += (t.n_items + kQueueBlock - 1) / kQueueBlock;
+            if (qsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
+        }
+        b->qb.push_back((int32_t)qsum);
         b->tv.push_back(t);
         b->tb.push_back((int32_t)tsum);
         if (w.kind != VAFR_VIEW_FULL && w.img_rgba_dev) {
@@ -129,7 +153,38 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     }
     *trace_blocks = (int32_t)tsum;
     *recon_blocks = (int32_t)rsum;
+    *queue_blocks = (int32_t)qsum;
     return VAFR_OK;
+}
+
+// Room for `items` queued paths in slot s (the slot is idle when called).
+int ensure_queue(Slot& s, int64_t items) {
+    if (items <= s.queue_cap) return VAFR_OK;
+    (void)hipFree(s.queue);
+    s.queue = nullptr;
+    s.queue_cap = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&s.queue), 4 * sizeof(float4) * (size_t)items) != hipSuccess)
+        return fail(VAFR_E_OOM, "path queue allocation failed");
+    s.queue_cap = items;
+    return VAFR_OK;
+}
+
+hipKernelNodeParams queue_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const TraceView** v,
+                                 const int32_t** qe, int32_t* n) {
+    *v = reinterpret_cast<const TraceView*>(dev);
+    *qe = reinterpret_cast<const int32_t*>(dev + b->off_qb);
+    *n = g.n_trace;
+    args[0] = v;
+    args[1] = qe;
+    args[2] = n;
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(trace_queue_batch_kernel(g.stack));
+    p.gridDim = dim3((unsigned)g.queue_blocks);
+    p.blockDim = dim3((unsigned)kQueueBlock);
+    p.sharedMemBytes = 0;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return p;
 }
 
 // Kernel arguments of a batched traversal node; the pointed-to values must
@@ -237,12 +292,13 @@ hipKernelNodeParams recon_params(vafr_batch b, const GraphEntry& g, char* dev, v
     return p;
 }
 
-int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s, GraphEntry** out) {
+int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t queue_blocks, Slot& s,
+              GraphEntry** out) {
     const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
     for (auto& g : b->graphs)
         if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
-            g.trace_block == b->cfg.trace_block && g.recon_rows == b->cfg.recon_rows && g.stack == b->stack &&
-            g.timed == b->profiling) {
+            g.queue_blocks == queue_blocks && g.trace_block == b->cfg.trace_block &&
+            g.recon_rows == b->cfg.recon_rows && g.stack == b->stack && g.timed == b->profiling) {
             *out = &g;
             return VAFR_OK;
         }
@@ -256,6 +312,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     g.n_recon = nr;
     g.trace_blocks = trace_blocks;
     g.recon_blocks = recon_blocks;
+    g.queue_blocks = queue_blocks;
     g.trace_block = b->cfg.trace_block;
     g.recon_rows = b->cfg.recon_rows;
     g.stack = b->stack;
@@ -281,8 +338,17 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
             e = hipGraphAddKernelNode(&g.ktrace, g.graph, &dep, 1, &p);
         }
     }
+    void* qa[3];
+    const TraceView* qv;
+    const int32_t* qe;
+    int32_t qn;
+    if (e == hipSuccess && g.ktrace && queue_blocks > 0) {
+        hipKernelNodeParams p = queue_params(b, g, s.dev, qa, &qv, &qe, &qn);
+        e = hipGraphAddKernelNode(&g.kqueue, g.graph, &g.ktrace, 1, &p);
+    }
+    hipGraphNode_t traced = g.kqueue ? g.kqueue : g.ktrace;
     if (e == hipSuccess && g.timed) {
-        hipGraphNode_t dep = g.ktrace ? g.ktrace : g.evn[1];
+        hipGraphNode_t dep = traced ? traced : g.evn[1];
         e = hipGraphAddEventRecordNode(&g.evn[2], g.graph, &dep, 1, s.ev[2]);
     }
     void* ra[3];
@@ -291,7 +357,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, Slot& s,
     int32_t rn;
     if (e == hipSuccess && recon_blocks > 0) {
         hipKernelNodeParams p = recon_params(b, g, s.dev, ra, &rvp, &rbe, &rn);
-        hipGraphNode_t dep = g.timed ? g.evn[2] : (g.ktrace ? g.ktrace : g.copy);
+        hipGraphNode_t dep = g.timed ? g.evn[2] : (traced ? traced : g.copy);
         e = hipGraphAddKernelNode(&g.krecon, g.graph, &dep, 1, &p);
     }
     if (e == hipSuccess && g.timed) {
@@ -328,8 +394,8 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     int dev = -1;
     VAFR_HIP(hipGetDevice(&dev));
     if (dev != b->device) return fail(VAFR_E_ARG, "batch was created on device %d, current is %d", b->device, dev);
-    int32_t tblocks = 0, rblocks = 0;
-    if (int rc = describe(b, views, n, &tblocks, &rblocks)) return rc;
+    int32_t tblocks = 0, rblocks = 0, qblocks = 0;
+    if (int rc = describe(b, views, n, &tblocks, &rblocks, &qblocks)) return rc;
     // launches too large to plan keep the fixed XCD order
     const bool planned = trace_plan_ok(tblocks);
     if (planned)
@@ -340,7 +406,17 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         VAFR_HIP(hipEventSynchronize(s.done));
         if (int rc = fold_slot(b, s)) return rc;
     }
+    if (qblocks > 0) {
+        if (int rc = ensure_queue(s, b->queue_items)) return rc;
+        uint32_t* counters = reinterpret_cast<uint32_t*>(s.dev + b->off_qc);
+        for (size_t i = 0; i < b->tv.size(); ++i)
+            if (b->tv[i].pt_split >= 0) {
+                b->tv[i].pt_queue = s.queue + 4 * b->qoff[i];
+                b->tv[i].pt_count = counters + i;
+            }
+    }
     std::memcpy(s.host, b->tv.data(), sizeof(TraceView) * b->tv.size());
+    std::memcpy(s.host + b->off_qb, b->qb.data(), sizeof(int32_t) * b->qb.size());
     std::memcpy(s.host + b->off_tb, b->tb.data(), sizeof(int32_t) * b->tb.size());
     if (!b->rv.empty()) {
         std::memcpy(s.host + b->off_rv, b->rv.data(), sizeof(ReconView) * b->rv.size());
@@ -348,7 +424,7 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     }
     if (b->cfg.use_graph) {
         GraphEntry* g;
-        if (int rc = graph_for(b, tblocks, rblocks, s, &g)) return rc;
+        if (int rc = graph_for(b, tblocks, rblocks, qblocks, s, &g)) return rc;
         VAFR_HIP(hipGraphExecMemcpyNodeSetParams1D(g->exec, g->copy, s.dev, s.host, b->bytes, hipMemcpyHostToDevice));
         if (g->timed)
             for (int k = 0; k < 4; ++k) VAFR_HIP(hipGraphExecEventRecordNodeSetEvent(g->exec, g->evn[k], s.ev[k]));
@@ -361,6 +437,14 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             }
             hipKernelNodeParams p = trace_params(b, *g, s, ta);
             VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->ktrace, &p));
+        }
+        void* qa[3];
+        const TraceView* qv;
+        const int32_t* qe;
+        int32_t qn;
+        if (g->kqueue) {
+            hipKernelNodeParams p = queue_params(b, *g, s.dev, qa, &qv, &qe, &qn);
+            VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->kqueue, &p));
         }
         void* ra[3];
         const ReconView* rvp;
@@ -382,6 +466,11 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
                                         tblocks, b->cfg.trace_block, b->stack, stream, nullptr,
                                         planned ? s.order : nullptr, planned ? b->cost : nullptr))
             return rc;
+        if (qblocks > 0)
+            if (int rc = launch_trace_queue_batch(reinterpret_cast<const TraceView*>(s.dev),
+                                                  reinterpret_cast<const int32_t*>(s.dev + b->off_qb),
+                                                  (int32_t)b->tv.size(), qblocks, b->stack, stream))
+                return rc;
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[2], stream));
         if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),
                                               reinterpret_cast<const int32_t*>(s.dev + b->off_rb),
@@ -415,7 +504,9 @@ extern "C" int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg
     b->off_tb = align256(sizeof(TraceView) * max_views);
     b->off_rv = b->off_tb + align256(sizeof(int32_t) * max_views);
     b->off_rb = b->off_rv + align256(sizeof(ReconView) * max_views);
-    b->bytes = b->off_rb + align256(sizeof(int32_t) * max_views);
+    b->off_qb = b->off_rb + align256(sizeof(int32_t) * max_views);
+    b->off_qc = b->off_qb + align256(sizeof(int32_t) * max_views);
+    b->bytes = b->off_qc + align256(sizeof(uint32_t) * max_views);
     auto bail = [&](int code) {
         vafr_batch_destroy(b);
         return code;
@@ -437,6 +528,8 @@ extern "C" int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg
         b->rv.reserve(max_views);
         b->tb.reserve(max_views);
         b->rb.reserve(max_views);
+        b->qb.reserve(max_views);
+        b->qoff.reserve(max_views);
     } catch (const std::bad_alloc&) {
         return bail(fail(VAFR_E_OOM, "batch allocation failed"));
     }
@@ -556,6 +649,7 @@ extern "C" void vafr_batch_destroy(vafr_batch b) {
             if (ev) (void)hipEventDestroy(ev);
         if (s.dev) (void)hipFree(s.dev);
         if (s.order) (void)hipFree(s.order);
+        if (s.queue) (void)hipFree(s.queue);
         if (s.host) (void)hipHostFree(s.host);
     }
     if (b->cost) (void)hipFree(b->cost);

@@ -488,15 +488,15 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
                        a.z * (v.ambient[2] + v.light_rgb[2] * lam * vis), 1.0f);
 }
 
+// Path from bounce b0 (ray r, throughput thr, radiance L so far): returns
+// true when the path has ended (L final), false when it stopped after
+// bounce b_last with r set to the next ray.  Bounce 0 reports the primary
+// hit id and point.
 template <int B, int S, bool kCount>
-__device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
-                             uint32_t& n_shadow, float4& p_out) {
+__device__ bool path_segment(const TraceView& v, RayPre& r, uint32_t texel, int* stk, float3& thr, float3& L,
+                             int b0, int b_last, int& id_out, float4& p_out, WorkCount& wc, uint32_t& n_shadow) {
     const TraceView& sc = v;
-    float3 thr = make_float3(1.0f, 1.0f, 1.0f);
-    float3 L = make_float3(0.0f, 0.0f, 0.0f);
-    id_out = -1;
-    p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int bnc = 0; bnc <= v.bounces; ++bnc) {
+    for (int bnc = b0; bnc <= v.bounces; ++bnc) {
         float t;
         int id;
         const int slot = closest_hit<B, S, kCount>(sc, r, stk, t, id, wc);
@@ -508,7 +508,7 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
             L.x += thr.x * v.background[0];
             L.y += thr.y * v.background[1];
             L.z += thr.z * v.background[2];
-            break;
+            return true;
         }
         const float4* tp = sc.tris + 3 * (size_t)slot;
         float3 n, os;
@@ -526,11 +526,56 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
         L.x += thr.x * (v.ambient[0] + v.light_rgb[0] * ndl * vis);
         L.y += thr.y * (v.ambient[1] + v.light_rgb[1] * ndl * vis);
         L.z += thr.z * (v.ambient[2] + v.light_rgb[2] * ndl * vis);
-        if (bnc == v.bounces) break;
+        if (bnc == v.bounces) return true;
         const float3 w = cosine_dir(v, n, texel, (uint32_t)bnc);
         ray_setup(os.x, os.y, os.z, w.x, w.y, w.z, r);
+        if (bnc == b_last) return false;
     }
+    return true;
+}
+
+template <int B, int S, bool kCount>
+__device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* stk, int& id_out, WorkCount& wc,
+                             uint32_t& n_shadow, float4& p_out) {
+    float3 thr = make_float3(1.0f, 1.0f, 1.0f);
+    float3 L = make_float3(0.0f, 0.0f, 0.0f);
+    id_out = -1;
+    p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    path_segment<B, S, kCount>(v, r, texel, stk, thr, L, 0, 0x7fffffff, id_out, p_out, wc, n_shadow);
     return make_float4(L.x, L.y, L.z, 1.0f);
+}
+
+// First pass of a two-pass path-mode view: bounces 0 .. pt_split; a path
+// still alive is appended to the view's queue (one atomic per wave: the
+// wave's first queuing lane reserves the entries, each lane takes the slot
+// of its rank among the queuing lanes).
+template <int B, int S>
+__device__ void path_first_pass(const TraceView& v, RayPre r, int64_t out, int* stk) {
+    float3 thr = make_float3(1.0f, 1.0f, 1.0f), L = make_float3(0.0f, 0.0f, 0.0f);
+    int id = -1;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    WorkCount wc;
+    uint32_t n_shadow = 0;
+    const bool ended = path_segment<B, S, false>(v, r, (uint32_t)out, stk, thr, L, 0, v.pt_split, id, p, wc,
+                                                 n_shadow);
+    if (v.out_id) v.out_id[out] = id;
+    if (v.out_p) v.out_p[out] = p;
+    const uint64_t queued = __ballot(!ended);
+    if (ended) {
+        v.out_rgba[out] = make_float4(L.x, L.y, L.z, 1.0f);
+        return;
+    }
+    const int lane = (int)__lane_id();
+    const int leader = __builtin_ctzll(queued);
+    const int rank = __popcll(queued & ((1ull << lane) - 1ull));
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(v.pt_count, (uint32_t)__popcll(queued));
+    base = __shfl(base, leader, 64);
+    float4* e = v.pt_queue + 4 * (size_t)(base + (uint32_t)rank);
+    e[0] = make_float4(r.ox, r.oy, r.oz, __int_as_float((int)out));
+    e[1] = make_float4(r.dx, r.dy, r.dz, __int_as_float(v.pt_split + 1));
+    e[2] = make_float4(thr.x, thr.y, thr.z, 0.0f);
+    e[3] = make_float4(L.x, L.y, L.z, 0.0f);
 }
 
 // One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
@@ -542,6 +587,10 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     int64_t out;
     if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
     int* stk = stack + threadIdx.x;
+    if (!kCount && v.pt_split >= 0) {
+        path_first_pass<B, S>(v, r, out, stk);
+        return;
+    }
     int id;
     float4 c, p;
     WorkCount wc;
@@ -579,6 +628,37 @@ __global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long lo
     __shared__ int stack[S * B];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     trace_item<B, S, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
+}
+
+// Queue pass of two-pass path-mode views (batched): workgroup b serves view
+// vid with qblock_end[vid-1] <= b < qblock_end[vid]; its thread q finishes
+// the view's queued path q while q < *pt_count (workgroups past the count
+// exit at once) and writes the pixel's radiance.
+template <int S>
+__global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceView* __restrict__ views,
+                                                                   const int32_t* __restrict__ qblock_end,
+                                                                   int32_t n_views) {
+    __shared__ int stack[S * kQueueBlock];
+    const int b = blockIdx.x;
+    int vid = 0;
+    while (vid + 1 < n_views && b >= qblock_end[vid]) ++vid;
+    const TraceView& v = views[vid];
+    const int first = vid ? qblock_end[vid - 1] : 0;
+    const int64_t q = (int64_t)(b - first) * kQueueBlock + threadIdx.x;
+    if (v.pt_split < 0 || q >= (int64_t)*v.pt_count) return;
+    const float4* e = v.pt_queue + 4 * q;
+    const float4 e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3];
+    RayPre r;
+    ray_setup(e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, r);
+    const int out = __float_as_int(e0.w);
+    float3 thr = make_float3(e2.x, e2.y, e2.z), L = make_float3(e3.x, e3.y, e3.z);
+    int id = -1;
+    float4 p;
+    WorkCount wc;
+    uint32_t n_shadow = 0;
+    path_segment<kQueueBlock, S, false>(v, r, (uint32_t)out, stack + threadIdx.x, thr, L, __float_as_int(e1.w),
+                                        0x7fffffff, id, p, wc, n_shadow);
+    v.out_rgba[out] = make_float4(L.x, L.y, L.z, 1.0f);
 }
 
 // List mode: thread q < *item_count traces item item_list[q].  The grid is
@@ -762,6 +842,26 @@ int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev,
 }
 
 bool trace_plan_ok(int32_t blocks) { return blocks / kXcds <= kPlanMaxPer; }
+
+const void* trace_queue_batch_kernel(int stack) {
+    if (stack == kStackShort) return reinterpret_cast<const void*>(&k_trace_queue_batch<kStackShort>);
+    if (stack == kStackLong) return reinterpret_cast<const void*>(&k_trace_queue_batch<kStackLong>);
+    return nullptr;
+}
+
+int launch_trace_queue_batch(const TraceView* views_dev, const int32_t* qblock_end_dev, int32_t n_views,
+                             int32_t blocks, int stack, hipStream_t stream) {
+    if (blocks <= 0) return VAFR_OK;
+    if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
+    if (stack == kStackShort)
+        hipLaunchKernelGGL((k_trace_queue_batch<kStackShort>), dim3((unsigned)blocks), dim3(kQueueBlock), 0, stream,
+                           views_dev, qblock_end_dev, n_views);
+    else
+        hipLaunchKernelGGL((k_trace_queue_batch<kStackLong>), dim3((unsigned)blocks), dim3(kQueueBlock), 0, stream,
+                           views_dev, qblock_end_dev, n_views);
+    VAFR_HIP(hipGetLastError());
+    return VAFR_OK;
+}
 
 const void* trace_plan_kernel() { return reinterpret_cast<const void*>(&k_trace_plan); }
 

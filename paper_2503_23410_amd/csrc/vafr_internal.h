@@ -197,6 +197,14 @@ struct TraceView {
     // traced, one per thread; n_items bounds the list.
     const int32_t* item_list;
     const int32_t* item_count;
+    // Path mode in two passes (pt_split >= 0, batched launches only): a path
+    // still alive after bounce pt_split is appended to pt_queue (4 float4:
+    // next ray origin | output index, direction | next bounce, throughput,
+    // radiance) and finished by the queue pass; *pt_count counts the entries
+    // (zeroed before the frame).  pt_split = -1: one pass.
+    float4* pt_queue;
+    uint32_t* pt_count;
+    int32_t pt_split;
 };
 
 // Work items of a view (padded to whole tiles for full-resolution / LMFR).
@@ -219,6 +227,16 @@ int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev,
 // cost[] is cleared as it is read).  trace_plan_ok: whether a launch of
 // that size can be planned.
 bool trace_plan_ok(int32_t blocks);
+// Queue pass of a batched path-mode launch: workgroup b serves view vid with
+// qblock_end[vid-1] <= b < qblock_end[vid]; thread q of that view finishes
+// its queued path q while q < *pt_count.
+int launch_trace_queue_batch(const TraceView* views_dev, const int32_t* qblock_end_dev, int32_t n_views,
+                             int32_t blocks, int stack, hipStream_t stream);
+const void* trace_queue_batch_kernel(int stack);
+constexpr int kQueueBlock = 128;
+// Bounce after which a batched path-mode view with at least two bounces
+// queues its live paths.
+constexpr int kPathSplitBounce = 1;
 int launch_trace_plan(uint32_t* cost, int32_t* order, int32_t blocks, hipStream_t stream);
 const void* trace_plan_kernel();
 

@@ -247,3 +247,36 @@ def test_random_batches_equal_individual_calls(env, scene, case):
         _assert_equal(torch, ref, vs, f"case {case} run {rep} (views {n}, block {tb}, rows {rows}, graph {use_graph})")
     b.close()
     log(f"random batch {case}: {n} views {kinds} mode {mode} block {tb} rows {rows} graph {use_graph}: equal")
+
+
+@pytest.mark.parametrize("bounces", [2, 3])
+def test_two_pass_path_mode_equals_single_pass(env, scene, bounces):
+    """Batched path-mode views with two or more bounces run their later
+    bounces in a second pass over a compacted queue of live paths; the
+    per-view calls run each path in one pass.  Both must agree bit for bit:
+    VaFR, LMFR and full-resolution views plus a Lambert view in one batch,
+    eager and graph, three frames in a row (graph replays with new gazes)."""
+    torch, V = env
+    sizes = [(1280, 720), (640, 480), (301, 177), (1920, 1080)]
+    kinds = [V.VAFR_VIEW_VAFR, V.VAFR_VIEW_LMFR, V.VAFR_VIEW_FULL, V.VAFR_VIEW_VAFR]
+    cams = [I.terrain_camera(0.01 * k) for k in range(4)]
+    path = V.shading(mode=V.VAFR_SHADE_PATH, bounces=bounces, frame=3, seed=99)
+    lam = V.shading()
+    shs = [path, path, path, lam]
+    for use_graph in (False, True):
+        b = V.Batch(8, trace_block=128, recon_rows=4, use_graph=use_graph)
+        for frame in range(3):
+            gazes = [(0.3 * w + 40.0 * frame, 0.6 * h - 25.0 * frame) for w, h in sizes]
+            vs = _views(torch, V, scene, sizes, gazes, cams, kinds)
+            for w, sh in zip(vs, shs):
+                w["sh"] = sh
+                _run_individual(V, scene, [w], sh)
+            torch.cuda.synchronize()
+            ref = _snapshot(vs)
+            _clear(torch, vs)
+            b.run([V.view(w["kind"], scene, w["cam"], w["gaze"], w["sh"], layout=w["layout"], disp=w["disp"],
+                          lp_rgba=w["lp"], hit_id=w["hit"], img_rgba=w["img"]) for w in vs])
+            torch.cuda.synchronize()
+            _assert_equal(torch, ref, vs, f"bounces {bounces} graph {use_graph} frame {frame}")
+        b.close()
+    log(f"two-pass path mode ({bounces} bounces) equals the single pass (eager and graph, 3 frames)")
