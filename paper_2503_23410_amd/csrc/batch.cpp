@@ -215,7 +215,7 @@ hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, const Slot& 
     a.p[5] = &a.cost;
     void** args = a.p;
     hipKernelNodeParams p{};
-    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack));
+    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack, g.queue_blocks > 0));
     p.gridDim = dim3((unsigned)g.trace_blocks);
     p.blockDim = dim3((unsigned)g.trace_block);
     p.sharedMemBytes = 0;
@@ -463,7 +463,7 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             if (int rc = launch_trace_plan(b->cost, s.order, tblocks, stream)) return rc;
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
-                                        tblocks, b->cfg.trace_block, b->stack, stream, nullptr,
+                                        tblocks, b->cfg.trace_block, b->stack, qblocks > 0, stream, nullptr,
                                         planned ? s.order : nullptr, planned ? b->cost : nullptr))
             return rc;
         if (qblocks > 0)

@@ -580,14 +580,16 @@ __device__ void path_first_pass(const TraceView& v, RayPre r, int64_t out, int* 
 
 // One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
 // counts work into counters[0..3] = primary rays, shadow rays, node visits,
-// triangle tests, and writes no image.
-template <int B, int S, bool kCount>
+// triangle tests, and writes no image.  kSplit: the kernel may serve
+// two-pass path-mode views (compiled only into the batched kernels that a
+// frame with such views launches, so the others keep their register count).
+template <int B, int S, bool kCount, bool kSplit = false>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
     if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
     int* stk = stack + threadIdx.x;
-    if (!kCount && v.pt_split >= 0) {
+    if (kSplit && v.pt_split >= 0) {
         path_first_pass<B, S>(v, r, out, stk);
         return;
     }
@@ -679,7 +681,7 @@ __global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
 // order (nullable): per XCD, the dispatch order of its workgroups'
 // blocks (see k_trace_plan); cost (nullable): each block's duration in
 // 100 MHz ticks, the larger of its waves', kept for the next frame's plan.
-template <int B, int S, bool kCount>
+template <int B, int S, bool kCount, bool kSplit>
 __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters, const int32_t* __restrict__ order,
@@ -695,7 +697,7 @@ __global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    trace_item<B, S, kCount>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount, kSplit>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
     if (cost && (threadIdx.x & 63) == 0) {
         const uint64_t dt = wall_clock64() - t0;
         atomicMax(cost + b, (uint32_t)(dt < 0xffffffffull ? dt : 0xffffffffull));
@@ -761,13 +763,16 @@ void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsig
 }
 
 template <int B, int S>
-void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks,
+void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, bool split,
                   hipStream_t stream, unsigned long long* counters, const int32_t* order, uint32_t* cost) {
     if (counters)
-        hipLaunchKernelGGL((k_trace_batch<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views, block_end,
-                           n_views, counters, order, cost);
+        hipLaunchKernelGGL((k_trace_batch<B, S, true, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
+                           block_end, n_views, counters, order, cost);
+    else if (split)
+        hipLaunchKernelGGL((k_trace_batch<B, S, false, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
+                           block_end, n_views, counters, order, cost);
     else
-        hipLaunchKernelGGL((k_trace_batch<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
+        hipLaunchKernelGGL((k_trace_batch<B, S, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
                            block_end, n_views, counters, order, cost);
 }
 
@@ -781,17 +786,19 @@ void launch_single_s(const TraceView& v, int64_t blocks, int block, hipStream_t 
 
 template <int S>
 void launch_batch_s(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, int block,
-                    hipStream_t stream, unsigned long long* counters, const int32_t* order, uint32_t* cost) {
-    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
-    else if (block == 128) launch_batch<128, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
-    else launch_batch<256, S>(views, block_end, n_views, blocks, stream, counters, order, cost);
+                    bool split, hipStream_t stream, unsigned long long* counters, const int32_t* order,
+                    uint32_t* cost) {
+    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
+    else if (block == 128)
+        launch_batch<128, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
+    else launch_batch<256, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
 }
 
-template <int S>
+template <int S, bool kSplit>
 const void* batch_kernel_s(int block) {
-    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false>);
-    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false>);
-    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false>);
+    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false, kSplit>);
+    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false, kSplit>);
+    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false, kSplit>);
     return nullptr;
 }
 
@@ -820,23 +827,25 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
     return VAFR_OK;
 }
 
-const void* trace_batch_kernel(int block, int stack) {
-    if (stack == kStackShort) return batch_kernel_s<kStackShort>(block);
-    if (stack == kStackLong) return batch_kernel_s<kStackLong>(block);
+const void* trace_batch_kernel(int block, int stack, bool split) {
+    if (stack == kStackShort) return split ? batch_kernel_s<kStackShort, true>(block) : batch_kernel_s<kStackShort, false>(block);
+    if (stack == kStackLong) return split ? batch_kernel_s<kStackLong, true>(block) : batch_kernel_s<kStackLong, false>(block);
     return nullptr;
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, hipStream_t stream, unsigned long long* counters, const int32_t* order,
-                       uint32_t* cost) {
+                       int block, int stack, bool split, hipStream_t stream, unsigned long long* counters,
+                       const int32_t* order, uint32_t* cost) {
     if (blocks <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
     if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
     if (order && !trace_plan_ok(blocks)) return fail(VAFR_E_ARG, "too many blocks for a planned launch");
     if (stack == kStackShort)
-        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, stream, counters, order, cost);
+        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, split, stream, counters, order,
+                                    cost);
     else
-        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, stream, counters, order, cost);
+        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, split, stream, counters, order,
+                                   cost);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }
