@@ -233,6 +233,10 @@ def main():
         f"{rays_per_s / 1e9:.2f} Grays/s; reconstruct {recon_gbs:.0f} GB/s")
 
     out = {}
+    # two frames in flight: alternate batches on two streams with double
+    # buffers, so one frame's reconstruction overlaps the next one's
+    # traversal (throughput up, per-frame latency up)
+    out["pipelined"] = pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm, min(steps, 600))
     # ------------------------------------------------------------ comparisons
     if not args.no_compare:
         # full resolution: one primary + shadow ray per display pixel, per eye
@@ -358,6 +362,43 @@ def main():
     }
     result.update(out)
     print(json.dumps(result), flush=True)
+
+
+def pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm, steps):
+    """Binocular 8K frames with two in flight: frame f runs as one batched
+    frame on stream f mod 2, into its own LP buffers and display images, so
+    the GPU overlaps one frame's reconstruction (HBM-bound) with the next
+    frame's traversal (VALU-bound).  Reports frames/s over the whole run and
+    each frame's own duration (its events on its stream)."""
+    lp = [[torch.empty((L.n_texels, 4), device="cuda") for _ in range(2)] for _ in range(2)]
+    img = [[torch.empty((H * W, 4), device="cuda") for _ in range(2)] for _ in range(2)]
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    batches = [V.Batch(2, trace_block=128, recon_rows=8, use_graph=True) for _ in range(2)]
+
+    def frame(f, k, ev=None):
+        if ev is not None:
+            ev[0].record(streams[k])
+        batches[k].run([V.view(V.VAFR_VIEW_VAFR, scene, cams[e], gazes[f], sh, layout=L, lp_rgba=lp[k][e],
+                               img_rgba=img[k][e]) for e in range(2)], streams[k])
+        if ev is not None:
+            ev[1].record(streams[k])
+
+    for f in range(warm):
+        frame(f, f % 2)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for f in range(steps):
+        frame(warm + f, f % 2, ev[f])
+    torch.cuda.synchronize()
+    fps = steps / (time.perf_counter() - t0)
+    ms = [a.elapsed_time(b) for a, b in ev]
+    for b in batches:
+        b.close()
+    log(f"pipelined (two frames in flight): {fps:.1f} frames/s, frame p50 {percentile(ms, 50):.3f} ms "
+        f"p99 {percentile(ms, 99):.3f} ms")
+    return {"frames": steps, "fps": round(fps, 2), "p50_frame_ms": round(percentile(ms, 50), 4),
+            "p99_frame_ms": round(percentile(ms, 99), 4)}
 
 
 def batch16(torch, V, I, scene, sh, steps):
