@@ -613,6 +613,11 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_p) v.out_p[out] = p;
 }
 
+// Register budget of the traversal kernels: at most 102 VGPRs, i.e. five
+// waves per SIMD, which the loop needs to cover its memory latency (the
+// path-mode variants would otherwise take 113 and run 8% slower).
+#define kFiveWaves __attribute__((amdgpu_waves_per_eu(5)))
+
 // Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
 // permuted so that XCD q receives the q-th contiguous eighth of the items:
 // rays of one screen region then share their XCD's L2 for the BVH levels
@@ -668,7 +673,7 @@ __global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceVi
 // Workgroups keep their hardware order, so a short list still spreads over
 // every XCD.
 template <int B, int S>
-__global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
+__global__ __launch_bounds__(B) kFiveWaves void k_trace_list(const TraceView v) {
     __shared__ int stack[S * B];
     const int64_t q = (int64_t)blockIdx.x * B + threadIdx.x;
     if (q >= *v.item_count) return;
@@ -682,7 +687,7 @@ __global__ __launch_bounds__(B) void k_trace_list(const TraceView v) {
 // blocks (see k_trace_plan); cost (nullable): each block's duration in
 // 100 MHz ticks, the larger of its waves', kept for the next frame's plan.
 template <int B, int S, bool kCount, bool kSplit>
-__global__ __launch_bounds__(B) void k_trace_batch(const TraceView* __restrict__ views,
+__global__ __launch_bounds__(B) kFiveWaves void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters, const int32_t* __restrict__ order,
                                                    uint32_t* __restrict__ cost) {
