@@ -101,6 +101,13 @@ def _declare(L):
                                       _I32, _P, _P, _P]),
         "or_vafr_reconstruct": (None, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _P, _P, _I64, _P, _P, _P]),
         "or_lmfr_reconstruct": (None, [_I32, _I32, _D, _D, _I32, _I32, _D, _P, _P, _I64, _P, _P, _P]),
+        "or_lafr_consts": (C.c_int, [_I32, _I32, _P, _D, _D, _D, _D, _P]),
+        "or_lafr_u": (None, [_P, _D, _I64, _P, _P]),
+        "or_lafr_z": (None, [_P, _D, _I64, _P, _P]),
+        "or_lafr_rays": (C.c_int, [_I32, _I32, _P, _D, _D, _I32, _I32, _D, _D, _D, _P, _I64, _P, _P, _P]),
+        "or_lafr_forward": (C.c_int, [_I32, _I32, _P, _D, _D, _I32, _I32, _D, _D, _D, _I64, _P, _P, _P]),
+        "or_lafr_reconstruct": (C.c_int, [_I32, _I32, _P, _D, _D, _I32, _I32, _D, _D, _D, _P, _P, _I64, _P, _P,
+                                          _P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -303,6 +310,67 @@ def lmfr_forward(W, H, gx, gy, w, h, alpha, xy):
     return u, v
 
 
+# LaFR (Sec. 4.1 Eq. (15)): a is LMFR's kernel exponent in the
+# buffer-to-screen direction (1/4); alpha and beta as printed for LaFR.
+LAFR_A = 0.25
+LAFR_ALPHA = 0.85
+LAFR_BETA = 0.7
+
+
+def lafr_consts(W, H, p, gx, gy, a=LAFR_A, alpha=LAFR_ALPHA):
+    """(ln L, Z_ef, Fa, U_ef) of Eq. (15) for one gaze; raises ValueError
+    where the kernel is undefined."""
+    out = np.empty(4)
+    p = _arr(p, np.float64)
+    rc = lib().or_lafr_consts(int(W), int(H), _ptr(p), float(gx), float(gy), float(a), float(alpha), _ptr(out))
+    if rc:
+        raise ValueError(f"LaFR kernel undefined: Z_ef={out[1]!r}, Fa={out[2]!r}")
+    return out
+
+
+def lafr_u(consts, z, beta=LAFR_BETA):
+    """u / w of Eq. (15) at log ratios z."""
+    c = _arr(consts, np.float64)
+    z = _arr(z, np.float64)
+    u = np.empty(z.size)
+    lib().or_lafr_u(_ptr(c), float(beta), z.size, _ptr(z), _ptr(u))
+    return u
+
+
+def lafr_z(consts, t, beta=LAFR_BETA):
+    """Inverse of Eq. (15): log ratio z at normalised abscissae t = u / w."""
+    c = _arr(consts, np.float64)
+    t = _arr(t, np.float64)
+    z = np.empty(t.size)
+    lib().or_lafr_z(_ptr(c), float(beta), t.size, _ptr(t), _ptr(z))
+    return z
+
+
+def lafr_rays(W, H, p, gx, gy, w, h, idx, cam, a=LAFR_A, alpha=LAFR_ALPHA, beta=LAFR_BETA):
+    idx = _arr(idx, np.int64)
+    org = np.empty((idx.size, 3), np.float32)
+    d = np.empty((idx.size, 3), np.float32)
+    p = _arr(p, np.float64)
+    c = _cam(cam)
+    rc = lib().or_lafr_rays(int(W), int(H), _ptr(p), float(gx), float(gy), int(w), int(h), float(a), float(alpha),
+                            float(beta), _ptr(idx), idx.size, _ptr(c), _ptr(org), _ptr(d))
+    if rc:
+        raise ValueError("LaFR kernel undefined for this display and gaze")
+    return org, d
+
+
+def lafr_forward(W, H, p, gx, gy, w, h, xy, a=LAFR_A, alpha=LAFR_ALPHA, beta=LAFR_BETA):
+    xy = _arr(xy, np.float64).reshape(-1, 2)
+    u = np.empty(xy.shape[0])
+    v = np.empty(xy.shape[0])
+    p = _arr(p, np.float64)
+    rc = lib().or_lafr_forward(int(W), int(H), _ptr(p), float(gx), float(gy), int(w), int(h), float(a),
+                               float(alpha), float(beta), xy.shape[0], _ptr(xy), _ptr(u), _ptr(v))
+    if rc:
+        raise ValueError("LaFR kernel undefined for this display and gaze")
+    return u, v
+
+
 def watertight_many(org, d, tri9):
     org = _arr(org, np.float32).reshape(-1, 3)
     d = _arr(d, np.float32).reshape(-1, 3)
@@ -444,6 +512,22 @@ def lmfr_reconstruct(W, H, gx, gy, w, h, alpha, lp, pix, tflag=None):
     return out, pf.astype(bool)
 
 
+def lafr_reconstruct(W, H, p, gx, gy, w, h, lp, pix, tflag=None, a=LAFR_A, alpha=LAFR_ALPHA, beta=LAFR_BETA):
+    lp = _arr(lp, np.float32).reshape(-1, 4)
+    assert lp.shape[0] == w * h
+    pix = _arr(pix, np.int64)
+    out = np.empty((pix.size, 4), np.float32)
+    pf = np.empty(pix.size, np.uint8)
+    tf = None if tflag is None else _arr(tflag, np.uint8)
+    p = _arr(p, np.float64)
+    rc = lib().or_lafr_reconstruct(int(W), int(H), _ptr(p), float(gx), float(gy), int(w), int(h), float(a),
+                                   float(alpha), float(beta), _ptr(lp), _ptr(pix), pix.size, _ptr(out), _ptr(tf),
+                                   _ptr(pf))
+    if rc:
+        raise ValueError("LaFR kernel undefined for this display and gaze")
+    return out, pf.astype(bool)
+
+
 # --------------------------------------------------------------------------
 # Whole-step helpers (shade an LP buffer / a display) used by tests & bench
 # --------------------------------------------------------------------------
@@ -464,6 +548,13 @@ def shade_full_pixels(scene: Scene, pix, W, H, fov, cam, sh):
 def shade_lmfr_texels(scene: Scene, idx, W, H, fov, gaze, w, h, alpha, cam, sh):
     p = film_pitch(W, H, *fov)
     org, d = lmfr_rays(W, H, p, gaze[0], gaze[1], w, h, alpha, idx, cam)
+    return scene.shade(org, d, sh)
+
+
+def shade_lafr_texels(scene: Scene, idx, W, H, fov, gaze, w, h, cam, sh, a=LAFR_A, alpha=LAFR_ALPHA,
+                      beta=LAFR_BETA):
+    p = film_pitch(W, H, *fov)
+    org, d = lafr_rays(W, H, p, gaze[0], gaze[1], w, h, idx, cam, a, alpha, beta)
     return scene.shade(org, d, sh)
 
 

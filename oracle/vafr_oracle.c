@@ -4,8 +4,8 @@
  * A plain, slow CPU reference for the VaFR hot path: the acuity-derived
  * log-polar (LP) layout, one primary ray per LP texel, closest hit against a
  * triangle soup, Lambert shading with one shadow ray, and the inverse map of
- * the LP buffer onto display pixels.  It also covers the LMFR log-polar
- * comparison mapping and the full-resolution ray cast.
+ * the LP buffer onto display pixels.  It also covers the LMFR and LaFR
+ * log-polar comparison mappings and the full-resolution ray cast.
  *
  * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
  * may load this library.  The product path never calls it, and it shares no
@@ -461,6 +461,118 @@ void or_lmfr_forward(int32_t W, int32_t H, double gx, double gy, int32_t w, int3
         u[q] = pow(z, alpha) * w;
         v[q] = th / 360.0 * h;
     }
+}
+
+/* ------------------------------------------------------------------------ */
+/* LaFR log-polar comparison mapping: Sec. 4.1 Eq. (15), Eq. (17)            */
+/* ------------------------------------------------------------------------ */
+
+/* Foveal boundary of the LaFR kernel (Sec. 4.1, Eq. (15)), degrees. */
+#define OR_LAFR_FOVEAL_DEG 4.89
+
+/*
+ * Constants of Eq. (15) for one gaze, written to out[4] = {ln L, Z_ef, Fa,
+ * U_ef}:
+ *  - ln L as in Eq. (1) (or_lmfr_L);
+ *  - z(e) = ln(tan e / c_r) / ln L with c_r the film pitch of one pixel
+ *    (p[1]), so Z_ef = z(4.89 deg);
+ *  - Fa = 1 - log_{Z_ef}((alpha Z_ef)^(1 - a) / (1 - a));
+ *  - U_ef = (Z_ef (1 - Fa))^(1 / Fa).
+ * Reading: the paper equates LaFR's a with LMFR's kernel exponent; the
+ * printed Fa has a real value only for a < 1, so a is that exponent in the
+ * buffer-to-screen direction (z = (u/w)^(1/4) for LMFR's z^4), i.e. 1/4.
+ * Returns 0, or -1 when Z_ef or Fa lies outside (0, 1) (the kernel is then
+ * undefined).
+ */
+int or_lafr_consts(int32_t W, int32_t H, const double* p, double gx, double gy, double a, double alpha,
+                   double* out) {
+    double lnL = or_lmfr_L(W, H, gx, gy);
+    double r_ef = tan(OR_LAFR_FOVEAL_DEG * OR_DEG) / p[1];
+    double Zef = log(r_ef) / lnL;
+    double Fa = 1.0 - log(pow(alpha * Zef, 1.0 - a) / (1.0 - a)) / log(Zef);
+    double Uef = pow(Zef * (1.0 - Fa), 1.0 / Fa);
+    out[0] = lnL;
+    out[1] = Zef;
+    out[2] = Fa;
+    out[3] = Uef;
+    if (!(lnL > 0.0) || !(Zef > 0.0 && Zef < 1.0) || !(Fa > 0.0 && Fa < 1.0)) return -1;
+    return 0;
+}
+
+/* Eq. (15): u / w at log ratio z in [0, 1], for constants c of
+ * or_lafr_consts.  The first piece covers e <= 4.89 deg (z <= Z_ef), the
+ * second the rest of the screen. */
+static double lafr_u(const double* c, double beta, double z) {
+    double Zef = c[1], Fa = c[2], Uef = c[3];
+    if (z <= Zef) return pow(z * (1.0 - Fa), 1.0 / Fa);
+    double Za = (1.0 / z - 1.0 / Zef) / (1.0 / Zef - 1.0);
+    if (Za < -1.0) Za = -1.0;
+    return pow((2.0 * acos(Za) - M_PI) / M_PI, beta / 0.7) * (1.0 - Uef) + Uef;
+}
+
+/* Inverse of Eq. (15): the log ratio z at which u / w = t (0 < t < 1).
+ * First piece: z = t^Fa / (1 - Fa).  Second piece: s = ((t - U_ef) /
+ * (1 - U_ef))^(0.7 / beta) is (2 acos(Za) - pi) / pi, so Za =
+ * cos(pi (s + 1) / 2), and 1/z = 1/Z_ef + Za (1/Z_ef - 1). */
+static double lafr_z(const double* c, double beta, double t) {
+    double Zef = c[1], Fa = c[2], Uef = c[3];
+    if (t <= Uef) return pow(t, Fa) / (1.0 - Fa);
+    double s = pow((t - Uef) / (1.0 - Uef), 0.7 / beta);
+    double Za = cos(0.5 * M_PI * (s + 1.0));
+    return 1.0 / (1.0 / Zef + Za * (1.0 / Zef - 1.0));
+}
+
+void or_lafr_u(const double* c, double beta, int64_t n, const double* z, double* u) {
+    for (int64_t q = 0; q < n; ++q) u[q] = lafr_u(c, beta, z[q]);
+}
+
+void or_lafr_z(const double* c, double beta, int64_t n, const double* t, double* z) {
+    for (int64_t q = 0; q < n; ++q) z[q] = lafr_z(c, beta, t[q]);
+}
+
+/*
+ * LaFR rays: texel (i, j) of the w x h buffer (k = i h + j) sits at
+ * z = lafr_z((i + 1/2)/w), pixel radius r = exp(z ln L) and polar angle
+ * theta = 360 (j + 1/2)/h from the gaze, through P = G + (r cos theta px,
+ * r sin theta py).  Returns or_lafr_consts' status.
+ */
+int or_lafr_rays(int32_t W, int32_t H, const double* p, double gx, double gy, int32_t w, int32_t h, double a,
+                 double alpha, double beta, const int64_t* idx, int64_t n, const float* cam, float* org,
+                 float* dir) {
+    double c[4];
+    if (or_lafr_consts(W, H, p, gx, gy, a, alpha, c)) return -1;
+    double G[2];
+    or_gaze_film(W, H, p, gx, gy, G);
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t k = idx[q];
+        int64_t i = k / h, j = k % h;
+        double z = lafr_z(c, beta, (i + 0.5) / w);
+        double r = exp(c[0] * z);
+        double th = 360.0 * (j + 0.5) / h;
+        double Px = G[0] + (r * cos(th * OR_DEG)) * p[0];
+        double Py = G[1] + (r * sin(th * OR_DEG)) * p[1];
+        make_ray(cam, Px, Py, org + 3 * q, dir + 3 * q);
+    }
+    return 0;
+}
+
+/* Forward map of Eq. (15) for continuous pixel points (radius clamped to
+ * >= 1 pixel so that z >= 0): u in columns, v in rows. */
+int or_lafr_forward(int32_t W, int32_t H, const double* p, double gx, double gy, int32_t w, int32_t h, double a,
+                    double alpha, double beta, int64_t n, const double* xy, double* u, double* v) {
+    double c[4];
+    if (or_lafr_consts(W, H, p, gx, gy, a, alpha, c)) return -1;
+    for (int64_t q = 0; q < n; ++q) {
+        double dx = xy[2 * q] - gx, dy = xy[2 * q + 1] - gy;
+        double r = sqrt(dx * dx + dy * dy);
+        if (r < 1.0) r = 1.0;
+        double z = log(r) / c[0];
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        u[q] = lafr_u(c, beta, z) * w;
+        v[q] = th / 360.0 * h;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1157,6 +1269,37 @@ void or_vafr_reconstruct(const or_acuity* a, int32_t n_cols, const int32_t* n_ro
 }
 
 /*
+ * Bilinear sample of a dense w x h log-polar buffer (k = i h + j) at column
+ * coordinate u and row coordinate v (texel centres at + 1/2): u clamped to
+ * the first / last column centre, v wrapping.  fl is set when one of the
+ * four texels is flagged in tflag.
+ */
+static void dense_sample(int32_t w, int32_t h, const float* lp, double u, double v, const uint8_t* tflag,
+                         float* out, uint8_t* fl) {
+    if (u < 0.5) u = 0.5;
+    if (u > w - 0.5) u = w - 0.5;
+    double ac = u - 0.5;
+    int64_t i0 = (int64_t)floor(ac);
+    if (i0 > w - 1) i0 = w - 1;
+    int64_t i1 = i0 + 1 < w ? i0 + 1 : w - 1;
+    double wc = ac - (double)i0;
+    double s = v - 0.5;
+    double fs = floor(s);
+    double tt = s - fs;
+    int64_t j0 = (int64_t)fmod_pos(fs, (double)h);
+    int64_t j1 = (j0 + 1) % h;
+    double acc[4] = {0, 0, 0, 0};
+    *fl = 0;
+    int64_t ks[4] = {i0 * h + j0, i0 * h + j1, i1 * h + j0, i1 * h + j1};
+    double ws[4] = {(1 - wc) * (1 - tt), (1 - wc) * tt, wc * (1 - tt), wc * tt};
+    for (int c = 0; c < 4; ++c) {
+        for (int ch = 0; ch < 4; ++ch) acc[ch] += ws[c] * (double)lp[4 * ks[c] + ch];
+        if (tflag && tflag[ks[c]]) *fl = 1;
+    }
+    for (int ch = 0; ch < 4; ++ch) out[ch] = (float)acc[ch];
+}
+
+/*
  * LMFR reconstruction: the pixel centre maps through Eq. (1) with K(z) =
  * z^alpha to (u, v); the dense w x h buffer is sampled bilinearly at
  * (u - 1/2, v - 1/2), clamped in u and wrapped in v.
@@ -1174,31 +1317,33 @@ void or_lmfr_reconstruct(int32_t W, int32_t H, double gx, double gy, int32_t w, 
         double z = log(r) / L;
         double th = atan2(dy, dx) / OR_DEG;
         if (th < 0.0) th += 360.0;
-        double u = pow(z, alpha) * w;
-        double v = th / 360.0 * h;
-        if (u < 0.5) u = 0.5;
-        if (u > w - 0.5) u = w - 0.5;
-        double ac = u - 0.5;
-        int64_t i0 = (int64_t)floor(ac);
-        if (i0 > w - 1) i0 = w - 1;
-        int64_t i1 = i0 + 1 < w ? i0 + 1 : w - 1;
-        double wc = ac - (double)i0;
-        double s = v - 0.5;
-        double fs = floor(s);
-        double tt = s - fs;
-        int64_t j0 = (int64_t)fmod_pos(fs, (double)h);
-        int64_t j1 = (j0 + 1) % h;
-        double acc[4] = {0, 0, 0, 0};
-        uint8_t fl = 0;
-        int64_t ks[4] = {i0 * h + j0, i0 * h + j1, i1 * h + j0, i1 * h + j1};
-        double ws[4] = {(1 - wc) * (1 - tt), (1 - wc) * tt, wc * (1 - tt), wc * tt};
-        for (int c = 0; c < 4; ++c) {
-            for (int ch = 0; ch < 4; ++ch) acc[ch] += ws[c] * (double)lp[4 * ks[c] + ch];
-            if (tflag && tflag[ks[c]]) fl = 1;
-        }
-        for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = (float)acc[ch];
+        uint8_t fl;
+        dense_sample(w, h, lp, pow(z, alpha) * w, th / 360.0 * h, tflag, out + 4 * q, &fl);
         if (pflag) pflag[q] = fl;
     }
+}
+
+/* LaFR reconstruction: as LMFR with the map of Eq. (15).  Returns
+ * or_lafr_consts' status. */
+int or_lafr_reconstruct(int32_t W, int32_t H, const double* p, double gx, double gy, int32_t w, int32_t h,
+                        double a, double alpha, double beta, const float* lp, const int64_t* pix, int64_t n,
+                        float* out, const uint8_t* tflag, uint8_t* pflag) {
+    double c[4];
+    if (or_lafr_consts(W, H, p, gx, gy, a, alpha, c)) return -1;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t x = pix[q] % W, y = pix[q] / W;
+        double dx = (double)x + 0.5 - gx, dy = (double)y + 0.5 - gy;
+        double r = sqrt(dx * dx + dy * dy);
+        if (r < 1.0) r = 1.0;
+        double z = log(r) / c[0];
+        double th = atan2(dy, dx) / OR_DEG;
+        if (th < 0.0) th += 360.0;
+        uint8_t fl;
+        dense_sample(w, h, lp, lafr_u(c, beta, z) * w, th / 360.0 * h, tflag, out + 4 * q, &fl);
+        if (pflag) pflag[q] = fl;
+    }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
