@@ -5,8 +5,8 @@ One step = one binocular frame at 7680 x 4320 per eye (100 x 100 degree field
 of view): for each eye, shade the constant-size LP buffer (one primary ray and
 one shadow ray per texel against a 4,521,984-triangle scene) and inverse-map it
 onto the display.  The gaze of frame f comes from a seeded fixation/saccade
-trace.  The same GPU also runs the full-resolution ray cast and the LMFR(1.8)
-mapping for the speed-ups.  Inputs are synthetic and already resident in HBM
+trace.  The same GPU also runs the full-resolution ray cast and the LMFR(1.8),
+LaFR(1.8) and LaFR(2.2) mappings for the speed-ups.  Inputs are synthetic and already resident in HBM
 when timing starts.
 
 Prints ONE JSON line (rank 0).
@@ -258,34 +258,46 @@ def main():
         full_fps = csteps / (time.perf_counter() - t0)
         full_ms = [ev[0].elapsed_time(ev[1]) for ev in fev]
         log(f"full resolution: {full_fps:.2f} frames/s (frame {np.mean(full_ms):.2f} ms)")
-        # LMFR(1.8)
-        lpl = torch.empty((LM.n_texels, 4), device="cuda", dtype=torch.float32)
+        # dense log-polar comparisons: LMFR(1.8), LaFR(1.8), LaFR(2.2)
+        def dense_fps(layout, shade, recon):
+            lpl = torch.empty((layout.n_texels, 4), device="cuda", dtype=torch.float32)
 
-        def lmfr_frame(f, ev=None):
-            g = gazes[warm + f]
-            if ev is not None:
-                ev[0].record(stream)
-            for e in range(2):
-                V.lmfr_shade_lp(scene, cams[e], g, sh, LM, lpl, None, stream)
-                V.lmfr_reconstruct(LM, g, lpl, img[e], stream)
-            if ev is not None:
-                ev[1].record(stream)
+            def frame(f, ev=None):
+                g = gazes[warm + f]
+                if ev is not None:
+                    ev[0].record(stream)
+                for e in range(2):
+                    shade(scene, cams[e], g, sh, layout, lpl, None, stream)
+                    recon(layout, g, lpl, img[e], stream)
+                if ev is not None:
+                    ev[1].record(stream)
 
-        lmfr_frame(0)
-        torch.cuda.synchronize()
-        lev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(csteps)]
-        t0 = time.perf_counter()
-        for f in range(csteps):
-            lmfr_frame(f, lev[f])
-        torch.cuda.synchronize()
-        lmfr_fps = csteps / (time.perf_counter() - t0)
-        lmfr_ms = [ev[0].elapsed_time(ev[1]) for ev in lev]
-        log(f"LMFR(1.8): {lmfr_fps:.2f} frames/s (frame {np.mean(lmfr_ms):.2f} ms)")
-        del lpl
+            frame(0)
+            torch.cuda.synchronize()
+            evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(csteps)]
+            t0 = time.perf_counter()
+            for f in range(csteps):
+                frame(f, evs[f])
+            torch.cuda.synchronize()
+            rate = csteps / (time.perf_counter() - t0)
+            return rate, float(np.mean([ev[0].elapsed_time(ev[1]) for ev in evs]))
+
+        lmfr_fps, lmfr_ms = dense_fps(LM, V.lmfr_shade_lp, V.lmfr_reconstruct)
+        log(f"LMFR(1.8): {lmfr_fps:.2f} frames/s (frame {lmfr_ms:.2f} ms)")
+        lafr = {}
+        for delta in (1.8, 2.2):
+            LA = V.Layout.lafr(disp, delta)
+            rate, ms = dense_fps(LA, V.lafr_shade_lp, V.lafr_reconstruct)
+            log(f"LaFR({delta}): {rate:.2f} frames/s (frame {ms:.2f} ms), {LA.n_texels} texels per eye")
+            lafr[str(delta)] = {"fps": round(rate, 3), "frame_ms": round(ms, 3), "texels_per_eye": LA.n_texels,
+                                "speedup": round(fps / rate, 2)}
+            LA.close()
+        out["lafr"] = lafr
         out.update({
             "fullres_fps": round(full_fps, 3), "fullres_frame_ms": round(float(np.mean(full_ms)), 3),
-            "lmfr_fps": round(lmfr_fps, 3), "lmfr_frame_ms": round(float(np.mean(lmfr_ms)), 3),
+            "lmfr_fps": round(lmfr_fps, 3), "lmfr_frame_ms": round(lmfr_ms, 3),
             "speedup_vs_fullres": round(fps / full_fps, 2), "speedup_vs_lmfr": round(fps / lmfr_fps, 2),
+            "speedup_vs_lafr": lafr["1.8"]["speedup"],
             "fullres_grays_per_s": round(2 * 2 * W * H * full_fps / 1e9, 3),
         })
 

@@ -6,8 +6,9 @@
  * 2503.23410): a constant-size log-polar (LP) buffer whose radial axis and
  * shading rate follow the acuity model (Sec. 3.2, 3.3) is shaded with one
  * ray-cast sample per texel (Sec. 6.1) and inverse-mapped onto every display
- * pixel (Sec. 3.2.3).  The LMFR log-polar mapping (Sec. 3.1 Eq. (1), Sec. 4.1
- * Eq. (14)) and a full-resolution ray cast are the same-GPU comparisons.
+ * pixel (Sec. 3.2.3).  The LMFR and LaFR log-polar mappings (Sec. 3.1
+ * Eq. (1), Sec. 4.1 Eq. (14), Eq. (15)) and a full-resolution ray cast are
+ * the same-GPU comparisons.
  *
  * Conventions
  *  - Every call returns int: VAFR_OK (0) or a negative VAFR_E_* code; the
@@ -128,12 +129,13 @@ typedef struct {
 
 #define VAFR_LAYOUT_VAFR 0
 #define VAFR_LAYOUT_LMFR 1
+#define VAFR_LAYOUT_LAFR 2
 
 /* Layout dimensions.  VaFR: n_cols columns of n_rows[i] texels stored
  * column-major and packed (texel k of column i is col_off[i] + j);
- * LMFR: a dense n_cols x max_rows buffer, k = i * max_rows + j. */
+ * LMFR / LaFR: a dense n_cols x max_rows buffer, k = i * max_rows + j. */
 typedef struct {
-    int32_t kind;          /* VAFR_LAYOUT_VAFR or VAFR_LAYOUT_LMFR */
+    int32_t kind;          /* VAFR_LAYOUT_VAFR, VAFR_LAYOUT_LMFR or VAFR_LAYOUT_LAFR */
     int32_t n_cols;
     int32_t max_rows;
     int32_t width, height; /* display the layout was made for */
@@ -162,11 +164,28 @@ int vafr_lp_layout(const vafr_display* display, const vafr_acuity* acuity, vafr_
  * delta >= 1, alpha > 0. */
 int lmfr_lp_layout(const vafr_display* display, double delta, double alpha, vafr_layout* out);
 
+/* LaFR comparison layout (Sec. 4.1 Eq. (15), Sec. 4.5, Sec. 5.2): the same
+ * round(W/delta) x round(H/delta) buffer as LMFR, with the two-piece LaFR
+ * kernel.  Columns at u/w <= U_ef hold z = (u/w)^Fa / (1 - Fa) (eccentricity
+ * up to 4.89 deg); the rest follow the arccos piece with exponent beta/0.7,
+ * reaching z = 1 at the last column edge.  Per gaze, with ln L as for LMFR
+ * and c_r the film pitch of one pixel:
+ *   Z_ef = ln(tan 4.89 deg / c_r) / ln L,
+ *   Fa   = 1 - log_{Z_ef}((alpha Z_ef)^(1 - a) / (1 - a)),
+ *   U_ef = (Z_ef (1 - Fa))^(1 / Fa).
+ * a is LMFR's kernel exponent in the buffer-to-screen direction (1/4 for
+ * LMFR's z^4); LaFR's own parameters are alpha = 0.85, beta = 0.7.
+ * delta >= 1, 0 < a < 1, 0 < alpha <= 1, 0 < beta <= 16.  The shading and
+ * reconstruction calls fail with VAFR_E_ARG for a gaze at which Z_ef or Fa
+ * leaves (0, 1). */
+int lafr_lp_layout(const vafr_display* display, double delta, double a, double alpha, double beta,
+                   vafr_layout* out);
+
 int vafr_layout_dims(vafr_layout layout, vafr_dims* out);
 
 /* Host views of the layout tables (valid until vafr_layout_destroy):
  * n_rows[n_cols], col_off[n_cols + 1], texel_dxy[2 * n_texels] (VaFR only;
- * NULL for LMFR).  These are the bit-exact contract of the layout. */
+ * NULL for LMFR / LaFR).  These are the bit-exact contract of the layout. */
 int vafr_layout_tables(vafr_layout layout, const int32_t** n_rows, const int64_t** col_off,
                        const float** texel_dxy);
 
@@ -213,11 +232,15 @@ void vafr_scene_destroy(vafr_scene scene);
  * with the FP32 watertight test (ties broken by the smaller triangle id),
  * then the shading model.  lp_rgba_dev[4 * n_texels]; hit_id_dev[n_texels]
  * (nullable) receives the primary hit triangle id or -1.  Works with a VaFR
- * layout; lmfr_shade_lp is the same call for an LMFR layout. */
+ * layout; lmfr_shade_lp and lafr_shade_lp are the same call for an LMFR and
+ * a LaFR layout. */
 int vafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
                   vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
 
 int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
+                  vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
+
+int lafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* shading,
                   vafr_layout layout, float* lp_rgba_dev, int32_t* hit_id_dev, hipStream_t stream);
 
 /* Anti-aliasing inside the LP buffer (Sec. 3.4: FXAA on the LP buffer before
@@ -278,6 +301,11 @@ int vafr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_de
 int lmfr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_dev, float* img_rgba_dev,
                      hipStream_t stream);
 
+/* LaFR inverse map: Eq. (15) forward (pixel radius clamped to >= 1 pixel),
+ * then the same bilinear sampling as lmfr_reconstruct. */
+int lafr_reconstruct(vafr_layout layout, vafr_gaze gaze, const float* lp_rgba_dev, float* img_rgba_dev,
+                     hipStream_t stream);
+
 /* Full-resolution ray cast (Sec. 5.2 "GT"): one ray per display pixel
  * centre, shaded as vafr_shade_lp, written to img_rgba_dev[4 * W * H];
  * hit_id_dev[W * H] nullable. */
@@ -289,8 +317,9 @@ int full_shade(vafr_scene scene, const vafr_camera* cam, const vafr_display* dis
 #define VAFR_VIEW_VAFR 0
 #define VAFR_VIEW_LMFR 1
 #define VAFR_VIEW_FULL 2
+#define VAFR_VIEW_LAFR 3
 
-/* One view of a batched frame.  VAFR / LMFR views shade layout's LP buffer
+/* One view of a batched frame.  VAFR / LMFR / LAFR views shade layout's LP buffer
  * into lp_rgba_dev and, when img_rgba_dev is not NULL, inverse-map it onto
  * the layout's display; FULL views ray-cast every pixel of `display` into
  * img_rgba_dev.  Same buffer contracts as the per-view calls. */
@@ -298,14 +327,14 @@ typedef struct {
     int32_t kind;            /* VAFR_VIEW_* */
     int32_t pad_;
     vafr_scene scene;
-    vafr_layout layout;      /* VAFR / LMFR views; NULL for FULL */
+    vafr_layout layout;      /* VAFR / LMFR / LAFR views; NULL for FULL */
     vafr_display display;    /* FULL views only */
     vafr_camera camera;
     vafr_gaze gaze;
     vafr_shading shading;
-    float* lp_rgba_dev;      /* VAFR / LMFR views */
+    float* lp_rgba_dev;      /* VAFR / LMFR / LAFR views */
     int32_t* hit_id_dev;     /* nullable */
-    float* img_rgba_dev;     /* nullable for LP-only VAFR / LMFR views */
+    float* img_rgba_dev;     /* nullable for LP-only VAFR / LMFR / LAFR views */
 } vafr_view;
 
 /* Launch shape of a batch: traversal workgroup size (64, 128 or 256 rays),

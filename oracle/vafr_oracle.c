@@ -24,7 +24,10 @@
  * Parity pins: each function below is pinned by a test in tests/ against a
  * value the paper prints, a closed form, an invariant or brute force; the
  * path-tracing shading mode is the one part whose colour values are pinned
- * only by closed-form special cases (see or_shade_path_rays).
+ * only by closed-form special cases (see or_shade_path_rays).  The value of
+ * the LaFR constant Fa (or_lafr_consts) rests on a reading of a garbled
+ * formula and is parity unpinned; the rest of the LaFR map is pinned
+ * through the shading rates the paper prints for it.
  */
 #include <math.h>
 #include <stdint.h>

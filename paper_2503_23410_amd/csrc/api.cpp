@@ -119,8 +119,30 @@ static double lmfr_log_extent(const vafr_layout_s* L, vafr_gaze g) {
     return std::log(best);
 }
 
-// kind: VAFR_LAYOUT_VAFR / VAFR_LAYOUT_LMFR (layout given) or -1 for the
-// full-resolution view of `disp`.
+// LaFR kernel constants at one gaze (Sec. 4.1 Eq. (15)): Z_ef = z(4.89 deg)
+// with z(e) = ln(tan e / c_r) / ln L and c_r the vertical film pitch of a
+// pixel; Fa = 1 - log_{Z_ef}((alpha Z_ef)^(1-a) / (1-a)); U_ef =
+// (Z_ef (1 - Fa))^(1/Fa).  FP64.
+struct LafrConsts {
+    double lnL, zef, fa, uef;
+};
+
+static int lafr_consts(const vafr_layout_s* L, vafr_gaze g, LafrConsts* c) {
+    constexpr double kFovealDeg = 4.89;
+    c->lnL = lmfr_log_extent(L, g);
+    if (!(c->lnL > 0.0)) return fail(VAFR_E_ARG, "display too small for the LaFR map");
+    c->zef = std::log(std::tan(kFovealDeg * M_PI / 180.0) / L->py) / c->lnL;
+    if (!(c->zef > 0.0 && c->zef < 1.0))
+        return fail(VAFR_E_ARG, "LaFR foveal boundary outside the screen at this gaze (Z_ef = %g)", c->zef);
+    const double a = L->lf_a;
+    c->fa = 1.0 - std::log(std::pow(L->alpha * c->zef, 1.0 - a) / (1.0 - a)) / std::log(c->zef);
+    if (!(c->fa > 0.0 && c->fa < 1.0)) return fail(VAFR_E_ARG, "LaFR kernel undefined at this gaze (Fa = %g)", c->fa);
+    c->uef = std::pow(c->zef * (1.0 - c->fa), 1.0 / c->fa);
+    return VAFR_OK;
+}
+
+// kind: VAFR_LAYOUT_VAFR / VAFR_LAYOUT_LMFR / VAFR_LAYOUT_LAFR (layout
+// given) or -1 for the full-resolution view of `disp`.
 int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
                     vafr_layout L, const vafr_display* disp, float* out_rgba, int32_t* hit, TraceView* out) {
     if (int rc = check_camera(cam)) return rc;
@@ -137,8 +159,9 @@ int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaz
     } else {
         if (!L) return fail(VAFR_E_ARG, "layout is NULL");
         if (L->kind != kind)
-            return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR ? "vafr_shade_lp needs a VaFR layout"
-                                                             : "lmfr_shade_lp needs an LMFR layout");
+            return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR   ? "vafr_shade_lp needs a VaFR layout"
+                                    : kind == VAFR_LAYOUT_LMFR ? "lmfr_shade_lp needs an LMFR layout"
+                                                               : "lafr_shade_lp needs a LaFR layout");
         if (int rc = check_gaze(gaze)) return rc;
     }
     if (int rc = scene_into_view(scene, &v)) return rc;
@@ -169,6 +192,16 @@ int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaz
             v.lm_h = L->max_rows;
             v.lm_L = lmfr_log_extent(L, gaze);
             if (!(v.lm_L > 0.0)) return fail(VAFR_E_ARG, "display too small for the LMFR map");
+            if (kind == VAFR_LAYOUT_LAFR) {
+                LafrConsts c;
+                if (int rc = lafr_consts(L, gaze, &c)) return rc;
+                v.lf_on = 1;
+                v.lf_fa = c.fa;
+                v.lf_uef = c.uef;
+                v.lf_sexp = 0.7 / L->lf_beta;
+                v.lf_zef_inv = 1.0 / c.zef;
+                v.lf_k = 1.0 / c.zef - 1.0;
+            }
         }
     }
     v.out_rgba = reinterpret_cast<float4*>(out_rgba);
@@ -217,6 +250,18 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
         r.cy = (float)(0.5 - gaze.y_px);
         r.inv_L = (float)(M_LN2 / Lg);
         r.alpha = (float)L->alpha;
+        if (L->kind == VAFR_LAYOUT_LAFR) {
+            LafrConsts c;
+            if (int rc = lafr_consts(L, gaze, &c)) return rc;
+            r.lf_on = 1;
+            r.lf_zef = (float)c.zef;
+            r.lf_fa1 = (float)(1.0 - c.fa);
+            r.lf_inv_fa = (float)(1.0 / c.fa);
+            r.lf_zef_inv = (float)(1.0 / c.zef);
+            r.lf_inv_k = (float)(1.0 / (1.0 / c.zef - 1.0));
+            r.lf_uef = (float)c.uef;
+            r.lf_bexp = (float)(L->lf_beta / 0.7);
+        }
     }
     *out = r;
     return VAFR_OK;
@@ -322,11 +367,20 @@ extern "C" int lmfr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze
     return launch_trace(v, stream);
 }
 
+extern "C" int lafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, const vafr_shading* sh,
+                             vafr_layout L, float* lp, int32_t* hit, hipStream_t stream) {
+    if (!lp) return fail(VAFR_E_ARG, "lp_rgba_dev is NULL");
+    TraceView v;
+    if (int rc = make_trace_view(VAFR_LAYOUT_LAFR, scene, cam, gaze, sh, L, nullptr, lp, hit, &v)) return rc;
+    return launch_trace(v, stream);
+}
+
 static int reconstruct_kind(int kind, vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
     if (!L) return fail(VAFR_E_ARG, "layout is NULL");
     if (L->kind != kind)
-        return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR ? "vafr_reconstruct needs a VaFR layout"
-                                                         : "lmfr_reconstruct needs an LMFR layout");
+        return fail(VAFR_E_ARG, kind == VAFR_LAYOUT_VAFR   ? "vafr_reconstruct needs a VaFR layout"
+                                : kind == VAFR_LAYOUT_LMFR ? "lmfr_reconstruct needs an LMFR layout"
+                                                           : "lafr_reconstruct needs a LaFR layout");
     ReconView r;
     if (int rc = make_recon_view(L, gaze, lp, img, &r)) return rc;
     return launch_reconstruct(r, stream);
@@ -338,6 +392,10 @@ extern "C" int vafr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, 
 
 extern "C" int lmfr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
     return reconstruct_kind(VAFR_LAYOUT_LMFR, L, gaze, lp, img, stream);
+}
+
+extern "C" int lafr_reconstruct(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, hipStream_t stream) {
+    return reconstruct_kind(VAFR_LAYOUT_LAFR, L, gaze, lp, img, stream);
 }
 
 extern "C" int vafr_rep_workspace_bytes(vafr_layout L, int64_t* bytes) {

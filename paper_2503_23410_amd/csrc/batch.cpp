@@ -119,9 +119,11 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
             if (!w.img_rgba_dev) return fail(VAFR_E_ARG, "view %d: img_rgba_dev is NULL", i);
             rc = make_trace_view(-1, w.scene, &w.camera, w.gaze, &w.shading, nullptr, &w.display, w.img_rgba_dev,
                                  w.hit_id_dev, &t);
-        } else if (w.kind == VAFR_VIEW_VAFR || w.kind == VAFR_VIEW_LMFR) {
+        } else if (w.kind == VAFR_VIEW_VAFR || w.kind == VAFR_VIEW_LMFR || w.kind == VAFR_VIEW_LAFR) {
             if (!w.lp_rgba_dev) return fail(VAFR_E_ARG, "view %d: lp_rgba_dev is NULL", i);
-            rc = make_trace_view(w.kind == VAFR_VIEW_VAFR ? VAFR_LAYOUT_VAFR : VAFR_LAYOUT_LMFR, w.scene, &w.camera,
+            const int lk = w.kind == VAFR_VIEW_VAFR ? VAFR_LAYOUT_VAFR
+                         : w.kind == VAFR_VIEW_LMFR ? VAFR_LAYOUT_LMFR : VAFR_LAYOUT_LAFR;
+            rc = make_trace_view(lk, w.scene, &w.camera,
                                  w.gaze, &w.shading, w.layout, nullptr, w.lp_rgba_dev, w.hit_id_dev, &t);
         } else {
             return fail(VAFR_E_ARG, "view %d: unknown kind %d", i, w.kind);

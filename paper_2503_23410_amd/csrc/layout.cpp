@@ -1,6 +1,7 @@
 // Host side of the LP layouts: FP64 acuity segments, the VaFR constant-size
-// LP buffer (Sec. 3.2.1-3.2.3, Sec. 3.3) and the LMFR comparison buffer
-// (Sec. 3.1 Eq. (1), Sec. 4.1 Eq. (14)), plus their per-device upload.
+// LP buffer (Sec. 3.2.1-3.2.3, Sec. 3.3) and the LMFR / LaFR comparison
+// buffers (Sec. 3.1 Eq. (1), Sec. 4.1 Eq. (14), Eq. (15)), plus their
+// per-device upload.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -171,8 +172,10 @@ int layout_device(vafr_layout L, const LayoutDev** out) {
     } else {
         std::vector<double2> cs(L->max_rows);
         for (int j = 0; j < L->max_rows; ++j) cs[j] = make_double2(L->lm_cos[j], L->lm_sin[j]);
-        VAFR_HIP(hipMalloc(&d.lm_z, sizeof(double) * L->lm_z.size()));
-        VAFR_HIP(hipMemcpy(d.lm_z, L->lm_z.data(), sizeof(double) * L->lm_z.size(), hipMemcpyHostToDevice));
+        if (!L->lm_z.empty()) {
+            VAFR_HIP(hipMalloc(&d.lm_z, sizeof(double) * L->lm_z.size()));
+            VAFR_HIP(hipMemcpy(d.lm_z, L->lm_z.data(), sizeof(double) * L->lm_z.size(), hipMemcpyHostToDevice));
+        }
         VAFR_HIP(hipMalloc(&d.lm_cs, sizeof(double2) * cs.size()));
         VAFR_HIP(hipMemcpy(d.lm_cs, cs.data(), sizeof(double2) * cs.size(), hipMemcpyHostToDevice));
     }
@@ -303,19 +306,16 @@ extern "C" int vafr_lp_layout(const vafr_display* display, const vafr_acuity* ac
     return VAFR_OK;
 }
 
-extern "C" int lmfr_lp_layout(const vafr_display* display, double delta, double alpha, vafr_layout* out) {
-    if (!out) return fail(VAFR_E_ARG, "out is NULL");
-    *out = nullptr;
-    if (int rc = check_display(display)) return rc;
-    if (!(delta >= 1.0 && delta < 1e6)) return fail(VAFR_E_ARG, "delta must be >= 1");
-    if (!(alpha > 0.0 && alpha < 64.0)) return fail(VAFR_E_ARG, "alpha must be in (0, 64)");
+// Dense log-polar buffer shared by LMFR and LaFR: round(W/delta) x
+// round(H/delta) texels (Sec. 5.2: delta^2 display pixels per texel), row j
+// at polar angle theta = 360 (j + 1/2)/h.
+static int dense_layout(const vafr_display* display, double delta, int kind, vafr_layout* out) {
     vafr_layout L = new (std::nothrow) vafr_layout_s;
     if (!L) return fail(VAFR_E_OOM, "layout allocation failed");
-    L->kind = VAFR_LAYOUT_LMFR;
+    L->kind = kind;
     L->disp = *display;
     film_pitch(*display, &L->px, &L->py);
     L->delta = delta;
-    L->alpha = alpha;
     const int32_t w = (int32_t)std::lround(display->width / delta);
     const int32_t h = (int32_t)std::lround(display->height / delta);
     L->n_cols = w < 1 ? 1 : w;
@@ -325,10 +325,6 @@ extern "C" int lmfr_lp_layout(const vafr_display* display, double delta, double 
         L->n_rows.assign(L->n_cols, L->max_rows);
         L->col_off.resize(L->n_cols + 1);
         for (int32_t i = 0; i <= L->n_cols; ++i) L->col_off[i] = (int64_t)i * L->max_rows;
-        // Inverse of Eq. (1) with K(z) = z^alpha: column i sits at
-        // z = ((i + 1/2)/w)^(1/alpha); row j at theta = 360 (j + 1/2)/h.
-        L->lm_z.resize(L->n_cols);
-        for (int32_t i = 0; i < L->n_cols; ++i) L->lm_z[i] = std::pow((i + 0.5) / L->n_cols, 1.0 / alpha);
         L->lm_cos.resize(L->max_rows);
         L->lm_sin.resize(L->max_rows);
         for (int32_t j = 0; j < L->max_rows; ++j) {
@@ -340,6 +336,48 @@ extern "C" int lmfr_lp_layout(const vafr_display* display, double delta, double 
         delete L;
         return fail(VAFR_E_OOM, "layout tables allocation failed");
     }
+    *out = L;
+    return VAFR_OK;
+}
+
+extern "C" int lmfr_lp_layout(const vafr_display* display, double delta, double alpha, vafr_layout* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_display(display)) return rc;
+    if (!(delta >= 1.0 && delta < 1e6)) return fail(VAFR_E_ARG, "delta must be >= 1");
+    if (!(alpha > 0.0 && alpha < 64.0)) return fail(VAFR_E_ARG, "alpha must be in (0, 64)");
+    vafr_layout L;
+    if (int rc = dense_layout(display, delta, VAFR_LAYOUT_LMFR, &L)) return rc;
+    L->alpha = alpha;
+    try {
+        // Inverse of Eq. (1) with K(z) = z^alpha: column i sits at
+        // z = ((i + 1/2)/w)^(1/alpha).
+        L->lm_z.resize(L->n_cols);
+        for (int32_t i = 0; i < L->n_cols; ++i) L->lm_z[i] = std::pow((i + 0.5) / L->n_cols, 1.0 / alpha);
+    } catch (const std::bad_alloc&) {
+        delete L;
+        return fail(VAFR_E_OOM, "layout tables allocation failed");
+    }
+    *out = L;
+    return VAFR_OK;
+}
+
+extern "C" int lafr_lp_layout(const vafr_display* display, double delta, double a, double alpha, double beta,
+                              vafr_layout* out) {
+    if (!out) return fail(VAFR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (int rc = check_display(display)) return rc;
+    if (!(delta >= 1.0 && delta < 1e6)) return fail(VAFR_E_ARG, "delta must be >= 1");
+    if (!(a > 0.0 && a < 1.0)) return fail(VAFR_E_ARG, "a must be in (0, 1)");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(VAFR_E_ARG, "alpha must be in (0, 1]");
+    if (!(beta > 0.0 && beta <= 16.0)) return fail(VAFR_E_ARG, "beta must be in (0, 16]");
+    vafr_layout L;
+    if (int rc = dense_layout(display, delta, VAFR_LAYOUT_LAFR, &L)) return rc;
+    // The column -> z map of Eq. (15) moves with the gaze (through ln L and
+    // Z_ef), so it is evaluated per ray from per-view constants.
+    L->alpha = alpha;
+    L->lf_a = a;
+    L->lf_beta = beta;
     *out = L;
     return VAFR_OK;
 }

@@ -203,10 +203,19 @@ __device__ __forceinline__ float4 sample_vafr(const ReconView& v, const Stage& s
     return blend4(A, w0 - w0 * t0, B, w0 * t0, C, w - w * t1, D, w * t1);
 }
 
+// u / w of the LaFR kernel (Sec. 4.1 Eq. (15)) at log ratio z in [0, 1].
+__device__ __forceinline__ float lafr_u(const ReconView& v, float z) {
+    if (z <= v.lf_zef) return powf(z * v.lf_fa1, v.lf_inv_fa);
+    const float za = fmaxf((1.0f / z - v.lf_zef_inv) * v.lf_inv_k, -1.0f);
+    const float s = (2.0f * acosf(za) - (float)M_PI) * (float)M_1_PI;
+    return (v.lf_bexp == 1.0f ? s : powf(s, v.lf_bexp)) * (1.0f - v.lf_uef) + v.lf_uef;
+}
+
 __device__ __forceinline__ float4 sample_lmfr(const ReconView& v, __amdgpu_buffer_rsrc_t lp, float dx, float dy) {
     const float r = fmaxf(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)), 1.0f);
     const float z = __log2f(r) * v.inv_L;                     // Eq. (1); inv_L = ln 2 / L
-    float u = (v.alpha == 4.0f ? (z * z) * (z * z) : __powf(z, v.alpha)) * (float)v.n_cols;   // Eq. (14)
+    float u = (v.lf_on ? lafr_u(v, z)                                          // Eq. (15)
+                       : v.alpha == 4.0f ? (z * z) * (z * z) : __powf(z, v.alpha)) * (float)v.n_cols;   // Eq. (14)
     u = fminf(fmaxf(u, 0.5f), (float)v.n_cols - 0.5f);
     const float a = u - 0.5f;
     int i0 = (int)a;

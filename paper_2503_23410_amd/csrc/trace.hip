@@ -1,6 +1,6 @@
 // Ray generation, BVH traversal, watertight closest hit and shading for the
 // LP buffer (Sec. 6.1: one ray per LP texel, closest-hit shading, miss
-// shader), the LMFR buffer and the full-resolution comparison.
+// shader), the LMFR / LaFR buffers and the full-resolution comparison.
 //
 // Build with -ffp-contract=off: the ray set-up and the triangle test below
 // are written operation by operation so that every rounding is stated, and
@@ -423,6 +423,17 @@ __device__ __forceinline__ void film_ray(const TraceView& v, double Px, double P
     ray_setup(v.eye[0], v.eye[1], v.eye[2], d[0], d[1], d[2], r);
 }
 
+// LaFR (Sec. 4.1 Eq. (15)) column -> log ratio z, inverting the kernel piece
+// that holds the column's abscissa t = (i + 1/2)/w; FP64 like the LMFR table.
+// Out of line and with scalar arguments, so that it adds neither registers
+// nor a private copy of the view to the traversal kernels.
+__device__ __noinline__ double lafr_column_z(double t, double fa, double uef, double sexp, double zef_inv,
+                                             double k) {
+    if (t <= uef) return pow(t, fa) / (1.0 - fa);
+    const double s = pow((t - uef) / (1.0 - uef), sexp);
+    return 1.0 / (zef_inv - sin(0.5 * M_PI * s) * k);
+}
+
 // Item -> (ray, output slot).  Returns false for padding items.
 __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, RayPre& r, int64_t& out) {
     if (v.mode == kModeVafr) {
@@ -440,7 +451,10 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
         const int64_t i = (tile / tiles_j) * 8 + (w >> 3);
         const int64_t j = (tile % tiles_j) * 8 + (w & 7);
         if (i >= v.lm_w || j >= v.lm_h) return false;
-        const double rad = exp(v.lm_L * v.lm_z[i]);
+        const double z = v.lf_on ? lafr_column_z(((double)i + 0.5) / (double)v.lm_w, v.lf_fa, v.lf_uef, v.lf_sexp,
+                                                 v.lf_zef_inv, v.lf_k)
+                                 : v.lm_z[i];
+        const double rad = exp(v.lm_L * z);
         const double2 cs = v.lm_cs[j];
         film_ray(v, v.gx + (rad * cs.x) * v.px, v.gy + (rad * cs.y) * v.py, r);
         out = i * v.lm_h + j;

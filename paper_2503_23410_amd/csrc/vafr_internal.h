@@ -70,9 +70,10 @@ struct vafr_layout_s {
     double rho_max = 0;                  // film radius of the last column centre
     std::vector<float> u_of_rho;         // 2 * (kURhoN + 1) floats
     double u_margin = 1.0;               // bound on the table's error, in columns
-    // LMFR
+    // LMFR / LaFR
     double delta = 0, alpha = 0;
-    std::vector<double> lm_z, lm_cos, lm_sin;
+    double lf_a = 0, lf_beta = 0;         // LaFR
+    std::vector<double> lm_z, lm_cos, lm_sin;   // lm_z: LMFR only
     // device copies
     std::mutex mu;
     std::deque<vafr::LayoutDev> dev;   // stable addresses across push_back
@@ -179,11 +180,16 @@ struct TraceView {
     // VaFR: item k traces texel ord[k] through film offset dxy[k]
     const float2* dxy;
     const int32_t* ord;
-    // LMFR
-    const double* lm_z;
+    // LMFR / LaFR (dense buffer)
+    const double* lm_z;     // LMFR: z per column; NULL for LaFR
     const double2* lm_cs;
     int32_t lm_w, lm_h;
     double lm_L;
+    // LaFR kernel (Sec. 4.1 Eq. (15)) at this view's gaze: column abscissa
+    // t <= U_ef holds z = t^Fa / (1 - Fa); above it, s = ((t - U_ef) /
+    // (1 - U_ef))^(0.7/beta) and 1/z = 1/Z_ef - sin(pi s / 2) (1/Z_ef - 1).
+    int32_t lf_on;
+    double lf_fa, lf_uef, lf_sexp, lf_zef_inv, lf_k;
     // shading
     float light_dir[3], light_rgb[3], ambient[3], background[3];
     int32_t shadow;
@@ -254,9 +260,14 @@ struct ReconView {
     float rho_scale;    // kURhoN / rho_max
     const float2* u_of_rho;
     const int2* col;    // (n_rows, col_off)
-    // LMFR
+    // LMFR / LaFR
     float inv_L;        // ln 2 / L (the kernel uses log2)
     float alpha;
+    // LaFR (Sec. 4.1 Eq. (15)): z <= Z_ef gives (z (1 - Fa))^(1/Fa); above,
+    // Za = (1/z - 1/Z_ef) / (1/Z_ef - 1) and
+    // ((2 acos Za - pi) / pi)^(beta/0.7) (1 - U_ef) + U_ef.
+    int32_t lf_on;
+    float lf_zef, lf_fa1, lf_inv_fa, lf_zef_inv, lf_inv_k, lf_uef, lf_bexp;
     const float4* lp;
     uint32_t lp_bytes;  // < 2^32
     float4* img;

@@ -26,6 +26,7 @@ VAFR_SHADE_LAMBERT = 0
 VAFR_SHADE_PATH = 1
 VAFR_LAYOUT_VAFR = 0
 VAFR_LAYOUT_LMFR = 1
+VAFR_LAYOUT_LAFR = 2
 
 # Symbols declared in include/vafr.h (checked by the CPU test suite).
 EXPORTS = (
@@ -37,11 +38,19 @@ EXPORTS = (
     "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
     "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
     "vafr_server_destroy", "vafr_acuity_capped", "vafr_fxaa_lp", "vafr_rep_workspace_bytes", "vafr_shade_lp_rep",
+    "lafr_lp_layout", "lafr_shade_lp", "lafr_reconstruct",
 )
 
 VAFR_VIEW_VAFR = 0
 VAFR_VIEW_LMFR = 1
 VAFR_VIEW_FULL = 2
+VAFR_VIEW_LAFR = 3
+
+# LaFR kernel parameters (Sec. 4.1 Eq. (15), Sec. 4.5): a is LMFR's kernel
+# exponent in the buffer-to-screen direction; alpha and beta are LaFR's own.
+LAFR_A = 0.25
+LAFR_ALPHA = 0.85
+LAFR_BETA = 0.7
 
 
 class VafrError(RuntimeError):
@@ -149,6 +158,8 @@ def load():
         "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
+        "lafr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.c_double, C.c_double,
+                                     C.POINTER(_P)]),
         "vafr_layout_dims": (C.c_int, [_P, C.POINTER(vafr_dims)]),
         "vafr_layout_tables": (C.c_int, [_P, C.POINTER(C.POINTER(C.c_int32)), C.POINTER(C.POINTER(C.c_int64)),
                                          C.POINTER(C.POINTER(C.c_float))]),
@@ -161,8 +172,11 @@ def load():
                                     _P]),
         "lmfr_shade_lp": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P,
                                     _P]),
+        "lafr_shade_lp": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P,
+                                    _P]),
         "vafr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
         "lmfr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
+        "lafr_reconstruct": (C.c_int, [_P, vafr_gaze, _P, _P, _P]),
         "full_shade": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_display), C.POINTER(vafr_shading), _P,
                                  _P, _P]),
         "vafr_count_work": (C.c_int, [_P, C.POINTER(vafr_camera), vafr_gaze, C.POINTER(vafr_shading), _P, _P, _P]),
@@ -256,7 +270,7 @@ def _dptr(t):
 # ------------------------------------------------------------------ handles
 
 class Layout:
-    """Owns a vafr_layout handle (VaFR or LMFR)."""
+    """Owns a vafr_layout handle (VaFR, LMFR or LaFR)."""
 
     def __init__(self, handle):
         self._h = handle
@@ -294,6 +308,12 @@ class Layout:
     def lmfr(cls, disp: vafr_display, delta=1.8, alpha=4.0):
         h = C.c_void_p()
         _check(load().lmfr_lp_layout(C.byref(disp), float(delta), float(alpha), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def lafr(cls, disp: vafr_display, delta=1.8, a=LAFR_A, alpha=LAFR_ALPHA, beta=LAFR_BETA):
+        h = C.c_void_p()
+        _check(load().lafr_lp_layout(C.byref(disp), float(delta), float(a), float(alpha), float(beta), C.byref(h)))
         return cls(h)
 
     @property
@@ -391,6 +411,11 @@ def lmfr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None)
                                 _dptr(hit_id), _stream(stream)))
 
 
+def lafr_shade_lp(scene, cam, gz, sh, layout, lp_rgba, hit_id=None, stream=None):
+    _check(load().lafr_shade_lp(scene.handle, C.byref(cam), gz, C.byref(sh), layout.handle, _dptr(lp_rgba),
+                                _dptr(hit_id), _stream(stream)))
+
+
 def rep_workspace_bytes(layout):
     n = C.c_int64()
     _check(load().vafr_rep_workspace_bytes(layout.handle, C.byref(n)))
@@ -420,6 +445,10 @@ def vafr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
 
 def lmfr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
     _check(load().lmfr_reconstruct(layout.handle, gz, _dptr(lp_rgba), _dptr(img_rgba), _stream(stream)))
+
+
+def lafr_reconstruct(layout, gz, lp_rgba, img_rgba, stream=None):
+    _check(load().lafr_reconstruct(layout.handle, gz, _dptr(lp_rgba), _dptr(img_rgba), _stream(stream)))
 
 
 def full_shade(scene, cam, disp, sh, img_rgba, hit_id=None, stream=None):

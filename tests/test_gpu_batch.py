@@ -42,7 +42,8 @@ def _views(torch, V, scene, sizes, gazes, cams, kinds):
             L = None
             lp = None
         else:
-            L = V.Layout.vafr(d) if kind == V.VAFR_VIEW_VAFR else V.Layout.lmfr(d, 1.8, 4.0)
+            L = (V.Layout.vafr(d) if kind == V.VAFR_VIEW_VAFR else
+                 V.Layout.lmfr(d, 1.8, 4.0) if kind == V.VAFR_VIEW_LMFR else V.Layout.lafr(d, 2.2))
             lp = torch.full((L.n_texels, 4), -1.0, device="cuda")
         n_hit = L.n_texels if L is not None else W * H
         hit = torch.full((n_hit,), -7, device="cuda", dtype=torch.int32)
@@ -58,9 +59,12 @@ def _run_individual(V, scene, vs, sh):
         elif w["kind"] == V.VAFR_VIEW_VAFR:
             V.vafr_shade_lp(scene, w["cam"], w["gaze"], sh, w["layout"], w["lp"], w["hit"])
             V.vafr_reconstruct(w["layout"], w["gaze"], w["lp"], w["img"])
-        else:
+        elif w["kind"] == V.VAFR_VIEW_LMFR:
             V.lmfr_shade_lp(scene, w["cam"], w["gaze"], sh, w["layout"], w["lp"], w["hit"])
             V.lmfr_reconstruct(w["layout"], w["gaze"], w["lp"], w["img"])
+        else:
+            V.lafr_shade_lp(scene, w["cam"], w["gaze"], sh, w["layout"], w["lp"], w["hit"])
+            V.lafr_reconstruct(w["layout"], w["gaze"], w["lp"], w["img"])
 
 
 def _descs(V, scene, vs, sh):
@@ -90,12 +94,14 @@ def _assert_equal(torch, ref, vs, what):
 
 def test_batch_equals_individual_calls(env, scene):
     """16 views of uneven size (sizes drawn from 720p..8K, gaze per view),
-    mostly VaFR plus one LMFR and one full-resolution view, eager and graph."""
+    mostly VaFR plus one LMFR, one LaFR(2.2) and one full-resolution view,
+    eager and graph."""
     torch, V = env
     sizes, gazes = I.batch_views(16, seed=4)
     kinds = [V.VAFR_VIEW_VAFR] * 16
     kinds[5] = V.VAFR_VIEW_LMFR
     kinds[11] = V.VAFR_VIEW_FULL
+    kinds[8] = V.VAFR_VIEW_LAFR
     cams = [I.terrain_camera(0.01 * k) for k in range(16)]
     vs = _views(torch, V, scene, sizes, gazes, cams, kinds)
     sh = V.shading()

@@ -1,0 +1,178 @@
+"""GPU parity of the LaFR comparison path (Sec. 4.1 Eq. (15)) against the
+CPU oracle, through the C ABI.
+
+Acceptance as for the other paths: hit ids identical on rays the oracle does
+not flag as near ties, flagged rays at most 1e-4 of the outputs, colours of
+shaded texels within 2e-3.  The reconstruction evaluates Eq. (15) in FP32:
+the log ratio z carries a relative error of a few 2^-24, and next to the
+farthest screen corner the arccos piece magnifies it (its slope grows as
+1 / sqrt(1 - Za^2) while Za tends to -1).  Evaluating the kernel's FP32
+formula and the oracle's FP64 map over every pixel centre gives shifts of
+at most 8.5e-4 columns at 640 x 360 and 4.7e-3 at 1920 x 1080.  With LP
+texels whose neighbours differ by at most 1, the colour error is bounded by
+the shift: 2e-3 at 640 x 360 and 6e-3 at 1920 x 1080.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_23410_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+COLOR_TOL = 2e-3
+RECON_TOL_1080P = 6e-3
+FLAG_FRAC = 1e-4
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env(O):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_23410_amd import vafr as V
+    V.load()
+    O.set_threads(16)
+    return torch, V
+
+
+@pytest.fixture(scope="module")
+def soup(env, O):
+    torch, V = env
+    v, f = I.soup_scene()
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+@pytest.fixture(scope="module")
+def terrain1m(env, O):
+    torch, V = env
+    v, f = I.make_scene("terrain1m")
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+def _shade(torch, V, scene, layout, gaze, cam, sh):
+    lp = torch.empty((layout.n_texels, 4), device="cuda", dtype=torch.float32)
+    hid = torch.empty(layout.n_texels, device="cuda", dtype=torch.int32)
+    V.lafr_shade_lp(scene, V.camera(cam), V.gaze(*gaze), sh, layout, lp, hid)
+    torch.cuda.synchronize()
+    return lp, hid
+
+
+def _compare(name, g_rgba, g_id, o_rgba, o_id, flag):
+    unf = flag == 0
+    n = len(o_id)
+    mism = int(((g_id != o_id) & unf).sum())
+    nflag = int(flag.sum())
+    diff = np.abs(g_rgba - o_rgba).max(axis=1)
+    worst = float(diff[unf].max()) if unf.any() else 0.0
+    log(f"{name}: n={n} id_mismatch_unflagged={mism} flagged={nflag} max_colour_err={worst:.2e} "
+        f"hit_frac={(o_id >= 0).mean():.3f}")
+    assert mism == 0, f"{name}: {mism} unflagged hit-id mismatches"
+    assert nflag <= FLAG_FRAC * n + 1e-9, f"{name}: {nflag} flagged rays exceed 1e-4 of {n}"
+    assert worst <= COLOR_TOL, f"{name}: colour error {worst}"
+
+
+@pytest.mark.parametrize("shadow", [False, True])
+def test_lafr_soup_all_texels_and_reconstruction(env, O, soup, shadow):
+    """Every texel of a 640 x 360 LaFR(1.8) buffer against the oracle, and
+    the inverse map of a random buffer on every pixel."""
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    gz = (400.0, 100.0)
+    L = V.Layout.lafr(V.display(W, H), 1.8)
+    lp, hid = _shade(torch, V, g_sc, L, gz, I.soup_camera(), V.shading(shadow=shadow))
+    w, h = O.lmfr_dims(W, H, 1.8)
+    assert (L.n_cols, L.max_rows) == (w, h)
+    o_rgba, o_id, o_fl = O.shade_lafr_texels(o_sc, np.arange(w * h), W, H, I.FOV, gz, w, h, I.soup_camera(),
+                                             O.shading_params(shadow=shadow))
+    _compare(f"soup lafr shadow={shadow}", lp.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+    lp_np = I.random_lp(w * h, seed=203)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.lafr_reconstruct(L, V.gaze(*gz), torch.from_numpy(lp_np).cuda(), img)
+    torch.cuda.synchronize()
+    ref, _ = O.lafr_reconstruct(W, H, O.film_pitch(W, H, *I.FOV), gz[0], gz[1], w, h, lp_np, np.arange(W * H))
+    err = np.abs(img.cpu().numpy() - ref).max()
+    log(f"soup lafr reconstruct max_err={err:.2e}")
+    assert err <= COLOR_TOL
+
+
+@pytest.mark.parametrize("delta,alpha,beta", [(1.8, 0.85, 0.7), (2.2, 0.78, 0.9)])
+def test_lafr_terrain_sampled(env, O, terrain1m, delta, alpha, beta):
+    """1920 x 1080 on the 1.13M-triangle terrain, LaFR's own parameters and
+    the retinal-resolution tuning of Sec. 4.5 (beta != 0.7 exercises the
+    general exponent): a quarter of the texels, and the image (GPU end to
+    end) against the oracle's LP reconstructed by the oracle on sampled
+    pixels, pixels next to flagged texels excluded."""
+    torch, V = env
+    g_sc, o_sc = terrain1m
+    W, H = 1920, 1080
+    cam = I.terrain_camera()
+    L = V.Layout.lafr(V.display(W, H), delta, V.LAFR_A, alpha, beta)
+    w, h = O.lmfr_dims(W, H, delta)
+    p = O.film_pitch(W, H, *I.FOV)
+    rng = np.random.default_rng(31)
+    for gz in I.uniform_gaze(2, W, H, seed=21):
+        gz = (float(gz[0]), float(gz[1]))
+        lp, hid = _shade(torch, V, g_sc, L, gz, cam, V.shading())
+        o_rgba, o_id, o_fl = O.shade_lafr_texels(o_sc, np.arange(w * h), W, H, I.FOV, gz, w, h, cam,
+                                                 O.shading_params(), O.LAFR_A, alpha, beta)
+        idx = np.sort(rng.choice(w * h, (w * h) // 4, replace=False))
+        _compare(f"terrain lafr({delta}) gaze={gz}", lp.cpu().numpy()[idx], hid.cpu().numpy()[idx], o_rgba[idx],
+                 o_id[idx], o_fl[idx])
+        img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+        V.lafr_reconstruct(L, V.gaze(*gz), lp, img)
+        torch.cuda.synchronize()
+        pix = rng.integers(0, W * H, 200000)
+        ref, pf = O.lafr_reconstruct(W, H, p, gz[0], gz[1], w, h, o_rgba, pix, o_fl, O.LAFR_A, alpha, beta)
+        err = np.abs(img.cpu().numpy()[pix] - ref).max(axis=1)
+        log(f"terrain lafr({delta}) image gaze={gz}: flagged_px={int(pf.sum())} max_err={err[~pf].max():.2e}")
+        assert err[~pf].max() <= RECON_TOL_1080P
+
+
+def test_lafr_gaze_outside_the_kernel_domain_is_rejected(env, soup):
+    """A display whose foveal boundary lies near (Fa >= 1) or beyond
+    (Z_ef >= 1) the farthest corner has no LaFR kernel: the calls fail with
+    VAFR_E_ARG before any launch, and the batch refuses the view."""
+    torch, V = env
+    g_sc, _ = soup
+    for fov in ((10.0, 10.0), (4.0, 4.0)):
+        d = V.display(640, 360, fov)
+        L = V.Layout.lafr(d, 1.8)
+        lp = torch.zeros((L.n_texels, 4), device="cuda")
+        img = torch.zeros((640 * 360, 4), device="cuda")
+        with pytest.raises(V.VafrError) as ei:
+            V.lafr_shade_lp(g_sc, V.camera(I.soup_camera()), V.gaze(320.0, 180.0), V.shading(), L, lp)
+        assert ei.value.code == V.VAFR_E_ARG
+        with pytest.raises(V.VafrError) as ei:
+            V.lafr_reconstruct(L, V.gaze(320.0, 180.0), lp, img)
+        assert ei.value.code == V.VAFR_E_ARG
+        b = V.Batch(2)
+        with pytest.raises(V.VafrError) as ei:
+            b.run([V.view(V.VAFR_VIEW_LAFR, g_sc, V.camera(I.soup_camera()), V.gaze(320.0, 180.0), V.shading(),
+                          layout=L, lp_rgba=lp, img_rgba=img)])
+        assert ei.value.code == V.VAFR_E_ARG
+        b.close()
+    torch.cuda.synchronize()
+
+
+def test_lafr_calls_reject_other_layouts(env, soup):
+    torch, V = env
+    g_sc, _ = soup
+    d = V.display(640, 360)
+    LM = V.Layout.lmfr(d, 1.8, 4.0)
+    LA = V.Layout.lafr(d, 1.8)
+    lp = torch.zeros((max(LM.n_texels, LA.n_texels), 4), device="cuda")
+    img = torch.zeros((640 * 360, 4), device="cuda")
+    for fn in (lambda: V.lafr_shade_lp(g_sc, V.camera(I.soup_camera()), V.gaze(300.0, 200.0), V.shading(), LM, lp),
+               lambda: V.lmfr_shade_lp(g_sc, V.camera(I.soup_camera()), V.gaze(300.0, 200.0), V.shading(), LA, lp),
+               lambda: V.lafr_reconstruct(LM, V.gaze(300.0, 200.0), lp, img)):
+        with pytest.raises(V.VafrError) as ei:
+            fn()
+        assert ei.value.code == V.VAFR_E_ARG

@@ -124,6 +124,31 @@ def test_lmfr_argument_validation(V):
         assert ei.value.code == V.VAFR_E_ARG
 
 
+def test_lafr_layout_dims_match_oracle(V, O):
+    """LaFR(delta) shades the same (W/delta) x (H/delta) buffer as LMFR."""
+    for W, H in ((640, 360), (1920, 1080), (7680, 4320), (11520, 6480)):
+        for delta in (1.8, 2.2):
+            L = V.Layout.lafr(V.display(W, H), delta)
+            assert (L.n_cols, L.max_rows) == O.lmfr_dims(W, H, delta)
+            assert L.kind == V.VAFR_LAYOUT_LAFR
+            n_rows, col_off, dxy = L.tables()
+            assert dxy is None and np.all(n_rows == L.max_rows)
+
+
+def test_lafr_argument_validation(V):
+    for delta, a, alpha, beta in ((0.5, 0.25, 0.85, 0.7), (1.8, 0.0, 0.85, 0.7), (1.8, 1.0, 0.85, 0.7),
+                                  (1.8, 0.25, 0.0, 0.7), (1.8, 0.25, 1.5, 0.7), (1.8, 0.25, 0.85, 0.0),
+                                  (float("nan"), 0.25, 0.85, 0.7)):
+        with pytest.raises(V.VafrError) as ei:
+            V.Layout.lafr(V.display(640, 360), delta, a, alpha, beta)
+        assert ei.value.code == V.VAFR_E_ARG
+
+
+def test_lafr_parameters_match_the_oracle(V, O):
+    """The binding's default LaFR parameters are the oracle's."""
+    assert (V.LAFR_A, V.LAFR_ALPHA, V.LAFR_BETA) == (O.LAFR_A, O.LAFR_ALPHA, O.LAFR_BETA)
+
+
 def _check_bvh(V, verts, tris):
     sc = V.Scene(verts, tris)
     info = sc.info()
