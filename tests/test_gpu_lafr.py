@@ -10,7 +10,9 @@ farthest screen corner the arccos piece magnifies it (its slope grows as
 formula and the oracle's FP64 map over every pixel centre gives shifts of
 at most 8.5e-4 columns at 640 x 360 and 4.7e-3 at 1920 x 1080.  With LP
 texels whose neighbours differ by at most 1, the colour error is bounded by
-the shift: 2e-3 at 640 x 360 and 6e-3 at 1920 x 1080.
+the shift: 2e-3 at 640 x 360 and 6e-3 at 1920 x 1080.  At 7680 x 4320 the
+image is checked on a buffer that holds each texel's column coordinate, so
+the error reads as the shift itself (COLUMN_TOL_8K).
 """
 import sys
 
@@ -134,6 +136,68 @@ def test_lafr_terrain_sampled(env, O, terrain1m, delta, alpha, beta):
         err = np.abs(img.cpu().numpy()[pix] - ref).max(axis=1)
         log(f"terrain lafr({delta}) image gaze={gz}: flagged_px={int(pf.sum())} max_err={err[~pf].max():.2e}")
         assert err[~pf].max() <= RECON_TOL_1080P
+
+
+@pytest.fixture(scope="module")
+def terrain4m(env, O):
+    torch, V = env
+    v, f = I.make_scene("terrain4m")
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+# Column shift of the FP32 inverse map at 7680 x 4320: replaying the kernel's
+# FP32 formula against the oracle over every pixel centre gives at most 0.035
+# columns (LaFR's own parameters) and 0.049 (the retinal tuning), all of it
+# next to the farthest corners.
+COLUMN_TOL_8K = 0.1
+
+
+@pytest.mark.parametrize("delta,alpha,beta,gaze", [(1.8, 0.85, 0.7, None), (2.2, 0.78, 0.9, (5000.3, 1500.7))])
+def test_lafr_binocular_8k(env, O, terrain4m, delta, alpha, beta, gaze):
+    """The bench's LaFR workload: both eyes of 7680 x 4320 on the
+    4.52M-triangle terrain.  100,000 sampled texels per eye against the
+    oracle; then the inverse map of a structured buffer (channel 0 = column
+    coordinate i + 1/2, channels 1-2 = cos / sin of the row angle, alpha 1)
+    on 300,000 sampled pixels plus the last row and column, so that the
+    image error reads directly as a column shift and an angle error."""
+    torch, V = env
+    g_sc, o_sc = terrain4m
+    W, H = 7680, 4320
+    gz = tuple(float(c) for c in (gaze or I.gaze_trace(1, W, H, seed=30)[0]))
+    L = V.Layout.lafr(V.display(W, H, I.FOV), delta, V.LAFR_A, alpha, beta)
+    w, h = O.lmfr_dims(W, H, delta)
+    rng = np.random.default_rng(41)
+    for eye, cam in enumerate(I.binocular_cameras()):
+        lp, hid = _shade(torch, V, g_sc, L, gz, cam, V.shading())
+        idx = np.sort(rng.choice(w * h, 100000, replace=False))
+        o_rgba, o_id, o_fl = O.shade_lafr_texels(o_sc, idx, W, H, I.FOV, gz, w, h, cam, O.shading_params(),
+                                                 O.LAFR_A, alpha, beta)
+        it = torch.from_numpy(idx).cuda()
+        _compare(f"8K lafr({delta}) eye {eye} gaze={gz}", lp[it].cpu().numpy(), hid[it].cpu().numpy(), o_rgba, o_id,
+                 o_fl)
+        del lp, hid
+    th = 2 * np.pi * (np.arange(h) + 0.5) / h
+    lp_np = np.empty((w, h, 4), np.float32)
+    lp_np[:, :, 0] = (np.arange(w) + 0.5)[:, None]
+    lp_np[:, :, 1] = np.cos(th)[None, :]
+    lp_np[:, :, 2] = np.sin(th)[None, :]
+    lp_np[:, :, 3] = 1.0
+    lp_np = lp_np.reshape(-1, 4)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    V.lafr_reconstruct(L, V.gaze(*gz), torch.from_numpy(lp_np).cuda(), img)
+    torch.cuda.synchronize()
+    pix = np.unique(np.concatenate([rng.integers(0, W * H, 300000), (H - 1) * W + np.arange(W),
+                                    np.arange(H) * W + W - 1]))
+    got = img[torch.from_numpy(pix).cuda()].cpu().numpy()
+    del img
+    ref, _ = O.lafr_reconstruct(W, H, O.film_pitch(W, H, *I.FOV), gz[0], gz[1], w, h, lp_np, pix, None, O.LAFR_A,
+                                alpha, beta)
+    shift = np.abs(got[:, 0] - ref[:, 0]).max()
+    ang = np.abs(got[:, 1:3] - ref[:, 1:3]).max()
+    log(f"8K lafr({delta}) image gaze={gz}: column shift {shift:.2e}, angle-channel error {ang:.2e}")
+    assert shift <= COLUMN_TOL_8K
+    assert ang <= 1e-3
+    assert np.all(np.abs(got[:, 3] - 1.0) <= 1e-6)
 
 
 def test_lafr_gaze_outside_the_kernel_domain_is_rejected(env, soup):
