@@ -627,9 +627,10 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_p) v.out_p[out] = p;
 }
 
-// Register budget of the traversal kernels: at most 102 VGPRs, i.e. five
-// waves per SIMD, which the loop needs to cover its memory latency (the
-// path-mode variants would otherwise take 113 and run 8% slower).
+// Register budget of the traversal kernels: five waves per SIMD, i.e. at
+// most 96 VGPRs (512 per lane over five waves, in allocation steps of 8).
+// The loop needs those waves to cover its memory latency; the path-mode
+// variant would otherwise take 113 and run 8% slower.
 #define kFiveWaves __attribute__((amdgpu_waves_per_eu(5)))
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
