@@ -42,6 +42,7 @@ struct Slot {
 struct GraphEntry {
     int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0, stack = 0;
     int queue_blocks = 0;
+    bool lambert = false;   // traversal kernel without the path-tracing code
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, kqueue = nullptr, krecon = nullptr;
@@ -68,6 +69,7 @@ struct vafr_batch_s {
     std::vector<vafr::TraceView> tv;
     std::vector<vafr::ReconView> rv;
     int stack = vafr::kStackShort;   // stack class of the frame's traversal launch
+    bool lambert = true;             // no view of the frame is path-traced
     std::vector<int32_t> tb, rb, qb;
     std::vector<int64_t> qoff;       // first queue entry of each view
     int64_t queue_items = 0;         // queue entries the frame needs
@@ -111,6 +113,7 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     b->queue_items = 0;
     int64_t tsum = 0, rsum = 0, qsum = 0;
     b->stack = kStackShort;
+    b->lambert = true;
     for (int32_t i = 0; i < n; ++i) {
         const vafr_view& w = views[i];
         TraceView t;
@@ -135,6 +138,7 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
         // path mode with two or more bounces: two passes (queue pointers
         // are filled in per slot)
         b->qoff.push_back(b->queue_items);
+        if (t.shade_mode == VAFR_SHADE_PATH) b->lambert = false;
         if (t.shade_mode == VAFR_SHADE_PATH && t.bounces > kPathSplitBounce) {
             t.pt_split = kPathSplitBounce;
             b->queue_items += t.n_items;
@@ -217,7 +221,7 @@ hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, const Slot& 
     a.p[5] = &a.cost;
     void** args = a.p;
     hipKernelNodeParams p{};
-    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack, g.queue_blocks > 0));
+    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack, g.queue_blocks > 0, g.lambert));
     p.gridDim = dim3((unsigned)g.trace_blocks);
     p.blockDim = dim3((unsigned)g.trace_block);
     p.sharedMemBytes = 0;
@@ -299,7 +303,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
     const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
     for (auto& g : b->graphs)
         if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
-            g.queue_blocks == queue_blocks && g.trace_block == b->cfg.trace_block &&
+            g.queue_blocks == queue_blocks && g.lambert == b->lambert && g.trace_block == b->cfg.trace_block &&
             g.recon_rows == b->cfg.recon_rows && g.stack == b->stack && g.timed == b->profiling) {
             *out = &g;
             return VAFR_OK;
@@ -315,6 +319,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
     g.trace_blocks = trace_blocks;
     g.recon_blocks = recon_blocks;
     g.queue_blocks = queue_blocks;
+    g.lambert = b->lambert;
     g.trace_block = b->cfg.trace_block;
     g.recon_rows = b->cfg.recon_rows;
     g.stack = b->stack;
@@ -465,7 +470,8 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             if (int rc = launch_trace_plan(b->cost, s.order, tblocks, stream)) return rc;
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
-                                        tblocks, b->cfg.trace_block, b->stack, qblocks > 0, stream, nullptr,
+                                        tblocks, b->cfg.trace_block, b->stack, qblocks > 0, b->lambert, stream,
+                                        nullptr,
                                         planned ? s.order : nullptr, planned ? b->cost : nullptr))
             return rc;
         if (qblocks > 0)

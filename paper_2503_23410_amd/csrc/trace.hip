@@ -597,7 +597,9 @@ __device__ void path_first_pass(const TraceView& v, RayPre r, int64_t out, int* 
 // triangle tests, and writes no image.  kSplit: the kernel may serve
 // two-pass path-mode views (compiled only into the batched kernels that a
 // frame with such views launches, so the others keep their register count).
-template <int B, int S, bool kCount, bool kSplit = false>
+// kLambert: every view of the launch is Lambert-shaded, so the path-tracing
+// code is left out of the kernel.
+template <int B, int S, bool kCount, bool kSplit = false, bool kLambert = false>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
@@ -611,7 +613,7 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     float4 c, p;
     WorkCount wc;
     uint32_t n_shadow = 0;
-    if (v.shade_mode == VAFR_SHADE_PATH)
+    if (!kLambert && v.shade_mode == VAFR_SHADE_PATH)
         c = shade_path<B, S, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
     else
         c = shade_lambert<B, S, kCount>(v, r, stk, id, wc, n_shadow, p);
@@ -627,11 +629,14 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (v.out_p) v.out_p[out] = p;
 }
 
-// Register budget of the traversal kernels: five waves per SIMD, i.e. at
-// most 96 VGPRs (512 per lane over five waves, in allocation steps of 8).
-// The loop needs those waves to cover its memory latency; the path-mode
-// variant would otherwise take 113 and run 8% slower.
-#define kFiveWaves __attribute__((amdgpu_waves_per_eu(5)))
+// Register budget of the traversal kernels, in waves per SIMD (512 VGPRs per
+// lane over that many waves, in allocation steps of 8).  Kernels that may
+// path-trace keep five waves (at most 96 VGPRs): below that their extra
+// state spills, and without the budget the path-mode batch variant takes 113
+// VGPRs and runs 8% slower.  The Lambert-only kernels need 65 VGPRs; their
+// budget of six only keeps them from growing.
+#define kTraceWaves(lambert) __attribute__((amdgpu_waves_per_eu((lambert) ? 6 : 5)))
+#define kFiveWaves kTraceWaves(false)
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
 // permuted so that XCD q receives the q-th contiguous eighth of the items:
@@ -645,11 +650,11 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 }
 
 // S = stack entries per lane (the scene's stack class).
-template <int B, int S, bool kCount>
-__global__ __launch_bounds__(B) void k_trace(const TraceView v, unsigned long long* counters) {
+template <int B, int S, bool kCount, bool kLambert>
+__global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace(const TraceView v, unsigned long long* counters) {
     __shared__ int stack[S * B];
     const int b = xcd_block(blockIdx.x, gridDim.x);
-    trace_item<B, S, kCount>(v, (int64_t)b * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount, false, kLambert>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
 
 // Queue pass of two-pass path-mode views (batched): workgroup b serves view
@@ -701,8 +706,8 @@ __global__ __launch_bounds__(B) kFiveWaves void k_trace_list(const TraceView v) 
 // order (nullable): per XCD, the dispatch order of its workgroups'
 // blocks (see k_trace_plan); cost (nullable): each block's duration in
 // 100 MHz ticks, the larger of its waves', kept for the next frame's plan.
-template <int B, int S, bool kCount, bool kSplit>
-__global__ __launch_bounds__(B) kFiveWaves void k_trace_batch(const TraceView* __restrict__ views,
+template <int B, int S, bool kCount, bool kSplit, bool kLambert>
+__global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters, const int32_t* __restrict__ order,
                                                    uint32_t* __restrict__ cost) {
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(B) kFiveWaves void k_trace_batch(const TraceView* _
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    trace_item<B, S, kCount, kSplit>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount, kSplit, kLambert>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
     if (cost && (threadIdx.x & 63) == 0) {
         const uint64_t dt = wall_clock64() - t0;
         atomicMax(cost + b, (uint32_t)(dt < 0xffffffffull ? dt : 0xffffffffull));
@@ -777,23 +782,29 @@ void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsig
     if (v.item_list)
         hipLaunchKernelGGL((k_trace_list<B, S>), dim3((unsigned)blocks), dim3(B), 0, stream, v);
     else if (counters)
-        hipLaunchKernelGGL((k_trace<B, S, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+        hipLaunchKernelGGL((k_trace<B, S, true, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+    else if (v.shade_mode == VAFR_SHADE_PATH)
+        hipLaunchKernelGGL((k_trace<B, S, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
     else
-        hipLaunchKernelGGL((k_trace<B, S, false>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
+        hipLaunchKernelGGL((k_trace<B, S, false, true>), dim3((unsigned)blocks), dim3(B), 0, stream, v, counters);
 }
 
 template <int B, int S>
 void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, bool split,
-                  hipStream_t stream, unsigned long long* counters, const int32_t* order, uint32_t* cost) {
+                  bool lambert, hipStream_t stream, unsigned long long* counters, const int32_t* order,
+                  uint32_t* cost) {
     if (counters)
-        hipLaunchKernelGGL((k_trace_batch<B, S, true, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
-                           block_end, n_views, counters, order, cost);
+        hipLaunchKernelGGL((k_trace_batch<B, S, true, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
+                           views, block_end, n_views, counters, order, cost);
     else if (split)
-        hipLaunchKernelGGL((k_trace_batch<B, S, false, true>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
-                           block_end, n_views, counters, order, cost);
+        hipLaunchKernelGGL((k_trace_batch<B, S, false, true, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
+                           views, block_end, n_views, counters, order, cost);
+    else if (!lambert)
+        hipLaunchKernelGGL((k_trace_batch<B, S, false, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
+                           views, block_end, n_views, counters, order, cost);
     else
-        hipLaunchKernelGGL((k_trace_batch<B, S, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream, views,
-                           block_end, n_views, counters, order, cost);
+        hipLaunchKernelGGL((k_trace_batch<B, S, false, false, true>), dim3((unsigned)blocks), dim3(B), 0, stream,
+                           views, block_end, n_views, counters, order, cost);
 }
 
 template <int S>
@@ -806,20 +817,27 @@ void launch_single_s(const TraceView& v, int64_t blocks, int block, hipStream_t 
 
 template <int S>
 void launch_batch_s(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, int block,
-                    bool split, hipStream_t stream, unsigned long long* counters, const int32_t* order,
+                    bool split, bool lambert, hipStream_t stream, unsigned long long* counters, const int32_t* order,
                     uint32_t* cost) {
-    if (block == 64) launch_batch<64, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
+    if (block == 64)
+        launch_batch<64, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
     else if (block == 128)
-        launch_batch<128, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
-    else launch_batch<256, S>(views, block_end, n_views, blocks, split, stream, counters, order, cost);
+        launch_batch<128, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
+    else launch_batch<256, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
 }
 
-template <int S, bool kSplit>
+template <int S, bool kSplit, bool kLambert>
 const void* batch_kernel_s(int block) {
-    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false, kSplit>);
-    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false, kSplit>);
-    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false, kSplit>);
+    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false, kSplit, kLambert>);
+    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false, kSplit, kLambert>);
+    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false, kSplit, kLambert>);
     return nullptr;
+}
+
+template <int S>
+const void* batch_kernel_any(int block, bool split, bool lambert) {
+    if (split) return batch_kernel_s<S, true, false>(block);
+    return lambert ? batch_kernel_s<S, false, true>(block) : batch_kernel_s<S, false, false>(block);
 }
 
 bool stack_ok(int stack) { return stack == kStackShort || stack == kStackLong; }
@@ -847,25 +865,25 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
     return VAFR_OK;
 }
 
-const void* trace_batch_kernel(int block, int stack, bool split) {
-    if (stack == kStackShort) return split ? batch_kernel_s<kStackShort, true>(block) : batch_kernel_s<kStackShort, false>(block);
-    if (stack == kStackLong) return split ? batch_kernel_s<kStackLong, true>(block) : batch_kernel_s<kStackLong, false>(block);
+const void* trace_batch_kernel(int block, int stack, bool split, bool lambert) {
+    if (stack == kStackShort) return batch_kernel_any<kStackShort>(block, split, lambert);
+    if (stack == kStackLong) return batch_kernel_any<kStackLong>(block, split, lambert);
     return nullptr;
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, bool split, hipStream_t stream, unsigned long long* counters,
-                       const int32_t* order, uint32_t* cost) {
+                       int block, int stack, bool split, bool lambert, hipStream_t stream,
+                       unsigned long long* counters, const int32_t* order, uint32_t* cost) {
     if (blocks <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
     if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
     if (order && !trace_plan_ok(blocks)) return fail(VAFR_E_ARG, "too many blocks for a planned launch");
     if (stack == kStackShort)
-        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, split, stream, counters, order,
-                                    cost);
+        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, split, lambert, stream,
+                                    counters, order, cost);
     else
-        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, split, stream, counters, order,
-                                   cost);
+        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, split, lambert, stream,
+                                   counters, order, cost);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

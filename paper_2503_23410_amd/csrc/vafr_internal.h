@@ -224,10 +224,12 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
 // One launch over several views: workgroup b serves the view whose running
 // workgroup count block_end[] first exceeds b.
 // stack = the largest stack class among the views' scenes; split: some view
-// is a two-pass path-mode view (TraceView::pt_split >= 0).
+// is a two-pass path-mode view (TraceView::pt_split >= 0); lambert: every
+// view is Lambert-shaded (selects the kernel without the path-tracing code).
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, bool split, hipStream_t stream, unsigned long long* counters = nullptr,
-                       const int32_t* order = nullptr, uint32_t* cost = nullptr);
+                       int block, int stack, bool split, bool lambert, hipStream_t stream,
+                       unsigned long long* counters = nullptr, const int32_t* order = nullptr,
+                       uint32_t* cost = nullptr);
 // Longest-first dispatch order of a batched traversal launch of `blocks`
 // workgroups from the block durations the previous launch recorded in
 // cost[] (order: `blocks` entries, one planned permutation per XCD;
@@ -318,7 +320,7 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
 
 // Kernel entry points of the batched launches (for graph nodes); their
 // parameters are (views, block_end, n_views[, counters]).
-const void* trace_batch_kernel(int block, int stack, bool split);
+const void* trace_batch_kernel(int block, int stack, bool split, bool lambert);
 const void* recon_batch_kernel(int rows);
 
 // common validation helpers
