@@ -205,6 +205,9 @@ struct WorkCount {
 // boxes; the result is the same (t, id) minimum or the same any-hit bit.
 constexpr int kParkNum = 5, kParkDen = 8;
 
+// LDS entries per lane of stack class S (the rest of the stack is scratch).
+constexpr int lds_entries(int s) { return s < kStackLds ? s : kStackLds; }
+
 // stk points at this lane's column of the block's LDS stack (stride B).
 // Closest hit (kAny = false): smallest (t, triangle id); returns the stored
 // slot or -1.  Any hit with t > 0 (kAny = true): returns 1 or -1.
@@ -213,22 +216,23 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
                              WorkCount& wc) {
     t_best = INFINITY;
     id_best = -1;
-    // entries 0 .. S-1 in the lane's LDS column, the rest in scratch (the
+    // entries 0 .. kLds-1 in the lane's LDS column, the rest in scratch (the
     // two kept in separate branches so that the common case stays an LDS
     // access rather than a generic one; volatile keeps the rarely used
     // spill area in memory instead of in registers)
-    volatile int spill[kStackSpill];
+    constexpr int kLds = lds_entries(S);
+    volatile int spill[S + kStackSpill - kLds];
     auto push = [&](int sp_, int v) {
-        if (sp_ < S) {
+        if (sp_ < kLds) {
             ((__attribute__((address_space(3))) int*)(stk))[sp_ * B] = v;
         } else {
-            spill[sp_ - S] = v;
+            spill[sp_ - kLds] = v;
         }
     };
     auto top = [&](int sp_) {
         int v;
-        if (sp_ < S) v = ((__attribute__((address_space(3))) int*)(stk))[sp_ * B];
-        else v = spill[sp_ - S];
+        if (sp_ < kLds) v = ((__attribute__((address_space(3))) int*)(stk))[sp_ * B];
+        else v = spill[sp_ - kLds];
         return v;
     };
     float tlim = INFINITY;   // boxes are tested over [0, t_best * kHitSlack]
@@ -633,8 +637,8 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
 // lane over that many waves, in allocation steps of 8).  Kernels that may
 // path-trace keep five waves (at most 96 VGPRs): below that their extra
 // state spills, and without the budget the path-mode batch variant takes 113
-// VGPRs and runs 8% slower.  The Lambert-only kernels need 65 VGPRs; their
-// budget of six only keeps them from growing.
+// VGPRs and runs 8% slower.  The Lambert-only kernels need 63-64 VGPRs
+// (eight waves); their budget of six only keeps them from growing.
 #define kTraceWaves(lambert) __attribute__((amdgpu_waves_per_eu((lambert) ? 6 : 5)))
 #define kFiveWaves kTraceWaves(false)
 
@@ -652,7 +656,7 @@ __device__ __forceinline__ int xcd_block(int b, int n) {
 // S = stack entries per lane (the scene's stack class).
 template <int B, int S, bool kCount, bool kLambert>
 __global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace(const TraceView v, unsigned long long* counters) {
-    __shared__ int stack[S * B];
+    __shared__ int stack[lds_entries(S) * B];
     const int b = xcd_block(blockIdx.x, gridDim.x);
     trace_item<B, S, kCount, false, kLambert>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
@@ -665,7 +669,7 @@ template <int S>
 __global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceView* __restrict__ views,
                                                                    const int32_t* __restrict__ qblock_end,
                                                                    int32_t n_views) {
-    __shared__ int stack[S * kQueueBlock];
+    __shared__ int stack[lds_entries(S) * kQueueBlock];
     const int b = blockIdx.x;
     int vid = 0;
     while (vid + 1 < n_views && b >= qblock_end[vid]) ++vid;
@@ -694,7 +698,7 @@ __global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceVi
 // every XCD.
 template <int B, int S>
 __global__ __launch_bounds__(B) kFiveWaves void k_trace_list(const TraceView v) {
-    __shared__ int stack[S * B];
+    __shared__ int stack[lds_entries(S) * B];
     const int64_t q = (int64_t)blockIdx.x * B + threadIdx.x;
     if (q >= *v.item_count) return;
     trace_item<B, S, false>(v, v.item_list[q], stack, nullptr);
@@ -711,7 +715,7 @@ __global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace_batch(const T
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters, const int32_t* __restrict__ order,
                                                    uint32_t* __restrict__ cost) {
-    __shared__ int stack[S * B];
+    __shared__ int stack[lds_entries(S) * B];
     const uint64_t t0 = cost ? wall_clock64() : 0;
     int b = xcd_block(blockIdx.x, gridDim.x);
     const int per = gridDim.x / kXcds;

@@ -116,12 +116,17 @@ constexpr int kMaxLeaf = 4;
 // sum of (children - 1) over the ancestors of the current node; the binary
 // build tree is kept below depth class - 1 and its collapse into 4-wide
 // nodes keeps that sum within class + kStackSpill.  Only traversals deeper
-// than the class touch the spill entries.  The short class
-// leaves room for more resident waves per CU (LDS per wave = entries x 64 x
-// 4 bytes), the long class admits every supported scene.
+// than the class touch the spill entries.  The short class keeps the
+// scratch part small, the long class admits every supported scene.
 constexpr int kStackShort = 24;
 constexpr int kStackLong = 32;
 constexpr int kStackSpill = 24;
+// Of a lane's class + kStackSpill entries, the first min(class, kStackLds)
+// live in LDS and the rest in scratch.  20 LDS entries (10 KB per
+// 128-thread workgroup) let the Lambert-only kernels (64 VGPRs) keep eight
+// waves per SIMD resident where 24 entries allowed 6.5; the deeper entries
+// are rarely touched.
+constexpr int kStackLds = 20;
 // Scenes whose leaf count needs at most this many balanced levels get the
 // short class (two levels of slack for the SAH splits).
 constexpr int kShortStackLevels = kStackShort - 3;
