@@ -112,7 +112,10 @@ typedef struct {
  * shadow_rays = 1.  Path mode: one sample, next-event estimation to the
  * directional light at each vertex and `bounces` cosine-weighted
  * continuation rays; random numbers are keyed by (seed, frame, view, texel).
- * light_dir must be a unit vector pointing toward the light. */
+ * light_dir points toward the light: any finite non-zero vector, which the
+ * library normalises (FP64 from the FP32 components, squares summed as
+ * (x x + y y) + z z, each component divided by the square root and rounded
+ * once to FP32); VAFR_E_ARG for a zero or non-finite vector. */
 typedef struct {
     float light_dir[3];
     float light_rgb[3];

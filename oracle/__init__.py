@@ -13,6 +13,7 @@ the two share no code.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 
@@ -400,10 +401,13 @@ def rng01(seed, frame, view, texel, slot):
 
 def shading_params(light_dir=(0.3, 1.0, -0.5), light_rgb=(1.0, 1.0, 1.0), ambient=(0.1, 0.1, 0.1),
                    background=(0.05, 0.05, 0.08), shadow=True):
-    """sh = {light_dir (unit, FP64-normalised then FP32), light_rgb, ambient,
-    background, shadow}; defaults are the shading reading of Sec. 6.1."""
-    ld = np.asarray(light_dir, np.float64)
-    ld = ld / np.sqrt(np.dot(ld, ld))
+    """sh = {light_dir, light_rgb, ambient, background, shadow}; defaults are
+    the shading reading of Sec. 6.1.  The light direction is an FP32 input
+    normalised in FP64 (squares summed as (x x + y y) + z z, each component
+    divided by the root) and rounded to FP32."""
+    x, y, z = (float(c) for c in np.float32(light_dir))
+    n = math.sqrt((x * x + y * y) + z * z)
+    ld = [x / n, y / n, z / n]
     return np.concatenate([ld, light_rgb, ambient, background, [1.0 if shadow else 0.0]]).astype(np.float32)
 
 
@@ -579,7 +583,7 @@ def warp_triangles(layout: Layout):
     return v, ids
 
 
-def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, sh, depth=None):
+def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, sh, depth=None, parts=False):
     """Binocular reprojection (Sec. 5.1, VaFR_Rep) by forward grid warping:
     the left LP buffer is shaded; its texels' hit points, as a grid of
     triangles, are warped into the right eye's LP grid (nearest surface
@@ -587,7 +591,11 @@ def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, s
     cast.  Returns (left rgba, right rgba, tri, flags, right ids):
     tri[r] = winning grid triangle of right texel r, or -1 where it was ray
     cast; flags mark texels that may legitimately differ.  depth: optional
-    float32 array that receives each warped texel's interpolated depth."""
+    float32 array that receives each warped texel's interpolated depth.
+    parts=True appends a dict of the flags' sources: "left" (near-tie left
+    rays, per left texel), "warp" (right texels inside the widened box of a
+    warp triangle that uses a flagged left texel) and "holes" (near-tie rays
+    among the ray-cast right texels, per right texel)."""
     idx = np.arange(layout.n_texels, dtype=np.int64)
     p = film_pitch(W, H, *fov)
     G = gaze_film(W, H, p, *gaze)
@@ -604,10 +612,14 @@ def rep_lp(scene: Scene, layout: Layout, W, H, fov, gaze, cam_left, cam_right, s
                       _ptr(org), _ptr(d), _ptr(t), _ptr(_arr(ids, np.int32)), _ptr(lfl8), _ptr(_arr(left, np.float32)),
                       _ptr(_cam(cam_right)), _ptr(right), _ptr(rid), _ptr(tri), _ptr(depth), _ptr(flag))
     rfl = flag.astype(bool)
+    hfl = np.zeros(n, bool)
     holes = np.nonzero(tri < 0)[0]
     if holes.size:
         h_rgba, h_id, h_fl = shade_vafr_texels(scene, layout, holes, W, H, fov, gaze, cam_right, sh)
         right[holes] = h_rgba
         rid[holes] = h_id
-        rfl[holes] |= h_fl.astype(bool)
+        hfl[holes] = h_fl.astype(bool)
+        rfl |= hfl
+    if parts:
+        return left, right, tri, rfl, rid, {"left": lfl.astype(bool), "warp": flag.astype(bool), "holes": hfl}
     return left, right, tri, rfl, rid

@@ -47,9 +47,10 @@ int check_shading(const vafr_shading* s) {
         if (!std::isfinite(s->light_dir[k]) || !std::isfinite(s->light_rgb[k]) || !std::isfinite(s->ambient[k]) ||
             !std::isfinite(s->background[k]))
             return fail(VAFR_E_ARG, "shading has a non-finite component");
-        l2 += (double)s->light_dir[k] * s->light_dir[k];
     }
-    if (std::fabs(l2 - 1.0) > 1e-5) return fail(VAFR_E_ARG, "light_dir must be a unit vector");
+    l2 = ((double)s->light_dir[0] * s->light_dir[0] + (double)s->light_dir[1] * s->light_dir[1]) +
+         (double)s->light_dir[2] * s->light_dir[2];
+    if (!(l2 >= 1e-30) || !std::isfinite(l2)) return fail(VAFR_E_ARG, "light_dir must be a non-zero vector");
     return VAFR_OK;
 }
 
@@ -86,7 +87,13 @@ static void fill_view_common(TraceView& v, const vafr_camera* cam, const vafr_sh
     std::memcpy(v.right, cam->right, sizeof(v.right));
     std::memcpy(v.up, cam->up, sizeof(v.up));
     std::memcpy(v.fwd, cam->forward, sizeof(v.fwd));
-    std::memcpy(v.light_dir, sh->light_dir, sizeof(v.light_dir));
+    // the light direction is normalised here: FP64 from the FP32 input,
+    // squares summed as (x x + y y) + z z, rounded once to FP32
+    const double lx = sh->light_dir[0], ly = sh->light_dir[1], lz = sh->light_dir[2];
+    const double len = std::sqrt((lx * lx + ly * ly) + lz * lz);
+    v.light_dir[0] = (float)(lx / len);
+    v.light_dir[1] = (float)(ly / len);
+    v.light_dir[2] = (float)(lz / len);
     std::memcpy(v.light_rgb, sh->light_rgb, sizeof(v.light_rgb));
     std::memcpy(v.ambient, sh->ambient, sizeof(v.ambient));
     std::memcpy(v.background, sh->background, sizeof(v.background));
@@ -248,6 +255,8 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
         r.sx = r.sy = 1.0f;
         r.cx = (float)(0.5 - gaze.x_px);
         r.cy = (float)(0.5 - gaze.y_px);
+        r.lm_cx = 0.5 - gaze.x_px;
+        r.lm_cy = 0.5 - gaze.y_px;
         r.inv_L = (float)(M_LN2 / Lg);
         r.alpha = (float)L->alpha;
         if (L->kind == VAFR_LAYOUT_LAFR) {
@@ -257,10 +266,11 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
             r.lf_zef = (float)c.zef;
             r.lf_fa1 = (float)(1.0 - c.fa);
             r.lf_inv_fa = (float)(1.0 / c.fa);
-            r.lf_zef_inv = (float)(1.0 / c.zef);
-            r.lf_inv_k = (float)(1.0 / (1.0 / c.zef - 1.0));
+            r.lf_k = (float)(1.0 / c.zef - 1.0);
             r.lf_uef = (float)c.uef;
             r.lf_bexp = (float)(L->lf_beta / 0.7);
+            r.lf_half_inv_lnl = (float)(0.5 / c.lnL);
+            r.lf_inv_r2 = std::exp(-2.0 * c.lnL);
         }
     }
     *out = r;
@@ -406,10 +416,11 @@ extern "C" int vafr_rep_workspace_bytes(vafr_layout L, int64_t* bytes) {
     return VAFR_OK;
 }
 
-extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right,
-                                 vafr_gaze gaze, const vafr_shading* sh, vafr_layout L, float* lp_left,
-                                 float* lp_right, int32_t* hit_left, int32_t* hit_right, void* ws, int64_t ws_bytes,
-                                 hipStream_t stream, hipStream_t right_stream) {
+namespace vafr {
+
+int shade_lp_rep_ws(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right, vafr_gaze gaze,
+                    const vafr_shading* sh, vafr_layout L, float* lp_left, float* lp_right, int32_t* hit_left,
+                    int32_t* hit_right, void* ws, int64_t ws_bytes, hipStream_t stream, hipStream_t right_stream) {
     int64_t need;
     if (int rc = vafr_rep_workspace_bytes(L, &need)) return rc;
     if (!lp_left || !lp_right) return fail(VAFR_E_ARG, "LP buffer is NULL");
@@ -465,6 +476,16 @@ extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, 
     (void)hipEventDestroy(ev);
     VAFR_HIP(e);
     return launch_trace(right, right_stream);
+}
+
+}  // namespace vafr
+
+extern "C" int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right,
+                                 vafr_gaze gaze, const vafr_shading* sh, vafr_layout L, float* lp_left,
+                                 float* lp_right, int32_t* hit_left, int32_t* hit_right, void* ws, int64_t ws_bytes,
+                                 hipStream_t stream, hipStream_t right_stream) {
+    return shade_lp_rep_ws(scene, cam_left, cam_right, gaze, sh, L, lp_left, lp_right, hit_left, hit_right, ws,
+                           ws_bytes, stream, right_stream);
 }
 
 extern "C" int vafr_fxaa_lp(vafr_layout L, const float* in, float* out, hipStream_t stream) {

@@ -137,6 +137,16 @@ static void build_trace_order(vafr_layout_s* L) {
     for (int64_t k = 0; k < n; ++k) L->ord[k] = (int32_t)(key[k] & 0xffffffffu);
 }
 
+int layout_resident(vafr_layout L, bool* resident) {
+    int dev = -1;
+    VAFR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(L->mu);
+    *resident = false;
+    for (auto& d : L->dev)
+        if (d.device == dev) *resident = true;
+    return VAFR_OK;
+}
+
 int layout_device(vafr_layout L, const LayoutDev** out) {
     int dev = -1;
     VAFR_HIP(hipGetDevice(&dev));

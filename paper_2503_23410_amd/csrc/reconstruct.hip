@@ -203,18 +203,38 @@ __device__ __forceinline__ float4 sample_vafr(const ReconView& v, const Stage& s
     return blend4(A, w0 - w0 * t0, B, w0 * t0, C, w - w * t1, D, w * t1);
 }
 
-// u / w of the LaFR kernel (Sec. 4.1 Eq. (15)) at log ratio z in [0, 1].
-__device__ __forceinline__ float lafr_u(const ReconView& v, float z) {
+// u / w of the LaFR kernel (Sec. 4.1 Eq. (15)) at log ratio z in [0, 1] of
+// a pixel at squared distance r2 (FP64) from the gaze point.
+//  - z <= Z_ef: (z (1 - Fa))^(1/Fa).
+//  - z > Z_ef: Eq. (15)'s arccos piece, ((2 acos Za - pi) / pi)^(beta/0.7)
+//    (1 - U_ef) + U_ef with Za = (1/z - 1/Z_ef) / (1/Z_ef - 1).  Next to the
+//    farthest screen corner Za tends to -1, where acos has an unbounded
+//    slope, so it is evaluated through eps = 1 + Za = (1 - z) / (z k),
+//    k = 1/Z_ef - 1, and acos(eps - 1) = pi - 2 asin(sqrt(eps / 2)):
+//    s = 1 - (4 / pi) asin(sqrt(eps / 2)).  1 - z = -ln q / (2 ln L) with
+//    q = r2 / R2 and R the farthest corner's distance (ln R = ln L), q formed
+//    in FP64: ln q is log1p(q - 1) for q > 1/2, so it keeps its relative
+//    precision as r approaches R, and log(q) below (where q - 1 rounded to
+//    FP32 would lose the small q's digits).
+__device__ __forceinline__ float lafr_u(const ReconView& v, float z, double r2) {
     if (z <= v.lf_zef) return powf(z * v.lf_fa1, v.lf_inv_fa);
-    const float za = fmaxf((1.0f / z - v.lf_zef_inv) * v.lf_inv_k, -1.0f);
-    const float s = (2.0f * acosf(za) - (float)M_PI) * (float)M_1_PI;
+    const double q = r2 * v.lf_inv_r2;
+    const float lq = q > 0.5 ? log1pf((float)(q - 1.0)) : logf((float)q);
+    const float omz = fmaxf(-lq * v.lf_half_inv_lnl, 0.0f);
+    const float eps = fminf(omz / ((1.0f - omz) * v.lf_k), 1.0f);
+    const float s = fmaf(-4.0f * (float)M_1_PI, asinf(__builtin_amdgcn_sqrtf(0.5f * eps)), 1.0f);
     return (v.lf_bexp == 1.0f ? s : powf(s, v.lf_bexp)) * (1.0f - v.lf_uef) + v.lf_uef;
 }
 
-__device__ __forceinline__ float4 sample_lmfr(const ReconView& v, __amdgpu_buffer_rsrc_t lp, float dx, float dy) {
-    const float r = fmaxf(__builtin_amdgcn_sqrtf(fmaf(dx, dx, dy * dy)), 1.0f);
+// Pixel (x, y) of an LMFR / LaFR view: the offset from the gaze point is
+// formed in FP64 (the gaze is a continuous FP64 position), then rounded.
+__device__ __forceinline__ float4 sample_lmfr(const ReconView& v, __amdgpu_buffer_rsrc_t lp, int x, int y) {
+    const double dxd = (double)x + v.lm_cx, dyd = (double)y + v.lm_cy;
+    const float dx = (float)dxd, dy = (float)dyd;
+    const double r2 = dxd * dxd + dyd * dyd;
+    const float r = fmaxf(__builtin_amdgcn_sqrtf((float)r2), 1.0f);
     const float z = __log2f(r) * v.inv_L;                     // Eq. (1); inv_L = ln 2 / L
-    float u = (v.lf_on ? lafr_u(v, z)                                          // Eq. (15)
+    float u = (v.lf_on ? lafr_u(v, z, r2)                                      // Eq. (15)
                        : v.alpha == 4.0f ? (z * z) * (z * z) : __powf(z, v.alpha)) * (float)v.n_cols;   // Eq. (14)
     u = fminf(fmaxf(u, 0.5f), (float)v.n_cols - 0.5f);
     const float a = u - 0.5f;
@@ -395,12 +415,10 @@ __device__ __forceinline__ void recon_tile(const ReconView& v, int id, Stage& st
         }
     } else {
         if (x >= v.width) return;
-        const float dx = fmaf((float)x, v.sx, v.cx);
         for (int r = 0; r < P; ++r) {
             const int ty = wave * P + r;
             if (ty >= rows) break;
-            const float dy = fmaf((float)(y0 + ty), v.sy, v.cy);
-            store_px(img, (uint32_t)(ty * v.width + x) * 16u, sample_lmfr(v, lp, dx, dy));
+            store_px(img, (uint32_t)(ty * v.width + x) * 16u, sample_lmfr(v, lp, x, y0 + ty));
         }
     }
 }

@@ -115,9 +115,10 @@ constexpr int kMaxLeaf = 4;
 // pushes the node's other hit children, so a traversal holds at most the
 // sum of (children - 1) over the ancestors of the current node; the binary
 // build tree is kept below depth class - 1 and its collapse into 4-wide
-// nodes keeps that sum within class + kStackSpill.  Only traversals deeper
-// than the class touch the spill entries.  The short class keeps the
-// scratch part small, the long class admits every supported scene.
+// nodes keeps that sum within class + kStackSpill.  The entries past
+// min(class, kStackLds) live in scratch (see kStackLds), so only traversals
+// holding more than that many entries touch scratch.  The short class keeps
+// the scratch part small, the long class admits every supported scene.
 constexpr int kStackShort = 24;
 constexpr int kStackLong = 32;
 constexpr int kStackSpill = 24;
@@ -268,13 +269,16 @@ struct ReconView {
     const float2* u_of_rho;
     const int2* col;    // (n_rows, col_off)
     // LMFR / LaFR
+    double lm_cx, lm_cy; // pixel (x, y) centre minus the gaze point = (x + lm_cx, y + lm_cy), FP64
     float inv_L;        // ln 2 / L (the kernel uses log2)
     float alpha;
     // LaFR (Sec. 4.1 Eq. (15)): z <= Z_ef gives (z (1 - Fa))^(1/Fa); above,
     // Za = (1/z - 1/Z_ef) / (1/Z_ef - 1) and
     // ((2 acos Za - pi) / pi)^(beta/0.7) (1 - U_ef) + U_ef.
     int32_t lf_on;
-    float lf_zef, lf_fa1, lf_inv_fa, lf_zef_inv, lf_inv_k, lf_uef, lf_bexp;
+    float lf_zef, lf_fa1, lf_inv_fa, lf_k, lf_uef, lf_bexp;
+    float lf_half_inv_lnl;  // 1 / (2 ln L)
+    double lf_inv_r2;       // 1 / R^2, R = e^(ln L) the farthest corner's distance in pixels
     const float4* lp;
     uint32_t lp_bytes;  // < 2^32
     float4* img;
@@ -316,6 +320,14 @@ int launch_rep(const LayoutDev& ld, const vafr_layout_s& L, double gx, double gy
 constexpr int kTexelBlock = 256;   // texels per workgroup of per-texel kernels
 int launch_fxaa(const int2* col_dev, const int32_t* blk_col_dev, int32_t n_cols, int64_t n_texels, const float* in,
                 float* out, hipStream_t stream);
+
+// vafr_shade_lp_rep on a given workspace (validation included); the
+// allocation-free entry point passes its static scratch array.
+int shade_lp_rep_ws(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right, vafr_gaze gaze,
+                    const vafr_shading* sh, vafr_layout L, float* lp_left, float* lp_right, int32_t* hit_left,
+                    int32_t* hit_right, void* ws, int64_t ws_bytes, hipStream_t stream, hipStream_t right_stream);
+// Whether the layout's tables are already on the current device (no upload).
+int layout_resident(vafr_layout L, bool* resident);
 
 // Per-view descriptors from the public arguments (validated; uploads the
 // layout tables to the current device on first use).

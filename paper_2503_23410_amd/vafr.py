@@ -237,11 +237,10 @@ def gaze(x, y):
 def shading(light_dir=(0.3, 1.0, -0.5), light_rgb=(1.0, 1.0, 1.0), ambient=(0.1, 0.1, 0.1),
             background=(0.05, 0.05, 0.08), shadow=True, mode=VAFR_SHADE_LAMBERT, bounces=0, frame=0, view=0,
             seed=0):
-    """Light direction is normalised in FP64 and rounded to FP32."""
-    ld = np.asarray(light_dir, np.float64)
-    ld = (ld / np.sqrt(np.dot(ld, ld))).astype(np.float32)
+    """light_dir: toward the light, any non-zero vector (the library
+    normalises it)."""
     s = vafr_shading()
-    s.light_dir[:] = [float(x) for x in ld]
+    s.light_dir[:] = [float(x) for x in np.float32(light_dir)]
     s.light_rgb[:] = [float(x) for x in np.float32(light_rgb)]
     s.ambient[:] = [float(x) for x in np.float32(ambient)]
     s.background[:] = [float(x) for x in np.float32(background)]

@@ -387,30 +387,54 @@ def test_tiny_and_ragged_displays(env, O, layout, soup, W, H, gaze):
     _compare(f"full {W}x{H}", out[:H * W].cpu().numpy(), hid[:H * W].cpu().numpy(), o_rgba, o_id, o_fl)
 
 
-@pytest.mark.parametrize("dist,fov", [(30.0, 4.0), (200.0, 0.6)])
-def test_far_eye_takes_both_slab_tests(env, O, soup, dist, fov):
-    """Narrow-field views from far away: eyes within 42 (1 + scene extent)
-    use the FMA slab test, farther ones the subtract-multiply test; both
-    give the oracle's hits."""
+def _look_at(eye, target):
+    eye = np.asarray(eye, np.float64)
+    fwd = np.asarray(target, np.float64) - eye
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross([0.0, 1.0, 0.0], fwd)
+    right /= np.linalg.norm(right)
+    return np.concatenate([eye, right, np.cross(fwd, right), fwd]).astype(np.float32)
+
+
+@pytest.mark.parametrize("scene,dist", [("terrain", 15.0), ("terrain", 200.0), ("soup", 30.0), ("soup", 200.0)])
+def test_far_eye_takes_both_slab_tests(env, O, soup, scene, dist):
+    """Narrow-field views from far away: eyes whose coordinates stay below
+    the scene's FMA limit (about 10.5 (1 + extent) - extent: 29.5 for the
+    terrain, 20 for the soup) use the FMA slab test, farther ones the
+    subtract-multiply test; both give the oracle's hits on every unflagged
+    ray.  Flagged rays: at most 1e-4 on the terrain, whose triangles do not
+    cross.  The soup's 4,096 triangles cross each other, and a ray near an
+    intersection line is a near tie when the two depths differ by less than
+    1e-6 t: the band around each line widens in proportion to the distance,
+    so the soup's bound is 1e-4 at the distance of its own configuration (3)
+    scaled by dist / 3."""
     torch, V = env
-    g_sc, o_sc = soup
     W, H = 256, 192
-    cam = I.soup_camera().copy()
-    cam[2] = -dist
+    if scene == "terrain":
+        v, f = I.terrain_scene(64, 32, 16, seed=9)
+        g_sc, o_sc = V.Scene(v, f), O.Scene(v, f)
+        eye = np.array([0.3, 1.0, -0.45]) / np.linalg.norm([0.3, 1.0, -0.45]) * dist
+        cam = _look_at(eye, [0.0, -0.6, 0.0])
+        fov = float(2 * np.degrees(np.arctan(1.6 / dist)))
+        flag_bound = FLAG_FRAC
+    else:
+        g_sc, o_sc = soup
+        cam = I.soup_camera().copy()
+        cam[2] = -dist
+        fov = {30.0: 4.0, 200.0: 0.6}[dist]
+        flag_bound = FLAG_FRAC * dist / 3.0
     img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
     hid = torch.empty(H * W, device="cuda", dtype=torch.int32)
     V.full_shade(g_sc, V.camera(cam), V.display(W, H, (fov, fov)), V.shading(), img, hid)
     torch.cuda.synchronize()
     o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, np.arange(W * H), W, H, (fov, fov), cam, O.shading_params())
     assert (o_id >= 0).mean() > 0.2
-    # the narrow view of 4096 crossing triangles has more near ties than the
-    # wide views above; they are excluded from the exact comparison
     unf = o_fl == 0
     g_id = hid.cpu().numpy()
     diff = np.abs(img.cpu().numpy() - o_rgba).max(axis=1)
-    log(f"far eye {dist}: flagged={int((~unf).sum())} mismatches={int((g_id != o_id)[unf].sum())} "
-        f"max_colour_err={diff[unf].max():.2e}")
-    assert (~unf).mean() < 0.01
+    log(f"far eye {scene} {dist}: flagged={int((~unf).sum())} ({(~unf).mean():.2e}, bound {flag_bound:.1e}) "
+        f"mismatches={int((g_id != o_id)[unf].sum())} max_colour_err={diff[unf].max():.2e}")
+    assert (~unf).sum() <= flag_bound * W * H
     assert np.array_equal(g_id[unf], o_id[unf])
     assert diff[unf].max() <= COLOR_TOL
 
@@ -469,9 +493,28 @@ def test_invalid_calls_raise_before_launch(env):
     with pytest.raises(V.VafrError):
         V.lmfr_reconstruct(L, V.gaze(1.0, 1.0), lp, lp)
     bad = V.shading()
-    bad.light_dir[0] = 3.0
+    bad.light_dir[0] = bad.light_dir[1] = bad.light_dir[2] = 0.0
     with pytest.raises(V.VafrError):
         V.vafr_shade_lp(sc, V.camera(I.soup_camera()), V.gaze(1.0, 1.0), bad, L, lp)
+
+
+def test_light_direction_is_normalised_by_the_library(env, O, layout, soup):
+    """light_dir is taken as a direction: a scaled copy (exact power-of-two
+    scaling) gives bit-identical LP buffers, and an arbitrary length matches
+    the oracle normalising the same FP32 input."""
+    torch, V = env
+    g_sc, o_sc = soup
+    W, H = 640, 360
+    L = V.Layout.vafr(V.display(W, H))
+    gz = (300.0, 200.0)
+    a, ha = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), V.shading(light_dir=(0.3, 1.0, -0.5)))
+    b, hb = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), V.shading(light_dir=(0.6, 2.0, -1.0)))
+    assert torch.equal(a, b) and torch.equal(ha, hb)
+    ld = (-1.7, 4.2, 0.9)
+    c, hc = _gpu_lp(torch, V, g_sc, L, gz, I.soup_camera(), V.shading(light_dir=ld))
+    o_rgba, o_id, o_fl = O.shade_vafr_texels(o_sc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz,
+                                             I.soup_camera(), O.shading_params(light_dir=ld))
+    _compare("light (-1.7, 4.2, 0.9)", c.cpu().numpy(), hc.cpu().numpy(), o_rgba, o_id, o_fl)
 
 
 def test_deep_stack_scene_matches_oracle(env, O):

@@ -9,7 +9,8 @@ Each case compares, through the C ABI:
     against the oracle's inverse map of the same buffer;
   - the full-resolution ray cast on every display pixel.
 Random soups hold long thin, tiny and degenerate triangles; flagged rays are
-reported and kept below 2% (their result is not unique)."""
+reported and, per case, kept to at most 1e-4 of the compared rays, the
+stated tolerance (their result is not unique)."""
 import numpy as np
 import pytest
 
@@ -74,7 +75,7 @@ def _check(name, g_rgba, g_id, o_rgba, o_id, flag):
           f"hit_frac={(o_id >= 0).mean():.3f}", flush=True)
     assert mism == 0
     assert worst <= COLOR_TOL
-    assert flag.mean() <= 0.02
+    assert flag.sum() <= 1e-4 * len(flag), f"{int(flag.sum())} flagged rays exceed 1e-4 of {len(flag)}"
 
 
 @pytest.mark.parametrize("k", range(N_CASES))

@@ -399,3 +399,136 @@ def test_lmfr_reconstruct_constant_and_linear(O):
     u, _ = O.lmfr_forward(W, H, gx, gy, w, h, 4.0, xs)
     want = 0.01 * (np.clip(u, 0.5, w - 0.5) - 0.5)
     assert np.max(np.abs(out[:, 0] - want)) < 1e-5
+
+
+# ------------------------------------------------- near-tie flag branches ---
+#
+# Flagged rays are left out of every exact id comparison, so each branch of
+# the flag must fire where a near tie really exists and stay quiet on clean
+# hits and misses; an over-eager flag would silently widen every parity test.
+# The right triangle (0,0), (1,0), (0,1) in the plane z = zp, seen from the
+# origin: the ray through film point (x, y) meets it at (x zp, y zp), whose
+# barycentric weights are (1 - zp(x + y), zp x, zp y).
+
+def _tri_at(zp, dx=0.0):
+    return np.array([[dx, 0, zp], [dx + 1, 0, zp], [dx, 1, zp]], np.float32)
+
+
+def _scene_of(O, *tris):
+    v = np.concatenate(tris).astype(np.float32)
+    f = np.arange(v.shape[0], dtype=np.int32).reshape(-1, 3)
+    return O.Scene(v, f, use_bvh=False), O.Scene(v, f, use_bvh=True)
+
+
+def _closest_both(O, scenes, d):
+    out = []
+    for sc in scenes:
+        ids, t, fl = sc.closest(np.zeros((len(d), 3), np.float32), np.asarray(d, np.float32))
+        out.append((ids, t, fl))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][2], out[1][2])
+    return out[0]
+
+
+# a film point 5e-7 inside the hypotenuse x + y = 1 of the triangle at z = 1,
+# one 5e-7 outside it, and a clean interior point
+_NEAR_IN = (0.25, 0.75 - 5e-7, 1.0)
+_NEAR_OUT = (0.25, 0.75 + 5e-7, 1.0)
+_CLEAN = (0.25, 0.25, 1.0)
+
+
+def test_flag_setup_margins(O):
+    """The film points above are what their names say under the watertight
+    test itself: a hit with margin below 1e-6, a miss with margin below
+    1e-6, and a hit with margin 0.25."""
+    tri = _tri_at(1.0).reshape(1, 9)
+    hit, t, m = O.watertight_many(np.zeros((3, 3), np.float32), np.array([_NEAR_IN, _NEAR_OUT, _CLEAN],
+                                                                          np.float32), np.tile(tri, (3, 1)))
+    assert list(hit) == [True, False, True]
+    assert 0 < m[0] < 1e-6 and 0 < m[1] < 1e-6 and abs(m[2] - 0.25) < 1e-6
+
+
+def test_flag_winner_near_edge(O):
+    """Branch 1: the winner's smallest barycentric weight is below 1e-6."""
+    sc = _scene_of(O, _tri_at(1.0))
+    ids, t, fl = _closest_both(O, sc, [_NEAR_IN, _CLEAN])
+    assert list(ids) == [0, 0]
+    assert list(fl) == [1, 0]
+
+
+def test_flag_runner_up_within_relative_t(O):
+    """Branch 2: a second hit lies within relative 1e-6 of the winner's t;
+    a second hit 1e-4 behind does not flag."""
+    z2_near = np.nextafter(np.float32(1.0), np.float32(2.0), dtype=np.float32) \
+        + np.float32(2 ** -23)                           # 1 + 2^-22: relative gap 2.4e-7
+    for z2, want in ((z2_near, 1), (np.float32(1.0001), 0)):
+        sc = _scene_of(O, _tri_at(1.0), _tri_at(float(z2)))
+        ids, t, fl = _closest_both(O, sc, [_CLEAN])
+        assert ids[0] == 0 and t[0] == np.float32(1.0)
+        assert fl[0] == want, (z2, fl[0])
+    # the runner-up found first (nearer triangle stored second) flags too
+    sc = _scene_of(O, _tri_at(float(z2_near)), _tri_at(1.0))
+    ids, t, fl = _closest_both(O, sc, [_CLEAN])
+    assert ids[0] == 1 and fl[0] == 1
+
+
+def test_flag_near_miss_in_front_of_winner(O):
+    """Branch 3: a triangle in front of the winner missed by less than 1e-6
+    flags the ray; the same near miss behind the winner, or a clear miss in
+    front, does not."""
+    # winner: a large triangle at z = 2 containing the whole ray bundle
+    big = np.array([[-10, -10, 2], [10, -10, 2], [0, 10, 2]], np.float32)
+    for zp, d, want in ((1.0, _NEAR_OUT, 1), (1.0, (0.25, 0.76, 1.0), 0), (3.0, (0.25 / 3, (0.75 + 5e-7) / 3, 1.0),
+                                                                             0)):
+        sc = _scene_of(O, big, _tri_at(zp))
+        hit, _, m = O.watertight_many(np.zeros((1, 3), np.float32), np.array([d], np.float32),
+                                      _tri_at(zp).reshape(1, 9))
+        ids, t, fl = _closest_both(O, sc, [d])
+        assert not hit[0] and ids[0] == 0
+        assert fl[0] == want, (zp, d, m[0], fl[0])
+
+
+def test_flag_near_miss_on_a_missing_ray(O):
+    """Branch 3 on a ray that hits nothing: a near miss anywhere in front
+    flags it; a clear miss does not."""
+    sc = _scene_of(O, _tri_at(1.0))
+    ids, t, fl = _closest_both(O, sc, [_NEAR_OUT, (0.25, 0.8, 1.0), (0.25, 0.75 + 5e-7, -1.0)])
+    assert list(ids) == [-1, -1, -1]
+    assert list(fl) == [1, 0, 0]          # the last one points away: t < 0
+
+
+def test_flag_shadow_ray_near_edge_only(O):
+    """Any-hit (shadow) rays: only near-edge candidates flag (whether the
+    test calls them hits or misses); a robust hit or a clean miss does
+    not, and a robust hit outweighs a near-edge one."""
+    z = np.zeros((1, 3), np.float32)
+    cases = [((_tri_at(1.0),), _NEAR_IN, True, 1), ((_tri_at(1.0),), _NEAR_OUT, False, 1),
+             ((_tri_at(1.0),), _CLEAN, True, 0), ((_tri_at(1.0),), (0.25, 0.8, 1.0), False, 0),
+             ((_tri_at(1.0), np.array([[-9, -9, 3], [9, -9, 3], [0, 9, 3]], np.float32)), _NEAR_OUT, True, 0)]
+    for tris, d, occ_want, fl_want in cases:
+        for sc in _scene_of(O, *tris):
+            occ, fl = sc.any(z, np.array([d], np.float32))
+            assert occ[0] == occ_want and fl[0] == fl_want, (d, occ[0], fl[0])
+
+
+def test_flag_shadow_branch_reaches_the_shaded_ray(O):
+    """A primary ray with a clean closest hit whose shadow ray only grazes
+    an occluder's edge is flagged by the shading step; moved 1e-2 away from
+    the edge it is not.  The primary ray comes in at 45 degrees so that it
+    passes nowhere near the occluder itself."""
+    ground = np.array([[-4, 0, -4], [4, 0, -4], [0, 0, 4]], np.float32)
+    org = np.array([[-0.625, 1.0, 0.125]], np.float32)
+    d = np.array([[1.0, -1.0, 0.0]], np.float32)           # hits (0.375, 0, 0.125) at t = 1
+    sh = O.shading_params(light_dir=(0.0, 1.0, 0.0))
+    for gap, want in ((5e-7, 1), (1e-2, 0)):
+        x0 = np.float32(0.375) + np.float32(gap)
+        occl = np.array([[x0, 0.5, -1.0], [x0, 0.5, 1.0], [x0 + 2.0, 0.5, 0.0]], np.float32)
+        v = np.concatenate([ground, occl])
+        f = np.arange(6, dtype=np.int32).reshape(2, 3)
+        for sc in (O.Scene(v, f, use_bvh=False), O.Scene(v, f, use_bvh=True)):
+            ids, t, cfl = sc.closest(org, d)
+            assert ids[0] == 0 and t[0] == np.float32(1.0) and cfl[0] == 0
+            rgba, sid, sfl = sc.shade(org, d, sh)
+            assert sid[0] == 0 and sfl[0] == want, (gap, sfl[0])
+            # the shadow ray misses the occluder in both cases: full light
+            alb = O.albedo([0])[0]
+            assert np.allclose(rgba[0, :3], alb * (0.1 + 1.0), atol=1e-6)
