@@ -292,6 +292,23 @@ int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_
                       int32_t* hit_left_dev, int32_t* hit_right_dev, void* workspace_dev, int64_t workspace_bytes,
                       hipStream_t stream, hipStream_t right_stream);
 
+/* Allocation-free reprojection, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): vafr_shade_lp_rep on one stream, with its workspace
+ * in a static device array of 32 MiB per GPU (held until the process ends)
+ * instead of caller memory; the call allocates nothing.  Layouts of up to
+ * 1,198,372 texels (vafr_rep_workspace_bytes <= 32 MiB; the paper's acuity
+ * layout has 1,063,314): larger ones fail with VAFR_E_BUDGET before any
+ * launch.  The layout's tables must already be on the current device (any
+ * per-frame call with the layout uploads them), else VAFR_E_UNSUPPORTED.
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents (the kernels clear what must start at zero): calls that
+ * overlap on one GPU, on any streams, race.  Buffers and other errors as
+ * vafr_shade_lp_rep. */
+int vafr_shade_lp_rep_noalloc(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right,
+                              vafr_gaze gaze, const vafr_shading* shading, vafr_layout layout, float* lp_left_dev,
+                              float* lp_right_dev, int32_t* hit_left_dev, int32_t* hit_right_dev, hipStream_t stream);
+
 /* Inverse map (Sec. 3.2.3, Eqs. (10)-(11)): every display pixel centre is
  * mapped to (u, theta) and the LP buffer is sampled with a two-column,
  * angle-consistent bilinear filter (u clamped to the first/last column

@@ -36,6 +36,7 @@ SOURCES = {
     "bvh.cpp": ["-x", "hip", "-ffp-contract=off"],
     "batch.cpp": ["-x", "hip", "-ffp-contract=off"],
     "server.cpp": ["-x", "hip", "-ffp-contract=off"],
+    "noalloc.cpp": ["-x", "hip", "-ffp-contract=off"],
     "trace.hip": ["-ffp-contract=off"],
     "reconstruct.hip": [],
     "fxaa.hip": ["-ffp-contract=off"],

@@ -38,7 +38,7 @@ EXPORTS = (
     "vafr_batch_set_profiling", "vafr_batch_stage_ms", "vafr_server_create", "vafr_server_add_headset",
     "vafr_server_submit", "vafr_server_poll", "vafr_server_release", "vafr_server_wait_idle", "vafr_server_get_stats",
     "vafr_server_destroy", "vafr_acuity_capped", "vafr_fxaa_lp", "vafr_rep_workspace_bytes", "vafr_shade_lp_rep",
-    "lafr_lp_layout", "lafr_shade_lp", "lafr_reconstruct",
+    "lafr_lp_layout", "lafr_shade_lp", "lafr_reconstruct", "vafr_shade_lp_rep_noalloc",
 )
 
 VAFR_VIEW_VAFR = 0
@@ -155,6 +155,8 @@ def load():
         "vafr_rep_workspace_bytes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
         "vafr_shade_lp_rep": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_camera), vafr_gaze,
                                         C.POINTER(vafr_shading), _P, _P, _P, _P, _P, _P, C.c_int64, _P, _P]),
+        "vafr_shade_lp_rep_noalloc": (C.c_int, [_P, C.POINTER(vafr_camera), C.POINTER(vafr_camera), vafr_gaze,
+                                                C.POINTER(vafr_shading), _P, _P, _P, _P, _P, _P]),
         "vafr_acuity_capped": (C.c_int, [C.POINTER(vafr_acuity), C.c_double, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32)]),
         "lmfr_lp_layout": (C.c_int, [C.POINTER(vafr_display), C.c_double, C.c_double, C.POINTER(_P)]),
@@ -432,6 +434,15 @@ def vafr_shade_lp_rep(scene, cam_left, cam_right, gz, sh, layout, lp_left, lp_ri
                                     _dptr(hit_right), _dptr(workspace),
                                     workspace.numel() * workspace.element_size(), _stream(stream),
                                     None if right_stream is None else _stream(right_stream)))
+
+
+def vafr_shade_lp_rep_noalloc(scene, cam_left, cam_right, gz, sh, layout, lp_left, lp_right, hit_left=None,
+                              hit_right=None, stream=None):
+    """vafr_shade_lp_rep with the library's static workspace (allocates
+    nothing; the layout must already be resident on the device)."""
+    _check(load().vafr_shade_lp_rep_noalloc(scene.handle, C.byref(cam_left), C.byref(cam_right), gz, C.byref(sh),
+                                            layout.handle, _dptr(lp_left), _dptr(lp_right), _dptr(hit_left),
+                                            _dptr(hit_right), _stream(stream)))
 
 
 def vafr_fxaa_lp(layout, lp_in, lp_out, stream=None):
