@@ -262,30 +262,37 @@ int lafr_shade_lp(vafr_scene scene, const vafr_camera* cam, vafr_gaze gaze, cons
 int vafr_fxaa_lp(vafr_layout layout, const float* lp_in_dev, float* lp_out_dev, hipStream_t stream);
 
 /* Binocular reprojection (Sec. 5.1, VaFR_Rep): shades the left eye's LP
- * buffer as vafr_shade_lp does, then builds the right eye's from it.  Each
- * left texel whose primary ray hits carries its hit point
- * p = fma(t, d, o) into the right eye: projected onto the right film plane
- * (FP32: q = p - eye; x, y, z = dot(q, right / up / forward) summed left to
- * right; film point (x / z, -(y / z)), z > 0), mapped to the LP cell holding
- * it (FP64: radius -> eccentricity by Eq. (3), abscissa by Eqs. (5)/(12),
- * column floor(u) if u < columns; row floor(theta / 360 n_i)).  The
- * nearest point wins a cell (ties: lower left texel) and the right texel
- * takes that left texel's colour and hit id; cells no point reached are
- * ray-cast with the right camera (only those: they are listed first and
- * traced as one compacted launch).  Both eyes use the gaze display point.
+ * buffer as vafr_shade_lp does, then builds the right eye's from it by
+ * forward grid warping.  The left texels' primary hit points p = fma(t, d,
+ * o) form a mesh in LP topology: the band between columns s and s + 1 is
+ * triangulated by a zipper over the two columns' texels merged by angle.
+ * Every vertex is projected onto the right film plane (FP32: q = p - eye;
+ * x, y, z = dot(q, right / up / forward) summed left to right; film point
+ * (x / z, -(y / z))); a triangle is dropped when a vertex missed, lies
+ * behind the right eye or projects to a non-finite point, when its depths
+ * differ by more than 1/10, when it is stretched to more than twice its
+ * left film size, or when its area is zero.  A right texel whose sample
+ * point (gaze + film offset) lies inside a kept triangle (FP64 edge
+ * functions) takes the triangle's perspective-correct depth; the least
+ * (depth, triangle id) wins the texel, whose colour is the
+ * perspective-correct interpolation of the three left colours and whose hit
+ * id is that of the vertex of largest weight.  Texels no kept triangle
+ * covers are ray-cast with the right camera (only those: they are listed
+ * and traced as one compacted launch).  Both eyes use the gaze display
+ * point.
  * workspace_dev: caller-owned device memory of vafr_rep_workspace_bytes()
- * bytes (hit points, cell keys, list of unreached cells), 16-byte aligned, reused across calls
- * on one stream (calls that overlap on one workspace race).  hit_left /
- * hit_right are nullable.  The LP buffers, hit-id buffers and workspace
- * must not overlap.  right_stream (nullable or equal to stream: one
- * stream) receives the ray casting of the uncovered texels, ordered after
- * the warp on stream; lp_right / hit_right are then complete in
- * right_stream's order, lp_left / hit_left in stream's, and the workspace
- * stays in use until right_stream's work is done.  A caller can so overlap
- * that latency-bound pass with work on stream, such as the left eye's
- * inverse map.  Errors: VAFR_E_ARG (NULL, overlapping or misaligned
- * buffers, small workspace, invalid camera / shading / gaze), VAFR_E_UNSUPPORTED
- * (LMFR layout), VAFR_E_HIP. */
+ * bytes (hit points, texel keys, list of uncovered texels), 16-byte
+ * aligned, reused across calls on one stream (calls that overlap on one
+ * workspace race).  hit_left / hit_right are nullable.  The LP buffers,
+ * hit-id buffers and workspace must not overlap.  right_stream (nullable or
+ * equal to stream: one stream) receives the ray casting of the uncovered
+ * texels, ordered after the warp on stream; lp_right / hit_right are then
+ * complete in right_stream's order, lp_left / hit_left in stream's, and the
+ * workspace stays in use until right_stream's work is done.  A caller can
+ * so overlap that latency-bound pass with work on stream, such as the left
+ * eye's inverse map.  Errors: VAFR_E_ARG (NULL, overlapping or misaligned
+ * buffers, small workspace, invalid camera / shading / gaze),
+ * VAFR_E_UNSUPPORTED (LMFR / LaFR layout), VAFR_E_HIP. */
 int vafr_rep_workspace_bytes(vafr_layout layout, int64_t* bytes);
 int vafr_shade_lp_rep(vafr_scene scene, const vafr_camera* cam_left, const vafr_camera* cam_right, vafr_gaze gaze,
                       const vafr_shading* shading, vafr_layout layout, float* lp_left_dev, float* lp_right_dev,

@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "vafr_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# a separately built copy (e.g. a sanitizer build) may be named instead
+_LIB_OVERRIDE = os.environ.get("VAFR_ORACLE_LIB")
 
 DEFAULT_ECC = (0.0, 10.0, 20.0, 30.0, 60.0)   # Sec. 3.3 pivots (degrees)
 DEFAULT_CPD = (40.0, 10.0, 6.0, 5.0, 4.0)     # Sec. 3.3 acuity at the pivots
@@ -42,6 +44,10 @@ def build() -> str:
 def lib():
     global _lib
     if _lib is None:
+        if _LIB_OVERRIDE:
+            _lib = C.CDLL(_LIB_OVERRIDE)
+            _declare(_lib)
+            return _lib
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
         _lib = C.CDLL(_LIB)

@@ -342,8 +342,10 @@ extern "C" int vafr_scene_get_info(vafr_scene s, vafr_scene_info* out) {
 
 extern "C" int vafr_scene_export(vafr_scene s, float* nodes, int32_t* tri_order) {
     if (!s) return fail(VAFR_E_ARG, "scene is NULL");
-    if (nodes) std::memcpy(nodes, s->host.nodes.data(), sizeof(BvhNode) * s->host.nodes.size());
-    if (tri_order) std::memcpy(tri_order, s->host.order.data(), sizeof(int32_t) * s->host.order.size());
+    if (nodes && !s->host.nodes.empty())
+        std::memcpy(nodes, s->host.nodes.data(), sizeof(BvhNode) * s->host.nodes.size());
+    if (tri_order && !s->host.order.empty())
+        std::memcpy(tri_order, s->host.order.data(), sizeof(int32_t) * s->host.order.size());
     return VAFR_OK;
 }
 
