@@ -34,26 +34,34 @@ FRAME_BUDGET_MS = 11.1    # one refresh at 90 Hz
 HBM_PEAK_GBS = 8000.0
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 
-# Algorithmic FP32 operations of one unit of traversal work, counted from the
-# arithmetic the traversal performs:
-#  - one node visit tests four quantised child boxes: per node 6 selects
-#    (entry / exit plane codes by the ray's direction signs), 3 FMAs and 3
-#    multiplies (distance to the node origin, scale / d); per child 6 code
-#    conversions and 6 FMAs for the slab distances (the benchmark's eyes are
-#    within the range where this form is conservative), 4 min/max to
-#    combine axes and clamp, 1 multiply (conservative exit) and 1 compare;
-#    then 3 adds (hit count), 4 selects (misses sort last) and a 5-exchange
-#    sorting network of (distance, reference) pairs, 1 compare + 4 selects
-#    each -> 12 + 4 * 18 + 3 + 4 + 25 = 116
+# FP32 operations of one unit of traversal work, counted from the arithmetic
+# the traversal performs:
+#  - one node visit tests four child boxes.  Algorithmic part: per node 3
+#    FMAs and 3 multiplies (distance to the node origin, scale / d); per
+#    child 6 FMAs for the slab distances (the benchmark's eyes are within
+#    the range where this form is conservative), 4 min/max to combine axes
+#    and clamp, 1 multiply (conservative exit) and 1 compare; then 3 adds
+#    (hit count), 4 selects (misses sort last) and a 5-exchange sorting
+#    network of (distance, reference) pairs, 1 compare + 4 selects each
+#    -> 6 + 4 * 12 + 3 + 4 + 25 = 86.
+#    Node-format part (the library's own 8-bit quantised node): 6 selects
+#    (entry / exit plane codes by the ray's direction signs) and per child 6
+#    byte-to-float code conversions -> 6 + 4 * 6 = 30.  These are counted
+#    separately: a node format that stored FP32 planes would not need them.
 #  - one watertight ray/triangle test: 9 subtractions (vertices - origin),
 #    6 FMAs (shear), 6 multiplies + 3 subtractions (edge functions), 2 adds
 #    (det), 3 multiplies (z scaling), 3 multiplies + 2 adds (T), 1 division,
 #    4 compares -> 39
 #  - ray set-up: 3 reciprocals, 3 multiplies (o/d), 3 divisions, 8
 #    compares/selects -> 17
-OPS_NODE = 116
+OPS_NODE = 86
+OPS_NODE_FORMAT = 30
 OPS_TRI = 39
 OPS_RAY = 17
+# frames of the comparison legs (full resolution, LMFR, LaFR, layouts, ...)
+# and of the two-frames-in-flight leg, whatever --steps says
+MIN_COMPARE_FRAMES = 20
+MIN_PIPELINED_FRAMES = 100
 
 
 def log(msg):
@@ -70,6 +78,23 @@ def kernel_source_hash():
         with open(os.path.join(ROOT, "paper_2503_23410_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def load_counters(kind):
+    """SQ counter summary of a kernel (VALU issue per SIMD per clock, active
+    lanes, resident waves) measured with rocprofv3 --pmc for the current
+    kernel sources, or None."""
+    path = os.path.join(ROOT, "profiles", "pmc_sq.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = d.get(kind)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return {k: e[k] for k in ("valu_per_simd_clock", "active_lane_frac", "resident_waves_per_simd",
+                              "wait_frac") if k in e}
 
 
 def load_traffic(kind):
@@ -99,7 +124,14 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip full-resolution and LMFR runs")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="duration of the served 8-headset workload per server configuration (0: skip)")
+    ap.add_argument("--no-pipelined", action="store_true",
+                    help="skip the two-frames-in-flight leg (kernel traces of the one-at-a-time frames)")
+    ap.add_argument("--profile-summary", metavar="DIR",
+                    help="summarise rocprofv3 output under DIR into profiles/ and exit (no GPU use)")
     args = ap.parse_args()
+    if args.profile_summary:
+        profile_summary(args.profile_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(views would be sharded across GPUs, each holding a replica of the scene, with no exchange).",
@@ -114,7 +146,7 @@ def main():
     torch.cuda.set_device(0)
     V.load()
     steps, warm = args.steps, args.warmup
-    csteps = args.compare_steps or max(3, steps // 20)
+    csteps = args.compare_steps or max(MIN_COMPARE_FRAMES, steps // 20)
 
     t = time.time()
     verts, tris = I.make_scene(SCENE)
@@ -128,7 +160,7 @@ def main():
     LM = V.Layout.lmfr(disp, 1.8, 4.0)
     cams = [V.camera(c) for c in I.binocular_cameras()]
     sh = V.shading()
-    trace = I.gaze_trace(warm + max(steps, csteps), W, H, seed=30)
+    trace = I.gaze_trace(warm + max(steps, csteps, MIN_PIPELINED_FRAMES), W, H, seed=30)
     gazes = [V.gaze(float(x), float(y)) for x, y in trace]
 
     lp = [torch.empty((L.n_texels, 4), device="cuda", dtype=torch.float32) for _ in range(2)]
@@ -215,15 +247,18 @@ def main():
     torch.cuda.synchronize()
     n_prim, n_shadow, n_nodes, n_tri = [int(x) for x in counters.cpu()]
     ops_frame = OPS_NODE * n_nodes + OPS_TRI * n_tri + OPS_RAY * (n_prim + n_shadow)
+    ops_frame_fmt = ops_frame + OPS_NODE_FORMAT * n_nodes
     recon_bytes_frame = 2 * (W * H * 16 + L.n_texels * 16)
     if path == "batched":
         # one traversal launch and one reconstruction launch per frame
         k_trace, k_recon = "k_trace_batch", "k_recon_batch"
         ops_per_launch, trace_s = ops_frame, b_trace_ms / 1e3
+        ops_fmt_per_launch = ops_frame_fmt
         recon_bytes, recon_s = recon_bytes_frame, b_recon_ms / 1e3
     else:
         k_trace, k_recon = "k_trace", "k_recon"
         ops_per_launch, trace_s = ops_frame / 2.0, float(np.mean(trace_ms)) / 1e3
+        ops_fmt_per_launch = ops_frame_fmt / 2.0
         recon_bytes, recon_s = recon_bytes_frame / 2.0, float(np.mean(recon_ms)) / 1e3
     achieved_gops = ops_per_launch / trace_s / 1e9
     rays_per_s = (n_prim + n_shadow) / (2.0 if path != "batched" else 1.0) / trace_s
@@ -236,7 +271,9 @@ def main():
     # two frames in flight: alternate batches on two streams with double
     # buffers, so one frame's reconstruction overlaps the next one's
     # traversal (throughput up, per-frame latency up)
-    out["pipelined"] = pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm, min(steps, 600))
+    if not args.no_pipelined:
+        out["pipelined"] = pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm,
+                                            max(MIN_PIPELINED_FRAMES, min(steps, 600)))
     # ------------------------------------------------------------ comparisons
     if not args.no_compare:
         # full resolution: one primary + shadow ray per display pixel, per eye
@@ -299,6 +336,7 @@ def main():
             "speedup_vs_fullres": round(fps / full_fps, 2), "speedup_vs_lmfr": round(fps / lmfr_fps, 2),
             "speedup_vs_lafr": lafr["1.8"]["speedup"],
             "fullres_grays_per_s": round(2 * 2 * W * H * full_fps / 1e9, 3),
+            "compare_frames": csteps,
         })
 
     # ------------------------------------------------------------ LP anti-aliasing
@@ -312,7 +350,7 @@ def main():
     # ------------------------------------------------------------ 16 views
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
-        out["layouts"] = layout_variants(torch, V, I, scene, sh, cams, gazes[warm:], max(20, csteps))
+        out["layouts"] = layout_variants(torch, V, I, scene, sh, cams, gazes, warm, max(20, csteps), tuned)
         out["resolutions"] = resolution_sweep(torch, V, I, scene, sh, cams, max(60, 10 * csteps), max(2, csteps))
 
     # ------------------------------------------------------------ serving
@@ -322,7 +360,7 @@ def main():
     # ------------------------------------------------------------ CPU baseline
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(verts, tris, trace[warm:], I)
+        cpu = cpu_baseline(verts, tris, trace[warm:], I, fps)
 
     del img, lp
     result = {
@@ -365,11 +403,15 @@ def main():
         "roofline": {"kernel": k_trace, "bound": "alu", "achieved": round(achieved_gops, 1),
                      "peak": round(VALU_PEAK_GOPS, 1), "unit": "Gop/s",
                      "frac": round(achieved_gops / VALU_PEAK_GOPS, 4), "traffic": load_traffic(k_trace),
-                     "launch_ms": round(trace_s * 1e3, 4), "ops_per_launch": int(ops_per_launch)},
+                     "launch_ms": round(trace_s * 1e3, 4), "ops_per_launch": int(ops_per_launch),
+                     "ops_per_unit": {"node_visit": OPS_NODE, "triangle_test": OPS_TRI, "ray": OPS_RAY},
+                     "frac_incl_node_format_decode": round(ops_fmt_per_launch / trace_s / 1e9 / VALU_PEAK_GOPS, 4),
+                     "node_format_decode_ops_per_visit": OPS_NODE_FORMAT,
+                     "counters": load_counters(k_trace)},
         "roofline_reconstruct": {"kernel": k_recon, "bound": "hbm", "achieved": round(recon_gbs, 1),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(recon_gbs / HBM_PEAK_GBS, 4),
                                  "traffic": load_traffic(k_recon), "launch_ms": round(recon_s * 1e3, 4),
-                                 "bytes_per_launch": int(recon_bytes)},
+                                 "bytes_per_launch": int(recon_bytes), "counters": load_counters(k_recon)},
         "cpu_baseline": cpu,
     }
     result.update(out)
@@ -610,11 +652,12 @@ def resolution_sweep(torch, V, I, scene, sh, cams, steps, full_steps):
     return res
 
 
-def layout_variants(torch, V, I, scene, sh, cams, gazes, steps):
+def layout_variants(torch, V, I, scene, sh, cams, gazes, warm, steps, shape):
     """Binocular 8K batched frames for the paper's layout and its variants:
     device-adapted curves held at 9 and 18 cpd (Sec. 3.3) and an
-    anisotropic tangential rate (Eq. (19)).  Same scene, cameras and gaze
-    trace; launch shape fixed (trace 64, reconstruction 8 rows)."""
+    anisotropic tangential rate (Eq. (19)).  Same scene, cameras, gaze trace,
+    launch shape (the headline's autotuned one) and warm-up as the headline
+    batched frames."""
     variants = {"standard": V.Layout.vafr(V.display(W, H, I.FOV))}
     for cap in (9.0, 18.0):
         e, c = V.acuity_capped(cap)
@@ -625,22 +668,22 @@ def layout_variants(torch, V, I, scene, sh, cams, gazes, steps):
     res = {}
     for name, Lv in variants.items():
         lp = [torch.empty((Lv.n_texels, 4), device="cuda") for _ in range(2)]
-        b = V.Batch(2, trace_block=64, recon_rows=8, use_graph=True)
+        b = V.Batch(2, trace_block=shape["trace_block"], recon_rows=shape["recon_rows"], use_graph=True)
 
         def frame(f):
             g = gazes[f % len(gazes)]
             b.run([V.view(V.VAFR_VIEW_VAFR, scene, cams[e], g, sh, layout=Lv, lp_rgba=lp[e], img_rgba=img[e])
                    for e in range(2)], stream)
 
-        for f in range(3):
+        for f in range(warm):
             frame(f)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for f in range(steps):
-            frame(f)
+            frame(warm + f)
         torch.cuda.synchronize()
         fps = steps / (time.perf_counter() - t0)
-        res[name] = {"columns": Lv.n_cols, "texels_per_eye": Lv.n_texels, "fps": round(fps, 2)}
+        res[name] = {"columns": Lv.n_cols, "texels_per_eye": Lv.n_texels, "fps": round(fps, 2), "frames": steps}
         log(f"layout {name}: {Lv.n_cols} columns, {Lv.n_texels} texels per eye, {fps:.1f} frames/s")
         b.close()
         del lp
@@ -687,7 +730,9 @@ def serving_bench(torch, V, I, scene4m, seconds):
         st = srv.stats()
         lat = serving.latency_stats(recs)
         launches = st["launches"] - st0["launches"]
-        entry = {"frames_per_s": round(lat["completed"] / wall, 2), "p50_ms": round(lat["p50_ms"], 3),
+        entry = {"frames_per_s": round(lat["completed"] / wall, 2),
+                 "completion_rate": round(lat["completed"] / max(len(arrivals), 1), 4),
+                 "p50_ms": round(lat["p50_ms"], 3),
                  "p99_ms": round(lat["p99_ms"], 3), "max_ms": round(lat["max_ms"], 3),
                  "mean_queue_ms": round(lat["mean_queue_ms"], 3), "completed": lat["completed"],
                  "refused": refused, "late": st["late"] - st0["late"],
@@ -700,41 +745,354 @@ def serving_bench(torch, V, I, scene4m, seconds):
     return res
 
 
-def cpu_baseline(verts, tris, gazes, I, n_frames=4):
-    """The oracle on the host cores, timed on whole binocular frames: both
-    eyes' LP buffers shaded in full and every display pixel reconstructed
-    (in bands of rows to bound memory), for n_frames gaze samples."""
+def cpu_baseline(verts, tris, gazes, I, gpu_fps=None):
+    """The oracle on the host cores, as it stands, in the same run: the
+    headline workload on all host threads and on one thread, each stage
+    timed on its own.  Bounded samples keep the whole leg to about 10-20 s
+    of host time:
+      - layout (FP64 tables) and the oracle's BVH build: timed once;
+      - VaFR, all threads: 2 whole binocular frames (every LP texel of both
+        eyes shaded with primary + shadow rays, every display pixel
+        reconstructed in bands of rows);
+      - VaFR, one thread: 1 binocular frame on a seeded 1/16 of the LP
+        texels and 1/64 of the display pixels, extrapolated;
+      - full resolution (GT): a seeded 1/64 of each eye's pixels (all
+        threads; 1/256 on one thread), extrapolated;
+      - LMFR(1.8): a seeded 1/64 of the LP texels and of the display pixels
+        (1/256 on one thread), extrapolated."""
     import oracle as O
     thr = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
-    O.set_threads(thr)
-    t = time.time()
-    osc = O.Scene(verts, tris)
-    log(f"oracle BVH built in {time.time() - t:.1f}s (not timed)")
+    rng = np.random.default_rng(77)
+    t0 = time.perf_counter()
     lay = O.Layout()
+    t_layout = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    osc = O.Scene(verts, tris)
+    t_bvh = time.perf_counter() - t0
     p = O.film_pitch(W, H, *I.FOV)
+    cams = I.binocular_cameras()
+    sh = O.shading_params()
+    lw, lh = O.lmfr_dims(W, H, 1.8)
     band = H // 8
-    t_shade = t_recon = 0.0
-    for f in range(n_frames):
-        gaze = (float(gazes[f][0]), float(gazes[f][1]))
-        G = O.gaze_film(W, H, p, *gaze)
-        for cam in I.binocular_cameras():
-            t0 = time.perf_counter()
-            lp, _, _ = O.shade_vafr_texels(osc, lay, np.arange(lay.n_texels), W, H, I.FOV, gaze, cam,
-                                           O.shading_params())
-            t_shade += time.perf_counter() - t0
-            for y0 in range(0, H, band):
-                pix = np.arange(y0 * W, min(H, y0 + band) * W, dtype=np.int64)
-                t0 = time.perf_counter()
-                O.vafr_reconstruct(lay, lp, W, H, p, G, pix)
-                t_recon += time.perf_counter() - t0
-    total = t_shade + t_recon
-    used = O.get_threads()
-    log(f"oracle: {n_frames} binocular frames, shade {t_shade:.2f}s, reconstruct {t_recon:.2f}s -> "
-        f"{n_frames / total:.4f} frames/s on {used} threads")
-    return {"value": round(n_frames / total, 5), "unit": "frames/s", "cores": used, "kind": "oracle",
-            "sample": f"{n_frames} whole binocular frames of the same workload (2 x {lay.n_texels} LP texels "
-                      f"shaded with primary + shadow rays, 2 x {W}x{H} pixels reconstructed), gazes from the "
-                      f"same trace; oracle BVH build excluded; shade {t_shade:.2f}s, reconstruct {t_recon:.2f}s"}
+
+    def subset(n, frac):
+        return np.sort(rng.choice(n, max(1, int(n * frac)), replace=False))
+
+    def run(threads, n_frames, tex_frac, pix_frac, gt_frac, lm_frac):
+        O.set_threads(threads)
+        used = O.get_threads()
+        t_shade = t_recon = t_full = t_lmfr = 0.0
+        for f in range(n_frames):
+            gaze = (float(gazes[f][0]), float(gazes[f][1]))
+            G = O.gaze_film(W, H, p, *gaze)
+            for cam in cams:
+                idx = np.arange(lay.n_texels) if tex_frac == 1 else subset(lay.n_texels, tex_frac)
+                a = time.perf_counter()
+                lp, _, _ = O.shade_vafr_texels(osc, lay, idx, W, H, I.FOV, gaze, cam, sh)
+                t_shade += (time.perf_counter() - a) / tex_frac
+                full_lp = lp if tex_frac == 1 else np.zeros((lay.n_texels, 4), np.float32)
+                if pix_frac == 1:
+                    for y0 in range(0, H, band):
+                        pix = np.arange(y0 * W, min(H, y0 + band) * W, dtype=np.int64)
+                        a = time.perf_counter()
+                        O.vafr_reconstruct(lay, full_lp, W, H, p, G, pix)
+                        t_recon += time.perf_counter() - a
+                else:
+                    pix = subset(W * H, pix_frac)
+                    a = time.perf_counter()
+                    O.vafr_reconstruct(lay, full_lp, W, H, p, G, pix)
+                    t_recon += (time.perf_counter() - a) / pix_frac
+            # comparisons on the first frame's gaze, both eyes
+            if f == 0:
+                for cam in cams:
+                    pix = subset(W * H, gt_frac)
+                    a = time.perf_counter()
+                    O.shade_full_pixels(osc, pix, W, H, I.FOV, cam, sh)
+                    t_full += (time.perf_counter() - a) / gt_frac
+                    idx = subset(lw * lh, lm_frac)
+                    a = time.perf_counter()
+                    O.shade_lmfr_texels(osc, idx, W, H, I.FOV, gaze, lw, lh, 4.0, cam, sh)
+                    b = time.perf_counter()
+                    O.lmfr_reconstruct(W, H, gaze[0], gaze[1], lw, lh, 4.0, np.zeros((lw * lh, 4), np.float32),
+                                       subset(W * H, lm_frac))
+                    t_lmfr += (b - a + time.perf_counter() - b) / lm_frac
+        per = (t_shade + t_recon) / n_frames
+        return {"fps": n_frames / (t_shade + t_recon), "threads": used,
+                "shade_s_per_frame": round(t_shade / n_frames, 4), "reconstruct_s_per_frame": round(t_recon / n_frames, 4),
+                "frame_s": round(per, 4), "fullres_fps": round(1.0 / t_full, 6), "lmfr_fps": round(1.0 / t_lmfr, 6)}
+
+    many = run(thr, 2, 1, 1, 1 / 64, 1 / 64)
+    one = run(1, 1, 1 / 16, 1 / 64, 1 / 256, 1 / 256)
+    log(f"oracle: layout {t_layout:.3f}s, BVH build {t_bvh:.2f}s (once); {many['threads']} threads: "
+        f"{many['fps']:.4f} binocular VaFR frames/s (shade {many['shade_s_per_frame']:.2f}s + reconstruct "
+        f"{many['reconstruct_s_per_frame']:.2f}s per frame), full resolution {many['fullres_fps']:.5f} frames/s, "
+        f"LMFR(1.8) {many['lmfr_fps']:.5f} frames/s; 1 thread: {one['fps']:.5f} VaFR frames/s, full resolution "
+        f"{one['fullres_fps']:.6f}, LMFR {one['lmfr_fps']:.6f}")
+    res = {"value": round(many["fps"], 5), "unit": "frames/s", "cores": many["threads"], "kind": "oracle",
+           "sample": f"VaFR binocular 7680x4320 frames on {many['threads']} threads: 2 whole frames (2 x "
+                     f"{lay.n_texels} LP texels with primary + shadow rays, 2 x {W}x{H} pixels reconstructed), "
+                     f"gazes from the same trace; the oracle's layout and BVH build are timed apart "
+                     f"(stages_s); full resolution and LMFR(1.8) on a seeded 1/64 of their rays / texels and "
+                     f"pixels, extrapolated",
+           "stages_s": {"layout": round(t_layout, 4), "bvh_build": round(t_bvh, 3),
+                        "shade_per_frame": many["shade_s_per_frame"],
+                        "reconstruct_per_frame": many["reconstruct_s_per_frame"]},
+           "fullres_fps": many["fullres_fps"], "lmfr_fps": many["lmfr_fps"],
+           "single_thread": {"value": round(one["fps"], 6), "unit": "frames/s", "cores": one["threads"],
+                             "sample": "1 binocular frame on a seeded 1/16 of the LP texels and 1/64 of the "
+                                       "display pixels, extrapolated; full resolution and LMFR(1.8) on a "
+                                       "seeded 1/256, extrapolated",
+                             "shade_s_per_frame": one["shade_s_per_frame"],
+                             "reconstruct_s_per_frame": one["reconstruct_s_per_frame"],
+                             "fullres_fps": one["fullres_fps"], "lmfr_fps": one["lmfr_fps"]}}
+    if gpu_fps:
+        res["gpu_over_oracle"] = round(gpu_fps / many["fps"], 1)
+    return res
+
+
+# ---------------------------------------------------------------- profiles
+# `python bench.py --profile-summary DIR` turns rocprofv3 output written
+# under DIR by the commands listed in PROFILE_COMMANDS (run from the
+# repository root with TMPDIR=/tmp, each under its own timeout) into the
+# summaries under profiles/ and the per-kernel traffic / counter files that
+# the benchmark reports while the kernel sources are unchanged.
+_HEAD = ("python3 bench.py --steps 200 --warmup 20 --no-cpu-baseline --no-compare --serve-seconds 0 "
+         "--no-pipelined")
+_SHORT = ("python3 bench.py --steps 10 --warmup 2 --no-cpu-baseline --no-compare --serve-seconds 0 "
+          "--no-pipelined")
+_SERVE = "python3 bench.py --steps 5 --warmup 2 --no-cpu-baseline --no-compare --no-pipelined --serve-seconds 3"
+_COPY = ("python3 -c \"import torch; a=torch.ones(1<<28, device='cuda'); b=torch.empty_like(a); "
+         "torch.cuda.synchronize(); [b.copy_(a) for _ in range(4)]; torch.cuda.synchronize(); print('copy done')\"")
+_SQ1 = "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_INSTS_VALU SQ_INSTS_VMEM_RD SQ_INSTS_SALU SQ_INSTS_LDS GRBM_GUI_ACTIVE"
+_SQ2 = "SQ_ACTIVE_INST_VALU SQ_THREAD_CYCLES_VALU SQ_WAIT_ANY TCC_HIT_sum TCC_MISS_sum"
+PROFILE_COMMANDS = {
+    "kt": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kt -o run -- {_HEAD} > DIR/kt.json",
+    "kts": f"rocprofv3 --kernel-trace --stats --output-format csv -d DIR/kts -o run -- {_SERVE} > DIR/kts.json",
+    "fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- {_SHORT}",
+    "write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- {_SHORT}",
+    "copy_fetch": f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/copy_fetch -o run -- {_COPY}",
+    "copy_write": f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/copy_write -o run -- {_COPY}",
+    "sq1": f"rocprofv3 --pmc {_SQ1} --output-format csv -d DIR/sq1 -o run -- {_SHORT}",
+    "sq2": f"rocprofv3 --pmc {_SQ2} --output-format csv -d DIR/sq2 -o run -- {_SHORT}",
+    "sq1s": f"rocprofv3 --pmc {_SQ1} --output-format csv -d DIR/sq1s -o run -- {_SERVE}",
+    "sq2s": f"rocprofv3 --pmc {_SQ2} --output-format csv -d DIR/sq2s -o run -- {_SERVE}",
+}
+
+
+def _short_kernel(name):
+    """Kernel name without namespace, return type and parameter list."""
+    for pre in ("vafr::(anonymous namespace)::", "void "):
+        name = name.replace(pre, "")
+    name = name.strip()
+    if name.endswith(")"):
+        depth = 0
+        for i in range(len(name) - 1, -1, -1):
+            depth += {")": 1, "(": -1}.get(name[i], 0)
+            if depth == 0:
+                name = name[:i]
+                break
+    return name.strip()
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _col(row, *names):
+    low = {k.lower(): v for k, v in row.items()}
+    for n in names:
+        if n.lower() in low:
+            return low[n.lower()]
+    raise KeyError(names)
+
+
+def _kernel_stats(d):
+    """Per kernel: calls, mean / min / max duration in microseconds, grid."""
+    out = {}
+    for r in _csv_rows(d, "kernel_trace.csv"):
+        k = _short_kernel(_col(r, "Kernel_Name"))
+        dur = (int(_col(r, "End_Timestamp")) - int(_col(r, "Start_Timestamp"))) / 1e3
+        grid = int(_col(r, "Grid_Size_X", "Grid_Size"))
+        e = out.setdefault(k, {"calls": 0, "sum": 0.0, "min": 1e30, "max": 0.0, "grid": grid})
+        e["calls"] += 1
+        e["sum"] += dur
+        e["min"] = min(e["min"], dur)
+        e["max"] = max(e["max"], dur)
+    for e in out.values():
+        e["avg"] = e["sum"] / e["calls"]
+    return out
+
+
+def _counters(d):
+    """Per (kernel, grid): mean of each counter over the dispatches."""
+    acc = {}
+    for r in _csv_rows(d, "counter_collection.csv"):
+        k = (_short_kernel(_col(r, "Kernel_Name")), int(_col(r, "Grid_Size")))
+        c = _col(r, "Counter_Name")
+        disp = _col(r, "Dispatch_Id", "Correlation_Id")
+        e = acc.setdefault(k, {}).setdefault(c, {})
+        e[disp] = e.get(disp, 0.0) + float(_col(r, "Counter_Value"))
+    return {k: {c: sum(v.values()) / len(v) for c, v in cs.items()} for k, cs in acc.items()}
+
+
+def _bench_json(path):
+    try:
+        with open(path) as f:
+            lines = [ln for ln in f.read().splitlines() if ln.startswith("{")]
+        return json.loads(lines[-1]) if lines else None
+    except OSError:
+        return None
+
+
+def profile_summary(d):
+    prof = os.path.join(ROOT, "profiles")
+    h = kernel_source_hash()
+    cmd = lambda k: PROFILE_COMMANDS[k].replace("DIR", d)
+    lines = []
+    # ---- kernel trace of the headline frames (and the roofline from it)
+    kt = _kernel_stats(os.path.join(d, "kt"))
+    bj = _bench_json(os.path.join(d, "kt.json"))
+    L = ["Kernel trace, binocular 7680x4320 VaFR on the 4,521,984-triangle terrain: per-view frames, then the",
+         "autotuner and the batched frames (one traversal + one reconstruction launch per frame, graph replay);",
+         "the two-frames-in-flight, comparison, serving and oracle legs are off, so no launch overlaps another.",
+         "", "Command (repository root, TMPDIR=/tmp):", "  " + cmd("kt"), "",
+         f"{'kernel':<52}{'grid':>10}{'calls':>7}{'avg us':>10}{'min us':>9}{'max us':>9}"]
+    for k, e in sorted(kt.items(), key=lambda kv: -kv[1]["sum"]):
+        L.append(f"{k:<52}{e['grid']:>10}{e['calls']:>7}{e['avg']:>10.2f}{e['min']:>9.2f}{e['max']:>9.2f}")
+    if bj:
+        rt, rr = bj["roofline"], bj["roofline_reconstruct"]
+        shape = bj.get("batch_shape", {})
+        kt_name = f"k_trace_batch<{shape.get('trace_block', 128)}, 24, false, false, true>"
+        kr_name = f"k_recon_batch<{shape.get('recon_rows', 8)}>"
+        L += ["", f"Roofline from these averages (work per launch from the same run's JSON line, {kt_name} and "
+                  f"{kr_name}):"]
+        if kt_name in kt:
+            a = kt[kt_name]["avg"] / 1e6
+            fr = rt["ops_per_launch"] / a / 1e9 / VALU_PEAK_GOPS
+            fr_fmt = rt["frac_incl_node_format_decode"] * rt["launch_ms"] / 1e3 / a
+            L.append(f"  traversal: {rt['ops_per_launch']:,} algorithmic ops / {a * 1e6:.2f} us = "
+                     f"{rt['ops_per_launch'] / a / 1e9:.0f} Gop/s = {fr:.3f} of {VALU_PEAK_GOPS:.0f} Gop/s "
+                     f"({fr_fmt:.3f} counting the node-format decode); the bench line's event time "
+                     f"{rt['launch_ms'] * 1e3:.2f} us gives {rt['frac']:.3f}")
+        if kr_name in kt:
+            a = kt[kr_name]["avg"] / 1e6
+            gbs = rr["bytes_per_launch"] / a / 1e9
+            L.append(f"  reconstruction: {rr['bytes_per_launch'] / 1e6:.1f} MB / {a * 1e6:.2f} us = {gbs:.0f} GB/s "
+                     f"= {gbs / HBM_PEAK_GBS:.3f} of {HBM_PEAK_GBS:.0f} GB/s; the bench line's event time "
+                     f"{rr['launch_ms'] * 1e3:.2f} us gives {rr['frac']:.3f}")
+    _write(os.path.join(prof, "binocular8k_kernel_trace.txt"), L)
+    # ---- serving kernels
+    kts = _kernel_stats(os.path.join(d, "kts"))
+    L = ["Kernel trace of the served workload: 8 headsets at 90 Hz (binocular 2560x1440 x3, 3840x2160 x3,",
+         "7680x4320 x2; 1.13M / 4.52M-triangle terrains), path-traced LP shading (1 sample, 2 bounces), 11.1 ms",
+         "frame budget, 3 s per server configuration (continuous batching, then one request per launch), after",
+         "a short headline run (5 frames).  Path-mode kernels: k_trace_batch<..., true, false> (bounces 0-1,",
+         "live paths queued) and k_trace_queue_batch (the queued second bounce).", "",
+         "Command (repository root, TMPDIR=/tmp):", "  " + cmd("kts"), "",
+         f"{'kernel':<52}{'grid':>10}{'calls':>7}{'avg us':>10}{'min us':>9}{'max us':>9}{'total ms':>10}"]
+    for k, e in sorted(kts.items(), key=lambda kv: -kv[1]["sum"]):
+        L.append(f"{k:<52}{e['grid']:>10}{e['calls']:>7}{e['avg']:>10.2f}{e['min']:>9.2f}{e['max']:>9.2f}"
+                 f"{e['sum'] / 1e3:>10.1f}")
+    _write(os.path.join(prof, "serving_path_kernel_trace.txt"), L)
+    # ---- HBM traffic
+    fe, wr = _counters(os.path.join(d, "fetch")), _counters(os.path.join(d, "write"))
+    cf, cw = _counters(os.path.join(d, "copy_fetch")), _counters(os.path.join(d, "copy_write"))
+    copy_kib = (1 << 30) / 1024.0
+    cfk = max((v.get("FETCH_SIZE", 0.0) for v in cf.values()), default=0.0)
+    cwk = max((v.get("WRITE_SIZE", 0.0) for v in cw.values()), default=0.0)
+    sf = copy_kib / cfk if cfk else 1.0
+    sw = copy_kib / cwk if cwk else 1.0
+    L = ["HBM traffic per launch from rocprofv3 PMC counters (one counter per run), binocular 7680x4320 VaFR.",
+         "", "Commands (repository root, TMPDIR=/tmp, each under timeout -s KILL):"]
+    L += ["  " + cmd(k) for k in ("fetch", "write", "copy_fetch", "copy_write")]
+    L += ["", f"Calibration: a 1 GiB device copy reads FETCH_SIZE = {cfk:.0f} KiB and WRITE_SIZE = {cwk:.0f} KiB "
+              f"per dispatch, so", f"FETCH_SIZE is scaled by {sf:.3f} and WRITE_SIZE by {sw:.3f}.", "",
+          f"{'kernel':<52}{'grid':>10}{'FETCH KiB':>12}{'WRITE KiB':>12}{'HBM MB/launch':>15}"]
+    traffic = {}
+    for key in sorted(set(fe) & set(wr)):
+        f_k, w_k = fe[key].get("FETCH_SIZE", 0.0), wr[key].get("WRITE_SIZE", 0.0)
+        mb = (f_k * sf + w_k * sw) * 1024 / 1e6
+        L.append(f"{key[0]:<52}{key[1]:>10}{f_k:>12.0f}{w_k:>12.0f}{mb:>15.1f}")
+        for kind, pre in (("k_trace_batch", "k_trace_batch<"), ("k_recon_batch", "k_recon_batch<")):
+            if key[0].startswith(pre) and bj:
+                shape = bj.get("batch_shape", {})
+                want = (f"k_trace_batch<{shape.get('trace_block', 128)}, 24, false, false, true>"
+                        if kind == "k_trace_batch" else f"k_recon_batch<{shape.get('recon_rows', 8)}>")
+                if key[0] == want:
+                    traffic[kind] = {"source_hash": h, "bytes_per_launch": int(mb * 1e6),
+                                     "calibration": {"fetch": round(sf, 4), "write": round(sw, 4)},
+                                     "kernel": want, "source": "profiles/binocular8k_hbm_traffic.txt"}
+    L += ["", "Algorithmic bytes: reconstruction of a binocular frame writes 2 x 33,177,600 x 16 B = 1061.7 MB and",
+          "reads the two LP buffers once (2 x 1,063,314 x 16 B = 34.0 MB): 1095.7 MB.  Traversal writes the two LP",
+          "buffers (34.0 MB) and reads the texel offsets and order (2 x 12.8 MB) besides the BVH and triangles",
+          "(287 MB resident, mostly served from L2 and the Infinity Cache)."]
+    _write(os.path.join(prof, "binocular8k_hbm_traffic.txt"), L)
+    if traffic:
+        with open(os.path.join(prof, "pmc_traffic.json"), "w") as f:
+            json.dump(traffic, f, indent=1)
+    # ---- SQ counters
+    sq = {}
+    L = ["Shader-sequencer and L2 counters (two passes per workload), binocular 7680x4320 VaFR and the served",
+         "path-traced workload.", "", "Commands (repository root, TMPDIR=/tmp, each under timeout -s KILL):"]
+    L += ["  " + cmd(k) for k in ("sq1", "sq2", "sq1s", "sq2s")]
+    L.append("")
+    seen = set()
+    for a, b in (("sq1", "sq2"), ("sq1s", "sq2s")):
+        c1, c2 = _counters(os.path.join(d, a)), _counters(os.path.join(d, b))
+        for key in sorted(set(c1) & set(c2), key=lambda k: (k[0], k[1])):
+            if not key[0].startswith(("k_trace", "k_recon")) or key[0].startswith("k_trace_plan"):
+                continue
+            # the serving run starts with a short headline run: list only its own kernels
+            if a == "sq1s" and key[0] in seen:
+                continue
+            if a == "sq1":
+                seen.add(key[0])
+            x = {**c1[key], **c2[key]}
+            cyc = x.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+            if cyc <= 0 or not x.get("SQ_WAVES"):
+                continue
+            valu = x.get("SQ_INSTS_VALU", 0.0)
+            per_clk = valu / (1024.0 * cyc)
+            lanes = x.get("SQ_THREAD_CYCLES_VALU", 0.0) / max(x.get("SQ_ACTIVE_INST_VALU", 1.0), 1.0) / 64.0
+            resident = x.get("SQ_WAVE_CYCLES", 0.0) * 4.0 / (1024.0 * cyc)
+            wait = x.get("SQ_WAIT_ANY", 0.0) / max(x.get("SQ_WAVE_CYCLES", 1.0), 1.0)
+            hit = x.get("TCC_HIT_sum", 0.0) / max(x.get("TCC_HIT_sum", 0.0) + x.get("TCC_MISS_sum", 0.0), 1.0)
+            L.append(f"{key[0]} (grid {key[1]}, {'served' if a == 'sq1s' else 'headline'}): GRBM_GUI_ACTIVE/8 = "
+                     f"{cyc:.0f} cycles; VALU instructions {valu:.0f} ({valu / x['SQ_WAVES']:.0f} per wave), SALU "
+                     f"{x.get('SQ_INSTS_SALU', 0):.0f}, VMEM {x.get('SQ_INSTS_VMEM_RD', 0):.0f}, LDS "
+                     f"{x.get('SQ_INSTS_LDS', 0):.0f}; wave64 VALU instructions per SIMD per clock {per_clk:.3f}; "
+                     f"active lanes per VALU instruction {lanes:.0%}; mean resident waves per SIMD {resident:.1f}; "
+                     f"waves waiting {wait:.0%} of their cycles; L2 hit rate {hit:.0%}")
+            L.append("")
+            entry = {"source_hash": h, "grid": key[1], "valu_per_simd_clock": round(per_clk, 4),
+                     "active_lane_frac": round(lanes, 4), "resident_waves_per_simd": round(resident, 2),
+                     "wait_frac": round(wait, 4), "source": "profiles/sq_counters.txt"}
+            if a == "sq1" and bj:
+                shape = bj.get("batch_shape", {})
+                if key[0] == f"k_trace_batch<{shape.get('trace_block', 128)}, 24, false, false, true>":
+                    sq["k_trace_batch"] = {**entry, "kernel": key[0]}
+                if key[0] == f"k_recon_batch<{shape.get('recon_rows', 8)}>":
+                    sq["k_recon_batch"] = {**entry, "kernel": key[0]}
+            sq.setdefault("by_kernel", {})[f"{key[0]} grid {key[1]}"] = entry
+    L += ["Cycles are GRBM_GUI_ACTIVE summed over the 8 XCDs divided by 8 (it matches the kernel duration at",
+          "2.4 GHz).  Active lanes = SQ_THREAD_CYCLES_VALU / SQ_ACTIVE_INST_VALU / 64.  Resident waves =",
+          "SQ_WAVE_CYCLES (quad-cycles) x 4 / (1024 SIMDs x cycles).  Waiting = SQ_WAIT_ANY / SQ_WAVE_CYCLES."]
+    _write(os.path.join(prof, "sq_counters.txt"), L)
+    if sq:
+        with open(os.path.join(prof, "pmc_sq.json"), "w") as f:
+            json.dump(sq, f, indent=1)
+    print(f"profiles written from {d} (kernel source hash {h})")
+
+
+def _write(path, lines):
+    with open(path, "w") as f:
+        f.write("\n".join(lines).rstrip() + "\n")
 
 
 if __name__ == "__main__":
