@@ -1,9 +1,11 @@
 // Batched frames: every view's rays in ONE traversal launch, every display
 // in ONE reconstruction launch, optionally replayed from a hipGraph whose
 // node parameters are updated per frame, and an autotuner for the launch
-// shape.  Path-mode views with two or more bounces run their later bounces
-// in a second traversal pass over the paths still alive (a compacted queue
-// per view), so that the waves of that pass are full of live paths.
+// shape.  Path-mode views run in phases: bounces 0-1 in the traversal
+// launch, each later bounce in a launch of its own over the paths still
+// alive (a compacted list per view), so that the waves of those launches
+// are full of live paths; between bounces every path's state lives in
+// memory, so none is held in registers across a traversal.
 //
 // Per frame the host writes the view descriptors into one slot of a ring of
 // pinned staging buffers; the slot is copied to its device twin on the
@@ -28,8 +30,9 @@ struct Slot {
     char* host = nullptr;   // pinned staging
     char* dev = nullptr;    // device twin
     int32_t* order = nullptr;   // planned dispatch order of this slot's traversal launch
-    float4* queue = nullptr;    // live paths of the two-pass path-mode views (4 float4 each)
-    int64_t queue_cap = 0;      // capacity in paths
+    float4* state = nullptr;    // path state of the phased path-mode views (4 float4 per path)
+    int32_t* list = nullptr;    // two lists of path ids per path-mode view
+    int64_t state_cap = 0;      // capacity in paths
     hipEvent_t done = nullptr;
     bool used = false;
     // stage timing (when profiling): before upload, after upload, after
@@ -41,11 +44,12 @@ struct Slot {
 // A graph for one launch shape.
 struct GraphEntry {
     int n_trace = 0, n_recon = 0, trace_blocks = 0, recon_blocks = 0, trace_block = 0, recon_rows = 0, stack = 0;
-    int queue_blocks = 0;
+    int queue_blocks = 0, bounces = 0;   // queue launches: one per bounce 1 .. bounces
     bool lambert = false;   // traversal kernel without the path-tracing code
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, kqueue = nullptr, krecon = nullptr;
+    hipGraphNode_t copy = nullptr, kplan = nullptr, ktrace = nullptr, krecon = nullptr;
+    hipGraphNode_t kqueue[vafr::kMaxBounces] = {};
     bool timed = false;
     hipGraphNode_t evn[4] = {nullptr, nullptr, nullptr, nullptr};
 };
@@ -58,8 +62,9 @@ struct vafr_batch_s {
     vafr_batch_config cfg{vafr::kTraceBlockDefault, vafr::kReconRowsDefault, 1};
     int device = -1;
     // staging layout: TraceView[], traversal block ends, ReconView[],
-    // reconstruction block ends, queue-pass block ends, queue counters (the
-    // counters stay zero on the host, so every upload clears them)
+    // reconstruction block ends, queue-pass block ends, per view the counts
+    // of listed paths per bounce (they stay zero on the host, so every
+    // upload clears them)
     size_t off_tb = 0, off_rv = 0, off_rb = 0, off_qb = 0, off_qc = 0, bytes = 0;
     vafr::Slot slot[vafr::kSlots];
     int next = 0;
@@ -71,8 +76,9 @@ struct vafr_batch_s {
     int stack = vafr::kStackShort;   // stack class of the frame's traversal launch
     bool lambert = true;             // no view of the frame is path-traced
     std::vector<int32_t> tb, rb, qb;
-    std::vector<int64_t> qoff;       // first queue entry of each view
-    int64_t queue_items = 0;         // queue entries the frame needs
+    std::vector<int64_t> qoff;       // first path-state entry of each view
+    int64_t queue_items = 0;         // path-state entries the frame needs
+    int bounces = 0;                 // most bounces of a path-mode view of the frame
     bool profiling = false;
     double stage_sum[3] = {0, 0, 0};   // accumulated stage times (ms)
     int64_t stage_frames = 0;
@@ -111,6 +117,7 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     b->qb.clear();
     b->qoff.clear();
     b->queue_items = 0;
+    b->bounces = 0;
     int64_t tsum = 0, rsum = 0, qsum = 0;
     b->stack = kStackShort;
     b->lambert = true;
@@ -135,14 +142,17 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
         tsum += (t.n_items + b->cfg.trace_block - 1) / b->cfg.trace_block;
         if (tsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
         b->stack = std::max(b->stack, (int)t.stack);
-        // path mode with two or more bounces: two passes (queue pointers
-        // are filled in per slot)
+        // path mode runs in phases (state and list pointers are filled in
+        // per slot)
         b->qoff.push_back(b->queue_items);
-        if (t.shade_mode == VAFR_SHADE_PATH) b->lambert = false;
-        if (t.shade_mode == VAFR_SHADE_PATH && t.bounces > kPathSplitBounce) {
-            t.pt_split = kPathSplitBounce;
+        if (t.shade_mode == VAFR_SHADE_PATH) {
+            if (t.n_items > 0x7fffffff)
+                return fail(VAFR_E_UNSUPPORTED, "view %d: path-mode views hold fewer than 2^31 rays", i);
+            b->lambert = false;
+            t.pt_phased = 1;
             b->queue_items += t.n_items;
-            qsum += (t.n_items + kQueueBlock - 1) / kQueueBlock;
+            b->bounces = std::max(b->bounces, (int)t.bounces);
+            if (t.bounces > kPathFuse) qsum += (t.n_items + kQueueBlock - 1) / kQueueBlock;
             if (qsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many rays in one batch");
         }
         b->qb.push_back((int32_t)qsum);
@@ -163,26 +173,42 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
     return VAFR_OK;
 }
 
-// Room for `items` queued paths in slot s (the slot is idle when called).
-int ensure_queue(Slot& s, int64_t items) {
-    if (items <= s.queue_cap) return VAFR_OK;
-    (void)hipFree(s.queue);
-    s.queue = nullptr;
-    s.queue_cap = 0;
-    if (hipMalloc(reinterpret_cast<void**>(&s.queue), 4 * sizeof(float4) * (size_t)items) != hipSuccess)
-        return fail(VAFR_E_OOM, "path queue allocation failed");
-    s.queue_cap = items;
+// Room for the state and lists of `items` paths in slot s (the slot is idle
+// when called).
+int ensure_state(Slot& s, int64_t items) {
+    if (items <= s.state_cap) return VAFR_OK;
+    (void)hipFree(s.state);
+    (void)hipFree(s.list);
+    s.state = nullptr;
+    s.list = nullptr;
+    s.state_cap = 0;
+    if (hipMalloc(reinterpret_cast<void**>(&s.state), 4 * sizeof(float4) * (size_t)items) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&s.list), 2 * sizeof(int32_t) * (size_t)items) != hipSuccess)
+        return fail(VAFR_E_OOM, "path state allocation failed");
+    s.state_cap = items;
     return VAFR_OK;
 }
 
-hipKernelNodeParams queue_params(vafr_batch b, const GraphEntry& g, char* dev, void** args, const TraceView** v,
-                                 const int32_t** qe, int32_t* n) {
-    *v = reinterpret_cast<const TraceView*>(dev);
-    *qe = reinterpret_cast<const int32_t*>(dev + b->off_qb);
-    *n = g.n_trace;
-    args[0] = v;
-    args[1] = qe;
-    args[2] = n;
+// Kernel arguments of one queue launch (bounce >= 1); the pointed-to values
+// must outlive the call that consumes the parameters.
+struct QueueArgs {
+    const TraceView* v;
+    const int32_t* qe;
+    int32_t n;
+    int32_t bounce;
+    void* p[4];
+};
+
+hipKernelNodeParams queue_params(vafr_batch b, const GraphEntry& g, char* dev, int bounce, QueueArgs& a) {
+    a.v = reinterpret_cast<const TraceView*>(dev);
+    a.qe = reinterpret_cast<const int32_t*>(dev + b->off_qb);
+    a.n = g.n_trace;
+    a.bounce = bounce;
+    a.p[0] = &a.v;
+    a.p[1] = &a.qe;
+    a.p[2] = &a.n;
+    a.p[3] = &a.bounce;
+    void** args = a.p;
     hipKernelNodeParams p{};
     p.func = const_cast<void*>(trace_queue_batch_kernel(g.stack));
     p.gridDim = dim3((unsigned)g.queue_blocks);
@@ -221,7 +247,7 @@ hipKernelNodeParams trace_params(vafr_batch b, const GraphEntry& g, const Slot& 
     a.p[5] = &a.cost;
     void** args = a.p;
     hipKernelNodeParams p{};
-    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack, g.queue_blocks > 0, g.lambert));
+    p.func = const_cast<void*>(trace_batch_kernel(g.trace_block, g.stack, !g.lambert, g.lambert));
     p.gridDim = dim3((unsigned)g.trace_blocks);
     p.blockDim = dim3((unsigned)g.trace_block);
     p.sharedMemBytes = 0;
@@ -303,7 +329,8 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
     const int nt = (int)b->tv.size(), nr = (int)b->rv.size();
     for (auto& g : b->graphs)
         if (g.n_trace == nt && g.n_recon == nr && g.trace_blocks == trace_blocks && g.recon_blocks == recon_blocks &&
-            g.queue_blocks == queue_blocks && g.lambert == b->lambert && g.trace_block == b->cfg.trace_block &&
+            g.queue_blocks == queue_blocks && g.bounces == (queue_blocks > 0 ? b->bounces : 0) &&
+            g.lambert == b->lambert && g.trace_block == b->cfg.trace_block &&
             g.recon_rows == b->cfg.recon_rows && g.stack == b->stack && g.timed == b->profiling) {
             *out = &g;
             return VAFR_OK;
@@ -319,6 +346,7 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
     g.trace_blocks = trace_blocks;
     g.recon_blocks = recon_blocks;
     g.queue_blocks = queue_blocks;
+    g.bounces = queue_blocks > 0 ? b->bounces : 0;
     g.lambert = b->lambert;
     g.trace_block = b->cfg.trace_block;
     g.recon_rows = b->cfg.recon_rows;
@@ -345,15 +373,13 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
             e = hipGraphAddKernelNode(&g.ktrace, g.graph, &dep, 1, &p);
         }
     }
-    void* qa[3];
-    const TraceView* qv;
-    const int32_t* qe;
-    int32_t qn;
-    if (e == hipSuccess && g.ktrace && queue_blocks > 0) {
-        hipKernelNodeParams p = queue_params(b, g, s.dev, qa, &qv, &qe, &qn);
-        e = hipGraphAddKernelNode(&g.kqueue, g.graph, &g.ktrace, 1, &p);
+    QueueArgs qa[kMaxBounces];
+    hipGraphNode_t traced = g.ktrace;
+    for (int k = kPathFuse + 1; e == hipSuccess && traced && k <= g.bounces; ++k) {
+        hipKernelNodeParams p = queue_params(b, g, s.dev, k, qa[k - 1]);
+        e = hipGraphAddKernelNode(&g.kqueue[k - 1], g.graph, &traced, 1, &p);
+        traced = g.kqueue[k - 1];
     }
-    hipGraphNode_t traced = g.kqueue ? g.kqueue : g.ktrace;
     if (e == hipSuccess && g.timed) {
         hipGraphNode_t dep = traced ? traced : g.evn[1];
         e = hipGraphAddEventRecordNode(&g.evn[2], g.graph, &dep, 1, s.ev[2]);
@@ -413,13 +439,14 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
         VAFR_HIP(hipEventSynchronize(s.done));
         if (int rc = fold_slot(b, s)) return rc;
     }
-    if (qblocks > 0) {
-        if (int rc = ensure_queue(s, b->queue_items)) return rc;
+    if (b->queue_items > 0) {
+        if (int rc = ensure_state(s, b->queue_items)) return rc;
         uint32_t* counters = reinterpret_cast<uint32_t*>(s.dev + b->off_qc);
         for (size_t i = 0; i < b->tv.size(); ++i)
-            if (b->tv[i].pt_split >= 0) {
-                b->tv[i].pt_queue = s.queue + 4 * b->qoff[i];
-                b->tv[i].pt_count = counters + i;
+            if (b->tv[i].pt_phased) {
+                b->tv[i].pt_state = s.state + 4 * b->qoff[i];
+                b->tv[i].pt_list = s.list + 2 * b->qoff[i];
+                b->tv[i].pt_count = counters + i * (kMaxBounces + 1);
             }
     }
     std::memcpy(s.host, b->tv.data(), sizeof(TraceView) * b->tv.size());
@@ -445,13 +472,10 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             hipKernelNodeParams p = trace_params(b, *g, s, ta);
             VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->ktrace, &p));
         }
-        void* qa[3];
-        const TraceView* qv;
-        const int32_t* qe;
-        int32_t qn;
-        if (g->kqueue) {
-            hipKernelNodeParams p = queue_params(b, *g, s.dev, qa, &qv, &qe, &qn);
-            VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->kqueue, &p));
+        QueueArgs qa[kMaxBounces];
+        for (int k = kPathFuse + 1; k <= g->bounces; ++k) {
+            hipKernelNodeParams p = queue_params(b, *g, s.dev, k, qa[k - 1]);
+            VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->kqueue[k - 1], &p));
         }
         void* ra[3];
         const ReconView* rvp;
@@ -470,14 +494,14 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             if (int rc = launch_trace_plan(b->cost, s.order, tblocks, stream)) return rc;
         if (int rc = launch_trace_batch(reinterpret_cast<const TraceView*>(s.dev),
                                         reinterpret_cast<const int32_t*>(s.dev + b->off_tb), (int32_t)b->tv.size(),
-                                        tblocks, b->cfg.trace_block, b->stack, qblocks > 0, b->lambert, stream,
+                                        tblocks, b->cfg.trace_block, b->stack, !b->lambert, b->lambert, stream,
                                         nullptr,
                                         planned ? s.order : nullptr, planned ? b->cost : nullptr))
             return rc;
-        if (qblocks > 0)
+        for (int k = kPathFuse + 1; qblocks > 0 && k <= b->bounces; ++k)
             if (int rc = launch_trace_queue_batch(reinterpret_cast<const TraceView*>(s.dev),
                                                   reinterpret_cast<const int32_t*>(s.dev + b->off_qb),
-                                                  (int32_t)b->tv.size(), qblocks, b->stack, stream))
+                                                  (int32_t)b->tv.size(), qblocks, b->stack, k, stream))
                 return rc;
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[2], stream));
         if (int rc = launch_reconstruct_batch(reinterpret_cast<const ReconView*>(s.dev + b->off_rv),
@@ -514,7 +538,7 @@ extern "C" int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg
     b->off_rb = b->off_rv + align256(sizeof(ReconView) * max_views);
     b->off_qb = b->off_rb + align256(sizeof(int32_t) * max_views);
     b->off_qc = b->off_qb + align256(sizeof(int32_t) * max_views);
-    b->bytes = b->off_qc + align256(sizeof(uint32_t) * max_views);
+    b->bytes = b->off_qc + align256(sizeof(uint32_t) * (kMaxBounces + 1) * max_views);
     auto bail = [&](int code) {
         vafr_batch_destroy(b);
         return code;
@@ -657,7 +681,8 @@ extern "C" void vafr_batch_destroy(vafr_batch b) {
             if (ev) (void)hipEventDestroy(ev);
         if (s.dev) (void)hipFree(s.dev);
         if (s.order) (void)hipFree(s.order);
-        if (s.queue) (void)hipFree(s.queue);
+        if (s.state) (void)hipFree(s.state);
+        if (s.list) (void)hipFree(s.list);
         if (s.host) (void)hipHostFree(s.host);
     }
     if (b->cost) (void)hipFree(b->cost);

@@ -563,61 +563,125 @@ __device__ float4 shade_path(const TraceView& v, RayPre r, uint32_t texel, int* 
     return make_float4(L.x, L.y, L.z, 1.0f);
 }
 
-// First pass of a two-pass path-mode view: bounces 0 .. pt_split; a path
-// still alive is appended to the view's queue (one atomic per wave: the
-// wave's first queuing lane reserves the entries, each lane takes the slot
-// of its rank among the queuing lanes).
+// Compiler-level memory fence: memory written before it is stored before
+// it, and memory read after it is loaded again, so that the path state of a
+// phased path-mode bounce lives in memory, not in registers, while a
+// traversal runs (no instruction is emitted).
+__device__ __forceinline__ void state_fence() { __asm__ __volatile__("" ::: "memory"); }
+
+// Bounce `bnc` of a phased path-mode view (batched launches): path p (its
+// trace item) with ray r and output index `out`; its throughput and
+// radiance so far are (1, 1, 1) and 0 on bounce 0 and come from the path's
+// state on later bounces.  The same operations as path_segment, in the
+// same order: closest hit; a miss adds thr x background and ends the path;
+// a hit multiplies thr by the albedo, and when bounces remain writes the
+// next ray (cosine-weighted about the face-forwarded normal, keyed by
+// (texel, bnc)) to the path's state and, with `list`, lists p for bounce
+// bnc + 1 (one atomic per wave); then the shadow ray toward the light when
+// n.l > 0, and L += thr (ambient + light n.l vis), the final radiance on
+// the last bounce.  Returns whether the path continues (its next ray is in
+// the state).
+// Throughput and radiance are read from the state after the closest-hit
+// traversal, and throughput, n.l and radiance go through it across the
+// shadow ray, so none of them is live during a traversal.  Bounce 0
+// reports the primary hit id and point.
 template <int B, int S>
-__device__ void path_first_pass(const TraceView& v, RayPre r, int64_t out, int* stk) {
-    float3 thr = make_float3(1.0f, 1.0f, 1.0f), L = make_float3(0.0f, 0.0f, 0.0f);
-    int id = -1;
-    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+__device__ bool path_bounce(const TraceView& v, RayPre& r, int32_t p, int32_t out, int bnc, int* stk, bool list) {
     WorkCount wc;
-    uint32_t n_shadow = 0;
-    const bool ended = path_segment<B, S, false>(v, r, (uint32_t)out, stk, thr, L, 0, v.pt_split, id, p, wc,
-                                                 n_shadow);
-    if (v.out_id) v.out_id[out] = id;
-    if (v.out_p) v.out_p[out] = p;
-    const uint64_t queued = __ballot(!ended);
-    if (ended) {
-        v.out_rgba[out] = make_float4(L.x, L.y, L.z, 1.0f);
-        return;
+    float t;
+    int id;
+    const int slot = closest_hit<B, S, false>(v, r, stk, t, id, wc);
+    if (bnc == 0) {
+        if (v.out_id) v.out_id[out] = id;
+        if (v.out_p)
+            v.out_p[out] = slot >= 0 ? make_float4(fmaf(t, r.dx, r.ox), fmaf(t, r.dy, r.oy), fmaf(t, r.dz, r.oz), 1.0f)
+                                     : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    const int lane = (int)__lane_id();
-    const int leader = __builtin_ctzll(queued);
-    const int rank = __popcll(queued & ((1ull << lane) - 1ull));
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(v.pt_count, (uint32_t)__popcll(queued));
-    base = __shfl(base, leader, 64);
-    float4* e = v.pt_queue + 4 * (size_t)(base + (uint32_t)rank);
-    e[0] = make_float4(r.ox, r.oy, r.oz, __int_as_float((int)out));
-    e[1] = make_float4(r.dx, r.dy, r.dz, __int_as_float(v.pt_split + 1));
-    e[2] = make_float4(thr.x, thr.y, thr.z, 0.0f);
-    e[3] = make_float4(L.x, L.y, L.z, 0.0f);
+    float4* st = v.pt_state + 4 * (size_t)p;
+    state_fence();
+    float3 thr = make_float3(1.0f, 1.0f, 1.0f), L = make_float3(0.0f, 0.0f, 0.0f);
+    if (bnc > 0) {
+        const float4 th = st[2], lr = st[3];
+        thr = make_float3(th.x, th.y, th.z);
+        L = make_float3(lr.x, lr.y, lr.z);
+    }
+    if (slot < 0) {
+        L.x += thr.x * v.background[0];
+        L.y += thr.y * v.background[1];
+        L.z += thr.z * v.background[2];
+        v.out_rgba[out] = make_float4(L.x, L.y, L.z, 1.0f);
+        return false;
+    }
+    const float4* tp = v.tris + 3 * (size_t)slot;
+    float3 n, os;
+    hit_frame(ldg4(tp, 0), ldg4(tp, 1), ldg4(tp, 2), r, t, n, os);
+    const float ndl = (n.x * v.light_dir[0] + n.y * v.light_dir[1]) + n.z * v.light_dir[2];
+    const float3 a = albedo_of(id);
+    thr = make_float3(thr.x * a.x, thr.y * a.y, thr.z * a.z);
+    const bool more = bnc < v.bounces;
+    if (more) {
+        const float3 w = cosine_dir(v, n, (uint32_t)out, (uint32_t)bnc);
+        st[0] = make_float4(os.x, os.y, os.z, __int_as_float(out));
+        st[1] = make_float4(w.x, w.y, w.z, 0.0f);
+        if (list) {
+            const uint64_t m = __ballot(1);
+            const int lane = (int)__lane_id();
+            const int leader = __builtin_ctzll(m);
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(v.pt_count + bnc + 1, (uint32_t)__popcll(m));
+            base = __shfl(base, leader, 64);
+            v.pt_list[((bnc + 1) & 1) * v.n_items + base + __popcll(m & ((1ull << lane) - 1ull))] = p;
+        }
+    }
+    st[2] = make_float4(thr.x, thr.y, thr.z, ndl);
+    st[3] = make_float4(L.x, L.y, L.z, 0.0f);
+    float vis = 0.0f;
+    state_fence();
+    if (ndl > 0.0f) {
+        RayPre s;
+        ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
+        vis = any_hit<B, S, false>(v, s, stk, wc) ? 0.0f : 1.0f;
+    }
+    state_fence();
+    const float4 th = st[2], lr = st[3];
+    const float4 c = make_float4(lr.x + th.x * (v.ambient[0] + v.light_rgb[0] * th.w * vis),
+                                 lr.y + th.y * (v.ambient[1] + v.light_rgb[1] * th.w * vis),
+                                 lr.z + th.z * (v.ambient[2] + v.light_rgb[2] * th.w * vis), more ? 0.0f : 1.0f);
+    if (more) st[3] = c;
+    else v.out_rgba[out] = c;
+    return more;
 }
 
 // One ray per thread: item `k` of view `v`.  kCount: diagnostic pass that
 // counts work into counters[0..3] = primary rays, shadow rays, node visits,
-// triangle tests, and writes no image.  kSplit: the kernel may serve
-// two-pass path-mode views (compiled only into the batched kernels that a
-// frame with such views launches, so the others keep their register count).
-// kLambert: every view of the launch is Lambert-shaded, so the path-tracing
-// code is left out of the kernel.
-template <int B, int S, bool kCount, bool kSplit = false, bool kLambert = false>
+// triangle tests, and writes no image.  kPhased: path-mode views of the
+// launch run their bounce 0 as the first phase of path_bounce (batched
+// launches only).  kLambert: every view of the launch is Lambert-shaded, so
+// the path-tracing code is left out of the kernel.
+template <int B, int S, bool kCount, bool kPhased = false, bool kLambert = false>
 __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* stack, unsigned long long* counters) {
     RayPre r;
     int64_t out;
     if (k >= v.n_items || !make_item_ray(v, k, r, out)) return;
     int* stk = stack + threadIdx.x;
-    if (kSplit && v.pt_split >= 0) {
-        path_first_pass<B, S>(v, r, out, stk);
+    if (kPhased && v.pt_phased) {
+        // bounces 0 .. kPathFuse by this thread (few paths end before then,
+        // and this launch's blocks are XCD-aware and planned); a path still
+        // alive after bounce kPathFuse is listed for the queue launches
+        const float4* st = v.pt_state + 4 * (size_t)k;
+        for (int bnc = 0;; ++bnc) {
+            if (!path_bounce<B, S>(v, r, (int32_t)k, (int32_t)out, bnc, stk, bnc >= kPathFuse) || bnc >= kPathFuse)
+                break;
+            const float4 e0 = st[0], e1 = st[1];
+            ray_setup(e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, r);
+        }
         return;
     }
     int id;
     float4 c, p;
     WorkCount wc;
     uint32_t n_shadow = 0;
-    if (!kLambert && v.shade_mode == VAFR_SHADE_PATH)
+    if (!kLambert && !kPhased && v.shade_mode == VAFR_SHADE_PATH)
         c = shade_path<B, S, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
     else
         c = shade_lambert<B, S, kCount>(v, r, stk, id, wc, n_shadow, p);
@@ -634,13 +698,16 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
 }
 
 // Register budget of the traversal kernels, in waves per SIMD (512 VGPRs per
-// lane over that many waves, in allocation steps of 8).  Kernels that may
-// path-trace keep five waves (at most 96 VGPRs): below that their extra
-// state spills, and without the budget the path-mode batch variant takes 113
-// VGPRs and runs 8% slower.  The Lambert-only kernels need 63-64 VGPRs
-// (eight waves); their budget of six only keeps them from growing.
+// lane over that many waves, in allocation steps of 8).  Kernels that trace
+// whole paths in one pass (per-view path mode, the reprojection's list)
+// keep five waves (at most 96 VGPRs): below that their extra state spills.
+// The Lambert-only kernels need 63-64 VGPRs (eight waves); their budget of
+// six only keeps them from growing.  The phased path-mode kernels hold no
+// path state across a traversal and take the eight-wave budget (64 VGPRs)
+// without spilling.
 #define kTraceWaves(lambert) __attribute__((amdgpu_waves_per_eu((lambert) ? 6 : 5)))
 #define kFiveWaves kTraceWaves(false)
+#define kBatchWaves(lambert, phased) __attribute__((amdgpu_waves_per_eu((phased) ? 8 : ((lambert) ? 6 : 5))))
 
 // Workgroups are dispatched to the 8 XCDs round-robin.  Work items are
 // permuted so that XCD q receives the q-th contiguous eighth of the items:
@@ -661,14 +728,13 @@ __global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace(const TraceVi
     trace_item<B, S, kCount, false, kLambert>(v, (int64_t)b * B + threadIdx.x, stack, counters);
 }
 
-// Queue pass of two-pass path-mode views (batched): workgroup b serves view
-// vid with qblock_end[vid-1] <= b < qblock_end[vid]; its thread q finishes
-// the view's queued path q while q < *pt_count (workgroups past the count
-// exit at once) and writes the pixel's radiance.
+// Bounce `bounce` > kPathFuse of the phased path-mode views (batched): workgroup b
+// serves view vid with qblock_end[vid-1] <= b < qblock_end[vid]; its thread q
+// traces path list[q] of the bounce while q < pt_count[bounce] (workgroups
+// past the count exit at once).
 template <int S>
-__global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceView* __restrict__ views,
-                                                                   const int32_t* __restrict__ qblock_end,
-                                                                   int32_t n_views) {
+__global__ __launch_bounds__(kQueueBlock) kBatchWaves(false, true) void k_trace_queue_batch(
+    const TraceView* __restrict__ views, const int32_t* __restrict__ qblock_end, int32_t n_views, int32_t bounce) {
     __shared__ int stack[lds_entries(S) * kQueueBlock];
     const int b = blockIdx.x;
     int vid = 0;
@@ -676,20 +742,13 @@ __global__ __launch_bounds__(kQueueBlock) void k_trace_queue_batch(const TraceVi
     const TraceView& v = views[vid];
     const int first = vid ? qblock_end[vid - 1] : 0;
     const int64_t q = (int64_t)(b - first) * kQueueBlock + threadIdx.x;
-    if (v.pt_split < 0 || q >= (int64_t)*v.pt_count) return;
-    const float4* e = v.pt_queue + 4 * q;
-    const float4 e0 = e[0], e1 = e[1], e2 = e[2], e3 = e[3];
+    if (!v.pt_phased || bounce > v.bounces || q >= (int64_t)v.pt_count[bounce]) return;
+    const int32_t p = v.pt_list[(bounce & 1) * v.n_items + q];
+    const float4* e = v.pt_state + 4 * (size_t)p;
+    const float4 e0 = e[0], e1 = e[1];
     RayPre r;
     ray_setup(e0.x, e0.y, e0.z, e1.x, e1.y, e1.z, r);
-    const int out = __float_as_int(e0.w);
-    float3 thr = make_float3(e2.x, e2.y, e2.z), L = make_float3(e3.x, e3.y, e3.z);
-    int id = -1;
-    float4 p;
-    WorkCount wc;
-    uint32_t n_shadow = 0;
-    path_segment<kQueueBlock, S, false>(v, r, (uint32_t)out, stack + threadIdx.x, thr, L, __float_as_int(e1.w),
-                                        0x7fffffff, id, p, wc, n_shadow);
-    v.out_rgba[out] = make_float4(L.x, L.y, L.z, 1.0f);
+    path_bounce<kQueueBlock, S>(v, r, p, __float_as_int(e0.w), bounce, stack + threadIdx.x, true);
 }
 
 // List mode: thread q < *item_count traces item item_list[q].  The grid is
@@ -710,8 +769,8 @@ __global__ __launch_bounds__(B) kFiveWaves void k_trace_list(const TraceView v) 
 // order (nullable): per XCD, the dispatch order of its workgroups'
 // blocks (see k_trace_plan); cost (nullable): each block's duration in
 // 100 MHz ticks, the larger of its waves', kept for the next frame's plan.
-template <int B, int S, bool kCount, bool kSplit, bool kLambert>
-__global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace_batch(const TraceView* __restrict__ views,
+template <int B, int S, bool kCount, bool kPhased, bool kLambert>
+__global__ __launch_bounds__(B) kBatchWaves(kLambert, kPhased) void k_trace_batch(const TraceView* __restrict__ views,
                                                    const int32_t* __restrict__ block_end, int32_t n_views,
                                                    unsigned long long* counters, const int32_t* __restrict__ order,
                                                    uint32_t* __restrict__ cost) {
@@ -726,7 +785,7 @@ __global__ __launch_bounds__(B) kTraceWaves(kLambert) void k_trace_batch(const T
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    trace_item<B, S, kCount, kSplit, kLambert>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
+    trace_item<B, S, kCount, kPhased, kLambert>(views[vid], (int64_t)(b - first) * B + threadIdx.x, stack, counters);
     if (cost && (threadIdx.x & 63) == 0) {
         const uint64_t dt = wall_clock64() - t0;
         atomicMax(cost + b, (uint32_t)(dt < 0xffffffffull ? dt : 0xffffffffull));
@@ -794,17 +853,14 @@ void launch_single(const TraceView& v, int64_t blocks, hipStream_t stream, unsig
 }
 
 template <int B, int S>
-void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, bool split,
+void launch_batch(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, bool phased,
                   bool lambert, hipStream_t stream, unsigned long long* counters, const int32_t* order,
                   uint32_t* cost) {
     if (counters)
         hipLaunchKernelGGL((k_trace_batch<B, S, true, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
                            views, block_end, n_views, counters, order, cost);
-    else if (split)
+    else if (phased || !lambert)
         hipLaunchKernelGGL((k_trace_batch<B, S, false, true, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
-                           views, block_end, n_views, counters, order, cost);
-    else if (!lambert)
-        hipLaunchKernelGGL((k_trace_batch<B, S, false, false, false>), dim3((unsigned)blocks), dim3(B), 0, stream,
                            views, block_end, n_views, counters, order, cost);
     else
         hipLaunchKernelGGL((k_trace_batch<B, S, false, false, true>), dim3((unsigned)blocks), dim3(B), 0, stream,
@@ -821,27 +877,27 @@ void launch_single_s(const TraceView& v, int64_t blocks, int block, hipStream_t 
 
 template <int S>
 void launch_batch_s(const TraceView* views, const int32_t* block_end, int32_t n_views, int32_t blocks, int block,
-                    bool split, bool lambert, hipStream_t stream, unsigned long long* counters, const int32_t* order,
+                    bool phased, bool lambert, hipStream_t stream, unsigned long long* counters, const int32_t* order,
                     uint32_t* cost) {
     if (block == 64)
-        launch_batch<64, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
+        launch_batch<64, S>(views, block_end, n_views, blocks, phased, lambert, stream, counters, order, cost);
     else if (block == 128)
-        launch_batch<128, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
-    else launch_batch<256, S>(views, block_end, n_views, blocks, split, lambert, stream, counters, order, cost);
+        launch_batch<128, S>(views, block_end, n_views, blocks, phased, lambert, stream, counters, order, cost);
+    else launch_batch<256, S>(views, block_end, n_views, blocks, phased, lambert, stream, counters, order, cost);
 }
 
-template <int S, bool kSplit, bool kLambert>
+template <int S, bool kPhased, bool kLambert>
 const void* batch_kernel_s(int block) {
-    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false, kSplit, kLambert>);
-    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false, kSplit, kLambert>);
-    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false, kSplit, kLambert>);
+    if (block == 64) return reinterpret_cast<const void*>(&k_trace_batch<64, S, false, kPhased, kLambert>);
+    if (block == 128) return reinterpret_cast<const void*>(&k_trace_batch<128, S, false, kPhased, kLambert>);
+    if (block == 256) return reinterpret_cast<const void*>(&k_trace_batch<256, S, false, kPhased, kLambert>);
     return nullptr;
 }
 
 template <int S>
-const void* batch_kernel_any(int block, bool split, bool lambert) {
-    if (split) return batch_kernel_s<S, true, false>(block);
-    return lambert ? batch_kernel_s<S, false, true>(block) : batch_kernel_s<S, false, false>(block);
+const void* batch_kernel_any(int block, bool phased, bool lambert) {
+    if (phased || !lambert) return batch_kernel_s<S, true, false>(block);
+    return batch_kernel_s<S, false, true>(block);
 }
 
 bool stack_ok(int stack) { return stack == kStackShort || stack == kStackLong; }
@@ -869,24 +925,24 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
     return VAFR_OK;
 }
 
-const void* trace_batch_kernel(int block, int stack, bool split, bool lambert) {
-    if (stack == kStackShort) return batch_kernel_any<kStackShort>(block, split, lambert);
-    if (stack == kStackLong) return batch_kernel_any<kStackLong>(block, split, lambert);
+const void* trace_batch_kernel(int block, int stack, bool phased, bool lambert) {
+    if (stack == kStackShort) return batch_kernel_any<kStackShort>(block, phased, lambert);
+    if (stack == kStackLong) return batch_kernel_any<kStackLong>(block, phased, lambert);
     return nullptr;
 }
 
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, bool split, bool lambert, hipStream_t stream,
+                       int block, int stack, bool phased, bool lambert, hipStream_t stream,
                        unsigned long long* counters, const int32_t* order, uint32_t* cost) {
     if (blocks <= 0) return VAFR_OK;
     if (!trace_block_ok(block)) return fail(VAFR_E_ARG, "trace workgroup size must be 64, 128 or 256");
     if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
     if (order && !trace_plan_ok(blocks)) return fail(VAFR_E_ARG, "too many blocks for a planned launch");
     if (stack == kStackShort)
-        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, split, lambert, stream,
+        launch_batch_s<kStackShort>(views_dev, block_end_dev, n_views, blocks, block, phased, lambert, stream,
                                     counters, order, cost);
     else
-        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, split, lambert, stream,
+        launch_batch_s<kStackLong>(views_dev, block_end_dev, n_views, blocks, block, phased, lambert, stream,
                                    counters, order, cost);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
@@ -901,15 +957,16 @@ const void* trace_queue_batch_kernel(int stack) {
 }
 
 int launch_trace_queue_batch(const TraceView* views_dev, const int32_t* qblock_end_dev, int32_t n_views,
-                             int32_t blocks, int stack, hipStream_t stream) {
+                             int32_t blocks, int stack, int bounce, hipStream_t stream) {
     if (blocks <= 0) return VAFR_OK;
     if (!stack_ok(stack)) return fail(VAFR_E_ARG, "unknown traversal stack class %d", stack);
+    if (bounce < 1 || bounce > kMaxBounces) return fail(VAFR_E_ARG, "bounce %d out of range", bounce);
     if (stack == kStackShort)
         hipLaunchKernelGGL((k_trace_queue_batch<kStackShort>), dim3((unsigned)blocks), dim3(kQueueBlock), 0, stream,
-                           views_dev, qblock_end_dev, n_views);
+                           views_dev, qblock_end_dev, n_views, (int32_t)bounce);
     else
         hipLaunchKernelGGL((k_trace_queue_batch<kStackLong>), dim3((unsigned)blocks), dim3(kQueueBlock), 0, stream,
-                           views_dev, qblock_end_dev, n_views);
+                           views_dev, qblock_end_dev, n_views, (int32_t)bounce);
     VAFR_HIP(hipGetLastError());
     return VAFR_OK;
 }

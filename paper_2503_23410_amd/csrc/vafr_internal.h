@@ -209,14 +209,20 @@ struct TraceView {
     // traced, one per thread; n_items bounds the list.
     const int32_t* item_list;
     const int32_t* item_count;
-    // Path mode in two passes (pt_split >= 0, batched launches only): a path
-    // still alive after bounce pt_split is appended to pt_queue (4 float4:
-    // next ray origin | output index, direction | next bounce, throughput,
-    // radiance) and finished by the queue pass; *pt_count counts the entries
-    // (zeroed before the frame).  pt_split = -1: one pass.
-    float4* pt_queue;
+    // Batched path mode in phases (pt_phased = 1): bounces 0 .. kPathFuse of
+    // every path run in the traversal launch, and each later bounce b in a
+    // queue launch over the compacted list of the paths still alive.  Per
+    // path (trace item p) pt_state[4 p ..] holds the next ray's origin |
+    // output index, its direction, the throughput | n.l of the last hit and
+    // the radiance so far; it is read and written around the traversals, so
+    // no path state stays live across them.  pt_list holds two lists of
+    // n_items path ids: bounce b reads list b & 1 and appends the paths that
+    // continue to list (b + 1) & 1, counted in pt_count[b + 1] (pt_count[0 ..
+    // kMaxBounces] is zeroed before the frame).
+    float4* pt_state;
+    int32_t* pt_list;
     uint32_t* pt_count;
-    int32_t pt_split;
+    int32_t pt_phased;
 };
 
 // Work items of a view (padded to whole tiles for full-resolution / LMFR).
@@ -229,11 +235,11 @@ int launch_trace(const TraceView& v, hipStream_t stream, unsigned long long* cou
                  int block = kTraceBlockDefault);
 // One launch over several views: workgroup b serves the view whose running
 // workgroup count block_end[] first exceeds b.
-// stack = the largest stack class among the views' scenes; split: some view
-// is a two-pass path-mode view (TraceView::pt_split >= 0); lambert: every
-// view is Lambert-shaded (selects the kernel without the path-tracing code).
+// stack = the largest stack class among the views' scenes; phased: some view
+// is a phased path-mode view (TraceView::pt_phased); lambert: every view is
+// Lambert-shaded (selects the kernel without the path-tracing code).
 int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev, int32_t n_views, int32_t blocks,
-                       int block, int stack, bool split, bool lambert, hipStream_t stream,
+                       int block, int stack, bool phased, bool lambert, hipStream_t stream,
                        unsigned long long* counters = nullptr, const int32_t* order = nullptr,
                        uint32_t* cost = nullptr);
 // Longest-first dispatch order of a batched traversal launch of `blocks`
@@ -242,16 +248,18 @@ int launch_trace_batch(const TraceView* views_dev, const int32_t* block_end_dev,
 // cost[] is cleared as it is read).  trace_plan_ok: whether a launch of
 // that size can be planned.
 bool trace_plan_ok(int32_t blocks);
-// Queue pass of a batched path-mode launch: workgroup b serves view vid with
-// qblock_end[vid-1] <= b < qblock_end[vid]; thread q of that view finishes
-// its queued path q while q < *pt_count.
+// Bounce `bounce` (> kPathFuse) of the phased path-mode views of a batched launch:
+// workgroup b serves view vid with qblock_end[vid-1] <= b < qblock_end[vid];
+// its thread q traces listed path q while q < pt_count[bounce].
 int launch_trace_queue_batch(const TraceView* views_dev, const int32_t* qblock_end_dev, int32_t n_views,
-                             int32_t blocks, int stack, hipStream_t stream);
+                             int32_t blocks, int stack, int bounce, hipStream_t stream);
 const void* trace_queue_batch_kernel(int stack);
 constexpr int kQueueBlock = 128;
-// Bounce after which a batched path-mode view with at least two bounces
-// queues its live paths.
-constexpr int kPathSplitBounce = 1;
+constexpr int kMaxBounces = 8;
+// Bounces 0 .. kPathFuse of a phased path-mode view run in the traversal
+// launch, one path per thread; the queue launches take bounce kPathFuse + 1
+// on.
+constexpr int kPathFuse = 1;
 int launch_trace_plan(uint32_t* cost, int32_t* order, int32_t blocks, hipStream_t stream);
 const void* trace_plan_kernel();
 
@@ -337,7 +345,7 @@ int make_recon_view(vafr_layout L, vafr_gaze gaze, const float* lp, float* img, 
 
 // Kernel entry points of the batched launches (for graph nodes); their
 // parameters are (views, block_end, n_views[, counters]).
-const void* trace_batch_kernel(int block, int stack, bool split, bool lambert);
+const void* trace_batch_kernel(int block, int stack, bool phased, bool lambert);
 const void* recon_batch_kernel(int rows);
 
 // common validation helpers

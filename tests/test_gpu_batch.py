@@ -255,20 +255,21 @@ def test_random_batches_equal_individual_calls(env, scene, case):
     log(f"random batch {case}: {n} views {kinds} mode {mode} block {tb} rows {rows} graph {use_graph}: equal")
 
 
-@pytest.mark.parametrize("bounces", [2, 3])
-def test_two_pass_path_mode_equals_single_pass(env, scene, bounces):
-    """Batched path-mode views with two or more bounces run their later
-    bounces in a second pass over a compacted queue of live paths; the
-    per-view calls run each path in one pass.  Both must agree bit for bit:
-    VaFR, LMFR and full-resolution views plus a Lambert view in one batch,
-    eager and graph, three frames in a row (graph replays with new gazes)."""
+@pytest.mark.parametrize("bounces", [(2, 2, 2), (3, 3, 3), (0, 0, 0), (1, 1, 1), (8, 8, 8), (2, 0, 3)])
+def test_phased_path_mode_equals_single_pass(env, scene, bounces):
+    """Batched path-mode views run in phases (bounce 0 in the traversal
+    launch, each later bounce in a launch over the compacted list of live
+    paths, path state in memory between launches); the per-view calls run
+    each path in one pass.  Both must agree bit for bit: VaFR, LMFR and
+    full-resolution path-mode views (bounce counts per view as given) plus a
+    Lambert view in one batch, eager and graph, three frames in a row (graph
+    replays with new gazes)."""
     torch, V = env
     sizes = [(1280, 720), (640, 480), (301, 177), (1920, 1080)]
     kinds = [V.VAFR_VIEW_VAFR, V.VAFR_VIEW_LMFR, V.VAFR_VIEW_FULL, V.VAFR_VIEW_VAFR]
     cams = [I.terrain_camera(0.01 * k) for k in range(4)]
-    path = V.shading(mode=V.VAFR_SHADE_PATH, bounces=bounces, frame=3, seed=99)
-    lam = V.shading()
-    shs = [path, path, path, lam]
+    shs = [V.shading(mode=V.VAFR_SHADE_PATH, bounces=bn, frame=3, view=k, seed=99) for k, bn in enumerate(bounces)]
+    shs.append(V.shading())
     for use_graph in (False, True):
         b = V.Batch(8, trace_block=128, recon_rows=4, use_graph=use_graph)
         for frame in range(3):
@@ -285,4 +286,4 @@ def test_two_pass_path_mode_equals_single_pass(env, scene, bounces):
             torch.cuda.synchronize()
             _assert_equal(torch, ref, vs, f"bounces {bounces} graph {use_graph} frame {frame}")
         b.close()
-    log(f"two-pass path mode ({bounces} bounces) equals the single pass (eager and graph, 3 frames)")
+    log(f"phased path mode (bounces {bounces}) equals the single pass (eager and graph, 3 frames)")
