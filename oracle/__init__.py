@@ -107,6 +107,7 @@ def _declare(L):
         "or_shade_path_rays": (None, [_P, _I64, _P, _P, _P, _P, C.c_uint64, C.c_uint32, C.c_uint32,
                                       _I32, _P, _P, _P]),
         "or_vafr_reconstruct": (None, [_P, _I32, _P, _P, _P, _I32, _I32, _P, _P, _P, _I64, _P, _P, _P]),
+        "or_vafr_taps": (None, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _P, _I64, _P]),
         "or_lmfr_reconstruct": (None, [_I32, _I32, _D, _D, _I32, _I32, _D, _P, _P, _I64, _P, _P, _P]),
         "or_lafr_consts": (C.c_int, [_I32, _I32, _P, _D, _D, _D, _D, _P]),
         "or_lafr_u": (None, [_P, _D, _I64, _P, _P]),
@@ -508,6 +509,18 @@ def vafr_reconstruct(layout: Layout, lp, W, H, p, G, pix, tflag=None):
                               _ptr(lp), int(W), int(H), _ptr(p), _ptr(G), _ptr(pix), pix.size, _ptr(out),
                               _ptr(tf), _ptr(pf))
     return out, pf.astype(bool)
+
+
+def vafr_taps(layout: Layout, W, H, p, G, pix):
+    """(n, 4) texel indices each display pixel reads: column i0's two rows,
+    then column i1's (the reconstruction's footprint)."""
+    pix = _arr(pix, np.int64)
+    taps = np.empty((pix.size, 4), np.int64)
+    p = _arr(p, np.float64)
+    G = _arr(G, np.float64)
+    lib().or_vafr_taps(layout.acuity.ptr, layout.n_cols, _ptr(layout.n_rows), _ptr(layout.col_off), int(W), int(H),
+                       _ptr(p), _ptr(G), _ptr(pix), pix.size, _ptr(taps))
+    return taps
 
 
 def lmfr_reconstruct(W, H, gx, gy, w, h, alpha, lp, pix, tflag=None):

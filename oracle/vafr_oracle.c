@@ -1229,45 +1229,77 @@ static double fmod_pos(double a, double m) {
  * although neighbouring columns hold different row counts.
  * pflag (optional) marks pixels that read a texel whose tflag is set.
  */
+/* Sampling positions of display pixel `pix`: per side (0: column i0, 1:
+ * column i1) the texels k[side][0..1] of the two rows around the pixel's
+ * angle, the row weight tt[side], and the column weight wc of side 1. */
+static void vafr_pixel_taps(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
+                            int32_t W, int32_t H, const double* p, const double* G, int64_t pix, int64_t k[2][2],
+                            double tt[2], double* wc_out) {
+    int64_t x = pix % W, y = pix / W;
+    double X = ((double)x + 0.5 - 0.5 * W) * p[0];
+    double Y = ((double)y + 0.5 - 0.5 * H) * p[1];
+    double dx = X - G[0], dy = Y - G[1];
+    double rho = sqrt(dx * dx + dy * dy);
+    double e = atan(rho) / OR_DEG;
+    double th = atan2(dy, dx) / OR_DEG;
+    if (th < 0.0) th += 360.0;
+    double u = or_u(a, e);
+    if (u < 0.5) u = 0.5;
+    if (u > n_cols - 0.5) u = n_cols - 0.5;
+    double ac = u - 0.5;
+    int64_t i0 = (int64_t)floor(ac);
+    if (i0 > n_cols - 1) i0 = n_cols - 1;
+    int64_t i1 = i0 + 1 < n_cols ? i0 + 1 : n_cols - 1;
+    *wc_out = ac - (double)i0;
+    for (int side = 0; side < 2; ++side) {
+        int64_t i = side ? i1 : i0;
+        int64_t ni = n_rows[i];
+        double s = th / 360.0 * (double)ni - 0.5;
+        double fs = floor(s);
+        tt[side] = s - fs;
+        int64_t j0 = (int64_t)fmod_pos(fs, (double)ni);
+        int64_t j1 = (j0 + 1) % ni;
+        k[side][0] = col_off[i] + j0;
+        k[side][1] = col_off[i] + j1;
+    }
+}
+
 void or_vafr_reconstruct(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off,
                          const float* lp, int32_t W, int32_t H, const double* p, const double* G,
                          const int64_t* pix, int64_t n, float* out, const uint8_t* tflag, uint8_t* pflag) {
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n; ++q) {
-        int64_t x = pix[q] % W, y = pix[q] / W;
-        double X = ((double)x + 0.5 - 0.5 * W) * p[0];
-        double Y = ((double)y + 0.5 - 0.5 * H) * p[1];
-        double dx = X - G[0], dy = Y - G[1];
-        double rho = sqrt(dx * dx + dy * dy);
-        double e = atan(rho) / OR_DEG;
-        double th = atan2(dy, dx) / OR_DEG;
-        if (th < 0.0) th += 360.0;
-        double u = or_u(a, e);
-        if (u < 0.5) u = 0.5;
-        if (u > n_cols - 0.5) u = n_cols - 0.5;
-        double ac = u - 0.5;
-        int64_t i0 = (int64_t)floor(ac);
-        if (i0 > n_cols - 1) i0 = n_cols - 1;
-        int64_t i1 = i0 + 1 < n_cols ? i0 + 1 : n_cols - 1;
-        double wc = ac - (double)i0;
+        int64_t k[2][2];
+        double tt[2], wc;
+        vafr_pixel_taps(a, n_cols, n_rows, col_off, W, H, p, G, pix[q], k, tt, &wc);
         double acc[4] = {0, 0, 0, 0};
         uint8_t fl = 0;
         for (int side = 0; side < 2; ++side) {
-            int64_t i = side ? i1 : i0;
             double wi = side ? wc : 1.0 - wc;
-            int64_t ni = n_rows[i];
-            double s = th / 360.0 * (double)ni - 0.5;
-            double fs = floor(s);
-            double tt = s - fs;
-            int64_t j0 = (int64_t)fmod_pos(fs, (double)ni);
-            int64_t j1 = (j0 + 1) % ni;
-            int64_t k0 = col_off[i] + j0, k1 = col_off[i] + j1;
+            int64_t k0 = k[side][0], k1 = k[side][1];
             for (int ch = 0; ch < 4; ++ch)
-                acc[ch] += wi * ((1.0 - tt) * (double)lp[4 * k0 + ch] + tt * (double)lp[4 * k1 + ch]);
+                acc[ch] += wi * ((1.0 - tt[side]) * (double)lp[4 * k0 + ch] + tt[side] * (double)lp[4 * k1 + ch]);
             if (tflag && (tflag[k0] || tflag[k1])) fl = 1;
         }
         for (int ch = 0; ch < 4; ++ch) out[4 * q + ch] = (float)acc[ch];
         if (pflag) pflag[q] = fl;
+    }
+}
+
+/* The four texels display pixel pix[q] reads: taps[4 q ..] = column i0's
+ * two rows, then column i1's (test infrastructure: reconstruction
+ * footprints). */
+void or_vafr_taps(const or_acuity* a, int32_t n_cols, const int32_t* n_rows, const int64_t* col_off, int32_t W,
+                  int32_t H, const double* p, const double* G, const int64_t* pix, int64_t n, int64_t* taps) {
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t k[2][2];
+        double tt[2], wc;
+        vafr_pixel_taps(a, n_cols, n_rows, col_off, W, H, p, G, pix[q], k, tt, &wc);
+        taps[4 * q] = k[0][0];
+        taps[4 * q + 1] = k[0][1];
+        taps[4 * q + 2] = k[1][0];
+        taps[4 * q + 3] = k[1][1];
     }
 }
 

@@ -156,7 +156,6 @@ int make_trace_view(int kind, vafr_scene scene, const vafr_camera* cam, vafr_gaz
     if (int rc = check_shading(sh)) return rc;
     TraceView v;
     std::memset(&v, 0, sizeof(v));
-    v.pt_split = -1;
     if (kind < 0) {
         if (!disp) return fail(VAFR_E_ARG, "display is NULL");
         if (disp->width <= 0 || disp->height <= 0 || disp->width > 65536 || disp->height > 65536)

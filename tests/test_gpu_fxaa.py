@@ -36,6 +36,31 @@ def _fxaa_gpu(torch, V, L, lp_np):
     return out.cpu().numpy()
 
 
+def _fxaa_window(layout, flagged):
+    """Output texels whose anti-aliasing can read one of the `flagged` input
+    texels.  Texel (i, j) of column i (n_i rows, angle t = (j + 1/2)/n_i
+    turns) reads columns i - 8 .. i + 8 only (radial end search up to 8
+    columns, clamped toward i), and in column c only rows within one row
+    spacing 1/n_c of an angle it samples; it samples its own and the
+    adjacent columns at up to t +- 8/n_i (angular end search) and the other
+    columns at t and t +- 1/n_i.  So it can read texel (c, j') only if
+    |c - i| <= 8 and the circular angular distance of j' from t is at most
+    8/n_i + 1/n_c; half a row of slack on each side covers the FP32
+    rounding of the sampled angles."""
+    n_rows, col_off = layout.n_rows.astype(np.int64), layout.col_off.astype(np.int64)
+    out = np.zeros(layout.n_texels, bool)
+    for k in flagged:
+        c = int(np.searchsorted(col_off, k, side="right") - 1)
+        tc = (k - col_off[c] + 0.5) / n_rows[c]
+        for i in range(max(0, c - 8), min(layout.n_cols, c + 9)):
+            n = n_rows[i]
+            reach = (8.5 / n + 1.5 / n_rows[c]) * n          # in rows of column i
+            centre = tc * n - 0.5
+            j = np.arange(int(np.floor(centre - reach)), int(np.ceil(centre + reach)) + 1)
+            out[col_off[i] + np.mod(j, n)] = True
+    return out
+
+
 def test_fxaa_random_and_shaded_lp_match_oracle(env, O, layout):
     torch, V = env
     W, H = 1920, 1080
@@ -82,20 +107,22 @@ def test_fxaa_frame_matches_oracle(env, O, layout):
     o_lp, o_id, o_fl = O.shade_vafr_texels(osc, layout, np.arange(layout.n_texels), W, H, I.FOV, gz,
                                            I.soup_camera(), O.shading_params())
     o_aa = O.fxaa_lp(layout, o_lp)
-    # a flagged texel may differ, and FXAA spreads it to its neighbourhood:
-    # compare texels whose 17 x 17 angular/radial window holds no flag
+    # a flagged texel may hold the other triangle's colour, and FXAA spreads
+    # it over the texels whose window reads it: compare every other texel
     g_aa = aa.cpu().numpy()
+    affected = _fxaa_window(layout, np.nonzero(o_fl)[0])
     diff = np.abs(g_aa - o_aa).max(axis=1)
-    log(f"fxaa frame: flagged texels={int(o_fl.sum())} max LP err={diff.max():.2e}")
-    if o_fl.sum() == 0:
-        assert diff.max() <= COLOR_TOL
+    log(f"fxaa frame: flagged texels={int(o_fl.sum())} in their windows={int(affected.sum())} "
+        f"max LP err outside={diff[~affected].max():.2e}")
+    assert o_fl.sum() <= 1e-4 * layout.n_texels
+    assert diff[~affected].max() <= COLOR_TOL
     p = O.film_pitch(W, H, *I.FOV)
     pix = np.arange(W * H)
-    ref, pf = O.vafr_reconstruct(layout, o_aa, W, H, p, O.gaze_film(W, H, p, *gz), pix, o_fl)
+    ref, pf = O.vafr_reconstruct(layout, o_aa, W, H, p, O.gaze_film(W, H, p, *gz), pix, affected.astype(np.uint8))
     err = np.abs(img.cpu().numpy() - ref).max(axis=1)
     ok = ~pf
-    log(f"fxaa frame image: max_err={err[ok].max():.2e} over {int(ok.sum())} pixels")
-    assert np.quantile(err[ok], 0.9999) <= COLOR_TOL
+    log(f"fxaa frame image: max_err={err[ok].max():.2e} over {int(ok.sum())} pixels ({int(pf.sum())} excluded)")
+    assert err[ok].max() <= COLOR_TOL
 
 
 def test_fxaa_rejects_bad_calls(env):

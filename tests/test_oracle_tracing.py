@@ -532,3 +532,26 @@ def test_flag_shadow_branch_reaches_the_shaded_ray(O):
             # the shadow ray misses the occluder in both cases: full light
             alb = O.albedo([0])[0]
             assert np.allclose(rgba[0, :3], alb * (0.1 + 1.0), atol=1e-6)
+
+
+def test_reconstruction_taps_are_its_footprint(O, layout):
+    """vafr_taps lists the texels each pixel reads: an LP buffer that is 1
+    at one texel and 0 elsewhere reconstructs to non-zero values only at
+    pixels whose taps hold that texel, and a flag on that texel reaches
+    exactly the pixels whose taps hold it."""
+    W, H = 320, 180
+    p = O.film_pitch(W, H, 100.0, 100.0)
+    G = O.gaze_film(W, H, p, 150.3, 70.9)
+    pix = np.arange(W * H)
+    taps = O.vafr_taps(layout, W, H, p, G, pix)
+    assert taps.shape == (W * H, 4) and taps.min() >= 0 and taps.max() < layout.n_texels
+    rng = np.random.default_rng(1)
+    for k in rng.choice(np.unique(taps), 12, replace=False):
+        lp = np.zeros((layout.n_texels, 4), np.float32)
+        lp[k] = 1.0
+        fl = np.zeros(layout.n_texels, np.uint8)
+        fl[k] = 1
+        img, pf = O.vafr_reconstruct(layout, lp, W, H, p, G, pix, fl)
+        has = (taps == k).any(axis=1)
+        assert not ((img[:, 0] != 0) & ~has).any()
+        assert np.array_equal(pf, has)
