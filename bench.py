@@ -715,7 +715,7 @@ def serving_bench(torch, V, I, scene4m, seconds):
     for name, kw in (("batched", dict(max_views_per_launch=16, max_inflight=2, n_streams=1)),
                      ("plain", dict(max_views_per_launch=2, max_inflight=1, n_streams=1))):
         srv = V.Server(max_queue=256, hbm_budget_bytes=64 << 30, frame_budget_ms=FRAME_BUDGET_MS, latest_only=True,
-                       **kw)
+                       watchdog_ms=2000.0, **kw)
         for k, sz in enumerate(sizes):
             srv.add_headset(scene1m if k % 2 == 0 else scene4m, layouts[sz], cl, cr, sh)
         # warm-up: one request per headset (buffers, graphs)
@@ -736,7 +736,7 @@ def serving_bench(torch, V, I, scene4m, seconds):
                  "p99_ms": round(lat["p99_ms"], 3), "max_ms": round(lat["max_ms"], 3),
                  "mean_queue_ms": round(lat["mean_queue_ms"], 3), "completed": lat["completed"],
                  "refused": refused, "late": st["late"] - st0["late"],
-                 "superseded": st["superseded"] - st0["superseded"],
+                 "superseded": st["superseded"] - st0["superseded"], "stalled": st["stalled"] - st0["stalled"],
                  "deferred": st["deferred"] - st0["deferred"], "launches": launches,
                  "requests_per_launch": round(lat["completed"] / max(launches, 1), 2)}
         log(f"serving ({name}): {entry}")

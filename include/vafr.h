@@ -45,6 +45,8 @@ extern "C" {
 #define VAFR_E_BUDGET (-5)       /* request exceeds a memory budget             */
 #define VAFR_E_LATE (-6)         /* request dropped: it could not complete by its
                                     deadline, or a newer request replaced it   */
+#define VAFR_E_TIMEOUT (-7)      /* the device made no progress within a
+                                    watchdog limit; the work was abandoned     */
 
 /* Message of the last failure on this thread ("" if none).  The pointer
  * stays valid until the next failing call on the same thread. */
@@ -439,6 +441,9 @@ typedef struct {
     int32_t latest_only;           /* 1: a new request of a headset replaces that headset's requests
                                       not yet launched (they finish with VAFR_E_LATE) */
     int32_t pad2_;
+    double watchdog_ms;            /* > 0: stall limit.  When launches are in flight and none has
+                                      completed for this many ms, the server gives them up (see
+                                      vafr_server_create); 0 = no watchdog */
 } vafr_server_config;
 
 /* A headset: resident scene and VaFR layout (display), one camera per eye
@@ -465,9 +470,10 @@ typedef struct {
  * eyes are ready at the device pointers, which stay valid until
  * vafr_server_release(slot).  VAFR_E_LATE: dropped before launch because it
  * could not complete by its deadline, or replaced by a newer request of the
- * headset.  VAFR_E_BUDGET: dropped while draining without memory.  No slot
- * and nothing to release for any error status.  Times are ms on the
- * server's clock. */
+ * headset.  VAFR_E_BUDGET: dropped while draining without memory.
+ * VAFR_E_TIMEOUT: launched (or waiting) when the watchdog gave up on the
+ * device.  No slot and nothing to release for any error status.  Times are
+ * ms on the server's clock. */
 typedef struct {
     uint64_t user_tag;
     int32_t headset;
@@ -480,11 +486,12 @@ typedef struct {
 } vafr_result;
 
 /* dropped counts every request finished with an error status; late and
- * superseded count the VAFR_E_LATE drops by cause. */
+ * superseded count the VAFR_E_LATE drops by cause, stalled the
+ * VAFR_E_TIMEOUT ones. */
 typedef struct {
     int64_t submitted, completed, refused, deferred, dropped, launches, views_launched, bytes_in_use;
     int32_t waiting, inflight;
-    int64_t late, superseded;
+    int64_t late, superseded, stalled;
 } vafr_server_stats;
 
 /* Starts the dispatcher thread on the current device.  Requests are
@@ -501,12 +508,26 @@ typedef struct {
  * device time.  A launch takes requests from the queue head while the
  * predicted end of the device's queued work plus the launch meets every
  * included deadline; a request that cannot meet its deadline even in a
- * launch of its own is dropped (VAFR_E_LATE). */
+ * launch of its own is dropped (VAFR_E_LATE).
+ *
+ * Watchdog (watchdog_ms > 0): the device is taken to have stalled when work
+ * is in flight and no launch has completed for watchdog_ms (measured from
+ * the last completion, or from the launch that found the device idle, so a
+ * deep but moving queue never trips it).  The server then finishes every
+ * launched and waiting request with VAFR_E_TIMEOUT, keeps the buffers of the
+ * abandoned launches out of the pool (the device may still write them),
+ * refuses further submissions with VAFR_E_TIMEOUT, and vafr_server_destroy
+ * neither waits for nor frees device objects that abandoned work may still
+ * use (they are leaked if that work has not finished by then). */
 int vafr_server_create(const vafr_server_config* cfg, vafr_server* out);
 int vafr_server_add_headset(vafr_server server, const vafr_headset* headset, int32_t* id);
-/* Non-blocking; VAFR_E_BUDGET when the queue is full (counted as refused). */
+/* Non-blocking; VAFR_E_BUDGET when the queue is full (counted as refused),
+ * VAFR_E_TIMEOUT after a watchdog stall. */
 int vafr_server_submit(vafr_server server, const vafr_request* request);
-/* Up to max finished requests, oldest first; *n_out set to the count. */
+/* Up to max finished requests, oldest first; *n_out set to the count.
+ * Returns VAFR_OK while it delivers results; once none is left it returns
+ * the server's sticky error, if any (a failed launch: VAFR_E_HIP; a stall:
+ * VAFR_E_TIMEOUT), so per-request statuses are always delivered first. */
 int vafr_server_poll(vafr_server server, vafr_result* out, int32_t max, int32_t* n_out);
 int vafr_server_release(vafr_server server, int32_t slot);
 /* Waits until nothing is queued or in flight (VAFR_E_BUDGET on timeout). */

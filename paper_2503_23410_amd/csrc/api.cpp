@@ -282,7 +282,7 @@ using namespace vafr;
 
 extern "C" const char* vafr_last_error(void) { return g_err; }
 
-extern "C" int vafr_abi_version(void) { return 1; }
+extern "C" int vafr_abi_version(void) { return 2; }
 
 extern "C" int vafr_scene_create(const float* xyz, int64_t n_verts, const int32_t* tri, int64_t n_tris,
                                  vafr_scene* out) {

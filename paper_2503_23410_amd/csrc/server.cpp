@@ -16,6 +16,11 @@
 // which the device drains the work already launched.  A launch only takes
 // requests that the model says will finish in time; a request that cannot
 // finish in time even alone is dropped before it costs device time.
+//
+// A watchdog watches the device's progress, not the age of launches: with
+// several launches queued the oldest may legitimately wait long, but some
+// launch must complete every watchdog_ms.  When none does, the launched work
+// is given up and reported, and the server stops taking work.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -85,11 +90,15 @@ struct vafr_server_s {
     std::deque<vafr_result> done;
     // stats
     int64_t n_submitted = 0, n_completed = 0, n_refused = 0, n_deferred = 0, n_dropped = 0, n_launches = 0;
-    int64_t views_launched = 0, n_late = 0, n_superseded = 0;
+    int64_t views_launched = 0, n_late = 0, n_superseded = 0, n_stalled = 0;
     // device-time model: launch cost + per-request cost of each headset
     double est_launch_ms = 0;
     std::vector<double> est_req_ms;
     double pred_free_ms = 0;                  // modelled end of the launched work
+    // watchdog
+    double progress_ms = 0;                   // last completion, or launch onto an idle device
+    bool stalled = false;
+    std::vector<vafr::Launch> abandoned;      // launches given up; their buffers stay out of the pool
     std::mutex mu;
     std::condition_variable cv;
     bool stop = false;
@@ -167,9 +176,8 @@ BufSet* acquire_set(vafr_server s, const vafr_headset& h) {
 
 void release_set(vafr_server s, BufSet* b) { s->free_sets.emplace(b->key, b); }
 
-// Finish a request that is not launched with an error status (caller holds
-// mu); its buffers go back to the pool.
-void finish_dropped(vafr_server s, Pending& p, int status, double t) {
+// Finish a request with an error status and no result slot (caller holds mu).
+void push_error(vafr_server s, const Pending& p, int status, double launch_ms, double t) {
     vafr_result r;
     std::memset(&r, 0, sizeof(r));
     r.user_tag = p.req.user_tag;
@@ -177,12 +185,19 @@ void finish_dropped(vafr_server s, Pending& p, int status, double t) {
     r.frame = p.req.frame;
     r.status = status;
     r.submit_ms = p.submit_ms;
-    r.launch_ms = r.done_ms = t;
-    if (p.bufs) release_set(s, p.bufs);
-    p.bufs = nullptr;
+    r.launch_ms = launch_ms;
+    r.done_ms = t;
     s->done.push_back(r);
     ++s->n_dropped;
     s->cv.notify_all();
+}
+
+// Finish a request that is not launched with an error status (caller holds
+// mu); its buffers go back to the pool.
+void finish_dropped(vafr_server s, Pending& p, int status, double t) {
+    push_error(s, p, status, t, t);
+    if (p.bufs) release_set(s, p.bufs);
+    p.bufs = nullptr;
 }
 
 // Initial device-time estimate of one request of headset h: rays traced for
@@ -272,6 +287,7 @@ void launch(vafr_server s, int k) {
         L.sim_done_ms = start + L.sim_cost_ms;
         s->sim_busy_until = L.sim_done_ms;
         s->pred_free_ms = L.pred_end_ms;
+        if (s->inflight.empty()) s->progress_ms = L.launch_ms;
         ++s->n_launches;
         s->views_launched += (int64_t)views.size();
         s->inflight.push_back(std::move(L));
@@ -289,25 +305,43 @@ void launch(vafr_server s, int k) {
     if (rc != VAFR_OK) {
         set_error(s, rc, vafr_last_error());
         for (Pending& p : L.reqs) {
-            vafr_result r;
-            std::memset(&r, 0, sizeof(r));
-            r.user_tag = p.req.user_tag;
-            r.headset = p.req.headset;
-            r.frame = p.req.frame;
-            r.status = rc;
-            r.submit_ms = p.submit_ms;
-            r.launch_ms = r.done_ms = L.launch_ms;
+            push_error(s, p, rc, L.launch_ms, L.launch_ms);
             release_set(s, p.bufs);
-            s->done.push_back(r);
         }
         if (L.done) s->free_events.push_back(L.done);
         s->free_events.push_back(L.start);
         return;
     }
     s->pred_free_ms = L.pred_end_ms;
+    if (s->inflight.empty()) s->progress_ms = L.launch_ms;
     ++s->n_launches;
     s->views_launched += (int64_t)views.size();
     s->inflight.push_back(std::move(L));
+}
+
+// The device made no progress for watchdog_ms: give up every launch in
+// flight (its buffers stay leased to the abandoned launch, since the device
+// may still write them) and every waiting request, and stop taking work
+// (caller holds mu).
+void abandon(vafr_server s, double t) {
+    char msg[160];
+    std::snprintf(msg, sizeof(msg), "device made no progress for %.1f ms with %d launch(es) in flight",
+                  t - s->progress_ms, (int)s->inflight.size());
+    set_error(s, VAFR_E_TIMEOUT, msg);
+    s->stalled = true;
+    for (Launch& L : s->inflight) {
+        for (const Pending& p : L.reqs) {
+            push_error(s, p, VAFR_E_TIMEOUT, L.launch_ms, t);
+            ++s->n_stalled;
+        }
+        s->abandoned.push_back(std::move(L));
+    }
+    s->inflight.clear();
+    for (Pending& p : s->waiting) {
+        finish_dropped(s, p, VAFR_E_TIMEOUT, t);
+        ++s->n_stalled;
+    }
+    s->waiting.clear();
 }
 
 // After launch L finished at time t: correct the model by the ratio of
@@ -364,15 +398,19 @@ void worker_main(vafr_server s) {
                 ++s->n_completed;
             }
             if (q != hipSuccess) set_error(s, VAFR_E_HIP, "a launched frame failed");
+            s->progress_ms = t;
             learn(s, L, t);
             if (L.done) s->free_events.push_back(L.done);
             if (L.start) s->free_events.push_back(L.start);
             s->inflight.erase(s->inflight.begin() + i);
             s->cv.notify_all();
         }
+        // watchdog
+        const double t = now_ms(s);
+        if (s->cfg.watchdog_ms > 0.0 && !s->inflight.empty() && t - s->progress_ms > s->cfg.watchdog_ms)
+            abandon(s, t);
         // admission: give buffers to waiting requests in arrival order;
         // drop requests whose deadline already passed
-        const double t = now_ms(s);
         for (auto it = s->waiting.begin(); it != s->waiting.end();) {
             if (t + s->est_launch_ms + s->est_req_ms[it->req.headset] > it->due_ms) {
                 ++s->n_late;
@@ -432,6 +470,8 @@ extern "C" int vafr_server_create(const vafr_server_config* cfg, vafr_server* ou
     if (!(cfg->frame_budget_ms >= 0) || !std::isfinite(cfg->frame_budget_ms))
         return fail(VAFR_E_ARG, "frame_budget_ms must be finite and >= 0");
     if (cfg->latest_only != 0 && cfg->latest_only != 1) return fail(VAFR_E_ARG, "latest_only must be 0 or 1");
+    if (!(cfg->watchdog_ms >= 0) || !std::isfinite(cfg->watchdog_ms))
+        return fail(VAFR_E_ARG, "watchdog_ms must be finite and >= 0");
     int n_dev = 0;
     if (!cfg->simulate && (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0))
         return fail(VAFR_E_HIP, "no HIP device available");
@@ -486,6 +526,7 @@ extern "C" int vafr_server_submit(vafr_server s, const vafr_request* r) {
     if (int rc = check_gaze(r->gaze)) return rc;
     std::lock_guard<std::mutex> lock(s->mu);
     if (s->stop) return fail(VAFR_E_ARG, "server is draining");
+    if (s->stalled) return fail(VAFR_E_TIMEOUT, "server stopped after a device stall: %s", s->error_msg);
     if (r->headset < 0 || r->headset >= (int32_t)s->headsets.size()) return fail(VAFR_E_ARG, "unknown headset");
     ++s->n_submitted;
     if ((int64_t)s->waiting.size() >= s->cfg.max_queue) {
@@ -520,7 +561,7 @@ extern "C" int vafr_server_poll(vafr_server s, vafr_result* out, int32_t max, in
         s->done.pop_front();
     }
     *n_out = n;
-    if (s->error != VAFR_OK) return fail(s->error, "%s", s->error_msg);
+    if (n == 0 && s->error != VAFR_OK) return fail(s->error, "%s", s->error_msg);
     return VAFR_OK;
 }
 
@@ -558,6 +599,7 @@ extern "C" int vafr_server_get_stats(vafr_server s, vafr_server_stats* out) {
     out->inflight = (int32_t)s->inflight.size();
     out->late = s->n_late;
     out->superseded = s->n_superseded;
+    out->stalled = s->n_stalled;
     return VAFR_OK;
 }
 
@@ -569,6 +611,20 @@ extern "C" void vafr_server_destroy(vafr_server s) {
         s->cv.notify_all();
     }
     if (s->worker.joinable()) s->worker.join();
+    bool hung = false;
+    for (auto& L : s->abandoned) hung = hung || (!s->cfg.simulate && hipEventQuery(L.done) == hipErrorNotReady);
+    if (hung) {
+        // Abandoned work is still on the device: waiting for it may never
+        // end and freeing what it uses is unsafe, so every device object
+        // (streams, events, batches, buffers) is leaked.
+        for (auto b : s->all_sets) delete b;
+        delete s;
+        return;
+    }
+    for (auto& L : s->abandoned) {
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.start) (void)hipEventDestroy(L.start);
+    }
     for (auto b : s->batches) vafr_batch_destroy(b);
     for (auto st : s->streams) {
         (void)hipStreamSynchronize(st);

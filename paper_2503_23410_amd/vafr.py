@@ -21,6 +21,8 @@ VAFR_E_HIP = -3
 VAFR_E_UNSUPPORTED = -4
 VAFR_E_BUDGET = -5
 VAFR_E_LATE = -6
+VAFR_E_TIMEOUT = -7
+ABI_VERSION = 2   # layout of the structures below
 
 VAFR_SHADE_LAMBERT = 0
 VAFR_SHADE_PATH = 1
@@ -104,7 +106,7 @@ class vafr_server_config(C.Structure):
                 ("max_queue", C.c_int32), ("hbm_budget_bytes", C.c_int64), ("batch", vafr_batch_config),
                 ("simulate", C.c_int32), ("pad_", C.c_int32), ("sim_ms_per_launch", C.c_double),
                 ("sim_ms_per_mray", C.c_double), ("sim_ms_per_mpix", C.c_double), ("frame_budget_ms", C.c_double),
-                ("latest_only", C.c_int32), ("pad2_", C.c_int32)]
+                ("latest_only", C.c_int32), ("pad2_", C.c_int32), ("watchdog_ms", C.c_double)]
 
 
 class vafr_headset(C.Structure):
@@ -126,7 +128,7 @@ class vafr_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("refused", C.c_int64), ("deferred", C.c_int64),
                 ("dropped", C.c_int64), ("launches", C.c_int64), ("views_launched", C.c_int64),
                 ("bytes_in_use", C.c_int64), ("waiting", C.c_int32), ("inflight", C.c_int32), ("late", C.c_int64),
-                ("superseded", C.c_int64)]
+                ("superseded", C.c_int64), ("stalled", C.c_int64)]
 
 
 class vafr_scene_info(C.Structure):
@@ -204,6 +206,8 @@ def load():
         f = getattr(L, name)
         f.restype = res
         f.argtypes = args
+    if L.vafr_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} has ABI {L.vafr_abi_version()}, the binding expects {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 
@@ -550,7 +554,7 @@ class Server:
     def __init__(self, max_views_per_launch=16, max_inflight=3, n_streams=2, max_queue=64,
                  hbm_budget_bytes=64 << 30, trace_block=128, recon_rows=4, use_graph=True, simulate=False,
                  sim_ms_per_launch=0.05, sim_ms_per_mray=0.5, sim_ms_per_mpix=0.002, frame_budget_ms=0.0,
-                 latest_only=False):
+                 latest_only=False, watchdog_ms=0.0):
         cfg = vafr_server_config()
         cfg.max_views_per_launch = int(max_views_per_launch)
         cfg.max_inflight = int(max_inflight)
@@ -564,6 +568,7 @@ class Server:
         cfg.sim_ms_per_mpix = float(sim_ms_per_mpix)
         cfg.frame_budget_ms = float(frame_budget_ms)
         cfg.latest_only = 1 if latest_only else 0
+        cfg.watchdog_ms = float(watchdog_ms)
         h = C.c_void_p()
         _check(load().vafr_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -229,11 +229,74 @@ static void serving() {
                 (long long)st.refused, (long long)st.launches);
 }
 
+// A simulated device that stops making progress: the watchdog gives up the
+// launched work while a second thread keeps submitting.
+static void stall() {
+    vafr_server_config cfg;
+    std::memset(&cfg, 0, sizeof(cfg));
+    cfg.max_views_per_launch = 4;
+    cfg.max_inflight = 2;
+    cfg.n_streams = 1;
+    cfg.max_queue = 16;
+    cfg.hbm_budget_bytes = (int64_t)1 << 30;
+    cfg.batch = vafr_batch_config{128, 8, 1};
+    cfg.simulate = 1;
+    cfg.sim_ms_per_launch = 60000.0;
+    cfg.watchdog_ms = 30.0;
+    vafr_server srv = nullptr;
+    CHECK(vafr_server_create(&cfg, &srv) == VAFR_OK);
+    const vafr_display d{640, 360, 100.0, 100.0};
+    vafr_layout L = nullptr;
+    CHECK(vafr_lp_layout(&d, nullptr, &L) == VAFR_OK);
+    vafr_headset hs;
+    std::memset(&hs, 0, sizeof(hs));
+    hs.layout = L;
+    for (int e = 0; e < 2; ++e) hs.camera[e].right[0] = hs.camera[e].up[1] = hs.camera[e].forward[2] = 1.0f;
+    hs.shading.light_dir[1] = 1.0f;
+    int32_t id = -1;
+    CHECK(vafr_server_add_headset(srv, &hs, &id) == VAFR_OK);
+    std::atomic<int64_t> accepted{0};
+    std::thread sub([&] {
+        for (int f = 0; f < 200; ++f) {
+            vafr_request r;
+            std::memset(&r, 0, sizeof(r));
+            r.frame = (uint32_t)f;
+            r.gaze = vafr_gaze{320.0, 180.0};
+            if (vafr_server_submit(srv, &r) == VAFR_OK) ++accepted;
+            std::this_thread::sleep_for(std::chrono::microseconds(500));
+        }
+    });
+    sub.join();
+    CHECK(vafr_server_wait_idle(srv, 5000) == VAFR_OK);   // the watchdog empties the queues
+    int64_t timed_out = 0;
+    std::vector<vafr_result> res(64);
+    for (int i = 0; i < 400; ++i) {
+        int32_t n = 0;
+        const int rc = vafr_server_poll(srv, res.data(), (int32_t)res.size(), &n);
+        for (int k = 0; k < n; ++k) {
+            CHECK(res[k].status == VAFR_E_TIMEOUT && res[k].slot == 0);
+            ++timed_out;
+        }
+        if (n == 0) {
+            CHECK(rc == VAFR_E_TIMEOUT);
+            break;
+        }
+    }
+    vafr_server_stats st;
+    CHECK(vafr_server_get_stats(srv, &st) == VAFR_OK);
+    CHECK(st.stalled > 0 && st.stalled == timed_out && st.completed == 0 && st.inflight == 0);
+    CHECK(st.dropped == accepted.load());
+    vafr_server_destroy(srv);
+    vafr_layout_destroy(L);
+    std::printf("stall: %lld accepted, %lld timed out\n", (long long)accepted.load(), (long long)timed_out);
+}
+
 int main(int argc, char** argv) {
     const char* what = argc > 1 ? argv[1] : "all";
     if (!std::strcmp(what, "all") || !std::strcmp(what, "layouts")) layouts();
     if (!std::strcmp(what, "all") || !std::strcmp(what, "scenes")) scenes();
     if (!std::strcmp(what, "all") || !std::strcmp(what, "serving")) serving();
+    if (!std::strcmp(what, "all") || !std::strcmp(what, "stall")) stall();
     std::printf("%s: %d failed checks\n", what, g_fail);
     return g_fail ? 1 : 0;
 }

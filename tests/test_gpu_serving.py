@@ -45,7 +45,9 @@ def rig(env):
 
 
 def _server(V, rig, **kw):
-    args = dict(max_views_per_launch=16, max_inflight=3, n_streams=2, max_queue=256, hbm_budget_bytes=16 << 30)
+    # the watchdog is on in every served test: real launches must never trip it
+    args = dict(max_views_per_launch=16, max_inflight=3, n_streams=2, max_queue=256, hbm_budget_bytes=16 << 30,
+                watchdog_ms=5000.0)
     args.update(kw)
     s = V.Server(**args)
     for h in rig["heads"]:
@@ -140,7 +142,7 @@ def test_poisson_serving_smoke(env, rig):
     lat = serving.latency_stats(recs)
     st = s.stats()
     log(f"poisson smoke: {len(arr)} requests, {lat}, launches {st['launches']}, refused {refused}")
-    assert refused == 0 and lat["completed"] == len(arr)
+    assert refused == 0 and lat["completed"] == len(arr) and st["stalled"] == 0
     s.close()
 
 
@@ -166,4 +168,5 @@ def test_frame_budget_holds_on_device(env, rig):
     assert lat["completed"] + late + sup == len(arr)
     assert lat["completed"] > 50
     assert lat["p99_ms"] <= 11.1
+    assert st["stalled"] == 0
     s.close()

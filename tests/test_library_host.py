@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol(V):
     lib = V.load()
     for name in declared:
         assert hasattr(lib, name), name
-    assert lib.vafr_abi_version() == 1
+    assert lib.vafr_abi_version() == 2
 
 
 def test_vafr_layout_tables_bit_exact_with_oracle(V, O, layout):

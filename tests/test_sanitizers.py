@@ -2,7 +2,8 @@
 
 - the host library (layouts, the threaded BVH builder, argument validation,
   and the serving dispatcher thread in its simulated mode, fed from two
-  submitting threads) under AddressSanitizer + UndefinedBehaviorSanitizer,
+  submitting threads, and its watchdog giving up a stalled simulated device
+  while a thread submits) under AddressSanitizer + UndefinedBehaviorSanitizer,
   and under ThreadSanitizer, through tests/sanitize_host.cpp;
 - the oracle (C, OpenMP) under AddressSanitizer + UndefinedBehaviorSanitizer,
   running its own pin tests in a child process.
@@ -101,14 +102,14 @@ def tsan_exe(tmp_path_factory):
     return _driver(tmp_path_factory, "tsan", "thread")
 
 
-@pytest.mark.parametrize("what", ["layouts", "scenes", "serving"])
+@pytest.mark.parametrize("what", ["layouts", "scenes", "serving", "stall"])
 def test_host_library_under_asan_ubsan(asan_exe, what):
     out = _run(asan_exe, what, {"ASAN_OPTIONS": "detect_leaks=0:abort_on_error=0",
                                 "UBSAN_OPTIONS": "print_stacktrace=1:halt_on_error=1"})
     assert "0 failed checks" in out
 
 
-@pytest.mark.parametrize("what", ["scenes", "serving"])
+@pytest.mark.parametrize("what", ["scenes", "serving", "stall"])
 def test_host_threads_under_tsan(tsan_exe, what):
     out = _run(tsan_exe, what, {"TSAN_OPTIONS": "halt_on_error=1:second_deadlock_stack=1"})
     assert "0 failed checks" in out

@@ -183,6 +183,56 @@ def test_headset_larger_than_budget_is_rejected(V):
 def test_server_config_validation(V):
     for bad in (dict(max_views_per_launch=1), dict(max_inflight=0), dict(n_streams=9), dict(hbm_budget_bytes=0),
                 dict(max_queue=0), dict(sim_ms_per_mray=-1.0), dict(frame_budget_ms=-1.0),
-                dict(frame_budget_ms=float("inf"))):
+                dict(frame_budget_ms=float("inf")), dict(watchdog_ms=-1.0), dict(watchdog_ms=float("nan"))):
         with pytest.raises(V.VafrError):
             V.Server(simulate=True, **bad)
+
+
+def test_watchdog_gives_up_a_stalled_device(V):
+    """A simulated device that takes 60 s per launch against a 100 ms
+    watchdog: the launched and the waiting requests finish with
+    VAFR_E_TIMEOUT (no slot), the server refuses further work, and closing
+    it does not wait for the abandoned launches."""
+    s, L = _server(V, n_headsets=1, max_inflight=2, max_views_per_launch=2, sim_ms_per_launch=60000.0,
+                   watchdog_ms=100.0)
+    g = V.gaze(640.0, 360.0)
+    for f in range(5):
+        assert s.submit(0, f, g)
+    t0 = time.time()
+    s.wait_idle(5000)
+    assert time.time() - t0 < 2.0
+    recs = _collect(s, 5)
+    assert sorted(r["frame"] for r in recs) == list(range(5))
+    assert all(r["status"] == V.VAFR_E_TIMEOUT and r["slot"] == 0 for r in recs)
+    launched = [r for r in recs if r["done_ms"] > r["launch_ms"]]
+    assert len(launched) == 2 and all(r["done_ms"] - r["launch_ms"] >= 100.0 for r in launched)
+    st = s.stats()
+    assert st["stalled"] == 5 and st["dropped"] == 5 and st["completed"] == 0 and st["inflight"] == 0
+    with pytest.raises(V.VafrError) as ei:           # nothing left to deliver: the sticky error
+        s.poll()
+    assert ei.value.code == V.VAFR_E_TIMEOUT and "no progress" in str(ei.value)
+    with pytest.raises(V.VafrError) as ei:
+        s.submit(0, 9, g)
+    assert ei.value.code == V.VAFR_E_TIMEOUT
+    t0 = time.time()
+    s.close()
+    assert time.time() - t0 < 1.0
+
+
+def test_watchdog_tolerates_a_deep_queue_that_moves(V):
+    """Launches of 30 ms queued four deep: the oldest waits up to 120 ms,
+    beyond the 80 ms watchdog, but one completes every 30 ms, so the device
+    is making progress and nothing is given up."""
+    s, L = _server(V, n_headsets=1, max_inflight=4, max_views_per_launch=2, sim_ms_per_launch=30.0,
+                   sim_ms_per_mray=0.0, sim_ms_per_mpix=0.0, watchdog_ms=80.0)
+    g = V.gaze(640.0, 360.0)
+    for f in range(16):
+        assert s.submit(0, f, g)
+    s.wait_idle(5000)
+    recs = _collect(s, 16)
+    st = s.stats()
+    assert st["stalled"] == 0 and st["completed"] == 16 and st["launches"] == 16
+    assert max(r["done_ms"] - r["launch_ms"] for r in recs) > 80.0   # queued longer than the limit
+    for r in recs:
+        s.release(r["slot"])
+    s.close()
