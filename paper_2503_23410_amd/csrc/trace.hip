@@ -81,19 +81,39 @@ __device__ __forceinline__ void ray_setup(float ox, float oy, float oz, float dx
     r.Sz = 1.0f / dkz;
 }
 
+// Component of (a0, a1, a2) on axis K when K is fixed at compile time, else
+// on the lane's axis k.
+template <int K>
+__device__ __forceinline__ float comp(int k, float a0, float a1, float a2) {
+    if constexpr (K == 0) return a0;
+    else if constexpr (K == 1) return a1;
+    else if constexpr (K == 2) return a2;
+    else return sel3(k, a0, a1, a2);
+}
+
+// Axis permutation (kx, ky, kz) of the watertight set-up as one number,
+// kz * 3 + kx (ky is the remaining axis).
+constexpr int perm_code(int kx, int kz) { return kz * 3 + kx; }
+
 // FP32 watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013).
-// Returns true on a hit with t > 0 and writes t = T / det.
+// Returns true on a hit with t > 0 and writes t = T / det.  KX, KY, KZ fix
+// the ray's axis permutation when every lane of the wave shares it, which
+// turns the per-lane component selects into plain register choices; -1
+// reads it from the ray.  Either way the same operations run on the same
+// values.
+template <int KX = -1, int KY = -1, int KZ = -1>
 __device__ __forceinline__ bool tri_hit(const RayPre& r, float4 v0, float4 v1, float4 v2, float& t_out) {
     const float A0 = v0.x - r.ox, A1 = v0.y - r.oy, A2 = v0.z - r.oz;
     const float B0 = v1.x - r.ox, B1 = v1.y - r.oy, B2 = v1.z - r.oz;
     const float C0 = v2.x - r.ox, C1 = v2.y - r.oy, C2 = v2.z - r.oz;
-    const float Akz = sel3(r.kz, A0, A1, A2), Bkz = sel3(r.kz, B0, B1, B2), Ckz = sel3(r.kz, C0, C1, C2);
-    const float Ax = fmaf(-r.Sx, Akz, sel3(r.kx, A0, A1, A2));
-    const float Ay = fmaf(-r.Sy, Akz, sel3(r.ky, A0, A1, A2));
-    const float Bx = fmaf(-r.Sx, Bkz, sel3(r.kx, B0, B1, B2));
-    const float By = fmaf(-r.Sy, Bkz, sel3(r.ky, B0, B1, B2));
-    const float Cx = fmaf(-r.Sx, Ckz, sel3(r.kx, C0, C1, C2));
-    const float Cy = fmaf(-r.Sy, Ckz, sel3(r.ky, C0, C1, C2));
+    const float Akz = comp<KZ>(r.kz, A0, A1, A2), Bkz = comp<KZ>(r.kz, B0, B1, B2);
+    const float Ckz = comp<KZ>(r.kz, C0, C1, C2);
+    const float Ax = fmaf(-r.Sx, Akz, comp<KX>(r.kx, A0, A1, A2));
+    const float Ay = fmaf(-r.Sy, Akz, comp<KY>(r.ky, A0, A1, A2));
+    const float Bx = fmaf(-r.Sx, Bkz, comp<KX>(r.kx, B0, B1, B2));
+    const float By = fmaf(-r.Sy, Bkz, comp<KY>(r.ky, B0, B1, B2));
+    const float Cx = fmaf(-r.Sx, Ckz, comp<KX>(r.kx, C0, C1, C2));
+    const float Cy = fmaf(-r.Sy, Ckz, comp<KY>(r.ky, C0, C1, C2));
     // Edge functions with plain products (a shared edge gets exactly
     // negated values in its two triangles).
     float U = Cx * By - Cy * Bx;
@@ -208,20 +228,69 @@ constexpr int kParkNum = 5, kParkDen = 8;
 // LDS entries per lane of stack class S (the rest of the stack is scratch).
 constexpr int lds_entries(int s) { return s < kStackLds ? s : kStackLds; }
 
+// Triangle step of one lane: the `count` triangles from `first` against the
+// ray (axis permutation fixed by KX, KY, KZ, or -1 for the lane's own).
+// Closest hit keeps the smallest (t, id) and narrows tlim; any hit stops at
+// the first hit (slot_best = 1, ref = kEmptyRef).
+template <int KX, int KY, int KZ, bool kAny>
+__device__ __forceinline__ void leaf_test(const TraceView& sc, const RayPre& r, int first, int count, float& t_best,
+                                          int& id_best, int& slot_best, float& tlim, int& ref) {
+    const float4* tp = sc.tris + 3 * (size_t)first;
+    for (int q = 0; q < count; ++q) {
+        const float4 v0 = ldg4(tp, 3 * q), v1 = ldg4(tp, 3 * q + 1), v2 = ldg4(tp, 3 * q + 2);
+        float t;
+        if (tri_hit<KX, KY, KZ>(r, v0, v1, v2, t)) {
+            if (kAny) {
+                slot_best = 1;
+                ref = kEmptyRef;
+                break;
+            }
+            const int id = __float_as_int(v0.w);
+            if (t < t_best || (t == t_best && id < id_best)) {
+                t_best = t;
+                id_best = id;
+                slot_best = first + q;
+                tlim = t * kHitSlack;
+            }
+        }
+    }
+}
+
+// Triangle step with the axis permutation fixed when perm names one (a
+// wave-uniform value, so the choice is a scalar branch).
+template <bool kAny, bool kPerm>
+__device__ __forceinline__ void leaf_step(int perm, const TraceView& sc, const RayPre& r, int first, int count,
+                                          float& tb, int& ib, int& sb, float& tl, int& ref) {
+    if (kPerm) {
+        if (perm == perm_code(1, 0)) return leaf_test<1, 2, 0, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+        if (perm == perm_code(2, 0)) return leaf_test<2, 1, 0, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+        if (perm == perm_code(2, 1)) return leaf_test<2, 0, 1, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+        if (perm == perm_code(0, 1)) return leaf_test<0, 2, 1, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+        if (perm == perm_code(0, 2)) return leaf_test<0, 1, 2, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+        if (perm == perm_code(1, 2)) return leaf_test<1, 0, 2, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+    }
+    leaf_test<-1, -1, -1, kAny>(sc, r, first, count, tb, ib, sb, tl, ref);
+}
+
 // stk points at this lane's column of the block's LDS stack (stride B).
 // Closest hit (kAny = false): smallest (t, triangle id); returns the stored
-// slot or -1.  Any hit with t > 0 (kAny = true): returns 1 or -1.
-template <int B, int S, bool kAny, bool kCount, bool kFma>
+// slot or -1.  Any hit with t > 0 (kAny = true): returns 1 or -1.  With
+// kPerm, perm is the rays' axis permutation (perm_code) when every lane of
+// the wave shares it, else -1.
+template <int B, int S, bool kAny, bool kCount, bool kFma, bool kPerm>
 __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
-                             WorkCount& wc) {
+                             WorkCount& wc, int perm) {
     t_best = INFINITY;
     id_best = -1;
     // entries 0 .. kLds-1 in the lane's LDS column, the rest in scratch (the
-    // two kept in separate branches so that the common case stays an LDS
-    // access rather than a generic one; volatile keeps the rarely used
-    // spill area in memory instead of in registers)
+    // two kept in separate branches and address spaces, so that the common
+    // case stays an LDS access and the rare one a scratch access, neither a
+    // generic one; volatile keeps the spill area in memory instead of in
+    // registers)
     constexpr int kLds = lds_entries(S);
-    volatile int spill[S + kStackSpill - kLds];
+    int spill_mem[S + kStackSpill - kLds];
+    volatile __attribute__((address_space(5))) int* spill =
+        (volatile __attribute__((address_space(5))) int*)spill_mem;
     auto push = [&](int sp_, int v) {
         if (sp_ < kLds) {
             ((__attribute__((address_space(3))) int*)(stk))[sp_ * B] = v;
@@ -299,26 +368,8 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
             const int x = ~parked;
             parked = 0;
             const int first = x >> 3, count = (x & 7) + 1;
-            const float4* tp = sc.tris + 3 * (size_t)first;
             if (kCount) wc.tris += count;
-            for (int q = 0; q < count; ++q) {
-                const float4 v0 = ldg4(tp, 3 * q), v1 = ldg4(tp, 3 * q + 1), v2 = ldg4(tp, 3 * q + 2);
-                float t;
-                if (tri_hit(r, v0, v1, v2, t)) {
-                    if (kAny) {
-                        slot_best = 1;
-                        ref = kEmptyRef;
-                        break;
-                    }
-                    const int id = __float_as_int(v0.w);
-                    if (t < t_best || (t == t_best && id < id_best)) {
-                        t_best = t;
-                        id_best = id;
-                        slot_best = first + q;
-                        tlim = t * kHitSlack;
-                    }
-                }
-            }
+            leaf_step<kAny, kPerm>(perm, sc, r, first, count, t_best, id_best, slot_best, tlim, ref);
         }
     }
     return slot_best;
@@ -326,27 +377,39 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
 
 // The FMA slab test is taken when every lane's origin is within the
 // scene's limit (wave-uniform choice, so both loops run without divergence).
-template <int B, int S, bool kAny, bool kCount>
+// kPerm: the triangle test's axis permutation is fixed for the whole
+// traversal when every active lane shares it -- always for shadow rays (one
+// light direction), and for most waves of primary rays (a wave covers a
+// small screen patch).  Kernels that also trace paths leave it off: their
+// bounce rays rarely share it, and the extra code costs them registers.
+template <int B, int S, bool kAny, bool kCount, bool kPerm>
 __device__ __forceinline__ int traverse(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
                                         WorkCount& wc) {
     const float om = fmaxf(fmaxf(fabsf(r.ox), fabsf(r.oy)), fabsf(r.oz));
     const float oi = fmaxf(fmaxf(fabsf(r.oix), fabsf(r.oiy)), fabsf(r.oiz));
     const bool fma_ok = om <= sc.fma_origin_limit && oi <= 3.0e38f;
-    if (__ballot(!fma_ok) == 0) return traverse_loop<B, S, kAny, kCount, true>(sc, r, stk, t_best, id_best, wc);
-    return traverse_loop<B, S, kAny, kCount, false>(sc, r, stk, t_best, id_best, wc);
+    int perm = -1;
+    if (kPerm) {
+        const int pc = perm_code(r.kx, r.kz);
+        const int p0 = __builtin_amdgcn_readfirstlane(pc);
+        perm = __ballot(pc != p0) == 0 ? p0 : -1;
+    }
+    if (__ballot(!fma_ok) == 0)
+        return traverse_loop<B, S, kAny, kCount, true, kPerm>(sc, r, stk, t_best, id_best, wc, perm);
+    return traverse_loop<B, S, kAny, kCount, false, kPerm>(sc, r, stk, t_best, id_best, wc, perm);
 }
 
-template <int B, int S, bool kCount>
+template <int B, int S, bool kCount, bool kPerm = false>
 __device__ __forceinline__ int closest_hit(const TraceView& sc, const RayPre& r, int* stk, float& t_best,
                                            int& id_best, WorkCount& wc) {
-    return traverse<B, S, false, kCount>(sc, r, stk, t_best, id_best, wc);
+    return traverse<B, S, false, kCount, kPerm>(sc, r, stk, t_best, id_best, wc);
 }
 
-template <int B, int S, bool kCount>
+template <int B, int S, bool kCount, bool kPerm = false>
 __device__ __forceinline__ bool any_hit(const TraceView& sc, const RayPre& r, int* stk, WorkCount& wc) {
     float t;
     int id;
-    return traverse<B, S, true, kCount>(sc, r, stk, t, id, wc) >= 0;
+    return traverse<B, S, true, kCount, kPerm>(sc, r, stk, t, id, wc) >= 0;
 }
 
 // 32-bit hash of Jarzynski and Olano, "Hash Functions for GPU Rendering",
@@ -477,13 +540,13 @@ __device__ __forceinline__ bool make_item_ray(const TraceView& v, int64_t k, Ray
     return true;
 }
 
-template <int B, int S, bool kCount>
+template <int B, int S, bool kCount, bool kPerm>
 __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, int& id_out, WorkCount& wc,
                                 uint32_t& n_shadow, float4& p_out) {
     const TraceView& sc = v;
     float t;
     int id;
-    const int slot = closest_hit<B, S, kCount>(sc, r, stk, t, id, wc);
+    const int slot = closest_hit<B, S, kCount, kPerm>(sc, r, stk, t, id, wc);
     id_out = id;
     p_out = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     if (slot < 0) return make_float4(v.background[0], v.background[1], v.background[2], 1.0f);
@@ -497,7 +560,7 @@ __device__ float4 shade_lambert(const TraceView& v, const RayPre& r, int* stk, i
         RayPre s;
         ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
         ++n_shadow;
-        if (any_hit<B, S, kCount>(sc, s, stk, wc)) vis = 0.0f;
+        if (any_hit<B, S, kCount, kPerm>(sc, s, stk, wc)) vis = 0.0f;
     }
     const float lam = ndl > 0.0f ? ndl : 0.0f;
     const float3 a = albedo_of(id);
@@ -684,7 +747,7 @@ __device__ __forceinline__ void trace_item(const TraceView& v, int64_t k, int* s
     if (!kLambert && !kPhased && v.shade_mode == VAFR_SHADE_PATH)
         c = shade_path<B, S, kCount>(v, r, (uint32_t)out, stk, id, wc, n_shadow, p);
     else
-        c = shade_lambert<B, S, kCount>(v, r, stk, id, wc, n_shadow, p);
+        c = shade_lambert<B, S, kCount, kLambert>(v, r, stk, id, wc, n_shadow, p);
     if (kCount) {
         atomicAdd(counters + 0, 1ull);
         atomicAdd(counters + 1, (unsigned long long)n_shadow);

@@ -452,6 +452,52 @@ def test_far_eye_takes_both_slab_tests(env, O, soup, scene, dist):
     assert diff[unf].max() <= COLOR_TOL
 
 
+@pytest.fixture(scope="module")
+def cell_grid(env, O):
+    """One random triangle strictly inside each cell of a 16^3 grid over
+    [-1, 1]^3: no two triangles meet, so no ray is a near tie between
+    crossing surfaces, and the scene looks alike from every axis."""
+    torch, V = env
+    rng = np.random.default_rng(17)
+    n = 16
+    cells = np.stack(np.meshgrid(*[np.arange(n)] * 3, indexing="ij"), -1).reshape(-1, 3).astype(np.float64)
+    v = ((cells[:, None, :] + rng.uniform(0.1, 0.9, (len(cells), 3, 3))) * (2.0 / n) - 1.0).astype(np.float32)
+    v = v.reshape(-1, 3)
+    f = np.arange(len(v), dtype=np.int32).reshape(-1, 3)
+    return V.Scene(v, f), O.Scene(v, f)
+
+
+@pytest.mark.parametrize("axis,sign", [(a, sg) for a in range(3) for sg in (1.0, -1.0)])
+def test_every_axis_permutation_of_the_triangle_test(env, O, cell_grid, axis, sign):
+    """Views straight along +-x, +-y, +-z with a 40 deg field: every primary
+    ray of a view has the same dominant axis and sign, i.e. the same axis
+    permutation of the watertight test, which the Lambert kernels then fix
+    for the whole wave; the light's dominant axis is the next one with the
+    same sign, so over the six views the shadow rays take all six
+    permutations as well.  Hit ids and colours equal the oracle's on every
+    unflagged pixel, as with per-lane permutations."""
+    torch, V = env
+    g_sc, o_sc = cell_grid
+    W = H = 160
+    fwd = np.zeros(3)
+    fwd[axis] = sign
+    up = np.array([0.0, 0.0, 1.0]) if axis == 1 else np.array([0.0, 1.0, 0.0])
+    right = np.cross(up, fwd)
+    right /= np.linalg.norm(right)
+    cam = np.concatenate([-3.0 * fwd, right, np.cross(fwd, right), fwd]).astype(np.float32)
+    light = np.full(3, 0.25)
+    light[(axis + 1) % 3] = sign
+    sh = V.shading(light_dir=light)
+    img = torch.empty((H * W, 4), device="cuda", dtype=torch.float32)
+    hid = torch.empty(H * W, device="cuda", dtype=torch.int32)
+    V.full_shade(g_sc, V.camera(cam), V.display(W, H, (40.0, 40.0)), sh, img, hid)
+    torch.cuda.synchronize()
+    o_rgba, o_id, o_fl = O.shade_full_pixels(o_sc, np.arange(W * H), W, H, (40.0, 40.0), cam,
+                                             O.shading_params(light_dir=light))
+    assert (o_id >= 0).mean() > 0.4
+    _compare(f"axis {axis} sign {sign:+.0f}", img.cpu().numpy(), hid.cpu().numpy(), o_rgba, o_id, o_fl)
+
+
 def test_degenerate_and_coincident_triangles(env, O, layout):
     """Zero-area triangles never hit; coincident duplicates resolve to the
     smaller id; rays through shared edges of a closed mesh never miss."""
