@@ -273,7 +273,7 @@ def main():
     # traversal (throughput up, per-frame latency up)
     if not args.no_pipelined:
         out["pipelined"] = pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm,
-                                            max(MIN_PIPELINED_FRAMES, min(steps, 600)))
+                                            max(MIN_PIPELINED_FRAMES, min(steps, 600)), tuned)
     # ------------------------------------------------------------ comparisons
     if not args.no_compare:
         # full resolution: one primary + shadow ray per display pixel, per eye
@@ -351,7 +351,8 @@ def main():
     if not args.no_compare:
         out["batch16"] = batch16(torch, V, I, scene, sh, csteps)
         out["layouts"] = layout_variants(torch, V, I, scene, sh, cams, gazes, warm, max(20, csteps), tuned)
-        out["resolutions"] = resolution_sweep(torch, V, I, scene, sh, cams, max(60, 10 * csteps), max(2, csteps))
+        out["resolutions"] = resolution_sweep(torch, V, I, scene, sh, cams, max(60, 10 * csteps), max(2, csteps),
+                                              tuned)
 
     # ------------------------------------------------------------ serving
     if args.serve_seconds > 0:
@@ -418,16 +419,18 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm, steps):
+def pipelined_frames(torch, V, scene, cams, sh, L, gazes, warm, steps, shape):
     """Binocular 8K frames with two in flight: frame f runs as one batched
-    frame on stream f mod 2, into its own LP buffers and display images, so
-    the GPU overlaps one frame's reconstruction (HBM-bound) with the next
-    frame's traversal (VALU-bound).  Reports frames/s over the whole run and
-    each frame's own duration (its events on its stream)."""
+    frame on stream f mod 2 (the headline's autotuned launch shape), into its
+    own LP buffers and display images, so the GPU overlaps one frame's
+    reconstruction (HBM-bound) with the next frame's traversal (VALU-bound).
+    Reports frames/s over the whole run and each frame's own duration (its
+    events on its stream)."""
     lp = [[torch.empty((L.n_texels, 4), device="cuda") for _ in range(2)] for _ in range(2)]
     img = [[torch.empty((H * W, 4), device="cuda") for _ in range(2)] for _ in range(2)]
     streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
-    batches = [V.Batch(2, trace_block=128, recon_rows=8, use_graph=True) for _ in range(2)]
+    batches = [V.Batch(2, trace_block=shape["trace_block"], recon_rows=shape["recon_rows"], use_graph=True)
+               for _ in range(2)]
 
     def frame(f, k, ev=None):
         if ev is not None:
@@ -602,10 +605,10 @@ def rep_bench(torch, V, scene, cams, sh, L, gazes, steps):
 ANISO_EXAMPLE = ((0.0, 30.0), (1.0, 0.5))
 
 
-def resolution_sweep(torch, V, I, scene, sh, cams, steps, full_steps):
+def resolution_sweep(torch, V, I, scene, sh, cams, steps, full_steps, shape):
     """Binocular frames at the display sizes of Table 1 (2K, 4K, 6K, 8K and
     retinal 11520 x 6480 per eye): batched VaFR (same LP buffer at every
-    size; launch shape fixed at trace 128, reconstruction 8 rows) against
+    size; the headline's autotuned launch shape) against
     the full-resolution ray cast (one primary + shadow ray per pixel).  Each
     size uses the seeded gaze trace scaled to its display."""
     sizes = [(2560, 1440), (3840, 2160), (5760, 3240), (7680, 4320), (11520, 6480)]
@@ -618,7 +621,7 @@ def resolution_sweep(torch, V, I, scene, sh, cams, steps, full_steps):
         gz = [V.gaze(float(x), float(y)) for x, y in tr]
         lp = [torch.empty((Ld.n_texels, 4), device="cuda") for _ in range(2)]
         img = [torch.empty((Hd * Wd, 4), device="cuda") for _ in range(2)]
-        b = V.Batch(2, trace_block=128, recon_rows=8, use_graph=True)
+        b = V.Batch(2, trace_block=shape["trace_block"], recon_rows=shape["recon_rows"], use_graph=True)
 
         def frame(f):
             b.run([V.view(V.VAFR_VIEW_VAFR, scene, cams[e], gz[f], sh, layout=Ld, lp_rgba=lp[e], img_rgba=img[e])

@@ -386,11 +386,14 @@ int vafr_batch_create(int32_t max_views, const vafr_batch_config* cfg, vafr_batc
 /* One frame of n_views views on `stream`: ONE traversal launch covering the
  * rays of every view (workgroups are assigned to views by a running count)
  * and ONE reconstruction launch covering every display of the VaFR / LMFR
- * views.  Path-mode views run in phases: bounce 0 in the traversal launch,
- * and bounce b >= 1 in a launch of its own over the paths still alive, one
- * per thread; between launches each path's state (next ray, throughput,
- * radiance) lives in memory the batch allocates, 72 bytes per ray of those
- * views, per descriptor slot on first use.  With
+ * views.  Two VaFR views with the same layout, gaze and display (the eyes of
+ * a binocular frame) share their reconstruction workgroups: each pixel's
+ * texel positions and weights are found once and applied to both LP
+ * buffers.  Path-mode views run in phases: bounces 0 and 1 in the traversal
+ * launch, and each bounce b >= 2 in a launch of its own over the paths still
+ * alive, one per thread; between launches each path's state (next ray,
+ * throughput, radiance) lives in memory the batch allocates, 72 bytes per
+ * ray of those views, per descriptor slot on first use.  With
  * use_graph the sequence (descriptor upload, kernels) is a hipGraph built
  * once per launch shape; later frames only update the node parameters and
  * replay it.  Results are identical to the per-view calls.  Blocks the host

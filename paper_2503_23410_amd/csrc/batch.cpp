@@ -107,7 +107,18 @@ void free_graphs(vafr_batch b) {
     b->graphs.clear();
 }
 
-// Descriptors of one frame into b->tv/tb/rv/rb.
+// Views whose reconstruction can share one pass: VaFR views with the same
+// layout tables, gaze and display (the two eyes of a binocular frame), the
+// first not yet paired.
+bool pairable(const ReconView& a, const ReconView& b) {
+    return a.mode == kModeVafr && b.mode == kModeVafr && !a.lp2 && a.u_of_rho == b.u_of_rho && a.col == b.col &&
+           a.n_cols == b.n_cols && a.lp_bytes == b.lp_bytes && a.width == b.width && a.height == b.height &&
+           a.sx == b.sx && a.sy == b.sy && a.cx == b.cx && a.cy == b.cy && a.rho_scale == b.rho_scale &&
+           a.img != b.img;
+}
+
+// Descriptors of one frame into b->tv/tb/rv/rb.  A view whose reconstruction
+// pairs with the previous reconstruction descriptor rides along in it.
 int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blocks, int32_t* recon_blocks,
              int32_t* queue_blocks) {
     b->tv.clear();
@@ -161,6 +172,11 @@ int describe(vafr_batch b, const vafr_view* views, int32_t n, int32_t* trace_blo
         if (w.kind != VAFR_VIEW_FULL && w.img_rgba_dev) {
             ReconView r;
             if (int rc2 = make_recon_view(w.layout, w.gaze, w.lp_rgba_dev, w.img_rgba_dev, &r)) return rc2;
+            if (!b->rv.empty() && pairable(b->rv.back(), r)) {
+                b->rv.back().lp2 = r.lp;
+                b->rv.back().img2 = r.img;
+                continue;
+            }
             rsum += recon_blocks_of(r, b->cfg.recon_rows);
             if (rsum > 0x7fffffff) return fail(VAFR_E_UNSUPPORTED, "too many pixels in one batch");
             b->rv.push_back(r);

@@ -18,6 +18,12 @@
 // the gaze point, where one display pixel maps to about one texel or the
 // tile surrounds the gaze -- read every texel from the LP buffer.
 //
+// A view may carry a second LP buffer and image with the same layout, gaze
+// and display (the other eye of a binocular frame): every pixel then reads
+// the same four texel positions with the same weights in both buffers, so
+// the tile stages both (half of the LDS budget each) and maps each pixel
+// once for both images.
+//
 // Tiles are taken in row-major order of the workgroup id, so the eight XCDs
 // (which receive consecutive ids in turn) write neighbouring tiles of the
 // same tile row at the same time.  Giving each XCD a contiguous band of rows
@@ -141,14 +147,24 @@ struct Stage {
     int total;              // staged texels
 };
 
-// Texel j of the column described by (off, n, j_start, cnt, base): from LDS
-// when staged, else from the LP buffer.
-__device__ __forceinline__ float4 texel(const Stage& st, __amdgpu_buffer_rsrc_t lp, uint32_t off, int n, int js,
-                                        int cnt, int base, int j) {
+// Where texel j of the column described by (off, n, j_start, cnt, base)
+// is: its LDS index when staged (else -1), and its LP byte offset.
+struct Tap {
+    int lds;
+    uint32_t src;
+};
+
+__device__ __forceinline__ Tap tap_of(uint32_t off, int n, int js, int cnt, int base, int j) {
     int rel = j - js;
     rel = rel < 0 ? rel + n : rel;
-    if (rel < cnt) return st.tex[base + rel];
-    return ld4(lp, (off + (uint32_t)j) * 16u);
+    return Tap{rel < cnt ? base + rel : -1, (off + (uint32_t)j) * 16u};
+}
+
+// The texel of tap t in the LP buffer whose staged copy starts at LDS
+// texel `half` (0, or kStageTexels / 2 for the second buffer of a pair).
+__device__ __forceinline__ float4 texel(const Stage& st, __amdgpu_buffer_rsrc_t lp, int half, const Tap& t) {
+    if (t.lds >= 0) return st.tex[half + t.lds];
+    return ld4(lp, t.src);
 }
 
 // Column i's (offset, rows, staged range): staged columns from LDS, others
@@ -174,9 +190,12 @@ __device__ __forceinline__ void column_of(const Stage& st, __amdgpu_buffer_rsrc_
 }
 
 // Pixel at film offset (dx, dy) from the gaze point whose column coordinate
-// a = u - 0.5 is already known.
-__device__ __forceinline__ float4 sample_vafr(const ReconView& v, const Stage& st, __amdgpu_buffer_rsrc_t lp,
-                                              __amdgpu_buffer_rsrc_t ct, float dx, float dy, float a) {
+// a = u - 0.5 is already known: c from the LP buffer lp and, with kPair, c2
+// from the paired buffer lp2 (same positions and weights).
+template <bool kPair>
+__device__ __forceinline__ void sample_vafr(const ReconView& v, const Stage& st, __amdgpu_buffer_rsrc_t lp,
+                                            __amdgpu_buffer_rsrc_t lp2, __amdgpu_buffer_rsrc_t ct, float dx,
+                                            float dy, float a, float4& c, float4& c2) {
     int i0 = (int)a;
     i0 = i0 > v.n_cols - 1 ? v.n_cols - 1 : (i0 < 0 ? 0 : i0);
     const int i1 = i0 + 1 < v.n_cols ? i0 + 1 : v.n_cols - 1;
@@ -190,12 +209,17 @@ __device__ __forceinline__ float4 sample_vafr(const ReconView& v, const Stage& s
     float t0, t1;
     column_rows(n0, turns, j00, j01, t0);
     column_rows(n1, turns, j10, j11, t1);
-    const float4 A = texel(st, lp, off0, n0, js0, cnt0, base0, j00);
-    const float4 B = texel(st, lp, off0, n0, js0, cnt0, base0, j01);
-    const float4 C = texel(st, lp, off1, n1, js1, cnt1, base1, j10);
-    const float4 D = texel(st, lp, off1, n1, js1, cnt1, base1, j11);
+    const Tap ta = tap_of(off0, n0, js0, cnt0, base0, j00), tb = tap_of(off0, n0, js0, cnt0, base0, j01);
+    const Tap tc = tap_of(off1, n1, js1, cnt1, base1, j10), td = tap_of(off1, n1, js1, cnt1, base1, j11);
     const float w0 = 1.0f - w;
-    return blend4(A, w0 - w0 * t0, B, w0 * t0, C, w - w * t1, D, w * t1);
+    const float wa = w0 - w0 * t0, wb = w0 * t0, wc = w - w * t1, wd = w * t1;
+    c = blend4(texel(st, lp, 0, ta), wa, texel(st, lp, 0, tb), wb, texel(st, lp, 0, tc), wc, texel(st, lp, 0, td),
+               wd);
+    if (kPair) {
+        constexpr int h = kStageTexels / 2;
+        c2 = blend4(texel(st, lp2, h, ta), wa, texel(st, lp2, h, tb), wb, texel(st, lp2, h, tc), wc,
+                    texel(st, lp2, h, td), wd);
+    }
 }
 
 // u / w of the LaFR kernel (Sec. 4.1 Eq. (15)) at log ratio z in [0, 1] of
@@ -250,7 +274,7 @@ __device__ __forceinline__ float4 sample_lmfr(const ReconView& v, __amdgpu_buffe
 // offsets [xl, xh] x [yl, yh] from the gaze point, written to st.col, and
 // st.i_lo / st.n_cols (n_cols = 0 when the footprint does not fit).
 __device__ void build_stage(const ReconView& v, Stage& st, __amdgpu_buffer_rsrc_t ut, __amdgpu_buffer_rsrc_t ct,
-                            float xl, float xh, float yl, float yh) {
+                            float xl, float xh, float yl, float yh, int budget) {
     const int lane = threadIdx.x;
     int n_cols = 0, i_lo = 0, total = 0;
     const bool around_gaze = xl <= 0.0f && xh >= 0.0f && yl <= 0.0f && yh >= 0.0f;
@@ -307,7 +331,7 @@ __device__ void build_stage(const ReconView& v, Stage& st, __amdgpu_buffer_rsrc_
             if (lane >= d) incl += o;
         }
         total = __shfl(incl, 63, 64);
-        if (total > kStageTexels || __ballot(n_cols == 0) != 0) n_cols = 0;
+        if (total > budget || __ballot(n_cols == 0) != 0) n_cols = 0;
         if (n_cols == 0) total = 0;
         if (lane < n_cols) {
             StageCol sc;
@@ -342,26 +366,38 @@ __device__ __forceinline__ uint32_t stage_source(const Stage& st, int k) {
 }
 
 // Thread t copies staged texels t, t + 256, ...: all of its loads are issued
-// before the first LDS write, so the copy costs one memory latency.
-__device__ __forceinline__ void fill_stage(Stage& st, __amdgpu_buffer_rsrc_t lp) {
-    constexpr int kPer = kStageTexels / kReconThreads;
+// before the first LDS write, so the copy costs one memory latency.  With
+// kPair (at most kStageTexels / 2 texels staged) the same texels of lp2 go
+// to the upper half.
+template <bool kPair>
+__device__ __forceinline__ void fill_stage(Stage& st, __amdgpu_buffer_rsrc_t lp, __amdgpu_buffer_rsrc_t lp2) {
+    constexpr int kPer = (kPair ? kStageTexels / 2 : kStageTexels) / kReconThreads;
+    constexpr int h = kStageTexels / 2;
     const int total = st.total;
-    float4 t[kPer];
+    float4 t[kPer], t2[kPair ? kPer : 1];
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
         const int k = threadIdx.x + m * kReconThreads;
-        if (k < total) t[m] = ld4(lp, stage_source(st, k) * 16u);
+        if (k < total) {
+            const uint32_t src = stage_source(st, k) * 16u;
+            t[m] = ld4(lp, src);
+            if (kPair) t2[m] = ld4(lp2, src);
+        }
     }
 #pragma unroll
     for (int m = 0; m < kPer; ++m) {
         const int k = threadIdx.x + m * kReconThreads;
-        if (k < total) st.tex[k] = t[m];
+        if (k < total) {
+            st.tex[k] = t[m];
+            if (kPair) st.tex[h + k] = t2[m];
+        }
     }
 }
 
 // Tile `id` of view v: 64 x 4P pixels, P rows per wave.  M is the mapping
-// (kModeVafr / kModeLmfr) or -1 to read it from the view.
-template <int P, int M>
+// (kModeVafr / kModeLmfr) or -1 to read it from the view.  kPair: a VaFR
+// view with a paired buffer (v.lp2, v.img2), written in the same pass.
+template <int P, int M, bool kPair = false>
 __device__ __forceinline__ void recon_tile(const ReconView& v, int id, Stage& st) {
     constexpr int kTileH = kWaves * P;
     const int nbx = (v.width + kTileW - 1) / kTileW;
@@ -381,10 +417,14 @@ __device__ __forceinline__ void recon_tile(const ReconView& v, int id, Stage& st
         if (wave == 0) {
             const int x_hi = bx * kTileW + kTileW - 1 < v.width - 1 ? bx * kTileW + kTileW - 1 : v.width - 1;
             build_stage(v, st, ut, ct, fmaf((float)(bx * kTileW), v.sx, v.cx), fmaf((float)x_hi, v.sx, v.cx),
-                        fmaf((float)y0, v.sy, v.cy), fmaf((float)(y0 + rows - 1), v.sy, v.cy));
+                        fmaf((float)y0, v.sy, v.cy), fmaf((float)(y0 + rows - 1), v.sy, v.cy),
+                        kPair ? kStageTexels / 2 : kStageTexels);
         }
+        const __amdgpu_buffer_rsrc_t lp2 = rsrc(kPair ? v.lp2 : v.lp, v.lp_bytes);
+        const __amdgpu_buffer_rsrc_t img2 =
+            rsrc((kPair ? v.img2 : v.img) + (size_t)y0 * v.width, (uint32_t)(rows * v.width) * 16u);
         __syncthreads();
-        fill_stage(st, lp);
+        fill_stage<kPair>(st, lp, lp2);
         __syncthreads();
         if (x >= v.width) return;
         const float dx = fmaf((float)x, v.sx, v.cx);
@@ -405,7 +445,10 @@ __device__ __forceinline__ void recon_tile(const ReconView& v, int id, Stage& st
                 const float dy = fmaf((float)(y0 + ty), v.sy, v.cy);
                 const float k = (float)(int)tq[r];
                 const float a = fmaf(tq[r] - k, __uint_as_float(uk[r].y), __uint_as_float(uk[r].x)) - 0.5f;
-                store_px(img, (uint32_t)(ty * v.width + x) * 16u, sample_vafr(v, st, lp, ct, dx, dy, a));
+                float4 c, c2;
+                sample_vafr<kPair>(v, st, lp, lp2, ct, dx, dy, a, c, c2);
+                store_px(img, (uint32_t)(ty * v.width + x) * 16u, c);
+                if (kPair) store_px(img2, (uint32_t)(ty * v.width + x) * 16u, c2);
             }
         }
     } else {
@@ -433,7 +476,9 @@ __global__ __launch_bounds__(kReconThreads) void k_recon_batch(const ReconView* 
     int vid = 0;
     while (vid + 1 < n_views && b >= block_end[vid]) ++vid;
     const int first = vid ? block_end[vid - 1] : 0;
-    recon_tile<P, -1>(views[vid], b - first, st);
+    const ReconView& v = views[vid];
+    if (v.lp2) recon_tile<P, kModeVafr, true>(v, b - first, st);
+    else recon_tile<P, -1>(v, b - first, st);
 }
 
 }  // namespace

@@ -290,6 +290,10 @@ struct ReconView {
     const float4* lp;
     uint32_t lp_bytes;  // < 2^32
     float4* img;
+    // batched frames: a second VaFR view with the same layout, gaze and
+    // display (the other eye), reconstructed in the same pass; or null
+    const float4* lp2;
+    float4* img2;
 };
 
 // Reconstruction workgroups have kReconThreads threads (4 waves); `rows` is

@@ -119,6 +119,44 @@ def test_batch_equals_individual_calls(env, scene):
     log("batch of 16 views equals the per-view calls (eager and graph)")
 
 
+@pytest.mark.parametrize("rows", [1, 4, 8])
+def test_paired_reconstruction_equals_individual_calls(env, scene, rows):
+    """VaFR views that share one layout object and one gaze (binocular eyes)
+    are reconstructed in shared workgroups.  Views: a pair on a ragged
+    1000x563 display; a pair plus a third view with the same gaze (it stays
+    single, since a descriptor holds one partner); a view with its own gaze;
+    an LMFR view between them.  Every image, LP buffer and hit id equals the
+    per-view calls bit for bit, eager and graph, at every tile height."""
+    torch, V = env
+    d1, d2 = V.display(1000, 563, I.FOV), V.display(1920, 1080, I.FOV)
+    L1, L2 = V.Layout.vafr(d1), V.Layout.vafr(d2)
+    Lm = V.Layout.lmfr(d2, 1.8, 4.0)
+    cl, cr = I.binocular_cameras()
+    specs = [(V.VAFR_VIEW_VAFR, d1, L1, (420.5, 300.25), cl), (V.VAFR_VIEW_VAFR, d1, L1, (420.5, 300.25), cr),
+             (V.VAFR_VIEW_VAFR, d2, L2, (700.0, 500.0), cl), (V.VAFR_VIEW_VAFR, d2, L2, (700.0, 500.0), cr),
+             (V.VAFR_VIEW_VAFR, d2, L2, (700.0, 500.0), I.terrain_camera(0.05)),
+             (V.VAFR_VIEW_LMFR, d2, Lm, (700.0, 500.0), cl),
+             (V.VAFR_VIEW_VAFR, d2, L2, (-50.0, 1200.0), cr)]
+    vs = []
+    for kind, d, L, gz, cam in specs:
+        vs.append(dict(kind=kind, disp=d, layout=L, lp=torch.full((L.n_texels, 4), -1.0, device="cuda"),
+                       hit=torch.full((L.n_texels,), -7, device="cuda", dtype=torch.int32),
+                       img=torch.full((d.width * d.height, 4), -1.0, device="cuda"), gaze=V.gaze(*gz),
+                       cam=V.camera(cam)))
+    sh = V.shading()
+    _run_individual(V, scene, vs, sh)
+    torch.cuda.synchronize()
+    ref = _snapshot(vs)
+    for use_graph in (False, True):
+        b = V.Batch(8, trace_block=128, recon_rows=rows, use_graph=use_graph)
+        for rep in range(2):
+            _clear(torch, vs)
+            b.run(_descs(V, scene, vs, sh))
+            torch.cuda.synchronize()
+            _assert_equal(torch, ref, vs, f"rows={rows} graph={use_graph} run {rep}")
+        b.close()
+
+
 def test_graph_replays_track_parameter_updates(env, scene):
     """Replay the captured frame with new gazes and cameras each time, with
     eager work between replays; every replay equals the eager result."""
