@@ -380,8 +380,9 @@ __device__ int traverse_loop(const TraceView& sc, const RayPre& r, int* stk, flo
 // kPerm: the triangle test's axis permutation is fixed for the whole
 // traversal when every active lane shares it -- always for shadow rays (one
 // light direction), and for most waves of primary rays (a wave covers a
-// small screen patch).  Kernels that also trace paths leave it off: their
-// bounce rays rarely share it, and the extra code costs them registers.
+// small screen patch).  The phased path kernels take it for their shadow
+// rays only: bounce rays rarely share a permutation, and fixing it for
+// every traversal there cost more in registers than it saved.
 template <int B, int S, bool kAny, bool kCount, bool kPerm>
 __device__ __forceinline__ int traverse(const TraceView& sc, const RayPre& r, int* stk, float& t_best, int& id_best,
                                         WorkCount& wc) {
@@ -703,7 +704,7 @@ __device__ bool path_bounce(const TraceView& v, RayPre& r, int32_t p, int32_t ou
     if (ndl > 0.0f) {
         RayPre s;
         ray_setup(os.x, os.y, os.z, v.light_dir[0], v.light_dir[1], v.light_dir[2], s);
-        vis = any_hit<B, S, false>(v, s, stk, wc) ? 0.0f : 1.0f;
+        vis = any_hit<B, S, false, true>(v, s, stk, wc) ? 0.0f : 1.0f;
     }
     state_fence();
     const float4 th = st[2], lr = st[3];
