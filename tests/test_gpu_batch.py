@@ -157,6 +157,51 @@ def test_paired_reconstruction_equals_individual_calls(env, scene, rows):
         b.close()
 
 
+def test_largest_batch_equals_individual_calls(env, scene):
+    """The batch's limit of 256 views, on small displays (1x1 to 97x61):
+    VaFR views in binocular pairs (shared layout and gaze), single VaFR
+    views with their own gaze, LMFR and full-resolution views (displays of
+    33x17 and up), eager and graph; every output equals the per-view calls
+    bit for bit, and a 257th view is refused."""
+    torch, V = env
+    rng = np.random.default_rng(256)
+    sizes = [(1, 1), (7, 5), (33, 17), (64, 16), (97, 61)]
+    layouts = {sz: V.Layout.vafr(V.display(sz[0], sz[1], I.FOV)) for sz in sizes}
+    cl, cr = I.binocular_cameras()
+    vs = []
+    while len(vs) < 256:
+        W, H = sizes[int(rng.integers(len(sizes)))]
+        d = V.display(W, H, I.FOV)
+        gz = (float(rng.uniform(-0.2, 1.2) * W), float(rng.uniform(-0.2, 1.2) * H))
+        kind = int(rng.choice([V.VAFR_VIEW_VAFR, V.VAFR_VIEW_VAFR, V.VAFR_VIEW_LMFR, V.VAFR_VIEW_FULL]))
+        if W * H < 33 * 17:
+            kind = V.VAFR_VIEW_VAFR                  # the LMFR map needs a few pixels of extent
+        pair = kind == V.VAFR_VIEW_VAFR and len(vs) < 255 and rng.random() < 0.6
+        for cam in ((cl, cr) if pair else (I.terrain_camera(float(rng.uniform(0.0, 0.1))),)):
+            L = (layouts[(W, H)] if kind == V.VAFR_VIEW_VAFR else
+                 V.Layout.lmfr(d, 1.8, 4.0) if kind == V.VAFR_VIEW_LMFR else None)
+            n = L.n_texels if L is not None else W * H
+            vs.append(dict(kind=kind, disp=d, layout=L,
+                           lp=None if L is None else torch.full((L.n_texels, 4), -1.0, device="cuda"),
+                           hit=torch.full((n,), -7, device="cuda", dtype=torch.int32),
+                           img=torch.full((W * H, 4), -1.0, device="cuda"), gaze=V.gaze(*gz), cam=V.camera(cam)))
+    assert len(vs) == 256
+    sh = V.shading()
+    _run_individual(V, scene, vs, sh)
+    torch.cuda.synchronize()
+    ref = _snapshot(vs)
+    for use_graph in (False, True):
+        b = V.Batch(256, use_graph=use_graph)
+        for rep in range(2):
+            _clear(torch, vs)
+            b.run(_descs(V, scene, vs, sh))
+            torch.cuda.synchronize()
+            _assert_equal(torch, ref, vs, f"256 views graph={use_graph} run {rep}")
+        with pytest.raises(V.VafrError):
+            b.run(_descs(V, scene, vs + vs[:1], sh))
+        b.close()
+
+
 def test_graph_replays_track_parameter_updates(env, scene):
     """Replay the captured frame with new gazes and cameras each time, with
     eager work between replays; every replay equals the eager result."""
