@@ -433,7 +433,9 @@ typedef struct {
     int32_t n_streams;             /* streams the launches are spread over, 1..8 */
     int32_t max_queue;             /* waiting requests beyond which submissions are refused */
     int64_t hbm_budget_bytes;      /* bound on per-request buffers (LP buffers + display images) */
-    vafr_batch_config batch;       /* launch shape of every batch */
+    vafr_batch_config batch;       /* launch shape of every batch; use_graph = 0 suits serving (each new
+                                      mix of requests would be a new graph to instantiate on the
+                                      dispatcher thread, for little replay gain on multi-ms launches) */
     int32_t simulate;              /* 1: no GPU; a launch of R Mrays (LP texels) and P Mpixels finishes
                                       sim_ms_per_launch + R sim_ms_per_mray + P sim_ms_per_mpix after the
                                       simulated device is free (capacity planning and policy tests) */

@@ -35,6 +35,7 @@ struct Slot {
     int64_t state_cap = 0;      // capacity in paths
     hipEvent_t done = nullptr;
     bool used = false;
+    uint64_t frame = 0;         // number of the frame that last used the slot
     // stage timing (when profiling): before upload, after upload, after
     // traversal, after reconstruction
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -52,7 +53,12 @@ struct GraphEntry {
     hipGraphNode_t kqueue[vafr::kMaxBounces] = {};
     bool timed = false;
     hipGraphNode_t evn[4] = {nullptr, nullptr, nullptr, nullptr};
+    uint64_t last_frame = 0;   // frame that last launched the graph, and its slot
+    int last_slot = -1;
 };
+
+// Launch shapes kept as graphs; past this the least recently used goes.
+constexpr size_t kGraphCache = 32;
 
 }  // namespace
 }  // namespace vafr
@@ -68,6 +74,7 @@ struct vafr_batch_s {
     size_t off_tb = 0, off_rv = 0, off_rb = 0, off_qb = 0, off_qc = 0, bytes = 0;
     vafr::Slot slot[vafr::kSlots];
     int next = 0;
+    uint64_t frames = 0;             // frames run so far
     std::vector<vafr::GraphEntry> graphs;
     std::mutex mu;
     // host-side descriptors of the frame being prepared
@@ -351,10 +358,23 @@ int graph_for(vafr_batch b, int32_t trace_blocks, int32_t recon_blocks, int32_t 
             *out = &g;
             return VAFR_OK;
         }
-    if (b->graphs.size() >= 16) {   // bounded cache of launch shapes
-        for (auto& sl : b->slot)
-            if (sl.used) VAFR_HIP(hipEventSynchronize(sl.done));
-        free_graphs(b);
+    if (b->graphs.size() >= kGraphCache) {
+        // Evict the least recently used shape.  Its last launch can only be
+        // in flight if its slot has not been reused since, so at most that
+        // one frame is waited for (serving mixes change the launch shape
+        // often; waiting for every frame in flight here would stall the
+        // caller for several frames).
+        auto victim = std::min_element(b->graphs.begin(), b->graphs.end(), [](const GraphEntry& x,
+                                                                              const GraphEntry& y) {
+            return x.last_frame < y.last_frame;
+        });
+        if (victim->last_slot >= 0) {
+            const Slot& sl = b->slot[victim->last_slot];
+            if (sl.used && sl.frame == victim->last_frame) VAFR_HIP(hipEventSynchronize(sl.done));
+        }
+        if (victim->exec) (void)hipGraphExecDestroy(victim->exec);
+        if (victim->graph) (void)hipGraphDestroy(victim->graph);
+        b->graphs.erase(victim);
     }
     GraphEntry g;
     g.n_trace = nt;
@@ -449,8 +469,10 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     const bool planned = trace_plan_ok(tblocks);
     if (planned)
         if (int rc = ensure_plan(b, tblocks)) return rc;
-    Slot& s = b->slot[b->next];
+    const int si = b->next;
+    Slot& s = b->slot[si];
     b->next = (b->next + 1) % kSlots;
+    const uint64_t fno = ++b->frames;
     if (s.used) {
         VAFR_HIP(hipEventSynchronize(s.done));
         if (int rc = fold_slot(b, s)) return rc;
@@ -502,6 +524,8 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
             VAFR_HIP(hipGraphExecKernelNodeSetParams(g->exec, g->krecon, &p));
         }
         VAFR_HIP(hipGraphLaunch(g->exec, stream));
+        g->last_frame = fno;
+        g->last_slot = si;
     } else {
         if (b->profiling) VAFR_HIP(hipEventRecord(s.ev[0], stream));
         VAFR_HIP(hipMemcpyAsync(s.dev, s.host, b->bytes, hipMemcpyHostToDevice, stream));
@@ -528,6 +552,7 @@ int run_locked(vafr_batch b, const vafr_view* views, int32_t n, hipStream_t stre
     }
     VAFR_HIP(hipEventRecord(s.done, stream));
     s.used = true;
+    s.frame = fno;
     s.timed = b->profiling;
     return VAFR_OK;
 }

@@ -549,10 +549,14 @@ class Batch:
 
 class Server:
     """Owns a vafr_server: request loop with HBM-budget admission and
-    continuous batching (or its simulated executor when simulate=True)."""
+    continuous batching (or its simulated executor when simulate=True).
+    Launches default to plain kernel launches (use_graph=False): a served
+    launch carries milliseconds of device work, so graph replay saves little,
+    while every new mix of requests is a new launch shape whose graph would
+    be instantiated on the dispatcher thread."""
 
     def __init__(self, max_views_per_launch=16, max_inflight=3, n_streams=2, max_queue=64,
-                 hbm_budget_bytes=64 << 30, trace_block=128, recon_rows=4, use_graph=True, simulate=False,
+                 hbm_budget_bytes=64 << 30, trace_block=128, recon_rows=4, use_graph=False, simulate=False,
                  sim_ms_per_launch=0.05, sim_ms_per_mray=0.5, sim_ms_per_mpix=0.002, frame_budget_ms=0.0,
                  latest_only=False, watchdog_ms=0.0):
         cfg = vafr_server_config()

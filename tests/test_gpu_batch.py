@@ -202,6 +202,37 @@ def test_largest_batch_equals_individual_calls(env, scene):
         b.close()
 
 
+def test_graph_cache_evicts_and_rebuilds_launch_shapes(env, scene):
+    """More launch shapes than the batch keeps as graphs (32): 40 frames of
+    two views on displays of different sizes, then the first shapes again
+    after they were evicted, all run back to back (up to four frames in
+    flight while shapes are evicted); every frame equals the per-view calls
+    bit for bit."""
+    torch, V = env
+    sh = V.shading()
+    cl, cr = I.binocular_cameras()
+    sizes = [(40 + 7 * k, 24 + 5 * k) for k in range(40)]
+    frames = list(range(40)) + [0, 1, 2, 39]
+    per_frame = []
+    for k in frames:
+        W, H = sizes[k]
+        vs = _views(torch, V, scene, [(W, H)] * 2, [(0.4 * W, 0.6 * H)] * 2, [cl, cr],
+                    [V.VAFR_VIEW_VAFR, V.VAFR_VIEW_VAFR])
+        _run_individual(V, scene, vs, sh)
+        per_frame.append(vs)
+    torch.cuda.synchronize()
+    refs = [_snapshot(vs) for vs in per_frame]
+    for vs in per_frame:
+        _clear(torch, vs)
+    b = V.Batch(2, trace_block=128, recon_rows=4, use_graph=True)
+    for vs in per_frame:
+        b.run(_descs(V, scene, vs, sh))
+    torch.cuda.synchronize()
+    for f, (vs, ref) in enumerate(zip(per_frame, refs)):
+        _assert_equal(torch, ref, vs, f"frame {f} (shape {frames[f]})")
+    b.close()
+
+
 def test_graph_replays_track_parameter_updates(env, scene):
     """Replay the captured frame with new gazes and cameras each time, with
     eager work between replays; every replay equals the eager result."""
