@@ -1,6 +1,7 @@
 """Batched frames (one traversal launch + one reconstruction launch over many
 views, optionally replayed from a hipGraph) must give exactly the results
 of the per-view calls, which the parity tests pin to the oracle."""
+import os
 import sys
 
 import numpy as np
@@ -322,15 +323,21 @@ def test_batch_rejects_bad_views(env, scene):
     b.close()
 
 
-@pytest.mark.parametrize("case", range(6))
+# 6 cases by default; VAFR_BATCH_CASES asks for more, for a longer sweep by hand.
+N_BATCH_CASES = int(os.environ.get("VAFR_BATCH_CASES", "6"))
+
+
+@pytest.mark.parametrize("case", range(N_BATCH_CASES))
 def test_random_batches_equal_individual_calls(env, scene, case):
     """Seeded random batches: 1-12 views of random kind (VaFR, LMFR, full
     resolution), display size (1-900 px per side), gaze (on and off
     screen), camera and scene (the terrain and a small soup in one batch),
     one shading per batch (Lambert, no shadows, or path mode), random launch
-    shape, eager or graph.  Each batch runs twice (the second run follows
-    the dispatch plan the first one recorded) and must equal the per-view
-    calls bit for bit."""
+    shape, eager or graph; a VaFR view followed by another becomes a
+    binocular pair (shared layout, display and gaze) half of the time, so
+    the two share reconstruction workgroups.  Each batch runs twice (the
+    second run follows the dispatch plan the first one recorded) and must
+    equal the per-view calls bit for bit."""
     torch, V = env
     rng = np.random.default_rng(900 + case)
     sv, sf = I.soup_scene()
@@ -347,7 +354,16 @@ def test_random_batches_equal_individual_calls(env, scene, case):
         sh = V.shading(mode=V.VAFR_SHADE_PATH, bounces=int(rng.integers(0, 3)), frame=case, seed=77 + case)
     else:
         sh = V.shading(shadow=mode == 0)
+    pair = [False] + [kinds[i - 1] == kinds[i] == V.VAFR_VIEW_VAFR and rng.uniform() < 0.5 for i in range(1, n)]
+    for i in range(1, n):
+        if pair[i] and not pair[i - 1]:
+            sizes[i], gazes[i] = sizes[i - 1], gazes[i - 1]
+        else:
+            pair[i] = False
     vs = _views(torch, V, scene, sizes, gazes, cams, kinds)
+    for i in range(1, n):
+        if pair[i]:
+            vs[i]["layout"] = vs[i - 1]["layout"]
     for w, sc in zip(vs, scenes):
         w["scene"] = sc
     for w in vs:
@@ -366,7 +382,8 @@ def test_random_batches_equal_individual_calls(env, scene, case):
         torch.cuda.synchronize()
         _assert_equal(torch, ref, vs, f"case {case} run {rep} (views {n}, block {tb}, rows {rows}, graph {use_graph})")
     b.close()
-    log(f"random batch {case}: {n} views {kinds} mode {mode} block {tb} rows {rows} graph {use_graph}: equal")
+    log(f"random batch {case}: {n} views {kinds} ({sum(pair)} pairs) mode {mode} block {tb} rows {rows} "
+        f"graph {use_graph}: equal")
 
 
 @pytest.mark.parametrize("bounces", [(2, 2, 2), (3, 3, 3), (0, 0, 0), (1, 1, 1), (8, 8, 8), (2, 0, 3)])
