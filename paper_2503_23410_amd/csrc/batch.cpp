@@ -65,7 +65,7 @@ constexpr size_t kGraphCache = 32;
 
 struct vafr_batch_s {
     int32_t max_views = 0;
-    vafr_batch_config cfg{vafr::kTraceBlockDefault, vafr::kReconRowsDefault, 1};
+    vafr_batch_config cfg{vafr::kTraceBlockDefault, vafr::kBatchReconRowsDefault, 1};
     int device = -1;
     // staging layout: TraceView[], traversal block ends, ReconView[],
     // reconstruction block ends, queue-pass block ends, per view the counts

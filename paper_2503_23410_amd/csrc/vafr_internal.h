@@ -300,7 +300,8 @@ struct ReconView {
 // the number of display rows each thread writes, so a tile is 64 x 4 rows.
 constexpr int kReconThreads = 256;
 bool recon_rows_ok(int rows);
-constexpr int kReconRowsDefault = 8;
+constexpr int kReconRowsDefault = 8;        // per-view calls
+constexpr int kBatchReconRowsDefault = 4;   // batches: binocular pairs fit 64 VGPRs at 4 rows, not at 8
 int64_t recon_blocks_of(const ReconView& v, int rows);
 int launch_reconstruct(const ReconView& v, hipStream_t stream, int rows = kReconRowsDefault);
 int launch_reconstruct_batch(const ReconView* views_dev, const int32_t* block_end_dev, int32_t n_views,

@@ -234,6 +234,20 @@ def test_graph_cache_evicts_and_rebuilds_launch_shapes(env, scene):
     b.close()
 
 
+def test_null_config_gives_the_documented_defaults(env):
+    """vafr_batch_create with a NULL configuration: trace_block 128,
+    recon_rows 4, use_graph 1, as the header states."""
+    import ctypes as C
+    torch, V = env
+    lib = V.load()
+    h = C.c_void_p()
+    assert lib.vafr_batch_create(2, None, C.byref(h)) == V.VAFR_OK
+    c = V.vafr_batch_config()
+    assert lib.vafr_batch_get_config(h, C.byref(c)) == V.VAFR_OK
+    lib.vafr_batch_destroy(h)
+    assert (c.trace_block, c.recon_rows, c.use_graph) == (128, 4, 1)
+
+
 def test_graph_replays_track_parameter_updates(env, scene):
     """Replay the captured frame with new gazes and cameras each time, with
     eager work between replays; every replay equals the eager result."""
